@@ -1,0 +1,379 @@
+"""Plain FP64 CPU oracle of the IBDL hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the package smoke check and the CPU-baseline leg of the
+benchmark may import this module.  The product path (the HIP library and its
+binding) never imports, links or calls it, and it shares no code with it: the
+only common module is the seeded input generator, which holds none of the
+method's arithmetic.
+
+Everything is written to be checked by eye against the paper (Leathers & Guy,
+"Immersed Boundary Double Layer method: an introduction of methodology on the
+Helmholtz equation"):
+
+* the Peskin four-point kernel phi and delta_h             (Sec. 5.2, Eqs. (delta eqn 1)-(delta eqn 2))
+* the spread S and interpolation S*                        (Sec. 5.2, Eqs. (spread operator again2), (interpolation again))
+* the dipole spread  S~Q = div(S Q n), centred divergence  (Sec. 5.2, Eq. (Stilde); Sec. 4.1, Eq. (ibdl))
+* L = Lap_h - alpha with the 5-/7-point Laplacian on a periodic box,
+  inverted by diagonalisation with the DFT                 (Sec. 5.1; Sec. 5.3)
+* the Dirichlet operator  -S* L^-1 S~ + 1/2 I  and RHS     (Sec. 5.3, Eq. (ibdl schur again))
+* the Neumann operator    -S* L^-1 S~ - 1/2 I  and RHS     (Sec. 4.3, Eq. (Neumann saddle point))
+* the grid solution  L u = g~ - S~Q  (- S V_b for Neumann) (Sec. 4.1 step 2; Sec. 4.3, Eq. (ib neumann 1))
+* unpreconditioned GMRES on the boundary density           (Sec. 5.3)
+* the mean-zero inverse for alpha = 0                      (Sec. 5.4.2; App. C)
+* the indicator-function construction                      (App. D)
+* the discrete L1/L2 norms rescaled by |Omega|             (Sec. 5.1)
+
+Library primitives used as single steps: numpy's FFT (the DFT that diagonalises
+the periodic Laplacian) and numpy/scipy dense linear algebra in tests.
+
+Readings taken where the paper is silent (also listed in the design notes):
+node-centred grid with node i at lo + i h; the stencil wraps periodically;
+cell index c = floor((X - lo)/h) mod n computed in IEEE FP64; alpha = k^2;
+for alpha = 0 the zero Fourier mode of the solution is set to 0 (mean-zero
+inverse); GMRES starts from x0 = 0 and stops on the relative residual
+||b - A x|| / ||b|| <= tol, counting one iteration per operator application.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+DIRICHLET = 0
+NEUMANN = 1
+PESKIN4 = "peskin4"
+COSINE4 = "cosine"
+
+
+# ----------------------------------------------------------------------------
+# the discrete delta (Sec. 5.2)
+# ----------------------------------------------------------------------------
+def phi_peskin4(r):
+    """Peskin's four-point kernel phi(r) (Eq. (delta eqn 2))."""
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    out = np.zeros_like(a)
+    m1 = a <= 1.0
+    m2 = (a > 1.0) & (a < 2.0)
+    a1 = a[m1]
+    a2 = a[m2]
+    out[m1] = (3.0 - 2.0 * a1 + np.sqrt(1.0 + 4.0 * a1 - 4.0 * a1 * a1)) / 8.0
+    out[m2] = (5.0 - 2.0 * a2 - np.sqrt(np.maximum(0.0, -7.0 + 12.0 * a2 - 4.0 * a2 * a2))) / 8.0
+    return out
+
+
+def phi_cosine4(r):
+    """The four-point cosine kernel phi(r) = (1 + cos(pi r / 2)) / 4 for |r| < 2."""
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    return np.where(a < 2.0, 0.25 * (1.0 + np.cos(0.5 * np.pi * a)), 0.0)
+
+
+def phi(r, kind=PESKIN4):
+    return phi_peskin4(r) if kind == PESKIN4 else phi_cosine4(r)
+
+
+# ----------------------------------------------------------------------------
+# grid and boundary description
+# ----------------------------------------------------------------------------
+@dataclass
+class Setup:
+    dim: int
+    n: int
+    lo: np.ndarray        # (dim,)
+    length: float
+    alpha: float
+    X: np.ndarray         # (M, dim)
+    normal: np.ndarray    # (M, dim), pointing out of Omega
+    weight: np.ndarray    # (M,) Delta s_i or dA_i
+    delta: str = PESKIN4
+
+    @property
+    def h(self):
+        return self.length / self.n
+
+    @property
+    def m(self):
+        return self.X.shape[0]
+
+    @property
+    def shape(self):
+        return (self.n,) * self.dim
+
+
+def setup_from_problem(prob, delta=PESKIN4) -> Setup:
+    g = prob.grid
+    return Setup(g.dim, g.n, np.asarray(g.lo, dtype=np.float64), float(g.length), float(prob.alpha),
+                 np.asarray(prob.geom.X, dtype=np.float64), np.asarray(prob.geom.normal, dtype=np.float64),
+                 np.asarray(prob.geom.weight, dtype=np.float64), delta)
+
+
+def _axis(st: Setup, d: int) -> int:
+    """Array axis of coordinate direction d (x is the last axis)."""
+    return st.dim - 1 - d
+
+
+def cell_and_offsets(st: Setup):
+    """Per point and direction: the unwrapped floor index and t - floor(t), t = (X - lo)/h."""
+    t = (st.X - st.lo[None, :]) / st.h
+    fl = np.floor(t)
+    return fl.astype(np.int64), t - fl
+
+
+def stencil(st: Setup):
+    """The 4^d nodes of each point's delta stencil and their weights Prod_d phi(p_d - t_d).
+
+    Returns (flat node index (M, 4^d), weight (M, 4^d)); nodes wrap periodically.
+    phi vanishes for |p - t| >= 2, so the nodes floor(t)-1 .. floor(t)+2 carry all of it.
+    """
+    fl, fr = cell_and_offsets(st)
+    m, d = st.m, st.dim
+    idx = np.zeros((m, 4 ** d), dtype=np.int64)
+    wts = np.ones((m, 4 ** d))
+    for combo in range(4 ** d):
+        flat = np.zeros(m, dtype=np.int64)
+        w = np.ones(m)
+        stride = 1
+        for dd in range(d):
+            i = (combo // (4 ** dd)) % 4          # offset -1..2 along direction dd
+            p = fl[:, dd] - 1 + i
+            w = w * phi(p - (fl[:, dd] + fr[:, dd]), st.delta)
+            flat = flat + np.mod(p, st.n) * stride
+            stride *= st.n
+        idx[:, combo] = flat
+        wts[:, combo] = w
+    return idx, wts
+
+
+# ----------------------------------------------------------------------------
+# spread and interpolation (Sec. 5.2)
+# ----------------------------------------------------------------------------
+def spread(st: Setup, F):
+    """(S F)(x) = sum_k F_k delta_h(x - X_k) Delta s_k  (Eq. (spread operator again2))."""
+    idx, wts = stencil(st)
+    vals = (np.asarray(F, dtype=np.float64) * st.weight)[:, None] * wts / st.h ** st.dim
+    out = np.bincount(idx.ravel(), weights=vals.ravel(), minlength=st.n ** st.dim)
+    return out.reshape(st.shape)
+
+
+def interp(st: Setup, u):
+    """(S* u)_k = sum_x u(x) delta_h(x - X_k) h^d  (Eq. (interpolation again))."""
+    idx, wts = stencil(st)
+    return np.sum(np.asarray(u, dtype=np.float64).ravel()[idx] * wts, axis=1)
+
+
+def divergence(st: Setup, v):
+    """Centred second-order divergence of a vector grid field v[d] (Sec. 5.2)."""
+    out = np.zeros(st.shape)
+    for d in range(st.dim):
+        ax = _axis(st, d)
+        out += (np.roll(v[d], -1, axis=ax) - np.roll(v[d], 1, axis=ax)) / (2.0 * st.h)
+    return out
+
+
+def gradient(st: Setup, u):
+    """Centred second-order gradient (the adjoint partner of ``divergence``)."""
+    return [(np.roll(u, -1, axis=_axis(st, d)) - np.roll(u, 1, axis=_axis(st, d))) / (2.0 * st.h)
+            for d in range(st.dim)]
+
+
+def spread_dipole(st: Setup, Q):
+    """S~ Q = div(S (Q n))  (Eq. (Stilde)): spread the vector Q n, then the centred divergence."""
+    Q = np.asarray(Q, dtype=np.float64)
+    v = [spread(st, Q * st.normal[:, d]) for d in range(st.dim)]
+    return divergence(st, v)
+
+
+# ----------------------------------------------------------------------------
+# L = Lap_h - alpha on the periodic box (Sec. 5.1, Sec. 5.3, App. C)
+# ----------------------------------------------------------------------------
+def symbol(st: Setup):
+    """Eigenvalues of the periodic 5-point (2-D) / 7-point (3-D) Laplacian minus alpha."""
+    lam = np.zeros(st.shape)
+    for d in range(st.dim):
+        m = np.arange(st.n)
+        ev = -(4.0 / st.h ** 2) * np.sin(np.pi * m / st.n) ** 2
+        sh = [1] * st.dim
+        sh[_axis(st, d)] = st.n
+        lam = lam + ev.reshape(sh)
+    return lam - st.alpha
+
+
+def apply_L(st: Setup, u):
+    """L u with the explicit stencil (used to check the inverse)."""
+    out = -st.alpha * u
+    for d in range(st.dim):
+        ax = _axis(st, d)
+        out = out + (np.roll(u, -1, axis=ax) - 2.0 * u + np.roll(u, 1, axis=ax)) / st.h ** 2
+    return out
+
+
+def solve_L(st: Setup, f):
+    """u = L^-1 f by the DFT; for alpha = 0 the mean-zero solution (Delta_0^-1, App. C)."""
+    fh = np.fft.fftn(np.asarray(f, dtype=np.float64))
+    lam = symbol(st)
+    if st.alpha == 0.0:
+        lam = lam.copy()
+        lam.flat[0] = 1.0
+        uh = fh / lam
+        uh.flat[0] = 0.0
+    else:
+        uh = fh / lam
+    return np.real(np.fft.ifftn(uh))
+
+
+# ----------------------------------------------------------------------------
+# the IBDL boundary operator and its right-hand sides
+# ----------------------------------------------------------------------------
+def apply_A(st: Setup, q, bc=DIRICHLET):
+    """Dirichlet: -S* L^-1 S~ q + q/2 (Eq. (ibdl schur again));
+    Neumann:   -S* L^-1 S~ q - q/2 (Eq. (Neumann saddle point))."""
+    q = np.asarray(q, dtype=np.float64)
+    w = -interp(st, solve_L(st, spread_dipole(st, q)))
+    return w + 0.5 * q if bc == DIRICHLET else w - 0.5 * q
+
+
+def rhs(st: Setup, data, g_tilde=None, bc=DIRICHLET):
+    """Dirichlet: U_b - S* L^-1 g~;  Neumann: S* L^-1 S V_b - S* L^-1 g~."""
+    data = np.asarray(data, dtype=np.float64)
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    if bc == DIRICHLET:
+        return data - interp(st, solve_L(st, g))
+    return interp(st, solve_L(st, spread(st, data))) - interp(st, solve_L(st, g))
+
+
+def eval_grid(st: Setup, sol, vb=None, g_tilde=None, bc=DIRICHLET):
+    """Grid solution: L u = g~ - S~ Q (Dirichlet, step 2 of Sec. 4.1), or
+    L u = g~ - S~ U_b - S V_b (Neumann, Eq. (ib neumann 1))."""
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    f = g - spread_dipole(st, sol)
+    if bc == NEUMANN:
+        f = f - spread(st, vb)
+    return solve_L(st, f)
+
+
+# ----------------------------------------------------------------------------
+# GMRES (Sec. 5.3): Arnoldi with modified Gram-Schmidt, Givens rotations
+# ----------------------------------------------------------------------------
+@dataclass
+class GmresResult:
+    x: np.ndarray
+    iters: int            # number of operator applications
+    rel_resid: float      # the Arnoldi residual estimate / ||b||
+    converged: bool
+    history: list
+
+
+def gmres(apply, b, tol=1e-8, restart=50, maxit=500, x0=None):
+    b = np.asarray(b, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    hist = []
+    if nb == 0.0:
+        return GmresResult(np.zeros_like(b), 0, 0.0, True, hist)
+    iters = 0
+    first = True
+    while True:
+        # residual of the current iterate (no operator application for x0 = 0);
+        # only Arnoldi steps count as iterations
+        r = b.copy() if (first and x0 is None) else b - apply(x)
+        first = False
+        beta = float(np.linalg.norm(r))
+        if beta / nb <= tol:
+            return GmresResult(x, iters, beta / nb, True, hist)
+        m = restart
+        V = np.zeros((m + 1, b.size))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        j_done = 0
+        conv = False
+        for j in range(m):
+            w = apply(V[j])
+            iters += 1
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = math.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            res = abs(g[j + 1]) / nb
+            hist.append(res)
+            j_done = j + 1
+            if res <= tol or iters >= maxit:
+                conv = res <= tol
+                break
+        y = np.zeros(j_done)
+        for i in range(j_done - 1, -1, -1):
+            y[i] = (g[i] - np.dot(H[i, i + 1:j_done], y[i + 1:j_done])) / H[i, i]
+        x = x + V[:j_done].T @ y
+        if conv or iters >= maxit:
+            return GmresResult(x, iters, hist[-1], conv, hist)
+
+
+def solve(st: Setup, data, g_tilde=None, bc=DIRICHLET, tol=1e-8, restart=50, maxit=500):
+    """Step 1 of the method: the boundary density Q (Dirichlet) or U_b (Neumann)."""
+    b = rhs(st, data, g_tilde, bc)
+    return gmres(lambda v: apply_A(st, v, bc), b, tol=tol, restart=restart, maxit=maxit), b
+
+
+# ----------------------------------------------------------------------------
+# cell binning (the ordering the GPU path builds): key and stable order
+# ----------------------------------------------------------------------------
+def cell_keys(st: Setup):
+    """Row-major cell index of floor((X - lo)/h) mod n, x fastest."""
+    fl, _ = cell_and_offsets(st)
+    key = np.zeros(st.m, dtype=np.int64)
+    stride = 1
+    for d in range(st.dim):
+        key += np.mod(fl[:, d], st.n) * stride
+        stride *= st.n
+    return key.astype(np.uint32)
+
+
+def binning(st: Setup):
+    """Keys and the stable sort permutation (equal keys keep the input order)."""
+    key = cell_keys(st)
+    perm = sorted(range(st.m), key=lambda k: int(key[k]))
+    return key, np.asarray(perm, dtype=np.uint32)
+
+
+# ----------------------------------------------------------------------------
+# indicator function (App. D) and error norms (Sec. 5.1)
+# ----------------------------------------------------------------------------
+def indicator(st: Setup, corner_index=0):
+    """chi_h = -Delta_0^-1 S~ 1 shifted so the chosen corner node is 0; and its 1/2 threshold."""
+    st0 = Setup(st.dim, st.n, st.lo, st.length, 0.0, st.X, st.normal, st.weight, st.delta)
+    u = -solve_L(st0, spread_dipole(st0, np.ones(st.m)))
+    chi_h = u - u.flat[corner_index]
+    return chi_h, (chi_h > 0.5).astype(np.int8)
+
+
+def norms(st: Setup, err, mask, area):
+    """Discrete L1, L2 (rescaled by |Omega|) and max norms over the masked nodes."""
+    e = np.abs(np.asarray(err))[mask]
+    hd = st.h ** st.dim
+    return (hd / area * float(np.sum(e)), math.sqrt(hd / area * float(np.sum(e * e))),
+            float(np.max(e)) if e.size else 0.0)
+
+
+def distance_to_points(st: Setup, nodes, X):
+    """Distance from grid nodes to the nearest boundary point (periodic minimum image)."""
+    from scipy.spatial import cKDTree
+    L = st.length
+    tree = cKDTree(np.mod(X - st.lo, L), boxsize=L)
+    d, _ = tree.query(np.mod(nodes - st.lo, L))
+    return d
