@@ -1,0 +1,164 @@
+/*
+ * ibdl.h -- C ABI of the MI355X (gfx950) IBDL hot path.
+ *
+ * The Immersed Boundary Double Layer method (Leathers & Guy) solves
+ *     Lap u - alpha u = g in Omega,   u = U_b (Dirichlet) or du/dn = V_b (Neumann) on Gamma
+ * on a periodic box by representing u with a regularised double layer (dipole
+ * spread) of strength Q on the boundary points.  Its hot path is the matrix-free
+ * boundary operator applied at every GMRES iteration:
+ *     Dirichlet:  A q = -S* L^-1 S~ q + q/2      (Sec. 5.3, Eq. (ibdl schur again))
+ *     Neumann:    A q = -S* L^-1 S~ q - q/2      (Sec. 4.3, Eq. (Neumann saddle point))
+ * with S~ q = div(S (q n)) the dipole spread (Sec. 5.2, Eq. (Stilde)), S the spread
+ * (Eq. (spread operator again2)), S* the interpolation (Eq. (interpolation again)),
+ * delta_h the Peskin four-point kernel (Eqs. (delta eqn 1)-(delta eqn 2)) and
+ * L = Lap_h - alpha the periodic 5-point (2-D) / 7-point (3-D) operator (Sec. 5.1).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (for example a torch tensor's
+ *    data_ptr on the current GPU) unless the comment says "host".
+ *  - Arrays are dense, C-ordered, FP64.  Boundary arrays are indexed in the
+ *    caller's point order.  Grid arrays are [iz][iy][ix] with x fastest; node
+ *    (ix,iy,iz) sits at lo + h*(ix,iy,iz), h = length/n.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Work is enqueued on it; "async" entry points return before it finishes.
+ *  - The caller owns every input and output buffer.  A plan owns its device
+ *    workspace and a sorted copy of the geometry; the geometry the caller passed
+ *    may be freed once ibdl_plan_create returns.
+ *  - Arguments are validated before anything is written.  On failure the
+ *    status is returned and ibdl_last_error() (thread-local) describes it.
+ *  - A plan is not thread-safe: use it from one host thread and one stream at a
+ *    time.  No C++ exception crosses this interface.
+ */
+#ifndef IBDL_H
+#define IBDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibdl_plan_s* ibdl_plan;
+
+typedef enum {
+    IBDL_OK = 0,
+    IBDL_ERR_ARG = 1,      /* invalid argument (sizes, pointers, enum values)      */
+    IBDL_ERR_OOM = 2,      /* device allocation failed                              */
+    IBDL_ERR_HIP = 3,      /* a HIP runtime call failed                             */
+    IBDL_ERR_NOCONV = 4,   /* GMRES stopped at maxit above tol (best iterate written) */
+    IBDL_ERR_NUMERIC = 5,  /* non-finite input or residual                          */
+    IBDL_ERR_STATE = 6     /* wrong state (e.g. request still pending)              */
+} ibdl_status;
+
+typedef enum { IBDL_DIRICHLET = 0, IBDL_NEUMANN = 1 } ibdl_bc;
+
+/* Discrete delta kernel phi (delta_h(x) = prod_d phi(x_d/h)/h):
+ * PESKIN4 is the paper's kernel (Sec. 5.2, Eq. (delta eqn 2));
+ * COSINE4 is phi(r) = (1 + cos(pi r/2))/4 for |r| < 2. */
+typedef enum { IBDL_DELTA_PESKIN4 = 0, IBDL_DELTA_COSINE4 = 1 } ibdl_delta;
+
+/* FP64: spread, FFT solve and interpolation in FP64.
+ * MIXED: spread (compensated sums), FFT solve and interpolation in FP32; the
+ *        identity term, all GMRES arithmetic and every output stay FP64. */
+typedef enum { IBDL_PREC_FP64 = 0, IBDL_PREC_MIXED = 1 } ibdl_prec;
+
+typedef struct {
+    int32_t dim;          /* 2 or 3                                                        */
+    int32_t n;            /* nodes per axis, n = 2^a 3^b, 8 <= n <= 2048 (2-D), <= 512 (3-D) */
+    double lo[3];         /* box origin (entries beyond dim ignored)                        */
+    double length;        /* periodic box side L > 0 (Sec. 5.1: dx = L/n)                   */
+    double alpha;         /* L = Lap_h - alpha, alpha >= 0 (alpha = k^2); 0 -> mean-zero inverse */
+    int32_t bc;           /* ibdl_bc                                                        */
+    int32_t delta;        /* ibdl_delta                                                     */
+    int32_t prec;         /* ibdl_prec                                                      */
+    int32_t npts;         /* M >= 1 boundary points                                         */
+    const double* X;      /* device [M][dim] point coordinates (any real values, wrapped periodically) */
+    const double* normal; /* device [M][dim] unit normals pointing OUT of Omega (Sec. 4.1)    */
+    const double* weight; /* device [M] quadrature weights: arclength Delta s_i (2-D, Sec. 5.2)
+                             or area dA_i (3-D, Sec. 6.7), > 0                               */
+} ibdl_desc;
+
+typedef struct {
+    double tol;           /* stop when ||b - A x||_2 <= tol ||b||_2 (Arnoldi estimate), Sec. 5.3 */
+    int32_t restart;      /* Krylov subspace size before restart, 1..200                    */
+    int32_t maxit;        /* maximum operator applications in the Krylov loop               */
+    const double* x0;     /* device [nrhs][M] initial guess, or NULL for x0 = 0 (the paper's) */
+    int32_t true_residual;/* 1: spend one more apply per rhs to report ||b - A x||/||b||     */
+} ibdl_solve_opts;
+
+typedef struct {
+    int32_t iters;          /* operator applications in the Krylov loop                     */
+    double rel_resid_est;   /* Arnoldi residual estimate / ||b||                            */
+    double rel_resid_true;  /* ||b - A x|| / ||b|| if requested, else -1                    */
+    int32_t status;         /* ibdl_status of this right-hand side                          */
+} ibdl_solve_info;
+
+/* Build a plan for one geometry (Sec. 5.1-5.2): cell binning of the points by the
+ * integer key  key = row-major index of floor((X - lo)/h) mod n  (x fastest, IEEE FP64),
+ * a stable sort of (key, point index), the per-point delta taps, the sparse dipole
+ * spread (and, for Neumann, monopole spread) structure, FFT twiddles and the symbol
+ * of L.  Copies the geometry; synchronises `stream` before returning.
+ * Errors: IBDL_ERR_ARG (bad desc), IBDL_ERR_NUMERIC (non-finite X/normal/weight),
+ * IBDL_ERR_OOM, IBDL_ERR_HIP.  *out is set only on success. */
+ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out);
+
+/* Free a plan and its device workspace (waits for work queued on the plan's last stream). */
+ibdl_status ibdl_plan_destroy(ibdl_plan plan);
+
+/* Host-only estimate of the device bytes a plan plus solve workspace for `nrhs`
+ * right-hand sides and Krylov size `restart` occupies (used for admission).
+ * Returns 0 for an invalid desc. */
+size_t ibdl_plan_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart);
+
+/* Aq[r] = A q[r] for r < nrhs (async).  q, Aq: device [nrhs][M], must not overlap.
+ * A is the Dirichlet or Neumann operator chosen by the plan's bc. */
+ibdl_status ibdl_apply(ibdl_plan plan, int32_t nrhs, const double* q, double* Aq, void* stream);
+
+/* Right-hand side of the boundary equation (async):
+ *   Dirichlet  b = U_b - S* L^-1 g~               (Eq. (ibdl schur again))
+ *   Neumann    b = S* L^-1 (S V_b - g~)           (Eq. (Neumann saddle point))
+ * data: device [nrhs][M] U_b or V_b;  g: device [nrhs][n^dim] g~ or NULL (zero);
+ * b: device [nrhs][M]. */
+ibdl_status ibdl_rhs(ibdl_plan plan, int32_t nrhs, const double* data, const double* g,
+                     double* b, void* stream);
+
+/* Step 1 of the method (Sec. 4.1, Sec. 5.3): form the right-hand side and run
+ * unpreconditioned restarted GMRES on the device (FP64 Arnoldi with classical
+ * Gram-Schmidt applied twice, Givens rotations) for each right-hand side.
+ * sol: device [nrhs][M] receives Q (Dirichlet) or U_b (Neumann).
+ * info: HOST [nrhs].  opts may be NULL (tol 1e-8, restart 50, maxit 500).
+ * Blocks until done.  Returns IBDL_ERR_NOCONV if any rhs missed tol (its best
+ * iterate is still written) and IBDL_ERR_NUMERIC on a non-finite residual. */
+ibdl_status ibdl_solve(ibdl_plan plan, int32_t nrhs, const double* data, const double* g,
+                       const ibdl_solve_opts* opts, double* sol, ibdl_solve_info* info,
+                       void* stream);
+
+/* Step 2 of the method: the grid solution (async).
+ *   Dirichlet  u = L^-1 (g~ - S~ Q)               (Sec. 4.1, Eq. (ibdl 1 again))
+ *   Neumann    u = L^-1 (g~ - S~ U_b - S V_b)     (Sec. 4.3, Eq. (ib neumann 1))
+ * sol: device [nrhs][M] (Q or U_b); vb: device [nrhs][M] V_b (Neumann only, else NULL);
+ * g: device [nrhs][n^dim] or NULL; u: device [nrhs][n^dim]. */
+ibdl_status ibdl_eval_grid(ibdl_plan plan, int32_t nrhs, const double* sol, const double* vb,
+                           const double* g, double* u, void* stream);
+
+/* The plan's binning (for inspection and tests), copied to HOST arrays of M
+ * entries: key[k] = cell key of caller point k; perm[s] = caller index of the
+ * s-th point in (key, index) order.  Either pointer may be NULL. */
+ibdl_status ibdl_plan_binning(ibdl_plan plan, uint32_t* key_host, uint32_t* perm_host);
+
+/* Per-stage device time of the most recent ibdl_apply in milliseconds, measured
+ * with HIP events on the apply's stream when timing is enabled (0 disables).
+ * ms_host receives up to `cap` stage times; *count the number of stages; names
+ * (may be NULL) receives a static string per stage. */
+ibdl_status ibdl_plan_set_timing(ibdl_plan plan, int32_t enable);
+ibdl_status ibdl_plan_stage_times(ibdl_plan plan, double* ms_host, const char** names,
+                                  int32_t cap, int32_t* count);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* ibdl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBDL_H */

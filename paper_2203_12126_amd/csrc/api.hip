@@ -1,0 +1,300 @@
+// C ABI of the IBDL library: argument checks, error reporting, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+ibdl_status fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return (ibdl_status)status;
+}
+
+bool size_ok(int n) {
+    if (n < 8) return false;
+    int t = n;
+    while (t % 2 == 0) t /= 2;
+    while (t % 3 == 0) t /= 3;
+    return t == 1;
+}
+
+const int kSizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+
+bool supported_n(int dim, int n) {
+    bool listed = false;
+    for (int s : kSizes) listed |= (s == n);
+    if (!listed || !size_ok(n)) return false;
+    return dim == 2 ? n <= 2048 : n <= 512;
+}
+
+std::string check_desc(const ibdl_desc* d) {
+    if (!d) return "desc is NULL";
+    if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
+    if (!supported_n(d->dim, d->n))
+        return "n must be one of 8,12,16,24,32,48,64,96,128,192,256,384,512,768,1024,1536,2048 "
+               "(<= 512 in 3-D)";
+    for (int i = 0; i < d->dim; ++i)
+        if (!std::isfinite(d->lo[i])) return "lo must be finite";
+    if (!(d->length > 0.0) || !std::isfinite(d->length)) return "length must be positive and finite";
+    if (!(d->alpha >= 0.0) || !std::isfinite(d->alpha)) return "alpha must be >= 0 and finite";
+    if (d->bc != IBDL_DIRICHLET && d->bc != IBDL_NEUMANN) return "bc must be IBDL_DIRICHLET or IBDL_NEUMANN";
+    if (d->delta != IBDL_DELTA_PESKIN4 && d->delta != IBDL_DELTA_COSINE4) return "unknown delta kernel";
+    if (d->prec != IBDL_PREC_FP64 && d->prec != IBDL_PREC_MIXED) return "unknown precision";
+    if (d->npts < 1) return "npts must be >= 1";
+    const long long per = d->dim == 2 ? 32 : 160;
+    if ((long long)d->npts * per >= (1LL << 31)) return "too many boundary points";
+    if (!d->X || !d->normal || !d->weight) return "X, normal and weight must be device pointers";
+    return "";
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+}  // namespace
+
+namespace ibdl {
+
+void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
+    ensure_workspace(p, nrhs);
+    if (p->prec == IBDL_PREC_FP64)
+        run_pipeline_f64(p, nrhs, in, out, st);
+    else
+        run_pipeline_f32(p, nrhs, in, out, st);
+}
+
+void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st) {
+    if (!p->timing || idx > 8) return;
+    if (!p->events_made) {
+        for (int i = 0; i < 9; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[i]));
+        p->events_made = 1;
+    }
+    IBDL_HIP_TRY(hipEventRecord(p->ev[idx], st));
+    if (name && idx < 8) p->stage_names[idx] = name;
+    if (!name) p->nstages = idx;
+}
+
+void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out, size_t ostride,
+                    hipStream_t st) {
+    // A q = -S* L^-1 S~ q + s q/2, s = +1 Dirichlet, -1 Neumann
+    PipeIn in;
+    in.q_dip = q;
+    in.c_dip = 1.0;
+    in.q_stride = qstride;
+    PipeOut o;
+    o.out = out;
+    o.out_stride = ostride;
+    o.cA = -1.0;
+    o.in = q;
+    o.in_stride = qstride;
+    o.cB = p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
+    run_pipeline(p, nrhs, in, o, st);
+}
+
+}  // namespace ibdl
+
+using namespace ibdl;
+
+#define IBDL_GUARD_BEGIN try {
+#define IBDL_GUARD_END                                                        \
+    }                                                                         \
+    catch (const ibdl::Error& e) { return fail(e.status, e.msg); }            \
+    catch (const std::bad_alloc&) { return fail(IBDL_ERR_OOM, "host allocation failed"); } \
+    catch (...) { return fail(IBDL_ERR_HIP, "unexpected failure"); }
+
+extern "C" {
+
+const char* ibdl_last_error(void) { return g_last_error.c_str(); }
+
+ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out) {
+    if (!out) return fail(IBDL_ERR_ARG, "out is NULL");
+    const std::string why = check_desc(desc);
+    if (!why.empty()) return fail(IBDL_ERR_ARG, why);
+    ibdl_plan p = new (std::nothrow) ibdl_plan_s();
+    if (!p) return fail(IBDL_ERR_OOM, "host allocation failed");
+    try {
+        p->dim = desc->dim;
+        p->n = desc->n;
+        p->bc = desc->bc;
+        p->delta = desc->delta;
+        p->prec = desc->prec;
+        p->M = desc->npts;
+        for (int i = 0; i < 3; ++i) p->lo[i] = i < desc->dim ? desc->lo[i] : 0.0;
+        p->length = desc->length;
+        p->h = desc->length / desc->n;
+        p->alpha = desc->alpha;
+        p->W = desc->n / 2 + 1;
+        p->P = (p->W + 15) / 16 * 16;
+        p->nlines = desc->dim == 2 ? desc->n : desc->n * desc->n;
+        p->spec_elems = (size_t)p->nlines * p->P;
+        p->gpp = desc->dim == 3 ? 16 : 4;
+        build_plan(p, desc, S(stream));
+    } catch (const ibdl::Error& e) {
+        ibdl_plan_destroy(p);
+        return fail(e.status, e.msg);
+    } catch (...) {
+        ibdl_plan_destroy(p);
+        return fail(IBDL_ERR_HIP, "plan construction failed");
+    }
+    *out = p;
+    g_last_error.clear();
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_plan_destroy(ibdl_plan p) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    (void)hipDeviceSynchronize();
+    for (void* a : p->allocs) (void)hipFree(a);
+    if (p->kr.host_pinned) (void)hipHostFree(p->kr.host_pinned);
+    if (p->events_made)
+        for (int i = 0; i < 9; ++i) (void)hipEventDestroy(p->ev[i]);
+    delete p;
+    return IBDL_OK;
+}
+
+size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
+    if (!check_desc(d).empty() || nrhs < 1 || restart < 1) return 0;
+    const size_t n = d->n, M = d->npts, dim = d->dim;
+    const size_t nlines = dim == 2 ? n : n * n;
+    const size_t P = (n / 2 + 1 + 15) / 16 * 16;
+    const size_t cs = d->prec == IBDL_PREC_FP64 ? 16 : 8;
+    const size_t npp = dim == 2 ? 32 : 160;
+    size_t b = 0;
+    b += (size_t)nrhs * nlines * P * cs;                 // spectra
+    b += (size_t)nrhs * M * (dim == 3 ? 16 : 4) * 8;     // partial sums
+    const size_t nnz = M * npp;
+    size_t n2 = 2048;
+    while (n2 < nnz) n2 <<= 1;
+    b += n2 * 8 + nnz * (4 + 8 + 4 + 4 + 4);             // sorted keys, weights, scan buffers
+    if (d->bc == IBDL_NEUMANN) b += nnz / 2 * 24;
+    b += M * (4 * 6 + 12 * 12 + 8 * 4) + nlines * 24;   // geometry, taps, tables, lists
+    b += (size_t)nrhs * ((restart + 1) * M * 8 + 3 * M * 8 + (restart + 2) * (restart + 8) * 8);
+    return b;
+}
+
+ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!q || !Aq) return fail(IBDL_ERR_ARG, "q and Aq must be device pointers");
+    if (q == Aq) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
+    IBDL_GUARD_BEGIN
+    apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_rhs(ibdl_plan p, int32_t nrhs, const double* data, const double* g, double* b,
+                     void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!data || !b) return fail(IBDL_ERR_ARG, "data and b must be device pointers");
+    IBDL_GUARD_BEGIN
+    PipeIn in;
+    PipeOut out;
+    out.out = b;
+    if (p->bc == IBDL_DIRICHLET) {
+        in.grid = g;
+        in.c_grid = 1.0;
+        out.cA = -1.0;
+        out.in = data;
+        out.cB = 1.0;
+        if (!g) {
+            IBDL_HIP_TRY(hipMemcpyAsync(b, data, (size_t)nrhs * p->M * sizeof(double),
+                                        hipMemcpyDeviceToDevice, S(stream)));
+            return IBDL_OK;
+        }
+    } else {
+        in.q_mono = data;
+        in.c_mono = 1.0;
+        in.grid = g;
+        in.c_grid = -1.0;
+        out.cA = 1.0;
+    }
+    run_pipeline(p, nrhs, in, out, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const double* g,
+                       const ibdl_solve_opts* opts, double* sol, ibdl_solve_info* info, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!data || !sol) return fail(IBDL_ERR_ARG, "data and sol must be device pointers");
+    ibdl_solve_opts o{1e-8, 50, 500, nullptr, 0};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(IBDL_ERR_ARG, "tol must be positive");
+    if (o.restart < 1 || o.restart > 200) return fail(IBDL_ERR_ARG, "restart must be in 1..200");
+    if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
+    IBDL_GUARD_BEGIN
+    int overall = IBDL_OK;
+    gmres_solve(p, nrhs, data, g, o, sol, info, S(stream), &overall);
+    if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
+    if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
+    g_last_error.clear();
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const double* vb,
+                           const double* g, double* u, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!sol || !u) return fail(IBDL_ERR_ARG, "sol and u must be device pointers");
+    if (p->bc == IBDL_NEUMANN && !vb) return fail(IBDL_ERR_ARG, "Neumann plans need V_b");
+    IBDL_GUARD_BEGIN
+    PipeIn in;
+    in.q_dip = sol;
+    in.c_dip = -1.0;
+    if (p->bc == IBDL_NEUMANN) {
+        in.q_mono = vb;
+        in.c_mono = -1.0;
+    }
+    in.grid = g;
+    in.c_grid = 1.0;
+    PipeOut out;
+    out.u = u;
+    run_pipeline(p, nrhs, in, out, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_plan_binning(ibdl_plan p, uint32_t* key_host, uint32_t* perm_host) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    IBDL_GUARD_BEGIN
+    if (key_host) IBDL_HIP_TRY(hipMemcpy(key_host, p->key, p->M * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (perm_host)
+        IBDL_HIP_TRY(hipMemcpy(perm_host, p->perm, p->M * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_plan_set_timing(ibdl_plan p, int32_t enable) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    p->timing = enable ? 1 : 0;
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_plan_stage_times(ibdl_plan p, double* ms_host, const char** names, int32_t cap,
+                                  int32_t* count) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (!p->events_made || p->nstages == 0) {
+        if (count) *count = 0;
+        return IBDL_OK;
+    }
+    IBDL_GUARD_BEGIN
+    IBDL_HIP_TRY(hipEventSynchronize(p->ev[p->nstages]));
+    for (int i = 0; i < p->nstages && i < cap; ++i) {
+        float ms = 0.f;
+        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+        if (ms_host) ms_host[i] = ms;
+        if (names) names[i] = p->stage_names[i];
+    }
+    if (count) *count = p->nstages;
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+}  // extern "C"

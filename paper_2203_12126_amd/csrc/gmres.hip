@@ -1,0 +1,478 @@
+// Unpreconditioned restarted GMRES on the boundary density (Sec. 5.3), FP64 on
+// the device for every right-hand side at once.
+//
+// Arnoldi step j of right-hand side r:  w = A v_j (one pass of the operator),
+// h_ij = <w, v_i> and w -= sum_i h_ij v_i done twice (classical Gram-Schmidt
+// applied twice), h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the previous Givens
+// rotations are applied to column j, a new rotation zeroes h_{j+1,j}, and the
+// rotated right-hand side g gives the residual estimate |g_{j+1}|.  All inner
+// products are two-level block reductions in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "plan.h"
+
+namespace ibdl {
+
+constexpr int GT = 256;             // threads per block
+constexpr int GPER = 4;             // elements per thread
+constexpr int GCHUNK = GT * GPER;   // elements per block
+
+enum { ST_DONE = 0, ST_ITERS = 1, ST_STATUS = 2, ST_J = 3 };
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < GT / 64; ++i) t += sh[i];
+    return t;  // valid in thread 0
+}
+
+struct KArgs {
+    double* V;          // [rhs][m+1][M]
+    size_t vstride;
+    int M, m, nblk;
+    double* part;       // [rhs][nblk][m+2] (two banks: part and part2)
+    double* part2;
+    size_t pstride;     // per rhs
+    double* hcol;       // [rhs][m+2]
+    double* H;          // [rhs][m][m+1] column j at H + j*(m+1)
+    double* cs;         // [rhs][m]
+    double* sn;
+    double* g;          // [rhs][m+1]
+    double* y;          // [rhs][m]
+    double* bnorm;      // [rhs]
+    double* resid;      // [rhs]
+    int32_t* state;     // [rhs][4]
+    double tol;
+};
+
+// sum of squares of x over each block's chunk
+__global__ __launch_bounds__(GT) void k_sumsq(const double* __restrict__ x, size_t xstride, int M,
+                                              double* part, size_t pstride) {
+    __shared__ double sh[GT / 64];
+    const int rhs = blockIdx.y;
+    const double* xr = x + (size_t)rhs * xstride;
+    double acc = 0.0;
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (m < (size_t)M) acc += xr[m] * xr[m];
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)rhs * pstride + blockIdx.x] = t;
+}
+
+__global__ void k_set_bnorm(const double* __restrict__ part, size_t pstride, int nblk,
+                            double* bnorm, int32_t* state, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)r * pstride + b];
+    bnorm[r] = sqrt(s);
+    state[4 * r + ST_DONE] = 0;
+    state[4 * r + ST_ITERS] = 0;
+    state[4 * r + ST_STATUS] = isfinite(s) ? IBDL_OK : IBDL_ERR_NUMERIC;
+    state[4 * r + ST_J] = 0;
+}
+
+// start a cycle: v_0 = r / ||r||, g = (||r||, 0, ...); rhs already done are left alone
+__global__ __launch_bounds__(GT) void k_init_cycle(const double* __restrict__ rv, size_t rstride,
+                                                   KArgs a) {
+    const int rhs = blockIdx.y;
+    int32_t* st = a.state + 4 * rhs;
+    if (st[ST_DONE]) return;
+    double s = 0.0;
+    for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)rhs * a.pstride + b];
+    const double beta = sqrt(s);
+    const double bn = a.bnorm[rhs];
+    const bool done = !(bn > 0.0) || beta <= a.tol * bn || !(beta > 0.0);
+    const double inv = (beta > 0.0) ? 1.0 / beta : 0.0;
+    double* v0 = a.V + (size_t)rhs * a.vstride;
+    const double* r = rv + (size_t)rhs * rstride;
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (m < (size_t)a.M) v0[m] = r[m] * inv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double* g = a.g + (size_t)rhs * (a.m + 1);
+        g[0] = beta;
+        for (int i = 1; i <= a.m; ++i) g[i] = 0.0;
+        a.resid[rhs] = bn > 0.0 ? beta / bn : 0.0;
+        st[ST_J] = 0;
+        if (!isfinite(s)) st[ST_STATUS] = IBDL_ERR_NUMERIC;
+        if (done || !isfinite(s)) st[ST_DONE] = 1;
+    }
+}
+
+// partial <w, v_i> for i <= j, w = v_{j+1} slot
+__global__ __launch_bounds__(GT) void k_dots(KArgs a, int j) {
+    __shared__ double sh[GT / 64];
+    const int rhs = blockIdx.y;
+    if (a.state[4 * rhs + ST_DONE]) return;
+    const double* V = a.V + (size_t)rhs * a.vstride;
+    const double* w = V + (size_t)(j + 1) * a.M;
+    double wl[GPER];
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        wl[i] = m < (size_t)a.M ? w[m] : 0.0;
+    }
+    for (int vi = 0; vi <= j; ++vi) {
+        const double* v = V + (size_t)vi * a.M;
+        double acc = 0.0;
+        for (int i = 0; i < GPER; ++i) {
+            const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+            if (m < (size_t)a.M) acc += v[m] * wl[i];
+        }
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) a.part[(size_t)rhs * a.pstride + (size_t)blockIdx.x * (a.m + 2) + vi] = t;
+    }
+}
+
+// h = sum of the block partials of pass `pass`; w -= V h; then the partials of
+// the next quantity: pass 0 -> <w, v_i> again, pass 1 -> ||w||^2
+__global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
+    __shared__ double sh[GT / 64];
+    __shared__ double hs[256];
+    const int rhs = blockIdx.y;
+    if (a.state[4 * rhs + ST_DONE]) return;
+    const double* pin = (pass == 0 ? a.part : a.part2) + (size_t)rhs * a.pstride;
+    double* pout = (pass == 0 ? a.part2 : a.part) + (size_t)rhs * a.pstride;
+    for (int vi = threadIdx.x; vi <= j; vi += GT) {
+        double s = 0.0;
+        for (int b = 0; b < a.nblk; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        hs[vi] = s;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double* hc = a.hcol + (size_t)rhs * (a.m + 2);
+        for (int vi = 0; vi <= j; ++vi) hc[vi] = (pass == 0 ? 0.0 : hc[vi]) + hs[vi];
+    }
+    double* V = a.V + (size_t)rhs * a.vstride;
+    double* w = V + (size_t)(j + 1) * a.M;
+    double wl[GPER];
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (m < (size_t)a.M) {
+            double acc = w[m];
+            for (int vi = 0; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * a.M + m];
+            wl[i] = acc;
+            w[m] = acc;
+        } else {
+            wl[i] = 0.0;
+        }
+    }
+    if (pass == 0) {
+        for (int vi = 0; vi <= j; ++vi) {
+            const double* v = V + (size_t)vi * a.M;
+            double acc = 0.0;
+            for (int i = 0; i < GPER; ++i) {
+                const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+                if (m < (size_t)a.M) acc += v[m] * wl[i];
+            }
+            const double t = block_sum(acc, sh);
+            if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2) + vi] = t;
+        }
+    } else {
+        double acc = 0.0;
+        for (int i = 0; i < GPER; ++i) acc += wl[i] * wl[i];
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2)] = t;
+    }
+}
+
+// v_{j+1} = w / ||w||; block 0 applies the Givens rotations and updates the state
+__global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
+    const int rhs = blockIdx.y;
+    int32_t* st = a.state + 4 * rhs;
+    if (st[ST_DONE]) return;
+    const double* pin = a.part + (size_t)rhs * a.pstride;
+    double s = 0.0;
+    for (int b = 0; b < a.nblk; ++b) s += pin[(size_t)b * (a.m + 2)];
+    const double hn = sqrt(s);
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    double* w = a.V + (size_t)rhs * a.vstride + (size_t)(j + 1) * a.M;
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (m < (size_t)a.M) w[m] *= inv;
+    }
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const double* hc = a.hcol + (size_t)rhs * (a.m + 2);
+    double* Hj = a.H + (size_t)rhs * a.m * (a.m + 1) + (size_t)j * (a.m + 1);
+    double* cs = a.cs + (size_t)rhs * a.m;
+    double* sn = a.sn + (size_t)rhs * a.m;
+    double* g = a.g + (size_t)rhs * (a.m + 1);
+    for (int i = 0; i <= j; ++i) Hj[i] = hc[i];
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+        Hj[i] = t;
+    }
+    const double den = hypot(Hj[j], Hj[j + 1]);
+    const double c = den > 0.0 ? Hj[j] / den : 1.0;
+    const double sv = den > 0.0 ? Hj[j + 1] / den : 0.0;
+    cs[j] = c;
+    sn[j] = sv;
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    g[j + 1] = -sv * g[j];
+    g[j] = c * g[j];
+    const double res = fabs(g[j + 1]) / a.bnorm[rhs];
+    a.resid[rhs] = res;
+    st[ST_ITERS] += 1;
+    st[ST_J] = j + 1;
+    if (!isfinite(res) || !isfinite(s)) {
+        st[ST_STATUS] = IBDL_ERR_NUMERIC;
+        st[ST_DONE] = 1;
+    } else if (res <= a.tol || !(hn > 0.0)) {
+        st[ST_DONE] = 1;
+    }
+}
+
+// y = R^-1 g over the steps of the current cycle, then mark the cycle as consumed
+__global__ void k_backsolve(KArgs a, int nrhs) {
+    const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rhs >= nrhs) return;
+    const int jr = a.state[4 * rhs + ST_J];
+    const double* H = a.H + (size_t)rhs * a.m * (a.m + 1);
+    const double* g = a.g + (size_t)rhs * (a.m + 1);
+    double* y = a.y + (size_t)rhs * a.m;
+    for (int i = jr - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < jr; ++k) t -= H[(size_t)k * (a.m + 1) + i] * y[k];
+        const double d = H[(size_t)i * (a.m + 1) + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
+// x += V[0..jr) y ; then the cycle position is reset
+__global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* x, size_t xstride) {
+    const int rhs = blockIdx.y;
+    const int jr = a.state[4 * rhs + ST_J];
+    if (jr == 0) return;
+    const double* V = a.V + (size_t)rhs * a.vstride;
+    const double* y = a.y + (size_t)rhs * a.m;
+    double* xr = x + (size_t)rhs * xstride;
+    for (int i = 0; i < GPER; ++i) {
+        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (m < (size_t)a.M) {
+            double acc = xr[m];
+            for (int vi = 0; vi < jr; ++vi) acc += y[vi] * V[(size_t)vi * a.M + m];
+            xr[m] = acc;
+        }
+    }
+}
+
+__global__ void k_reset_j(int32_t* state, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrhs) state[4 * r + ST_J] = 0;
+}
+
+__global__ void k_fill0(double* x, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+__global__ void k_copy(double* dst, const double* src, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ host
+static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
+    Krylov& k = p->kr;
+    if (k.cap_rhs >= nrhs && k.cap_m >= m) return;
+    const int M = p->M;
+    const int nblk = (M + GCHUNK - 1) / GCHUNK;
+    nrhs = std::max(nrhs, k.cap_rhs);
+    m = std::max(m, k.cap_m);
+    auto A = [&](size_t n) { return reinterpret_cast<double*>(dev_alloc(p, n * sizeof(double))); };
+    k.V = A((size_t)nrhs * (m + 1) * M);
+    k.H = A((size_t)nrhs * m * (m + 1));
+    k.cs = A((size_t)nrhs * m);
+    k.sn = A((size_t)nrhs * m);
+    k.g = A((size_t)nrhs * (m + 1));
+    k.y = A((size_t)nrhs * m);
+    k.partial = A((size_t)nrhs * nblk * (m + 2) * 2);
+    k.hcol = A((size_t)nrhs * (m + 2));
+    k.bnorm = A(nrhs);
+    k.resid = A(nrhs);
+    k.b = A((size_t)nrhs * M);
+    k.r = A((size_t)nrhs * M);
+    k.state = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * 4 * sizeof(int32_t)));
+    if (k.host_pinned) (void)hipHostFree(k.host_pinned);
+    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * (4 * sizeof(int32_t) + 2 * sizeof(double))));
+    k.cap_rhs = nrhs;
+    k.cap_m = m;
+    k.nblk = nblk;
+}
+
+void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out,
+                    size_t ostride, hipStream_t st);
+
+// b - A x for every rhs into r
+static void residual(ibdl_plan p, int nrhs, const double* b, const double* x, double* r,
+                     hipStream_t st) {
+    // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
+    PipeIn in;
+    in.q_dip = x;
+    in.c_dip = 1.0;
+    PipeOut out;
+    out.out = r;
+    out.cA = 1.0;
+    out.in = x;
+    out.cB = p->bc == IBDL_DIRICHLET ? -0.5 : 0.5;
+    out.in2 = b;
+    out.cC = 1.0;
+    run_pipeline(p, nrhs, in, out, st);
+}
+
+void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
+                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall) {
+    const int M = p->M;
+    const int m = o.restart;
+    ensure_krylov(p, nrhs, m);
+    Krylov& k = p->kr;
+    const int nblk = k.nblk;
+    KArgs a{};
+    a.V = k.V;
+    a.vstride = (size_t)(m + 1) * M;
+    a.M = M;
+    a.m = m;
+    a.nblk = nblk;
+    a.part = k.partial;
+    a.pstride = (size_t)nblk * (m + 2);
+    a.part2 = k.partial + (size_t)nrhs * a.pstride;
+    a.hcol = k.hcol;
+    a.H = k.H;
+    a.cs = k.cs;
+    a.sn = k.sn;
+    a.g = k.g;
+    a.y = k.y;
+    a.bnorm = k.bnorm;
+    a.resid = k.resid;
+    a.state = k.state;
+    a.tol = o.tol;
+    const dim3 vg(nblk, nrhs);
+    const size_t tot = (size_t)nrhs * M;
+
+    // right-hand side b (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~))
+    {
+        PipeIn in;
+        PipeOut out;
+        out.out = k.b;
+        if (p->bc == IBDL_DIRICHLET) {
+            if (g) {
+                in.grid = g;
+                in.c_grid = 1.0;
+                out.cA = -1.0;
+                out.in = data;
+                out.cB = 1.0;
+                run_pipeline(p, nrhs, in, out, st);
+            } else {
+                hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, k.b, data, tot);
+            }
+        } else {
+            in.q_mono = data;
+            in.c_mono = 1.0;
+            if (g) {
+                in.grid = g;
+                in.c_grid = -1.0;
+            }
+            out.cA = 1.0;
+            run_pipeline(p, nrhs, in, out, st);
+        }
+    }
+    // ||b||, state reset
+    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.b, (size_t)M, M, k.partial, a.pstride);
+    hipLaunchKernelGGL(k_set_bnorm, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.partial, a.pstride, nblk,
+                       k.bnorm, k.state, nrhs);
+    // initial residual
+    const double* r0 = k.b;
+    if (o.x0) {
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, o.x0, tot);
+        residual(p, nrhs, k.b, sol, k.r, st);
+        r0 = k.r;
+    } else {
+        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, tot);
+    }
+    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, r0, (size_t)M, M, k.partial, a.pstride);
+    hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, r0, (size_t)M, a);
+
+    int32_t* hstate = reinterpret_cast<int32_t*>(k.host_pinned);
+    auto all_done = [&]() {
+        IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st));
+        IBDL_HIP_TRY(hipStreamSynchronize(st));
+        for (int r = 0; r < nrhs; ++r)
+            if (!hstate[4 * r + ST_DONE]) return false;
+        return true;
+    };
+
+    int total = 0;
+    bool finished = all_done();
+    while (!finished) {
+        int j = 0;
+        for (; j < m; ++j) {
+            apply_operator(p, nrhs, k.V + (size_t)j * M, a.vstride, k.V + (size_t)(j + 1) * M, a.vstride, st);
+            hipLaunchKernelGGL(k_dots, vg, dim3(GT), 0, st, a, j);
+            hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 0);
+            hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 1);
+            hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st, a, j);
+            ++total;
+            if (all_done() || total >= o.maxit) break;
+        }
+        hipLaunchKernelGGL(k_backsolve, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
+        hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st, a, sol, (size_t)M);
+        hipLaunchKernelGGL(k_reset_j, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.state, nrhs);
+        if (all_done() || total >= o.maxit) break;
+        // restart the rhs still running from their current iterate
+        residual(p, nrhs, k.b, sol, k.r, st);
+        hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);
+        hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, k.r, (size_t)M, a);
+        finished = all_done();
+    }
+    IBDL_HIP_TRY(hipGetLastError());
+
+    // report
+    std::vector<double> hres(nrhs), htrue(nrhs, -1.0), hbn(nrhs);
+    IBDL_HIP_TRY(hipMemcpyAsync(hres.data(), k.resid, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipMemcpyAsync(hbn.data(), k.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (o.true_residual) {
+        residual(p, nrhs, k.b, sol, k.r, st);
+        hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);
+        std::vector<double> hp((size_t)nrhs * a.pstride);
+        IBDL_HIP_TRY(hipMemcpyAsync(hp.data(), k.partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        IBDL_HIP_TRY(hipStreamSynchronize(st));
+        for (int r = 0; r < nrhs; ++r) {
+            double s = 0.0;
+            for (int b = 0; b < nblk; ++b) s += hp[(size_t)r * a.pstride + b];
+            htrue[r] = hbn[r] > 0.0 ? std::sqrt(s) / hbn[r] : 0.0;
+        }
+    }
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    int worst = IBDL_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        int s = hstate[4 * r + ST_STATUS];
+        if (s == IBDL_OK && !(hres[r] <= o.tol)) s = IBDL_ERR_NOCONV;
+        if (info) {
+            info[r].iters = hstate[4 * r + ST_ITERS];
+            info[r].rel_resid_est = hres[r];
+            info[r].rel_resid_true = htrue[r];
+            info[r].status = s;
+        }
+        if (s == IBDL_ERR_NUMERIC) worst = IBDL_ERR_NUMERIC;
+        else if (s == IBDL_ERR_NOCONV && worst == IBDL_OK) worst = IBDL_ERR_NOCONV;
+    }
+    *overall = worst;
+}
+
+}  // namespace ibdl

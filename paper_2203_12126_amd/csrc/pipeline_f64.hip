@@ -1,0 +1,8 @@
+// FP64 instantiation of the grid pipeline.
+#include "pipeline.h"
+
+namespace ibdl {
+void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
+    run_pipeline_t<double>(p, nrhs, in, out, st);
+}
+}  // namespace ibdl

@@ -1,0 +1,149 @@
+// Internal plan structure of the IBDL library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/ibdl.h"
+#include "common.h"
+
+namespace ibdl {
+
+// Sparse spread operator over the active grid nodes, rows sorted by node id and
+// entries within a row by caller point index (a fixed summation order).
+struct Csr {
+    int64_t nnz = 0;
+    int32_t nact = 0;
+    uint32_t* act_node = nullptr;   // [nact] flat node id (x fastest)
+    int32_t* act_ptr = nullptr;     // [nact+1] first entry of each active node
+    uint32_t* k = nullptr;          // [nnz] caller point index
+    double* w64 = nullptr;          // [nnz] weight
+    float* w32 = nullptr;           // [nnz] weight rounded to FP32
+    int32_t* line_act = nullptr;    // [nlines+1] first active node of each x-line
+};
+
+struct Workspace {
+    int cap_rhs = 0;
+    void* spec = nullptr;       // [cap][nlines*P] complex
+    void* part = nullptr;       // [cap][M][4^(dim-1)] gather partial sums
+};
+
+struct Krylov {
+    int cap_rhs = 0, cap_m = 0, nblk = 0;
+    double* V = nullptr;        // [rhs][m+1][M]
+    double* H = nullptr;        // [rhs][m+1][m]  (column-major by j: H[j*(m+1) + i])
+    double* cs = nullptr;       // [rhs][m]
+    double* sn = nullptr;       // [rhs][m]
+    double* g = nullptr;        // [rhs][m+1]
+    double* y = nullptr;        // [rhs][m]
+    double* partial = nullptr;  // [rhs][nblk][m+2]
+    double* hcol = nullptr;     // [rhs][m+2]
+    double* bnorm = nullptr;    // [rhs]
+    double* resid = nullptr;    // [rhs]
+    int32_t* state = nullptr;   // [rhs][4]: done flag, iterations, status, j
+    double* b = nullptr;        // [rhs][M]
+    double* x = nullptr;        // [rhs][M]
+    double* r = nullptr;        // [rhs][M]
+    void* host_pinned = nullptr;
+};
+
+struct ibdl_plan_impl;
+
+}  // namespace ibdl
+
+struct ibdl_plan_s {
+    // description
+    int dim = 2, n = 0, bc = 0, delta = 0, prec = 0, M = 0;
+    double lo[3] = {0, 0, 0}, length = 1, h = 1, alpha = 0;
+    int P = 0;          // half-spectrum pitch (complex elements)
+    int W = 0;          // half-spectrum width n/2+1
+    int nlines = 0;     // n^(dim-1) x-lines
+    size_t spec_elems = 0;  // nlines * P
+    int gpp = 0;        // gather partials per point: 4^(dim-1)
+
+    // geometry in (key, index) order
+    uint32_t* perm = nullptr;       // [M] caller index of sorted point s
+    uint32_t* invperm = nullptr;    // [M] sorted position of caller point k
+    uint32_t* key = nullptr;        // [M] key of caller point k
+    uint32_t* skey = nullptr;       // [M] key of sorted point s
+    int32_t* cell = nullptr;        // [M][3] cell of sorted point s
+    double* taps64 = nullptr;       // [M][3][4] phi(p - t) for p = c-1..c+2, sorted order
+    float* taps32 = nullptr;
+    double* nrm = nullptr;          // [M][3] caller order
+    double* wgt = nullptr;          // [M] caller order
+    int32_t* line_start = nullptr;  // [nlines+1] first sorted point of each x-line (cell key / n)
+
+    ibdl::Csr dip, mono;
+
+    // line/plane sets
+    uint8_t* spread_line_mask = nullptr;   // [nlines]
+    uint8_t* gather_line_mask = nullptr;   // [nlines]
+    uint8_t* spread_plane_mask = nullptr;  // [n] (3-D)
+    uint8_t* gather_plane_mask = nullptr;  // [n] (3-D)
+    int32_t* spread_lines = nullptr;
+    int32_t* gather_lines = nullptr;
+    int32_t* spread_planes = nullptr;
+    int32_t* gather_planes = nullptr;
+    int n_spread_lines = 0, n_gather_lines = 0, n_spread_planes = 0, n_gather_planes = 0;
+
+    // tables
+    double* tw64 = nullptr;   // [n] exp(-2 pi i m/n) as (re, im)
+    float* tw32 = nullptr;
+    double* s2_64 = nullptr;  // [n] (4/h^2) sin^2(pi m/n)
+    float* s2_32 = nullptr;
+
+    ibdl::Workspace ws;
+    ibdl::Krylov kr;
+
+    // stage timing
+    int timing = 0;
+    int nstages = 0;
+    hipEvent_t ev[9] = {};
+    const char* stage_names[8] = {};
+    double stage_ms[8] = {};
+    int events_made = 0;
+
+    std::vector<void*> allocs;  // everything to free
+};
+
+namespace ibdl {
+
+// Inputs and outputs of one pass of L^-1 through the grid.
+struct PipeIn {
+    const double* q_dip = nullptr;   // [nrhs][M] dipole strengths (S~ q)
+    double c_dip = 0;
+    const double* q_mono = nullptr;  // [nrhs][M] monopole strengths (S q)
+    double c_mono = 0;
+    const double* grid = nullptr;    // [nrhs][n^dim] grid forcing
+    double c_grid = 0;
+    size_t q_stride = 0;             // distance between right-hand sides of q_dip/q_mono (0: M)
+};
+struct PipeOut {
+    // gather: out[k] = cA * (S* u)_k + cB * in[k] + cC * in2[k]   (strides 0: M)
+    double* out = nullptr;
+    size_t out_stride = 0;
+    double cA = 0;
+    const double* in = nullptr;
+    size_t in_stride = 0;
+    double cB = 0;
+    const double* in2 = nullptr;
+    size_t in2_stride = 0;
+    double cC = 0;
+    // grid: u = the full grid field
+    double* u = nullptr;
+};
+
+void* dev_alloc(ibdl_plan p, size_t bytes);
+void ensure_workspace(ibdl_plan p, int nrhs);
+void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+void run_pipeline_f32(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
+void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
+                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall);
+
+// timing helpers used by the pipeline
+void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st);
+
+}  // namespace ibdl

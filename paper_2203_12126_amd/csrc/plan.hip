@@ -1,0 +1,585 @@
+// Plan construction: everything that depends only on the geometry and grid.
+//
+//  * cell binning: c_d = floor((X_d - lo_d)/h) mod n in IEEE FP64, key = row-major
+//    cell index with x fastest; stable order of (key, caller index) by a bitonic
+//    sort of the 64-bit composite keys (key << 32 | index) -- unique, so the
+//    order of equal cell keys is the caller order;
+//  * per point the 1-D delta taps phi(p - t) for p = c-1..c+2 (Sec. 5.2);
+//  * the sparse dipole spread S~ q = div(S (q n)) (Sec. 5.2, Eq. (Stilde)) and,
+//    for Neumann plans, the monopole spread S (Eq. (spread operator again2)),
+//    as rows over the active grid nodes: every (node, point) pair the stencil
+//    reaches is emitted, sorted by (node, point), and weighed;
+//  * the x-lines that receive forcing and the x-lines interpolated from;
+//  * twiddles exp(-2 pi i m/n) and the symbol terms (4/h^2) sin^2(pi m/n).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "plan.h"
+
+namespace ibdl {
+
+// ------------------------------------------------------------------ alloc
+void* dev_alloc(ibdl_plan p, size_t bytes) {
+    void* ptr = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{IBDL_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    p->allocs.push_back(ptr);
+    return ptr;
+}
+
+template <typename T>
+static T* alloc_n(ibdl_plan p, size_t n) {
+    return reinterpret_cast<T*>(dev_alloc(p, n * sizeof(T)));
+}
+
+static inline int nblocks(size_t n, int t) { return (int)((n + t - 1) / t); }
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_bin(const double* __restrict__ X, int M, int dim, int n, double lo0, double lo1,
+                      double lo2, double h, uint32_t* key, int32_t* cell_c, double* frac,
+                      int* bad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const double lo[3] = {lo0, lo1, lo2};
+    uint32_t kk = 0, stride = 1;
+    for (int d = 0; d < dim; ++d) {
+        const double x = X[(size_t)k * dim + d];
+        if (!isfinite(x)) bad[0] = 1;
+        const double t = (x - lo[d]) / h;
+        const double fl = floor(t);
+        long long c = (long long)fl % n;
+        if (c < 0) c += n;
+        cell_c[3 * k + d] = (int32_t)c;
+        frac[3 * k + d] = t - fl;
+        kk += (uint32_t)c * stride;
+        stride *= (uint32_t)n;
+    }
+    for (int d = dim; d < 3; ++d) { cell_c[3 * k + d] = 0; frac[3 * k + d] = 0.0; }
+    key[k] = kk;
+}
+
+__global__ void k_check_geom(const double* __restrict__ nrm, const double* __restrict__ w, int M,
+                             int dim, int* bad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    double s = 0;
+    for (int d = 0; d < dim; ++d) {
+        const double v = nrm[(size_t)k * dim + d];
+        if (!isfinite(v)) bad[0] = 1;
+        s += v * v;
+    }
+    if (!(fabs(s - 1.0) < 1e-6)) bad[1] = 1;
+    if (!(w[k] > 0.0) || !isfinite(w[k])) bad[2] = 1;
+}
+
+__global__ void k_copy_geom(const double* __restrict__ nrm, const double* __restrict__ w, int M,
+                            int dim, double* nrm3, double* w1) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    for (int d = 0; d < 3; ++d) nrm3[3 * k + d] = d < dim ? nrm[(size_t)k * dim + d] : 0.0;
+    w1[k] = w[k];
+}
+
+__global__ void k_composite(const uint32_t* __restrict__ key, int M, size_t n2, uint64_t* out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    out[i] = i < (size_t)M ? (((uint64_t)key[i]) << 32) | (uint64_t)i : ~0ull;
+}
+
+// bitonic sort ------------------------------------------------------------
+constexpr int BIT_BLOCK = 2048;  // elements held in LDS by one 1024-thread block
+
+__device__ __forceinline__ void bit_cmpx(uint64_t* a, size_t lo, size_t hi, bool asc) {
+    const uint64_t x = a[lo], y = a[hi];
+    if ((x > y) == asc) { a[lo] = y; a[hi] = x; }
+}
+
+// all stages with k <= BIT_BLOCK inside each block
+__global__ __launch_bounds__(1024) void k_bitonic_local_sort(uint64_t* a) {
+    __shared__ uint64_t s[BIT_BLOCK];
+    const size_t base = (size_t)blockIdx.x * BIT_BLOCK;
+    s[threadIdx.x] = a[base + threadIdx.x];
+    s[threadIdx.x + 1024] = a[base + threadIdx.x + 1024];
+    __syncthreads();
+    for (int k = 2; k <= BIT_BLOCK; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int t = threadIdx.x;
+            const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+            const int hi = lo | j;
+            const bool asc = (((base + lo) & (size_t)k) == 0);
+            const uint64_t x = s[lo], y = s[hi];
+            if ((x > y) == asc) { s[lo] = y; s[hi] = x; }
+            __syncthreads();
+        }
+    }
+    a[base + threadIdx.x] = s[threadIdx.x];
+    a[base + threadIdx.x + 1024] = s[threadIdx.x + 1024];
+}
+
+// stages j < BIT_BLOCK of a merge with k > BIT_BLOCK
+__global__ __launch_bounds__(1024) void k_bitonic_local_merge(uint64_t* a, size_t k) {
+    __shared__ uint64_t s[BIT_BLOCK];
+    const size_t base = (size_t)blockIdx.x * BIT_BLOCK;
+    s[threadIdx.x] = a[base + threadIdx.x];
+    s[threadIdx.x + 1024] = a[base + threadIdx.x + 1024];
+    __syncthreads();
+    const bool asc = ((base & k) == 0);
+    for (int j = BIT_BLOCK >> 1; j > 0; j >>= 1) {
+        const int t = threadIdx.x;
+        const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int hi = lo | j;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == asc) { s[lo] = y; s[hi] = x; }
+        __syncthreads();
+    }
+    a[base + threadIdx.x] = s[threadIdx.x];
+    a[base + threadIdx.x + 1024] = s[threadIdx.x + 1024];
+}
+
+__global__ void k_bitonic_global(uint64_t* a, size_t npairs, size_t k, size_t j) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npairs) return;
+    const size_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+    const size_t hi = lo | j;
+    bit_cmpx(a, lo, hi, (lo & k) == 0);
+}
+
+static size_t pow2_at_least(size_t n, size_t minv) {
+    size_t p = minv;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// sorts a[0..n2) ascending; n2 a power of two >= BIT_BLOCK
+static void bitonic_sort(uint64_t* a, size_t n2, hipStream_t st) {
+    const int nb = (int)(n2 / BIT_BLOCK);
+    hipLaunchKernelGGL(k_bitonic_local_sort, dim3(nb), dim3(1024), 0, st, a);
+    for (size_t k = 2 * BIT_BLOCK; k <= n2; k <<= 1) {
+        for (size_t j = k >> 1; j >= (size_t)BIT_BLOCK; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(n2 / 2, 256)), dim3(256), 0, st, a,
+                               n2 / 2, k, j);
+        hipLaunchKernelGGL(k_bitonic_local_merge, dim3(nb), dim3(1024), 0, st, a, k);
+    }
+    IBDL_HIP_TRY(hipGetLastError());
+}
+
+// exclusive scan of int32 ----------------------------------------------------
+constexpr int SCAN_T = 256, SCAN_PER = 8, SCAN_TILE = SCAN_T * SCAN_PER;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tile(const int32_t* in, int32_t* out, size_t n,
+                                                      int32_t* sums) {
+    __shared__ int32_t s[SCAN_T];
+    const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
+    int32_t v[SCAN_PER];
+    int32_t tot = 0;
+    for (int i = 0; i < SCAN_PER; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        tot += v[i];
+    }
+    s[threadIdx.x] = tot;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int32_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = s[threadIdx.x] - tot;
+    for (int i = 0; i < SCAN_PER; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == SCAN_T - 1 && sums) sums[blockIdx.x] = s[SCAN_T - 1];
+}
+
+__global__ void k_scan_add(int32_t* out, size_t n, const int32_t* offs) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += offs[i / SCAN_TILE];
+}
+
+// out = exclusive scan of in (n entries); returns nothing, total = out[n-1] + in[n-1]
+static void scan_excl(ibdl_plan p, const int32_t* in, int32_t* out, size_t n, hipStream_t st) {
+    const size_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nt <= 1) {
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (int32_t*)nullptr);
+        return;
+    }
+    int32_t* sums = alloc_n<int32_t>(p, nt);
+    int32_t* soff = alloc_n<int32_t>(p, nt);
+    hipLaunchKernelGGL(k_scan_tile, dim3((int)nt), dim3(SCAN_T), 0, st, in, out, n, sums);
+    scan_excl(p, sums, soff, nt, st);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblocks(n, 256)), dim3(256), 0, st, out, n, soff);
+}
+
+static int32_t read_i32(const int32_t* d, hipStream_t st) {
+    int32_t v = 0;
+    IBDL_HIP_TRY(hipMemcpyAsync(&v, d, sizeof(v), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    return v;
+}
+
+// ------------------------------------------------------------------ sorted geometry
+__global__ void k_unpack(const uint64_t* __restrict__ srt, int M, uint32_t* perm, uint32_t* skey,
+                         uint32_t* invperm) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    const uint64_t v = srt[s];
+    const uint32_t k = (uint32_t)(v & 0xffffffffull);
+    perm[s] = k;
+    skey[s] = (uint32_t)(v >> 32);
+    invperm[k] = (uint32_t)s;
+}
+
+__global__ void k_taps(const uint32_t* __restrict__ perm, const int32_t* __restrict__ cell_c,
+                       const double* __restrict__ frac, int M, int dim, int kind,
+                       int32_t* cell_s, double* taps64, float* taps32) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    const uint32_t k = perm[s];
+    for (int d = 0; d < 3; ++d) {
+        cell_s[3 * s + d] = cell_c[3 * k + d];
+        for (int i = 0; i < 4; ++i) {
+            double v = 0.0;
+            if (d < dim) {
+                // node p = c - 1 + i, p - t = i - 1 - frac
+                const double r = (double)(i - 1) - frac[3 * k + d];
+                v = kind == IBDL_DELTA_PESKIN4 ? phi_peskin4(r) : phi_cosine4(r);
+            }
+            taps64[12 * s + 4 * d + i] = v;
+            taps32[12 * s + 4 * d + i] = (float)v;
+        }
+    }
+}
+
+// first sorted position whose key / n >= line, for line in [0, nlines]
+__global__ void k_line_start(const uint32_t* __restrict__ skey, int M, int n, int nlines,
+                             int32_t* ls) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > nlines) return;
+    int lo = 0, hi = M;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(skey[mid] / (uint32_t)n) < l) lo = mid + 1; else hi = mid;
+    }
+    ls[l] = lo;
+}
+
+// ------------------------------------------------------------------ spread matrices
+// Stencil offsets r in -2..3 (dipole) or -1..2 (monopole) per axis; the dipole
+// keeps the nodes where at most one axis offset lies outside -1..2 (elsewhere
+// every term of div(S q n) vanishes).
+__device__ __forceinline__ int dip_offsets(int j, int dim, int* r) {
+    // enumerate 6^dim boxes and keep the structurally nonzero ones in order
+    int cnt = -1;
+    const int tot = dim == 2 ? 36 : 216;
+    for (int b = 0; b < tot; ++b) {
+        int o[3] = {b % 6 - 2, (b / 6) % 6 - 2, dim == 3 ? b / 36 - 2 : 0};
+        int outside = 0;
+        for (int d = 0; d < dim; ++d) outside += (o[d] < -1 || o[d] > 2);
+        if (outside <= 1) {
+            if (++cnt == j) { r[0] = o[0]; r[1] = o[1]; r[2] = o[2]; return 1; }
+        }
+    }
+    return 0;
+}
+
+__global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
+                       int M, int dim, int n, int dipole, int npp, uint64_t* out) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (size_t)M * npp) return;
+    const int s = (int)(id / npp), j = (int)(id % npp);
+    int r[3] = {0, 0, 0};
+    if (dipole) {
+        dip_offsets(j, dim, r);
+    } else {
+        r[0] = j % 4 - 1;
+        r[1] = (j / 4) % 4 - 1;
+        r[2] = dim == 3 ? j / 16 - 1 : 0;
+    }
+    uint32_t node = 0, stride = 1;
+    for (int d = 0; d < dim; ++d) {
+        const int c = (cell_s[3 * s + d] + r[d] + n) % n;
+        node += (uint32_t)c * stride;
+        stride *= (uint32_t)n;
+    }
+    out[id] = ((uint64_t)node << 32) | (uint64_t)perm[s];
+}
+
+// A_d(r) = phi(c - 1 + i - t) at r = i - 1 in -1..2, zero outside
+__device__ __forceinline__ double tap_at(const double* t4, int r) {
+    return (r >= -1 && r <= 2) ? t4[r + 1] : 0.0;
+}
+
+__global__ void k_weights(const uint64_t* __restrict__ srt, size_t nnz,
+                          const uint32_t* __restrict__ invperm, const int32_t* __restrict__ cell_s,
+                          const double* __restrict__ taps64, const double* __restrict__ nrm3,
+                          const double* __restrict__ w1, int dim, int n, double h, int dipole,
+                          uint32_t* K, double* W64, float* W32, int32_t* head) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const uint64_t v = srt[e];
+    const uint32_t node = (uint32_t)(v >> 32);
+    const uint32_t k = (uint32_t)(v & 0xffffffffull);
+    const uint32_t s = invperm[k];
+    int r[3] = {0, 0, 0};
+    uint32_t rem = node;
+    for (int d = 0; d < dim; ++d) {
+        const int p = (int)(rem % (uint32_t)n);
+        rem /= (uint32_t)n;
+        r[d] = ((p - cell_s[3 * s + d] + 2 + 2 * n) % n) - 2;   // in -2..3
+    }
+    const double* t = taps64 + 12 * (size_t)s;
+    double hd = 1.0;
+    for (int d = 0; d < dim; ++d) hd *= h;
+    double wv;
+    if (dipole) {
+        // (w_k / h^d) sum_d n_d (A_d(r_d+1) - A_d(r_d-1)) / (2h) prod_{e != d} A_e(r_e)
+        double acc = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            double term = (tap_at(t + 4 * d, r[d] + 1) - tap_at(t + 4 * d, r[d] - 1)) / (2.0 * h);
+            for (int q = 0; q < dim; ++q)
+                if (q != d) term *= tap_at(t + 4 * q, r[q]);
+            acc += nrm3[3 * k + d] * term;
+        }
+        wv = w1[k] / hd * acc;
+    } else {
+        double prod = 1.0;
+        for (int d = 0; d < dim; ++d) prod *= tap_at(t + 4 * d, r[d]);
+        wv = w1[k] / hd * prod;
+    }
+    K[e] = k;
+    W64[e] = wv;
+    W32[e] = (float)wv;
+    head[e] = (e == 0) || ((uint32_t)(srt[e - 1] >> 32) != node);
+}
+
+__global__ void k_compact_heads(const uint64_t* __restrict__ srt, size_t nnz,
+                                const int32_t* __restrict__ head, const int32_t* __restrict__ idx,
+                                uint32_t* act_node, int32_t* act_ptr) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    if (head[e]) {
+        act_node[idx[e]] = (uint32_t)(srt[e] >> 32);
+        act_ptr[idx[e]] = (int32_t)e;
+    }
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+// first active node index with node / n >= line
+__global__ void k_line_act(const uint32_t* __restrict__ act_node, int nact, int n, int nlines,
+                           int32_t* la) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > nlines) return;
+    int lo = 0, hi = nact;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(act_node[mid] / (uint32_t)n) < l) lo = mid + 1; else hi = mid;
+    }
+    la[l] = lo;
+}
+
+// ------------------------------------------------------------------ line sets
+__global__ void k_spread_mask(const int32_t* __restrict__ la, int nlines, uint8_t* mask,
+                              int32_t* flag) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlines) return;
+    const int v = la[l + 1] > la[l];
+    mask[l] = (uint8_t)v;
+    flag[l] = v;
+}
+
+// every x-line (cy-1..cy+2, cz-1..cz+2) a point interpolates from
+__global__ void k_gather_mark(const int32_t* __restrict__ cell_s, int M, int dim, int n,
+                              uint8_t* mask) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = dim == 3 ? 16 : 4;
+    if (id >= M * per) return;
+    const int s = id / per, j = id % per;
+    const int cy = (cell_s[3 * s + 1] - 1 + (j % 4) + n) % n;
+    const int cz = dim == 3 ? (cell_s[3 * s + 2] - 1 + j / 4 + n) % n : 0;
+    mask[cz * n + cy] = 1;  // all writers store the same value
+}
+
+__global__ void k_mask_to_flag(const uint8_t* __restrict__ mask, int n, int32_t* flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = mask[i];
+}
+
+__global__ void k_plane_mask(const uint8_t* __restrict__ lmask, int n, uint8_t* pmask,
+                             int32_t* flag) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= n) return;
+    int any = 0;
+    for (int y = 0; y < n; ++y) any |= lmask[z * n + y];
+    pmask[z] = (uint8_t)any;
+    flag[z] = any;
+}
+
+__global__ void k_compact_list(const int32_t* __restrict__ flag, const int32_t* __restrict__ idx,
+                               int n, int32_t* list) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) list[idx[i]] = i;
+}
+
+// ------------------------------------------------------------------ tables
+__global__ void k_tables(int n, double h, double* tw64, float* tw32, double* s264, float* s232) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double sv, cv;
+    sincospi(2.0 * (double)m / (double)n, &sv, &cv);
+    tw64[2 * m] = cv;
+    tw64[2 * m + 1] = -sv;
+    tw32[2 * m] = (float)cv;
+    tw32[2 * m + 1] = (float)(-sv);
+    const double sp = sinpi((double)m / (double)n);
+    const double v = 4.0 / (h * h) * sp * sp;
+    s264[m] = v;
+    s232[m] = (float)v;
+}
+
+// ------------------------------------------------------------------ host
+static int compact(ibdl_plan p, const int32_t* flag, int n, int32_t** list, hipStream_t st) {
+    int32_t* idx = alloc_n<int32_t>(p, (size_t)n + 1);
+    scan_excl(p, flag, idx, (size_t)n, st);
+    const int cnt = read_i32(idx + n - 1, st) + read_i32(flag + n - 1, st);
+    *list = alloc_n<int32_t>(p, (size_t)std::max(cnt, 1));
+    hipLaunchKernelGGL(k_compact_list, dim3(nblocks(n, 256)), dim3(256), 0, st, flag, idx, n, *list);
+    return cnt;
+}
+
+static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
+    const int dim = p->dim, n = p->n, M = p->M;
+    const int npp = dipole ? (dim == 2 ? 32 : 160) : (dim == 2 ? 16 : 64);
+    const size_t nnz = (size_t)M * npp;
+    if (nnz >= (size_t)INT32_MAX) throw Error{IBDL_ERR_ARG, "too many spread entries"};
+    const size_t n2 = pow2_at_least(nnz, BIT_BLOCK);
+    uint64_t* keys = alloc_n<uint64_t>(p, n2);
+    hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, (const uint32_t*)nullptr,
+                       0, n2, keys);  // fill with padding
+    hipLaunchKernelGGL(k_emit, dim3(nblocks(nnz, 256)), dim3(256), 0, st, p->cell, p->perm, M, dim, n,
+                       dipole ? 1 : 0, npp, keys);
+    bitonic_sort(keys, n2, st);
+    c.nnz = (int64_t)nnz;
+    c.k = alloc_n<uint32_t>(p, nnz);
+    c.w64 = alloc_n<double>(p, nnz);
+    c.w32 = alloc_n<float>(p, nnz);
+    int32_t* head = alloc_n<int32_t>(p, nnz);
+    int32_t* idx = alloc_n<int32_t>(p, nnz);
+    hipLaunchKernelGGL(k_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, p->invperm,
+                       p->cell, p->taps64, p->nrm, p->wgt, dim, n, p->h, dipole ? 1 : 0, c.k, c.w64,
+                       c.w32, head);
+    scan_excl(p, head, idx, nnz, st);
+    c.nact = read_i32(idx + nnz - 1, st) + read_i32(head + nnz - 1, st);
+    c.act_node = alloc_n<uint32_t>(p, (size_t)c.nact);
+    c.act_ptr = alloc_n<int32_t>(p, (size_t)c.nact + 1);
+    hipLaunchKernelGGL(k_compact_heads, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, head, idx,
+                       c.act_node, c.act_ptr);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, st, c.act_ptr + c.nact, (int32_t)nnz);
+    c.line_act = alloc_n<int32_t>(p, (size_t)p->nlines + 1);
+    hipLaunchKernelGGL(k_line_act, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
+                       c.act_node, c.nact, n, p->nlines, c.line_act);
+    IBDL_HIP_TRY(hipGetLastError());
+}
+
+void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
+    const int dim = p->dim, n = p->n, M = p->M;
+    int32_t* bad = alloc_n<int32_t>(p, 4);
+    IBDL_HIP_TRY(hipMemsetAsync(bad, 0, 4 * sizeof(int32_t), st));
+    p->key = alloc_n<uint32_t>(p, M);
+    int32_t* cell_c = alloc_n<int32_t>(p, 3 * (size_t)M);
+    double* frac = alloc_n<double>(p, 3 * (size_t)M);
+    hipLaunchKernelGGL(k_bin, dim3(nblocks(M, 256)), dim3(256), 0, st, d->X, M, dim, n, p->lo[0],
+                       p->lo[1], p->lo[2], p->h, p->key, cell_c, frac, bad);
+    hipLaunchKernelGGL(k_check_geom, dim3(nblocks(M, 256)), dim3(256), 0, st, d->normal, d->weight, M,
+                       dim, bad);
+    int32_t hb[4];
+    IBDL_HIP_TRY(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    if (hb[0]) throw Error{IBDL_ERR_NUMERIC, "non-finite point coordinate or normal"};
+    if (hb[1]) throw Error{IBDL_ERR_ARG, "normals must have unit length"};
+    if (hb[2]) throw Error{IBDL_ERR_ARG, "weights must be positive and finite"};
+
+    p->nrm = alloc_n<double>(p, 3 * (size_t)M);
+    p->wgt = alloc_n<double>(p, M);
+    hipLaunchKernelGGL(k_copy_geom, dim3(nblocks(M, 256)), dim3(256), 0, st, d->normal, d->weight, M,
+                       dim, p->nrm, p->wgt);
+
+    // stable order of (key, index)
+    const size_t n2 = pow2_at_least((size_t)M, BIT_BLOCK);
+    uint64_t* comp = alloc_n<uint64_t>(p, n2);
+    hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, p->key, M, n2, comp);
+    bitonic_sort(comp, n2, st);
+    p->perm = alloc_n<uint32_t>(p, M);
+    p->skey = alloc_n<uint32_t>(p, M);
+    p->invperm = alloc_n<uint32_t>(p, M);
+    hipLaunchKernelGGL(k_unpack, dim3(nblocks(M, 256)), dim3(256), 0, st, comp, M, p->perm, p->skey,
+                       p->invperm);
+
+    p->cell = alloc_n<int32_t>(p, 3 * (size_t)M);
+    p->taps64 = alloc_n<double>(p, 12 * (size_t)M);
+    p->taps32 = alloc_n<float>(p, 12 * (size_t)M);
+    hipLaunchKernelGGL(k_taps, dim3(nblocks(M, 256)), dim3(256), 0, st, p->perm, cell_c, frac, M, dim,
+                       p->delta, p->cell, p->taps64, p->taps32);
+    p->line_start = alloc_n<int32_t>(p, (size_t)p->nlines + 1);
+    hipLaunchKernelGGL(k_line_start, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
+                       p->skey, M, n, p->nlines, p->line_start);
+
+    build_csr(p, p->dip, true, st);
+    if (p->bc == IBDL_NEUMANN) build_csr(p, p->mono, false, st);
+
+    // line and plane sets
+    int32_t* flag = alloc_n<int32_t>(p, (size_t)std::max(p->nlines, n));
+    p->spread_line_mask = alloc_n<uint8_t>(p, p->nlines);
+    hipLaunchKernelGGL(k_spread_mask, dim3(nblocks(p->nlines, 256)), dim3(256), 0, st, p->dip.line_act,
+                       p->nlines, p->spread_line_mask, flag);
+    p->n_spread_lines = compact(p, flag, p->nlines, &p->spread_lines, st);
+
+    p->gather_line_mask = alloc_n<uint8_t>(p, p->nlines);
+    IBDL_HIP_TRY(hipMemsetAsync(p->gather_line_mask, 0, p->nlines, st));
+    const int per = dim == 3 ? 16 : 4;
+    hipLaunchKernelGGL(k_gather_mark, dim3(nblocks((size_t)M * per, 256)), dim3(256), 0, st, p->cell, M,
+                       dim, n, p->gather_line_mask);
+    hipLaunchKernelGGL(k_mask_to_flag, dim3(nblocks(p->nlines, 256)), dim3(256), 0, st,
+                       p->gather_line_mask, p->nlines, flag);
+    p->n_gather_lines = compact(p, flag, p->nlines, &p->gather_lines, st);
+
+    if (dim == 3) {
+        p->spread_plane_mask = alloc_n<uint8_t>(p, n);
+        p->gather_plane_mask = alloc_n<uint8_t>(p, n);
+        hipLaunchKernelGGL(k_plane_mask, dim3(nblocks(n, 256)), dim3(256), 0, st, p->spread_line_mask, n,
+                           p->spread_plane_mask, flag);
+        p->n_spread_planes = compact(p, flag, n, &p->spread_planes, st);
+        hipLaunchKernelGGL(k_plane_mask, dim3(nblocks(n, 256)), dim3(256), 0, st, p->gather_line_mask, n,
+                           p->gather_plane_mask, flag);
+        p->n_gather_planes = compact(p, flag, n, &p->gather_planes, st);
+    }
+
+    p->tw64 = alloc_n<double>(p, 2 * (size_t)n);
+    p->tw32 = alloc_n<float>(p, 2 * (size_t)n);
+    p->s2_64 = alloc_n<double>(p, n);
+    p->s2_32 = alloc_n<float>(p, n);
+    hipLaunchKernelGGL(k_tables, dim3(nblocks(n, 256)), dim3(256), 0, st, n, p->h, p->tw64, p->tw32,
+                       p->s2_64, p->s2_32);
+    IBDL_HIP_TRY(hipGetLastError());
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+}
+
+void ensure_workspace(ibdl_plan p, int nrhs) {
+    if (p->ws.cap_rhs >= nrhs) return;
+    const size_t cs = p->prec == IBDL_PREC_FP64 ? 16 : 8;
+    const size_t rs = p->prec == IBDL_PREC_FP64 ? 8 : 4;
+    // grow: the old buffers stay owned by the plan until it is destroyed
+    p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
+    p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);
+    p->ws.cap_rhs = nrhs;
+}
+
+}  // namespace ibdl

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of ``libibdl.so`` (the C ABI in ``include/ibdl.h``).
+
+Argument marshalling only: every step of the IBDL path runs in the HIP
+library.  Torch tensors provide device memory and the current HIP stream.
+If the library has not been built, every call raises ``RuntimeError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibdl.so")
+
+OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC, ERR_STATE = range(7)
+DIRICHLET, NEUMANN = 0, 1
+PESKIN4, COSINE4 = 0, 1
+FP64, MIXED = 0, 1
+
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NUMERIC",
+           6: "ERR_STATE"}
+
+
+class IbdlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("lo", ctypes.c_double * 3),
+                ("length", ctypes.c_double), ("alpha", ctypes.c_double), ("bc", ctypes.c_int32),
+                ("delta", ctypes.c_int32), ("prec", ctypes.c_int32), ("npts", ctypes.c_int32),
+                ("X", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("x0", ctypes.c_void_p), ("true_residual", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_resid_est", ctypes.c_double),
+                ("rel_resid_true", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libibdl.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int32
+    st = ctypes.c_int
+    sig = {
+        "ibdl_plan_create": ([ctypes.POINTER(Desc), P, ctypes.POINTER(P)], st),
+        "ibdl_plan_destroy": ([P], st),
+        "ibdl_plan_footprint": ([ctypes.POINTER(Desc), I, I], ctypes.c_size_t),
+        "ibdl_apply": ([P, I, P, P, P], st),
+        "ibdl_rhs": ([P, I, P, P, P, P], st),
+        "ibdl_solve": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P], st),
+        "ibdl_eval_grid": ([P, I, P, P, P, P, P], st),
+        "ibdl_plan_binning": ([P, P, P], st),
+        "ibdl_plan_set_timing": ([P, I], st),
+        "ibdl_plan_stage_times": ([P, P, P, I, ctypes.POINTER(I)], st),
+        "ibdl_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().ibdl_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise IbdlError(status, f"{what}: {last_error()}")
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, name, shape=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and t.numel() != shape:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=None, weight=None):
+    d = Desc()
+    d.dim, d.n = dim, n
+    for i in range(3):
+        d.lo[i] = float(lo[i]) if i < len(lo) else 0.0
+    d.length, d.alpha = float(length), float(alpha)
+    d.bc, d.delta, d.prec, d.npts = bc, delta, prec, npts
+    d.X = X.data_ptr() if X is not None else None
+    d.normal = normal.data_ptr() if normal is not None else None
+    d.weight = weight.data_ptr() if weight is not None else None
+    return d
+
+
+def footprint(dim, n, npts, bc=DIRICHLET, prec=FP64, nrhs=1, restart=50) -> int:
+    """Device bytes of a plan plus solve workspace (host-only estimate)."""
+    d = make_desc(dim, n, (0, 0, 0), 1.0, 1.0, bc, PESKIN4, prec, npts)
+    d.X = d.normal = d.weight = 1  # non-null placeholders: the estimate never dereferences them
+    return int(lib().ibdl_plan_footprint(ctypes.byref(d), nrhs, restart))
+
+
+class Plan:
+    """One geometry on one periodic grid (``ibdl_plan``)."""
+
+    def __init__(self, dim, n, lo, length, alpha, X, normal, weight, bc=DIRICHLET, delta=PESKIN4,
+                 prec=FP64, stream=None):
+        import torch
+        self._keep = [t.contiguous() for t in (X, normal, weight)]
+        X, normal, weight = self._keep
+        m = int(weight.numel())
+        _dptr(X, "X", m * dim)
+        _dptr(normal, "normal", m * dim)
+        _dptr(weight, "weight", m)
+        self.dim, self.n, self.m, self.bc, self.prec = dim, n, m, bc, prec
+        self.grid_size = n ** dim
+        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight)
+        h = ctypes.c_void_p()
+        _check(lib().ibdl_plan_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)),
+               "ibdl_plan_create")
+        self._h = h
+        self._keep = None
+        self._torch = torch
+
+    @classmethod
+    def from_problem(cls, prob, delta=PESKIN4, prec=FP64, device="cuda"):
+        import torch
+        g = prob.grid
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
+        return cls(g.dim, g.n, tuple(g.lo), g.length, prob.alpha, t(prob.geom.X), t(prob.geom.normal),
+                   t(prob.geom.weight), bc=prob.bc, delta=delta, prec=prec)
+
+    # ------------------------------------------------------------------
+    def _empty(self, *shape):
+        return self._torch.empty(*shape, dtype=self._torch.float64, device="cuda")
+
+    def _nrhs(self, t, per):
+        if t.numel() % per:
+            raise ValueError("array size is not a multiple of the per-rhs size")
+        return t.numel() // per
+
+    def apply(self, q, out=None, stream=None):
+        nrhs = self._nrhs(q, self.m)
+        out = self._empty(*q.shape) if out is None else out
+        _check(lib().ibdl_apply(self._h, nrhs, _dptr(q, "q"), _dptr(out, "Aq", q.numel()),
+                                _stream(stream)), "ibdl_apply")
+        return out
+
+    def rhs(self, data, g=None, out=None, stream=None):
+        nrhs = self._nrhs(data, self.m)
+        out = self._empty(*data.shape) if out is None else out
+        _check(lib().ibdl_rhs(self._h, nrhs, _dptr(data, "data"),
+                              _dptr(g, "g", nrhs * self.grid_size), _dptr(out, "b", data.numel()),
+                              _stream(stream)), "ibdl_rhs")
+        return out
+
+    def solve(self, data, g=None, tol=1e-8, restart=50, maxit=500, x0=None, true_residual=False,
+              out=None, stream=None, raise_on_noconv=True):
+        nrhs = self._nrhs(data, self.m)
+        out = self._empty(*data.shape) if out is None else out
+        o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
+        if x0 is not None:
+            o.x0 = _dptr(x0, "x0", data.numel()).value
+        info = (SolveInfo * nrhs)()
+        st = lib().ibdl_solve(self._h, nrhs, _dptr(data, "data"), _dptr(g, "g", nrhs * self.grid_size),
+                              ctypes.byref(o), _dptr(out, "sol", data.numel()), info, _stream(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            _check(st, "ibdl_solve")
+        return out, [dict(iters=i.iters, rel_resid_est=i.rel_resid_est,
+                          rel_resid_true=i.rel_resid_true, status=i.status) for i in info]
+
+    def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
+        nrhs = self._nrhs(sol, self.m)
+        out = self._empty(nrhs, *([self.n] * self.dim)) if out is None else out
+        _check(lib().ibdl_eval_grid(self._h, nrhs, _dptr(sol, "sol"), _dptr(vb, "vb", sol.numel()),
+                                    _dptr(g, "g", nrhs * self.grid_size),
+                                    _dptr(out, "u", nrhs * self.grid_size), _stream(stream)),
+               "ibdl_eval_grid")
+        return out
+
+    def binning(self):
+        import numpy as np
+        key = np.zeros(self.m, dtype=np.uint32)
+        perm = np.zeros(self.m, dtype=np.uint32)
+        _check(lib().ibdl_plan_binning(self._h, key.ctypes.data_as(ctypes.c_void_p),
+                                       perm.ctypes.data_as(ctypes.c_void_p)), "ibdl_plan_binning")
+        return key, perm
+
+    def set_timing(self, on=True):
+        _check(lib().ibdl_plan_set_timing(self._h, 1 if on else 0), "ibdl_plan_set_timing")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * 8)()
+        names = (ctypes.c_char_p * 8)()
+        cnt = ctypes.c_int32()
+        _check(lib().ibdl_plan_stage_times(self._h, ms, names, 8, ctypes.byref(cnt)),
+               "ibdl_plan_stage_times")
+        return [(names[i].decode() if names[i] else f"stage{i}", ms[i]) for i in range(cnt.value)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ibdl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,288 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: binning keys and order bit-exact; FP64 operator/rhs/grid within 1e-12
+relative; mixed (FP32 grid pipeline, FP64 Krylov) within the FP32 bound stated
+per test; solves against the oracle's solution of the same system.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ibdl_oracle as O
+from paper_2203_12126_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2203_12126_amd import ibdl  # noqa: E402
+
+DEV = "cuda"
+FP64_TOL = 1e-12
+# FP32 grid pipeline: ~log2(n^d) rounding steps of 6e-8 in the FFTs, amplified
+# by at most the ratio of the largest to the smallest |symbol| seen by the data.
+MIXED_TOL = 2e-5
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def plan_for(prob, delta=O.PESKIN4, prec=ibdl.FP64):
+    d = ibdl.PESKIN4 if delta == O.PESKIN4 else ibdl.COSINE4
+    return ibdl.Plan.from_problem(prob, delta=d, prec=prec)
+
+
+def random_problem(dim, n, m, seed, bc=W.DIRICHLET, alpha=1.0, lo=None, length=1.0, spread=(-0.2, 1.2)):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(spread[0], spread[1], size=(m, dim)) * length
+    nr = rng.standard_normal((m, dim))
+    nr /= np.linalg.norm(nr, axis=1, keepdims=True)
+    w = rng.uniform(0.5, 1.5, size=m) / m
+    lo = tuple([0.0] * dim) if lo is None else lo
+    grid = W.Grid(dim, n, lo, length)
+    geom = W.Geometry(dim, X, nr, w, lambda p: np.zeros(p.shape[0], bool), 1.0)
+    sol = W.sol_random_fourier(dim, seed, kmax=2, length=length)
+    return W.make_problem(grid, geom, alpha, bc, sol, forcing=False)
+
+
+# ------------------------------------------------------------------ binning
+@pytest.mark.parametrize("dim,n,m,seed", [(2, 64, 1000, 1), (2, 12, 333, 2), (3, 16, 2000, 3), (2, 1024, 4096, 4)])
+def test_binning_bit_exact(dim, n, m, seed):
+    p = random_problem(dim, n, m, seed)
+    # force ties and points on cell faces
+    p.geom.X[::5] = p.geom.X[0]
+    p.geom.X[1::7, 0] = (np.arange(p.geom.X[1::7].shape[0]) % n) / n
+    pl = plan_for(p)
+    key, perm = pl.binning()
+    st = O.setup_from_problem(p)
+    okey, operm = O.binning(st)
+    assert np.array_equal(key, okey)
+    assert np.array_equal(perm, operm)
+
+
+# ------------------------------------------------------------------ operator
+CASES = [
+    # dim, n, m, bc, alpha, delta
+    (2, 64, 128, W.DIRICHLET, 1.0, O.COSINE4),
+    (2, 64, 300, W.NEUMANN, 1.0, O.PESKIN4),
+    (2, 12, 17, W.DIRICHLET, 3.0, O.PESKIN4),
+    (2, 8, 1, W.DIRICHLET, 1.0, O.PESKIN4),
+    (2, 96, 500, W.NEUMANN, 100.0, O.PESKIN4),
+    (2, 192, 700, W.DIRICHLET, 0.0, O.PESKIN4),
+    (2, 384, 2000, W.DIRICHLET, 10.0, O.PESKIN4),
+    (3, 16, 200, W.DIRICHLET, 1.0, O.PESKIN4),
+    (3, 24, 500, W.NEUMANN, 5.0, O.COSINE4),
+    (3, 32, 900, W.DIRICHLET, 0.0, O.PESKIN4),
+]
+
+
+@pytest.mark.parametrize("dim,n,m,bc,alpha,delta", CASES)
+def test_apply_fp64_matches_oracle(dim, n, m, bc, alpha, delta):
+    p = random_problem(dim, n, m, seed=n + m, bc=bc, alpha=alpha)
+    st = O.setup_from_problem(p, delta=delta)
+    pl = plan_for(p, delta=delta)
+    q = W.random_density(m, seed=7, nrhs=3)
+    out = N(pl.apply(T(q)))
+    for r in range(3):
+        ref = O.apply_A(st, q[r], bc)
+        assert relerr(out[r], ref) < FP64_TOL, (r, relerr(out[r], ref))
+        assert maxrel(out[r], ref) < 10 * FP64_TOL
+
+
+@pytest.mark.parametrize("dim,n,m,bc,alpha,delta", CASES)
+def test_apply_mixed_matches_oracle(dim, n, m, bc, alpha, delta):
+    p = random_problem(dim, n, m, seed=n + m, bc=bc, alpha=alpha)
+    st = O.setup_from_problem(p, delta=delta)
+    pl = plan_for(p, delta=delta, prec=ibdl.MIXED)
+    q = W.random_density(m, seed=8, nrhs=2)
+    out = N(pl.apply(T(q)))
+    for r in range(2):
+        ref = O.apply_A(st, q[r], bc)
+        assert relerr(out[r], ref) < MIXED_TOL, relerr(out[r], ref)
+
+
+@pytest.mark.parametrize("dim,n,m,bc,alpha", [(2, 64, 200, W.DIRICHLET, 1.0), (2, 96, 300, W.NEUMANN, 2.0),
+                                              (3, 16, 300, W.NEUMANN, 1.0), (3, 24, 400, W.DIRICHLET, 0.0)])
+def test_rhs_and_eval_grid_fp64(dim, n, m, bc, alpha):
+    p = random_problem(dim, n, m, seed=3 * n + m, bc=bc, alpha=alpha)
+    st = O.setup_from_problem(p)
+    pl = plan_for(p)
+    rng = np.random.default_rng(11)
+    data = rng.standard_normal((2, m))
+    g = rng.standard_normal((2,) + (n,) * dim)
+    if alpha == 0.0:
+        g -= g.reshape(2, -1).mean(1).reshape((2,) + (1,) * dim)
+    b = N(pl.rhs(T(data), T(g)))
+    for r in range(2):
+        ref = O.rhs(st, data[r], g[r], bc)
+        assert relerr(b[r], ref) < FP64_TOL
+    b0 = N(pl.rhs(T(data)))
+    for r in range(2):
+        assert relerr(b0[r], O.rhs(st, data[r], None, bc)) < FP64_TOL
+    sol = rng.standard_normal((2, m))
+    vb = rng.standard_normal((2, m)) if bc == W.NEUMANN else None
+    u = N(pl.eval_grid(T(sol), T(vb) if vb is not None else None, T(g)))
+    u0 = N(pl.eval_grid(T(sol), T(vb) if vb is not None else None))
+    for r in range(2):
+        ref = O.eval_grid(st, sol[r], None if vb is None else vb[r], g[r], bc)
+        assert relerr(u[r], ref) < FP64_TOL
+        ref0 = O.eval_grid(st, sol[r], None if vb is None else vb[r], None, bc)
+        assert relerr(u0[r], ref0) < FP64_TOL
+
+
+def test_apply_is_deterministic():
+    p = random_problem(2, 256, 3000, seed=5)
+    for prec in (ibdl.FP64, ibdl.MIXED):
+        pl = plan_for(p, prec=prec)
+        q = T(W.random_density(3000, seed=1, nrhs=2))
+        a = pl.apply(q).clone()
+        for _ in range(5):
+            assert torch.equal(pl.apply(q), a)
+
+
+def test_multi_rhs_equals_single_rhs():
+    p = random_problem(2, 128, 700, seed=6, bc=W.NEUMANN)
+    pl = plan_for(p, prec=ibdl.MIXED)
+    q = T(W.random_density(700, seed=2, nrhs=4))
+    allr = pl.apply(q)
+    for r in range(4):
+        assert torch.equal(pl.apply(q[r:r + 1].contiguous())[0], allr[r])
+
+
+# ------------------------------------------------------------------ full-size workloads
+@pytest.mark.parametrize("bc,alpha", [(W.DIRICHLET, 1.0), (W.NEUMANN, 100.0)])
+def test_star1024_apply(bc, alpha):
+    """The 1024^2 star workload (M=4096) in both precisions."""
+    p = W.config_star1024(m=4096, alpha=alpha, bc=bc)
+    st = O.setup_from_problem(p)
+    q = W.random_density(4096, seed=3, nrhs=1)
+    ref = O.apply_A(st, q[0], bc)
+    out64 = N(plan_for(p).apply(T(q)))[0]
+    assert relerr(out64, ref) < FP64_TOL
+    out32 = N(plan_for(p, prec=ibdl.MIXED).apply(T(q)))[0]
+    assert relerr(out32, ref) < MIXED_TOL
+
+
+def test_sphere256_apply_mixed():
+    """The 256^3 sphere workload (M=40000): mixed operator against the oracle."""
+    p = W.config_sphere256()
+    st = O.setup_from_problem(p)
+    q = W.random_density(p.geom.m, seed=4, nrhs=1)
+    ref = O.apply_A(st, q[0], W.DIRICHLET)
+    out = N(plan_for(p, prec=ibdl.MIXED).apply(T(q)))[0]
+    assert relerr(out, ref) < MIXED_TOL
+
+
+def test_largest_2d_grid():
+    p = random_problem(2, 2048, 5000, seed=9, alpha=3.0)
+    st = O.setup_from_problem(p)
+    q = W.random_density(5000, seed=5, nrhs=1)
+    ref = O.apply_A(st, q[0], W.DIRICHLET)
+    assert relerr(N(plan_for(p).apply(T(q)))[0], ref) < FP64_TOL
+    assert relerr(N(plan_for(p, prec=ibdl.MIXED).apply(T(q)))[0], ref) < MIXED_TOL
+
+
+# ------------------------------------------------------------------ solves
+def test_circle64_solve_fp64():
+    p = W.config_circle64()
+    st = O.setup_from_problem(p, delta=O.COSINE4)
+    res, _ = O.solve(st, p.data, p.g_tilde, tol=1e-10)
+    pl = plan_for(p, delta=O.COSINE4)
+    sol, info = pl.solve(T(p.data[None]), T(p.g_tilde[None]), tol=1e-10, true_residual=True)
+    assert abs(info[0]["iters"] - res.iters) <= 1
+    assert info[0]["rel_resid_true"] < 2e-10
+    tight, _ = O.solve(st, p.data, p.g_tilde, tol=1e-14)
+    assert relerr(N(sol)[0], tight.x) < 1e-9
+    u = N(pl.eval_grid(sol, g=T(p.g_tilde[None])))[0]
+    uref = O.eval_grid(st, tight.x, g_tilde=p.g_tilde)
+    assert relerr(u, uref) < 1e-9
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_neumann_solve_fp64_and_mixed(n):
+    p = W.neumann_circle_problem(n)
+    st = O.setup_from_problem(p)
+    tight, _ = O.solve(st, p.data, p.g_tilde, bc=O.NEUMANN, tol=1e-14)
+    res8, _ = O.solve(st, p.data, p.g_tilde, bc=O.NEUMANN, tol=1e-8)
+    sol, info = plan_for(p).solve(T(p.data[None]), T(p.g_tilde[None]), tol=1e-8)
+    assert abs(info[0]["iters"] - res8.iters) <= 1
+    assert relerr(N(sol)[0], tight.x) < 1e-6
+    sol, info = plan_for(p).solve(T(p.data[None]), T(p.g_tilde[None]), tol=1e-13)
+    assert relerr(N(sol)[0], tight.x) < 1e-11
+    solm, infom = plan_for(p, prec=ibdl.MIXED).solve(T(p.data[None]), T(p.g_tilde[None]), tol=1e-7)
+    assert relerr(N(solm)[0], tight.x) < MIXED_TOL
+
+
+def test_table1_iterations_on_gpu():
+    for n in (64, 128, 256):
+        for c in (2.0, 0.75):
+            p = W.table1_problem(n, c)
+            st = O.setup_from_problem(p)
+            res, _ = O.solve(st, p.data, p.g_tilde, tol=1e-8)
+            _, info = plan_for(p).solve(T(p.data[None]), None, tol=1e-8)
+            assert abs(info[0]["iters"] - res.iters) <= 1, (n, c)
+
+
+def test_3d_solve():
+    p = W.table2_problem(32, 900)
+    st = O.setup_from_problem(p)
+    tight, _ = O.solve(st, p.data, p.g_tilde, tol=1e-13)
+    sol, info = plan_for(p).solve(T(p.data[None]), T(p.g_tilde[None]), tol=1e-12)
+    assert relerr(N(sol)[0], tight.x) < 1e-10
+    assert 4 <= info[0]["iters"] <= 12
+
+
+def test_batched_rhs_solve_equals_single():
+    p = W.config_star1024(m=1116, n=256, alpha=100.0)
+    pl = plan_for(p)
+    rng = np.random.default_rng(1)
+    data = np.stack([p.data, rng.standard_normal(p.geom.m), 0.5 * p.data])
+    g = np.stack([p.g_tilde, np.zeros_like(p.g_tilde), p.g_tilde])
+    sols, infos = pl.solve(T(data), T(g), tol=1e-10)
+    for r in range(3):
+        s1, i1 = pl.solve(T(data[r:r + 1]), T(g[r:r + 1]), tol=1e-10)
+        assert i1[0]["iters"] == infos[r]["iters"]
+        assert torch.equal(s1[0], sols[r])
+
+
+def test_restart_and_noconv():
+    p = W.table1_problem(64, 1.0)
+    st = O.setup_from_problem(p)
+    tight, _ = O.solve(st, p.data, p.g_tilde, tol=1e-14)
+    pl = plan_for(p)
+    sol, info = pl.solve(T(p.data[None]), None, tol=1e-11, restart=2, maxit=200)
+    assert relerr(N(sol)[0], tight.x) < 1e-9
+    with pytest.raises(ibdl.IbdlError) as e:
+        pl.solve(T(p.data[None]), None, tol=1e-12, maxit=1)
+    assert e.value.status == ibdl.ERR_NOCONV
+    sol, info = pl.solve(T(p.data[None]), None, tol=1e-12, maxit=1, raise_on_noconv=False)
+    assert info[0]["iters"] == 1 and info[0]["status"] == ibdl.ERR_NOCONV
+
+
+def test_nonfinite_geometry_rejected():
+    p = random_problem(2, 32, 10, seed=1)
+    X = p.geom.X.copy()
+    X[3, 1] = np.nan
+    with pytest.raises(ibdl.IbdlError) as e:
+        ibdl.Plan(2, 32, (0.0, 0.0), 1.0, 1.0, T(X), T(p.geom.normal), T(p.geom.weight))
+    assert e.value.status == ibdl.ERR_NUMERIC
