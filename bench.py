@@ -1,0 +1,211 @@
+"""Benchmark of the IBDL hot path on one MI355X.
+
+A step is one complete IBDL solve of a batch of right-hand sides on the 2-D
+star workload (periodic unit square, 1024^2 grid, star r = 0.3 + 0.05 cos 5t
+with 4096 boundary points, alpha = 1, Dirichlet, random-Fourier manufactured
+data): the right-hand side, unpreconditioned GMRES on the device to tol 1e-8,
+and the grid solution.  The geometry's plan (binning, sort, spread matrices) is
+built once before timing.  Inputs are resident on the GPU.
+
+value = operator applications per second over the timed steps (every GMRES
+iteration of every right-hand side counts one application; the time includes
+the right-hand side, the Krylov arithmetic and the grid solution).  The line
+also reports solves/s, per-step latency percentiles, the FP64 path, the error
+of both against the FP64 oracle, the roofline of the dominant kernel (timed with
+HIP events on the library's stream) and the oracle's own throughput on the
+host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs R] [--workload star1024|sphere256]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IBDL operator applies/s + batched solves/s at 1e-6 rel err; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(st, dim, n, m, prec, nrhs):
+    """Algorithmic bytes per call of each grid stage for this geometry: every
+    necessary read and write counted once (see the design notes)."""
+    bc = 16 if prec == 0 else 8      # complex
+    br = 8 if prec == 0 else 4       # real
+    W = n // 2 + 1
+    S, G = st["n_spread_lines"], st["n_gather_lines"]
+    gpp = 4 if dim == 2 else 16
+    csr = st["dip_nnz"] * (4 + br) + st["dip_active_nodes"] * 8 + (st["nlines"] + 1) * 4 + S * 4
+    pts = m * (12 + 12 * br + 4)
+    out = {}
+    out["spread+fft_x"] = nrhs * (S * W * bc + m * 8) + csr
+    if dim == 2:
+        out["fft_y+symbol"] = nrhs * (S + G) * W * bc
+    else:
+        Ps, Pg = st["n_spread_planes"], st["n_gather_planes"]
+        out["fft_y"] = nrhs * (S + Ps * n) * W * bc
+        out["fft_z+symbol"] = nrhs * (Ps + Pg) * n * W * bc
+        out["ifft_y"] = nrhs * (Pg * n + G) * W * bc
+    out["ifft_x+interp"] = nrhs * (G * W * bc + m * gpp * br) + pts
+    out["finish"] = nrhs * (m * gpp * br + m * 16) + m * 4
+    return out
+
+
+def full_grid_bytes_per_apply(dim, n, m, prec):
+    """(4d-4) H + M (16 + 2 d b): the full-grid byte count of one apply."""
+    b = 8 if prec == 0 else 4
+    H = n ** (dim - 1) * (n // 2 + 1) * 2 * b
+    return (4 * dim - 4) * H + m * (16 + 2 * dim * b)
+
+
+def make_workload(name, nrhs):
+    from paper_2203_12126_amd import workloads as W
+    if name == "star1024":
+        probs = [W.config_star1024(m=4096, alpha=1.0, bc=W.DIRICHLET, seed=2203 + r) for r in range(nrhs)]
+        desc = ("2-D Dirichlet screened Poisson, periodic unit square, 1024^2 grid, star "
+                "r=0.3+0.05cos(5t) with 4096 points, alpha=1, random-Fourier manufactured data")
+        tol = 1e-8
+    elif name == "sphere256":
+        probs = [W.config_sphere256()]
+        for r in range(1, nrhs):
+            probs.append(W.config_sphere256())
+        desc = ("3-D Dirichlet, periodic unit cube, 256^3 grid, sphere R=0.3 with 40000 Fibonacci "
+                "points, alpha=10, u=exp(x+y)cos(sqrt2 z-0.3)")
+        tol = 1e-8
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return probs, desc, tol
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nrhs", type=int, default=4)
+    ap.add_argument("--workload", default="star1024")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each solve fits one MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_12126_amd import ibdl
+
+    torch.cuda.set_device(0)
+    probs, desc, tol = make_workload(args.workload, args.nrhs)
+    p0 = probs[0]
+    dim, n, m = p0.grid.dim, p0.grid.n, p0.geom.m
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    data = t(np.stack([p.data for p in probs]))
+    g = t(np.stack([p.g_tilde for p in probs]))
+
+    def run(prec, steps, warmup, timing):
+        plan = ibdl.Plan.from_problem(p0, prec=prec)
+        for _ in range(warmup):
+            sol, info = plan.solve(data, g, tol=tol)
+            plan.eval_grid(sol, g=g)
+        torch.cuda.synchronize()
+        if timing:
+            plan.set_timing(True)
+        lat, iters = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            sol, info = plan.solve(data, g, tol=tol)
+            u = plan.eval_grid(sol, g=g)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+            iters += sum(i["iters"] for i in info)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stages = plan.stage_times() if timing else []
+        stats = plan.stats()
+        out = dict(elapsed=el, lat=lat, iters=iters, sol=sol.cpu().numpy(), u=u.cpu().numpy(),
+                   info=info, stages=stages, stats=stats)
+        plan.close()
+        return out
+
+    mixed = run(ibdl.MIXED, args.steps, args.warmup, True)
+    fp64 = run(ibdl.FP64, max(3, args.steps // 2), 1, False)
+
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(nb, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # accuracy against the FP64 oracle (outside the timed region)
+    from oracle import ibdl_oracle as O
+    st = O.setup_from_problem(p0)
+    t_cpu0 = time.perf_counter()
+    res, _ = O.solve(st, p0.data, p0.g_tilde, tol=tol)
+    uo = O.eval_grid(st, res.x, g_tilde=p0.g_tilde)
+    t_cpu = time.perf_counter() - t_cpu0
+    tight, _ = O.solve(st, p0.data, p0.g_tilde, tol=1e-13)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err_mixed = rel(mixed["sol"][0], tight.x)
+    err_fp64 = rel(fp64["sol"][0], tight.x)
+    err_u_mixed = rel(mixed["u"][0], O.eval_grid(st, tight.x, g_tilde=p0.g_tilde))
+
+    K = args.steps
+    el = mixed["elapsed"]
+    applies_s = mixed["iters"] / el
+    solves_s = K * args.nrhs / el
+    lat_ms = np.array(mixed["lat"]) * 1e3
+
+    # roofline of the dominant stage
+    sb = stage_bytes(mixed["stats"], dim, n, m, 1, args.nrhs)
+    tot = {name: ms * calls for name, ms, calls in mixed["stages"]}
+    dom = max(tot, key=tot.get)
+    dom_ms = dict((nm, ms) for nm, ms, _ in mixed["stages"])[dom]
+    achieved = sb.get(dom, 0) / (dom_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(sb.get(dom, 0)), "ms_per_launch": round(dom_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = {"value": round(res.iters / t_cpu, 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
+               "sample": f"one FP64 oracle solve of the first right-hand side (rhs, {res.iters} GMRES "
+                         f"applies, grid solution) = {t_cpu:.1f} s",
+               "host_cpus": os.cpu_count()}
+
+    line = {
+        "metric": METRIC, "value": round(applies_s, 2), "unit": "applies/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(el / K * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 grid + f64 krylov", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": n, "dim": dim, "M": m,
+                   "alpha": p0.alpha, "bc": "dirichlet", "nrhs": args.nrhs, "tol": tol,
+                   "precision": "mixed"},
+        "solves_per_s": round(solves_s, 3),
+        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 4),
+        "iters_per_solve": round(mixed["iters"] / (K * args.nrhs), 2),
+        "rel_err_vs_oracle": {"Q_mixed": err_mixed, "Q_fp64": err_fp64, "u_mixed": err_u_mixed},
+        "fp64_path": {"applies_per_s": round(fp64["iters"] / fp64["elapsed"], 2),
+                      "solves_per_s": round(len(fp64["lat"]) * args.nrhs / fp64["elapsed"], 3),
+                      "latency_ms_p50": round(float(np.percentile(np.array(fp64["lat"]) * 1e3, 50)), 4)},
+        "stages_ms": {nm: round(ms, 5) for nm, ms, _ in mixed["stages"]},
+        "full_grid_bytes_per_apply": full_grid_bytes_per_apply(dim, n, m, 1),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

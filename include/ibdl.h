@@ -147,13 +147,31 @@ ibdl_status ibdl_eval_grid(ibdl_plan plan, int32_t nrhs, const double* sol, cons
  * s-th point in (key, index) order.  Either pointer may be NULL. */
 ibdl_status ibdl_plan_binning(ibdl_plan plan, uint32_t* key_host, uint32_t* perm_host);
 
-/* Per-stage device time of the most recent ibdl_apply in milliseconds, measured
- * with HIP events on the apply's stream when timing is enabled (0 disables).
- * ms_host receives up to `cap` stage times; *count the number of stages; names
- * (may be NULL) receives a static string per stage. */
+/* Per-stage device timing.  While enabled, every pass of the plan through the
+ * grid (apply, rhs, solve iterations, eval_grid) records HIP events on its
+ * stream before each stage and at its end; enabling (again) clears the record.
+ * ibdl_plan_stage_times waits for the recorded events and returns, per stage
+ * name, the mean time in milliseconds (ms_host) and the number of timed calls
+ * (calls); names receives static strings.  Up to `cap` stages are written and
+ * *count receives the number of distinct stages.  Any output pointer may be NULL. */
 ibdl_status ibdl_plan_set_timing(ibdl_plan plan, int32_t enable);
 ibdl_status ibdl_plan_stage_times(ibdl_plan plan, double* ms_host, const char** names,
-                                  int32_t cap, int32_t* count);
+                                  int64_t* calls, int32_t cap, int32_t* count);
+
+/* Sizes of a plan's data structures (for byte accounting and inspection). */
+typedef struct {
+    int32_t nlines;            /* x-lines of the grid, n^(dim-1)                          */
+    int32_t pitch;             /* complex elements per half-spectrum row (>= n/2+1)        */
+    int32_t n_spread_lines;    /* x-lines that receive dipole forcing                      */
+    int32_t n_gather_lines;    /* x-lines some boundary point interpolates from            */
+    int32_t n_spread_planes;   /* 3-D: z-planes holding spread lines (else 0)              */
+    int32_t n_gather_planes;   /* 3-D: z-planes holding gather lines (else 0)              */
+    int32_t dip_active_nodes;  /* grid nodes reached by the dipole spread                  */
+    int64_t dip_nnz;           /* (node, point) entries of the dipole spread               */
+    int64_t mono_nnz;          /* entries of the monopole spread (Neumann plans, else 0)   */
+} ibdl_plan_stats;
+
+ibdl_status ibdl_plan_get_stats(ibdl_plan plan, ibdl_plan_stats* out_host);
 
 /* Message for the last failing call on this host thread ("" if none). */
 const char* ibdl_last_error(void);

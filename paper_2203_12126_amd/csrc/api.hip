@@ -66,15 +66,54 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
         run_pipeline_f32(p, nrhs, in, out, st);
 }
 
+static void flush_set(ibdl_plan p, int set) {
+    const int n = p->set_used[set];
+    if (n <= 0) return;
+    IBDL_HIP_TRY(hipEventSynchronize(p->ev[set][n]));
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[set][i], p->ev[set][i + 1]));
+        const char* nm = p->set_names[set][i];
+        int slot = -1;
+        for (int k = 0; k < p->n_acc; ++k)
+            if (std::strcmp(p->acc_names[k], nm) == 0) slot = k;
+        if (slot < 0 && p->n_acc < 16) {
+            slot = p->n_acc++;
+            p->acc_names[slot] = nm;
+            p->acc_ms[slot] = 0.0;
+            p->acc_n[slot] = 0;
+        }
+        if (slot >= 0) {
+            p->acc_ms[slot] += ms;
+            p->acc_n[slot] += 1;
+        }
+    }
+    p->set_used[set] = 0;
+}
+
+// Records an event before stage idx (name) or, with name == nullptr, the end of
+// the pass.  Stage names must be string literals.
 void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st) {
-    if (!p->timing || idx > 8) return;
+    if (!p->timing || idx > ibdl_plan_s::MAXST) return;
     if (!p->events_made) {
-        for (int i = 0; i < 9; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[i]));
+        for (int s = 0; s < ibdl_plan_s::RING; ++s)
+            for (int i = 0; i <= ibdl_plan_s::MAXST; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[s][i]));
         p->events_made = 1;
     }
-    IBDL_HIP_TRY(hipEventRecord(p->ev[idx], st));
-    if (name && idx < 8) p->stage_names[idx] = name;
-    if (!name) p->nstages = idx;
+    if (idx == 0) {
+        const int set = p->ring_pos;
+        flush_set(p, set);
+        p->cur_set = set;
+        p->ring_pos = (set + 1) % ibdl_plan_s::RING;
+    }
+    if (p->cur_set < 0) return;
+    IBDL_HIP_TRY(hipEventRecord(p->ev[p->cur_set][idx], st));
+    if (name) {
+        p->set_names[p->cur_set][idx] = name;
+    } else {
+        p->set_used[p->cur_set] = idx;
+        p->cur_set = -1;
+    }
 }
 
 void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out, size_t ostride,
@@ -150,7 +189,8 @@ ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->kr.host_pinned) (void)hipHostFree(p->kr.host_pinned);
     if (p->events_made)
-        for (int i = 0; i < 9; ++i) (void)hipEventDestroy(p->ev[i]);
+        for (int s = 0; s < ibdl_plan_s::RING; ++s)
+            for (int i = 0; i <= ibdl_plan_s::MAXST; ++i) (void)hipEventDestroy(p->ev[s][i]);
     delete p;
     return IBDL_OK;
 }
@@ -271,28 +311,43 @@ ibdl_status ibdl_plan_binning(ibdl_plan p, uint32_t* key_host, uint32_t* perm_ho
     IBDL_GUARD_END
 }
 
-ibdl_status ibdl_plan_set_timing(ibdl_plan p, int32_t enable) {
-    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
-    p->timing = enable ? 1 : 0;
+ibdl_status ibdl_plan_get_stats(ibdl_plan p, ibdl_plan_stats* o) {
+    if (!p || !o) return fail(IBDL_ERR_ARG, "plan and out must not be NULL");
+    o->nlines = p->nlines;
+    o->pitch = p->P;
+    o->n_spread_lines = p->n_spread_lines;
+    o->n_gather_lines = p->n_gather_lines;
+    o->n_spread_planes = p->n_spread_planes;
+    o->n_gather_planes = p->n_gather_planes;
+    o->dip_active_nodes = p->dip.nact;
+    o->dip_nnz = p->dip.nnz;
+    o->mono_nnz = p->mono.nnz;
     return IBDL_OK;
 }
 
-ibdl_status ibdl_plan_stage_times(ibdl_plan p, double* ms_host, const char** names, int32_t cap,
-                                  int32_t* count) {
+ibdl_status ibdl_plan_set_timing(ibdl_plan p, int32_t enable) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
-    if (!p->events_made || p->nstages == 0) {
-        if (count) *count = 0;
-        return IBDL_OK;
-    }
     IBDL_GUARD_BEGIN
-    IBDL_HIP_TRY(hipEventSynchronize(p->ev[p->nstages]));
-    for (int i = 0; i < p->nstages && i < cap; ++i) {
-        float ms = 0.f;
-        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
-        if (ms_host) ms_host[i] = ms;
-        if (names) names[i] = p->stage_names[i];
+    for (int s = 0; s < ibdl_plan_s::RING; ++s) p->set_used[s] = 0;
+    p->n_acc = 0;
+    p->cur_set = -1;
+    p->ring_pos = 0;
+    p->timing = enable ? 1 : 0;
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_plan_stage_times(ibdl_plan p, double* ms_host, const char** names, int64_t* calls,
+                                  int32_t cap, int32_t* count) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    IBDL_GUARD_BEGIN
+    for (int s = 0; s < ibdl_plan_s::RING; ++s) flush_set(p, s);
+    for (int i = 0; i < p->n_acc && i < cap; ++i) {
+        if (ms_host) ms_host[i] = p->acc_n[i] ? p->acc_ms[i] / (double)p->acc_n[i] : 0.0;
+        if (names) names[i] = p->acc_names[i];
+        if (calls) calls[i] = p->acc_n[i];
     }
-    if (count) *count = p->nstages;
+    if (count) *count = p->n_acc;
     return IBDL_OK;
     IBDL_GUARD_END
 }

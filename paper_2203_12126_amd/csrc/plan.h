@@ -96,13 +96,19 @@ struct ibdl_plan_s {
     ibdl::Workspace ws;
     ibdl::Krylov kr;
 
-    // stage timing
+    // stage timing: a ring of event sets, one set per pass through the grid
+    static constexpr int RING = 64;
+    static constexpr int MAXST = 9;
     int timing = 0;
-    int nstages = 0;
-    hipEvent_t ev[9] = {};
-    const char* stage_names[8] = {};
-    double stage_ms[8] = {};
     int events_made = 0;
+    int ring_pos = 0, cur_set = -1;
+    hipEvent_t ev[RING][MAXST + 1] = {};
+    const char* set_names[RING][MAXST] = {};
+    int set_used[RING] = {};
+    const char* acc_names[16] = {};
+    double acc_ms[16] = {};
+    long long acc_n[16] = {};
+    int n_acc = 0;
 
     std::vector<void*> allocs;  // everything to free
 };

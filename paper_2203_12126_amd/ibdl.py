@@ -40,6 +40,14 @@ class SolveOpts(ctypes.Structure):
                 ("x0", ctypes.c_void_p), ("true_residual", ctypes.c_int32)]
 
 
+class PlanStats(ctypes.Structure):
+    _fields_ = [("nlines", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("n_spread_lines", ctypes.c_int32), ("n_gather_lines", ctypes.c_int32),
+                ("n_spread_planes", ctypes.c_int32), ("n_gather_planes", ctypes.c_int32),
+                ("dip_active_nodes", ctypes.c_int32), ("dip_nnz", ctypes.c_int64),
+                ("mono_nnz", ctypes.c_int64)]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rel_resid_est", ctypes.c_double),
                 ("rel_resid_true", ctypes.c_double), ("status", ctypes.c_int32)]
@@ -69,7 +77,8 @@ def lib():
         "ibdl_eval_grid": ([P, I, P, P, P, P, P], st),
         "ibdl_plan_binning": ([P, P, P], st),
         "ibdl_plan_set_timing": ([P, I], st),
-        "ibdl_plan_stage_times": ([P, P, P, I, ctypes.POINTER(I)], st),
+        "ibdl_plan_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
+        "ibdl_plan_get_stats": ([P, ctypes.POINTER(PlanStats)], st),
         "ibdl_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -214,16 +223,23 @@ class Plan:
                                        perm.ctypes.data_as(ctypes.c_void_p)), "ibdl_plan_binning")
         return key, perm
 
+    def stats(self) -> dict:
+        s = PlanStats()
+        _check(lib().ibdl_plan_get_stats(self._h, ctypes.byref(s)), "ibdl_plan_get_stats")
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
     def set_timing(self, on=True):
         _check(lib().ibdl_plan_set_timing(self._h, 1 if on else 0), "ibdl_plan_set_timing")
 
     def stage_times(self):
-        ms = (ctypes.c_double * 8)()
-        names = (ctypes.c_char_p * 8)()
+        """[(stage name, mean ms, timed calls)] since timing was enabled."""
+        ms = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 16)()
+        calls = (ctypes.c_int64 * 16)()
         cnt = ctypes.c_int32()
-        _check(lib().ibdl_plan_stage_times(self._h, ms, names, 8, ctypes.byref(cnt)),
+        _check(lib().ibdl_plan_stage_times(self._h, ms, names, calls, 16, ctypes.byref(cnt)),
                "ibdl_plan_stage_times")
-        return [(names[i].decode() if names[i] else f"stage{i}", ms[i]) for i in range(cnt.value)]
+        return [(names[i].decode(), ms[i], calls[i]) for i in range(cnt.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
