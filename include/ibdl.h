@@ -92,6 +92,7 @@ typedef struct {
     double rel_resid_est;   /* Arnoldi residual estimate / ||b||                            */
     double rel_resid_true;  /* ||b - A x|| / ||b|| if requested, else -1                    */
     int32_t status;         /* ibdl_status of this right-hand side                          */
+    int32_t fp64_applies;   /* FP64 operator passes spent on residuals (mixed refinement)    */
 } ibdl_solve_info;
 
 /* Build a plan for one geometry (Sec. 5.1-5.2): cell binning of the points by the
@@ -126,6 +127,10 @@ ibdl_status ibdl_rhs(ibdl_plan plan, int32_t nrhs, const double* data, const dou
 /* Step 1 of the method (Sec. 4.1, Sec. 5.3): form the right-hand side and run
  * unpreconditioned restarted GMRES on the device (FP64 Arnoldi with classical
  * Gram-Schmidt applied twice, Givens rotations) for each right-hand side.
+ * The right-hand side is formed in FP64 for every plan.  MIXED plans iterate
+ * with the FP32-grid operator and refine: r = b - A x with the FP64 operator,
+ * a further FP32-operator GMRES solve of A d = r, x += d, until the FP64
+ * residual meets tol (at most 5 rounds); rel_resid_true is that FP64 residual.
  * sol: device [nrhs][M] receives Q (Dirichlet) or U_b (Neumann).
  * info: HOST [nrhs].  opts may be NULL (tol 1e-8, restart 50, maxit 500).
  * Blocks until done.  Returns IBDL_ERR_NOCONV if any rhs missed tol (its best

@@ -58,9 +58,10 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 namespace ibdl {
 
-void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
+void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st,
+                  bool fp64) {
     ensure_workspace(p, nrhs);
-    if (p->prec == IBDL_PREC_FP64)
+    if (fp64 || p->prec == IBDL_PREC_FP64)
         run_pipeline_f64(p, nrhs, in, out, st);
     else
         run_pipeline_f32(p, nrhs, in, out, st);
@@ -253,7 +254,7 @@ ibdl_status ibdl_rhs(ibdl_plan p, int32_t nrhs, const double* data, const double
         in.c_grid = -1.0;
         out.cA = 1.0;
     }
-    run_pipeline(p, nrhs, in, out, S(stream));
+    run_pipeline(p, nrhs, in, out, S(stream), true);
     return IBDL_OK;
     IBDL_GUARD_END
 }
@@ -296,7 +297,7 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     in.c_grid = 1.0;
     PipeOut out;
     out.u = u;
-    run_pipeline(p, nrhs, in, out, S(stream));
+    run_pipeline(p, nrhs, in, out, S(stream), true);
     return IBDL_OK;
     IBDL_GUARD_END
 }

@@ -51,7 +51,7 @@ struct KArgs {
     double* bnorm;      // [rhs]
     double* resid;      // [rhs]
     int32_t* state;     // [rhs][4]
-    double tol;
+    const double* tolv; // [rhs] tolerance relative to ||b_r||
 };
 
 // sum of squares of x over each block's chunk
@@ -70,13 +70,13 @@ __global__ __launch_bounds__(GT) void k_sumsq(const double* __restrict__ x, size
 }
 
 __global__ void k_set_bnorm(const double* __restrict__ part, size_t pstride, int nblk,
-                            double* bnorm, int32_t* state, int nrhs) {
+                            double* bnorm, int32_t* state, const int32_t* skip, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[(size_t)r * pstride + b];
     bnorm[r] = sqrt(s);
-    state[4 * r + ST_DONE] = 0;
+    state[4 * r + ST_DONE] = skip[r];
     state[4 * r + ST_ITERS] = 0;
     state[4 * r + ST_STATUS] = isfinite(s) ? IBDL_OK : IBDL_ERR_NUMERIC;
     state[4 * r + ST_J] = 0;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(GT) void k_init_cycle(const double* __restrict__ rv
     for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)rhs * a.pstride + b];
     const double beta = sqrt(s);
     const double bn = a.bnorm[rhs];
-    const bool done = !(bn > 0.0) || beta <= a.tol * bn || !(beta > 0.0);
+    const bool done = !(bn > 0.0) || beta <= a.tolv[rhs] * bn || !(beta > 0.0);
     const double inv = (beta > 0.0) ? 1.0 / beta : 0.0;
     double* v0 = a.V + (size_t)rhs * a.vstride;
     const double* r = rv + (size_t)rhs * rstride;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
     if (!isfinite(res) || !isfinite(s)) {
         st[ST_STATUS] = IBDL_ERR_NUMERIC;
         st[ST_DONE] = 1;
-    } else if (res <= a.tol || !(hn > 0.0)) {
+    } else if (res <= a.tolv[rhs] || !(hn > 0.0)) {
         st[ST_DONE] = 1;
     }
 }
@@ -275,9 +275,13 @@ __global__ void k_reset_j(int32_t* state, int nrhs) {
     if (r < nrhs) state[4 * r + ST_J] = 0;
 }
 
-__global__ void k_fill0(double* x, size_t n) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0.0;
+__global__ void k_fill0_masked(double* x, size_t stride, int M, const int32_t* skip) {
+    const int rhs = blockIdx.y;
+    if (skip[rhs]) return;
+    for (int i = 0; i < GPER; ++i) {
+        const size_t mm = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
+        if (mm < (size_t)M) x[(size_t)rhs * stride + mm] = 0.0;
+    }
 }
 
 __global__ void k_copy(double* dst, const double* src, size_t n) {
@@ -304,11 +308,16 @@ static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
     k.hcol = A((size_t)nrhs * (m + 2));
     k.bnorm = A(nrhs);
     k.resid = A(nrhs);
+    k.tolv = A(nrhs);
     k.b = A((size_t)nrhs * M);
     k.r = A((size_t)nrhs * M);
+    k.rr = A((size_t)nrhs * M);
+    k.d = A((size_t)nrhs * M);
     k.state = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * 4 * sizeof(int32_t)));
+    k.skip = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * sizeof(int32_t)));
     if (k.host_pinned) (void)hipHostFree(k.host_pinned);
-    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * (4 * sizeof(int32_t) + 2 * sizeof(double))));
+    k.host_pinned = nullptr;
+    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * 64));
     k.cap_rhs = nrhs;
     k.cap_m = m;
     k.nblk = nblk;
@@ -317,9 +326,9 @@ static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
 void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out,
                     size_t ostride, hipStream_t st);
 
-// b - A x for every rhs into r
+// r = b - A x for every rhs (operator in FP64 when fp64, else the plan's precision)
 static void residual(ibdl_plan p, int nrhs, const double* b, const double* x, double* r,
-                     hipStream_t st) {
+                     hipStream_t st, bool fp64) {
     // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
     PipeIn in;
     in.q_dip = x;
@@ -331,14 +340,38 @@ static void residual(ibdl_plan p, int nrhs, const double* b, const double* x, do
     out.cB = p->bc == IBDL_DIRICHLET ? -0.5 : 0.5;
     out.in2 = b;
     out.cC = 1.0;
-    run_pipeline(p, nrhs, in, out, st);
+    run_pipeline(p, nrhs, in, out, st, fp64);
 }
 
-void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
-                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall) {
+// host copies of per-rhs norms: sqrt of the summed block partials of k_sumsq
+static void norms(ibdl_plan p, int nrhs, const double* x, hipStream_t st, std::vector<double>& out) {
+    Krylov& k = p->kr;
+    const size_t pstride = (size_t)k.nblk;
+    hipLaunchKernelGGL(k_sumsq, dim3(k.nblk, nrhs), dim3(GT), 0, st, x, (size_t)p->M, p->M, k.partial,
+                       pstride);
+    std::vector<double> hp((size_t)nrhs * pstride);
+    IBDL_HIP_TRY(hipMemcpyAsync(hp.data(), k.partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    out.assign(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+        double s = 0.0;
+        for (int b = 0; b < k.nblk; ++b) s += hp[(size_t)r * pstride + b];
+        out[r] = std::sqrt(s);
+    }
+}
+
+struct KrylovResult {
+    std::vector<int> iters, status;
+    std::vector<double> est;
+};
+
+// Restarted GMRES on A x = b with the operator in the plan's precision, for every
+// rhs not marked in skip.  x holds the initial iterate (x_zero: it is set to 0).
+// tol[r] is relative to ||b_r||.  Iterations add to res.iters.
+static void krylov(ibdl_plan p, int nrhs, const double* b, double* x, bool x_zero,
+                   const std::vector<double>& tol, int m, int maxit, const std::vector<int>& skip,
+                   hipStream_t st, KrylovResult& res) {
     const int M = p->M;
-    const int m = o.restart;
-    ensure_krylov(p, nrhs, m);
     Krylov& k = p->kr;
     const int nblk = k.nblk;
     KArgs a{};
@@ -359,54 +392,34 @@ void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, con
     a.bnorm = k.bnorm;
     a.resid = k.resid;
     a.state = k.state;
-    a.tol = o.tol;
+    a.tolv = k.tolv;
     const dim3 vg(nblk, nrhs);
     const size_t tot = (size_t)nrhs * M;
 
-    // right-hand side b (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~))
-    {
-        PipeIn in;
-        PipeOut out;
-        out.out = k.b;
-        if (p->bc == IBDL_DIRICHLET) {
-            if (g) {
-                in.grid = g;
-                in.c_grid = 1.0;
-                out.cA = -1.0;
-                out.in = data;
-                out.cB = 1.0;
-                run_pipeline(p, nrhs, in, out, st);
-            } else {
-                hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, k.b, data, tot);
-            }
-        } else {
-            in.q_mono = data;
-            in.c_mono = 1.0;
-            if (g) {
-                in.grid = g;
-                in.c_grid = -1.0;
-            }
-            out.cA = 1.0;
-            run_pipeline(p, nrhs, in, out, st);
-        }
+    // per-rhs tolerances and skip flags
+    double* hbuf = reinterpret_cast<double*>(k.host_pinned);
+    int32_t* hint = reinterpret_cast<int32_t*>(hbuf + nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        hbuf[r] = tol[r];
+        hint[r] = skip[r];
     }
-    // ||b||, state reset
-    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.b, (size_t)M, M, k.partial, a.pstride);
+    IBDL_HIP_TRY(hipMemcpyAsync(k.tolv, hbuf, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+    IBDL_HIP_TRY(hipMemcpyAsync(k.skip, hint, nrhs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+
+    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, b, (size_t)M, M, k.partial, a.pstride);
     hipLaunchKernelGGL(k_set_bnorm, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.partial, a.pstride, nblk,
-                       k.bnorm, k.state, nrhs);
-    // initial residual
-    const double* r0 = k.b;
-    if (o.x0) {
-        hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, o.x0, tot);
-        residual(p, nrhs, k.b, sol, k.r, st);
-        r0 = k.r;
+                       k.bnorm, k.state, k.skip, nrhs);
+    const double* r0 = b;
+    if (x_zero) {
+        hipLaunchKernelGGL(k_fill0_masked, vg, dim3(GT), 0, st, x, (size_t)M, M, k.skip);
     } else {
-        hipLaunchKernelGGL(k_fill0, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, tot);
+        residual(p, nrhs, b, x, k.r, st, false);
+        r0 = k.r;
     }
     hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, r0, (size_t)M, M, k.partial, a.pstride);
     hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, r0, (size_t)M, a);
 
-    int32_t* hstate = reinterpret_cast<int32_t*>(k.host_pinned);
+    int32_t* hstate = reinterpret_cast<int32_t*>(hbuf + 2 * nrhs);
     auto all_done = [&]() {
         IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t),
                                     hipMemcpyDeviceToHost, st));
@@ -419,55 +432,163 @@ void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, con
     int total = 0;
     bool finished = all_done();
     while (!finished) {
-        int j = 0;
-        for (; j < m; ++j) {
+        for (int j = 0; j < m; ++j) {
             apply_operator(p, nrhs, k.V + (size_t)j * M, a.vstride, k.V + (size_t)(j + 1) * M, a.vstride, st);
             hipLaunchKernelGGL(k_dots, vg, dim3(GT), 0, st, a, j);
             hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 0);
             hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 1);
             hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st, a, j);
             ++total;
-            if (all_done() || total >= o.maxit) break;
+            if (all_done() || total >= maxit) break;
         }
         hipLaunchKernelGGL(k_backsolve, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
-        hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st, a, sol, (size_t)M);
+        hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st, a, x, (size_t)M);
         hipLaunchKernelGGL(k_reset_j, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.state, nrhs);
-        if (all_done() || total >= o.maxit) break;
+        if (all_done() || total >= maxit) break;
         // restart the rhs still running from their current iterate
-        residual(p, nrhs, k.b, sol, k.r, st);
+        residual(p, nrhs, b, x, k.r, st, false);
         hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);
         hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, k.r, (size_t)M, a);
         finished = all_done();
     }
     IBDL_HIP_TRY(hipGetLastError());
-
-    // report
-    std::vector<double> hres(nrhs), htrue(nrhs, -1.0), hbn(nrhs);
+    std::vector<double> hres(nrhs);
     IBDL_HIP_TRY(hipMemcpyAsync(hres.data(), k.resid, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    IBDL_HIP_TRY(hipMemcpyAsync(hbn.data(), k.bnorm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    if (o.true_residual) {
-        residual(p, nrhs, k.b, sol, k.r, st);
-        hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);
-        std::vector<double> hp((size_t)nrhs * a.pstride);
-        IBDL_HIP_TRY(hipMemcpyAsync(hp.data(), k.partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        IBDL_HIP_TRY(hipStreamSynchronize(st));
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) {
+        if (skip[r]) continue;
+        res.iters[r] += hstate[4 * r + ST_ITERS];
+        res.est[r] = hres[r];
+        int s = hstate[4 * r + ST_STATUS];
+        if (s == IBDL_OK && !(hres[r] <= tol[r])) s = IBDL_ERR_NOCONV;
+        res.status[r] = s;
+    }
+}
+
+__global__ void k_axpy_masked(double* x, const double* d, size_t stride, int M, const int32_t* skip) {
+    const int rhs = blockIdx.y;
+    if (skip[rhs]) return;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)M) x[(size_t)rhs * stride + i] += d[(size_t)rhs * stride + i];
+}
+
+void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
+                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall) {
+    const int M = p->M;
+    const int m = o.restart;
+    ensure_krylov(p, nrhs, m);
+    Krylov& k = p->kr;
+    const size_t tot = (size_t)nrhs * M;
+
+    // right-hand side b in FP64 (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~))
+    {
+        PipeIn in;
+        PipeOut out;
+        out.out = k.b;
+        if (p->bc == IBDL_DIRICHLET) {
+            if (g) {
+                in.grid = g;
+                in.c_grid = 1.0;
+                out.cA = -1.0;
+                out.in = data;
+                out.cB = 1.0;
+                run_pipeline(p, nrhs, in, out, st, true);
+            } else {
+                hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, k.b, data, tot);
+            }
+        } else {
+            in.q_mono = data;
+            in.c_mono = 1.0;
+            if (g) {
+                in.grid = g;
+                in.c_grid = -1.0;
+            }
+            out.cA = 1.0;
+            run_pipeline(p, nrhs, in, out, st, true);
+        }
+    }
+    std::vector<double> bn;
+    norms(p, nrhs, k.b, st, bn);
+
+    KrylovResult res;
+    res.iters.assign(nrhs, 0);
+    res.status.assign(nrhs, IBDL_OK);
+    res.est.assign(nrhs, 0.0);
+    std::vector<double> tol(nrhs, o.tol);
+    std::vector<int> skip(nrhs, 0);
+    std::vector<double> truer(nrhs, -1.0);
+    std::vector<int> fp64_applies(nrhs, 0);
+
+    if (o.x0) {
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, o.x0, tot);
+    }
+    krylov(p, nrhs, k.b, sol, o.x0 == nullptr, tol, m, o.maxit, skip, st, res);
+
+    if (p->prec == IBDL_PREC_MIXED) {
+        // FP64 iterative refinement: r = b - A x with the FP64 operator, correct
+        // with the FP32-operator Krylov solve of A d = r, x += d.
+        for (int round = 0; round < 5; ++round) {
+            residual(p, nrhs, k.b, sol, k.rr, st, true);
+            std::vector<double> rn;
+            norms(p, nrhs, k.rr, st, rn);
+            bool all = true;
+            for (int r = 0; r < nrhs; ++r) {
+                fp64_applies[r] += skip[r] ? 0 : 1;
+                const double rel = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
+                if (!skip[r]) {
+                    truer[r] = rel;
+                    res.est[r] = rel;
+                }
+                if (!std::isfinite(rel)) {
+                    res.status[r] = IBDL_ERR_NUMERIC;
+                    skip[r] = 1;
+                } else if (rel <= o.tol || res.status[r] == IBDL_ERR_NUMERIC) {
+                    if (res.status[r] == IBDL_ERR_NOCONV) res.status[r] = IBDL_OK;
+                    skip[r] = 1;
+                } else {
+                    all = false;
+                    // reduce the correction's residual to the target, no further than the FP32 floor
+                    tol[r] = std::max(o.tol * bn[r] / rn[r], 1e-6);
+                }
+            }
+            if (all || round == 4) {
+                for (int r = 0; r < nrhs; ++r)
+                    if (!(truer[r] <= o.tol) && res.status[r] == IBDL_OK) res.status[r] = IBDL_ERR_NOCONV;
+                break;
+            }
+            int used = 0;
+            for (int r = 0; r < nrhs; ++r) used = std::max(used, res.iters[r]);
+            const int left = o.maxit - used;
+            if (left <= 0) {
+                for (int r = 0; r < nrhs; ++r)
+                    if (!skip[r]) res.status[r] = IBDL_ERR_NOCONV;
+                break;
+            }
+            krylov(p, nrhs, k.rr, k.d, true, tol, m, left, skip, st, res);
+            hipLaunchKernelGGL(k_axpy_masked, dim3((M + 255) / 256, nrhs), dim3(256), 0, st, sol, k.d,
+                               (size_t)M, M, k.skip);
+        }
+    } else if (o.true_residual) {
+        residual(p, nrhs, k.b, sol, k.rr, st, true);
+        std::vector<double> rn;
+        norms(p, nrhs, k.rr, st, rn);
         for (int r = 0; r < nrhs; ++r) {
-            double s = 0.0;
-            for (int b = 0; b < nblk; ++b) s += hp[(size_t)r * a.pstride + b];
-            htrue[r] = hbn[r] > 0.0 ? std::sqrt(s) / hbn[r] : 0.0;
+            truer[r] = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
+            fp64_applies[r] = 1;
         }
     }
     IBDL_HIP_TRY(hipStreamSynchronize(st));
+
     int worst = IBDL_OK;
     for (int r = 0; r < nrhs; ++r) {
-        int s = hstate[4 * r + ST_STATUS];
-        if (s == IBDL_OK && !(hres[r] <= o.tol)) s = IBDL_ERR_NOCONV;
+        const int s = res.status[r];
         if (info) {
-            info[r].iters = hstate[4 * r + ST_ITERS];
-            info[r].rel_resid_est = hres[r];
-            info[r].rel_resid_true = htrue[r];
+            info[r].iters = res.iters[r];
+            info[r].rel_resid_est = res.est[r];
+            info[r].rel_resid_true = truer[r];
             info[r].status = s;
+            info[r].fp64_applies = fp64_applies[r];
         }
         if (s == IBDL_ERR_NUMERIC) worst = IBDL_ERR_NUMERIC;
         else if (s == IBDL_ERR_NOCONV && worst == IBDL_OK) worst = IBDL_ERR_NOCONV;

@@ -41,10 +41,13 @@ struct Krylov {
     double* hcol = nullptr;     // [rhs][m+2]
     double* bnorm = nullptr;    // [rhs]
     double* resid = nullptr;    // [rhs]
+    double* tolv = nullptr;     // [rhs]
     int32_t* state = nullptr;   // [rhs][4]: done flag, iterations, status, j
-    double* b = nullptr;        // [rhs][M]
-    double* x = nullptr;        // [rhs][M]
-    double* r = nullptr;        // [rhs][M]
+    int32_t* skip = nullptr;    // [rhs]
+    double* b = nullptr;        // [rhs][M] right-hand side
+    double* r = nullptr;        // [rhs][M] restart residual
+    double* rr = nullptr;       // [rhs][M] refinement residual
+    double* d = nullptr;        // [rhs][M] refinement correction
     void* host_pinned = nullptr;
 };
 
@@ -142,7 +145,9 @@ struct PipeOut {
 
 void* dev_alloc(ibdl_plan p, size_t bytes);
 void ensure_workspace(ibdl_plan p, int nrhs);
-void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+// fp64 forces the FP64 pipeline on a mixed plan (right-hand sides, residuals, grid solutions)
+void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st,
+                  bool fp64 = false);
 void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
 void run_pipeline_f32(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);

@@ -574,8 +574,9 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
 
 void ensure_workspace(ibdl_plan p, int nrhs) {
     if (p->ws.cap_rhs >= nrhs) return;
-    const size_t cs = p->prec == IBDL_PREC_FP64 ? 16 : 8;
-    const size_t rs = p->prec == IBDL_PREC_FP64 ? 8 : 4;
+    // sized for FP64: mixed plans run their once-per-solve passes in FP64
+    const size_t cs = 16;
+    const size_t rs = 8;
     // grow: the old buffers stay owned by the plan until it is destroyed
     p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
     p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);

@@ -50,7 +50,8 @@ class PlanStats(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("rel_resid_est", ctypes.c_double),
-                ("rel_resid_true", ctypes.c_double), ("status", ctypes.c_int32)]
+                ("rel_resid_true", ctypes.c_double), ("status", ctypes.c_int32),
+                ("fp64_applies", ctypes.c_int32)]
 
 
 _lib = None
@@ -204,7 +205,8 @@ class Plan:
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_solve")
         return out, [dict(iters=i.iters, rel_resid_est=i.rel_resid_est,
-                          rel_resid_true=i.rel_resid_true, status=i.status) for i in info]
+                          rel_resid_true=i.rel_resid_true, status=i.status,
+                          fp64_applies=i.fp64_applies) for i in info]
 
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
         nrhs = self._nrhs(sol, self.m)
