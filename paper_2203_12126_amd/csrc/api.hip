@@ -1,6 +1,7 @@
 // C ABI of the IBDL library: argument checks, error reporting, dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -70,10 +71,10 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
 static void flush_set(ibdl_plan p, int set) {
     const int n = p->set_used[set];
     if (n <= 0) return;
-    IBDL_HIP_TRY(hipEventSynchronize(p->ev[set][n]));
+    IBDL_HIP_TRY(hipEventSynchronize(p->ev[set][2 * n - 1]));
     for (int i = 0; i < n; ++i) {
         float ms = 0.f;
-        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[set][i], p->ev[set][i + 1]));
+        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[set][2 * i], p->ev[set][2 * i + 1]));
         const char* nm = p->set_names[set][i];
         int slot = -1;
         for (int k = 0; k < p->n_acc; ++k)
@@ -92,13 +93,13 @@ static void flush_set(ibdl_plan p, int set) {
     p->set_used[set] = 0;
 }
 
-// Records an event before stage idx (name) or, with name == nullptr, the end of
-// the pass.  Stage names must be string literals.
-void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st) {
-    if (!p->timing || idx > ibdl_plan_s::MAXST) return;
+// Stage names must be string literals.
+StageEv stage_events(ibdl_plan p, int idx, const char* name) {
+    StageEv e;
+    if (!p->timing || idx >= ibdl_plan_s::MAXST) return e;
     if (!p->events_made) {
         for (int s = 0; s < ibdl_plan_s::RING; ++s)
-            for (int i = 0; i <= ibdl_plan_s::MAXST; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[s][i]));
+            for (int i = 0; i < 2 * ibdl_plan_s::MAXST; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[s][i]));
         p->events_made = 1;
     }
     if (idx == 0) {
@@ -107,14 +108,12 @@ void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st) {
         p->cur_set = set;
         p->ring_pos = (set + 1) % ibdl_plan_s::RING;
     }
-    if (p->cur_set < 0) return;
-    IBDL_HIP_TRY(hipEventRecord(p->ev[p->cur_set][idx], st));
-    if (name) {
-        p->set_names[p->cur_set][idx] = name;
-    } else {
-        p->set_used[p->cur_set] = idx;
-        p->cur_set = -1;
-    }
+    if (p->cur_set < 0) return e;
+    p->set_names[p->cur_set][idx] = name;
+    p->set_used[p->cur_set] = idx + 1;
+    e.a = p->ev[p->cur_set][2 * idx];
+    e.b = p->ev[p->cur_set][2 * idx + 1];
+    return e;
 }
 
 void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out, size_t ostride,
@@ -167,7 +166,7 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
         p->h = desc->length / desc->n;
         p->alpha = desc->alpha;
         p->W = desc->n / 2 + 1;
-        p->P = (p->W + 15) / 16 * 16;
+        p->P = std::max(tile_pitch_f64(desc->n), tile_pitch_f32(desc->n));
         p->nlines = desc->dim == 2 ? desc->n : desc->n * desc->n;
         p->spec_elems = (size_t)p->nlines * p->P;
         p->gpp = desc->dim == 3 ? 16 : 4;
@@ -191,7 +190,7 @@ ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     if (p->kr.host_pinned) (void)hipHostFree(p->kr.host_pinned);
     if (p->events_made)
         for (int s = 0; s < ibdl_plan_s::RING; ++s)
-            for (int i = 0; i <= ibdl_plan_s::MAXST; ++i) (void)hipEventDestroy(p->ev[s][i]);
+            for (int i = 0; i < 2 * ibdl_plan_s::MAXST; ++i) (void)hipEventDestroy(p->ev[s][i]);
     delete p;
     return IBDL_OK;
 }

@@ -1,33 +1,102 @@
-// LDS-resident mixed-radix (2, 3, 4, 8) Stockham FFT over C interleaved lines.
+// Mixed-radix Stockham FFT over C interleaved lines, register-resident stages.
 //
-// Element i of line c lives at s[i*C + c].  Each stage reads the RAD inputs of
-// its butterflies into registers, synchronises, and writes the outputs in the
-// Stockham order, so the result is in natural order without a bit reversal.
-// Twiddles come from a table of W_N^m = exp(-2 pi i m / N), m < N, read with a
-// compile-time stride TWS so that one table serves lengths N and N/2.
+// A length-L transform is split into S stages of radix R_1..R_S (each a product
+// of 2s and 3s, at most RMAX).  In a stage every thread owns whole butterflies:
+// it loads the RAD inputs of a butterfly into registers, multiplies by the
+// stage twiddles, runs a length-RAD DFT in registers (itself split into radix
+// 2/3/4/8 pieces with internal twiddles) and stores the outputs in Stockham
+// order, so the result is in natural order without a bit reversal.  Stages pass
+// data through LDS; the first stage may read straight from global memory and
+// the last may write straight to global memory through the load/store functors.
+//
+// Element i of line c is addressed as (i, c); LDS holds it at s[i*C + c].
+// Twiddles come from one table W_NT^m = exp(-2 pi i m / NT), m < NT, where NT
+// is a multiple of every length used with it.
 #pragma once
+#include <utility>
+
 #include "common.h"
 
 namespace ibdl {
 
-constexpr int radix_for(int rem) {
-    int a = 0, b = 0, t = rem;
-    while (t % 2 == 0) { t /= 2; ++a; }
-    while (t % 3 == 0) { t /= 3; ++b; }
-    if (b > 0) return 3;
-    if (a % 3 == 0) return 8;
-    if (a == 1) return 2;
-    return 4;
-}
-
-constexpr bool fft_size_ok(int n) {
-    if (n < 2) return false;
+// ------------------------------------------------------------------ radix plans
+constexpr bool smooth23(int n) {
+    if (n < 1) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
     return n == 1;
 }
 
-// Length-RAD DFT in registers; SIGN = -1 forward, +1 inverse (unnormalised).
+constexpr bool splittable(int L, int S, int RMAX) {
+    if (S == 1) return L >= 2 && L <= RMAX && smooth23(L);
+    for (int d = 2; d <= RMAX; ++d)
+        if (L % d == 0 && smooth23(d) && splittable(L / d, S - 1, RMAX)) return true;
+    return false;
+}
+
+struct RadixPlan {
+    int n = 0;
+    int r[4] = {1, 1, 1, 1};
+};
+
+constexpr double cpow(double x, int e) {
+    double v = 1.0;
+    for (int i = 0; i < e; ++i) v *= x;
+    return v;
+}
+
+// fewest stages, then factors as close as possible to the geometric mean
+constexpr RadixPlan make_plan(int L, int RMAX) {
+    RadixPlan p{};
+    int S = 1;
+    while (S < 4 && !splittable(L, S, RMAX)) ++S;
+    int rem = L;
+    for (int s = 0; s < S; ++s) {
+        const int left = S - s;
+        if (left == 1) {
+            p.r[s] = rem;
+            break;
+        }
+        int best = -1;
+        double bestq = 1e300;
+        for (int d = 2; d <= RMAX; ++d) {
+            if (rem % d || !smooth23(d) || !splittable(rem / d, left - 1, RMAX)) continue;
+            const double a = cpow((double)d, left), b = (double)rem;
+            const double q = a > b ? a / b : b / a;
+            if (q < bestq) { bestq = q; best = d; }
+        }
+        p.r[s] = best;
+        rem /= best;
+    }
+    p.n = S;
+    return p;
+}
+
+constexpr int plan_max(const RadixPlan& p) {
+    int m = 1;
+    for (int i = 0; i < p.n; ++i) m = p.r[i] > m ? p.r[i] : m;
+    return m;
+}
+
+template <int... Rs>
+struct Radices {};
+
+template <int L, int RMAX, size_t... I>
+constexpr auto radices_fwd(std::index_sequence<I...>) -> Radices<make_plan(L, RMAX).r[I]...> {
+    return {};
+}
+template <int L, int RMAX, size_t... I>
+constexpr auto radices_rev(std::index_sequence<I...>)
+    -> Radices<make_plan(L, RMAX).r[make_plan(L, RMAX).n - 1 - I]...> {
+    return {};
+}
+template <int L, int RMAX>
+using FwdRadices = decltype(radices_fwd<L, RMAX>(std::make_index_sequence<make_plan(L, RMAX).n>{}));
+template <int L, int RMAX>
+using RevRadices = decltype(radices_rev<L, RMAX>(std::make_index_sequence<make_plan(L, RMAX).n>{}));
+
+// ------------------------------------------------------------------ register DFTs
+// Length-RAD DFT of the base radices; SIGN = -1 forward, +1 inverse (unnormalised).
 template <int RAD, int SIGN, typename R>
 __device__ __forceinline__ void butterfly(cplx<R>* v) {
     if constexpr (RAD == 2) {
@@ -51,14 +120,13 @@ __device__ __forceinline__ void butterfly(cplx<R>* v) {
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, t3);
         v[3] = csub(t1, t3);
-    } else {  // RAD == 8: two length-4 DFTs of the even and odd samples
+    } else {
         static_assert(RAD == 8, "radix");
         cplx<R> e[4] = {v[0], v[2], v[4], v[6]};
         cplx<R> o[4] = {v[1], v[3], v[5], v[7]};
         butterfly<4, SIGN>(e);
         butterfly<4, SIGN>(o);
         const R h = R(0.70710678118654752440);
-        // W8^k = exp(SIGN * 2 pi i k / 8)
         cplx<R> w1 = cmul(o[1], cplx<R>{h, SIGN * h});
         cplx<R> w2 = cmul_si<SIGN>(o[2]);
         cplx<R> w3 = cmul(o[3], cplx<R>{-h, SIGN * h});
@@ -73,53 +141,173 @@ __device__ __forceinline__ void butterfly(cplx<R>* v) {
     }
 }
 
-template <typename R, int L, int C, int T, int RAD, int NS, int SIGN, int TWS>
-__device__ __forceinline__ void fft_stage(cplx<R>* s, const cplx<R>* __restrict__ tw) {
-    constexpr int NB = L / RAD;     // butterflies per line
-    constexpr int TOT = NB * C;     // butterflies in the block
-    constexpr int PER = (TOT + T - 1) / T;
+// exp(-2 pi i m / n) at compile time: the angle is reduced exactly in integers to
+// phi in [0, pi/4] (quarter turns and the complement), then sin/cos of phi by
+// their Taylor series.
+struct CD {
+    double re, im;
+};
+constexpr CD expm2pi(long m, long n) {
+    m %= n;
+    if (m < 0) m += n;
+    const long q = (4 * m) / n;          // quarter turns
+    const long r = 4 * m - q * n;        // remaining angle (pi/2) r/n
+    const bool comp = 2 * r > n;
+    const long rr = comp ? n - r : r;
+    const double phi = 1.57079632679489661923132169163975144 * (double)rr / (double)n;
+    double s = 0.0, c = 0.0, ts = phi, tc = 1.0;
+    for (int k = 1; k < 15; ++k) {
+        s += ts;
+        ts *= -phi * phi / (double)((2 * k) * (2 * k + 1));
+        c += tc;
+        tc *= -phi * phi / (double)((2 * k - 1) * (2 * k));
+    }
+    if (comp) {
+        const double t = s;
+        s = c;
+        c = t;
+    }
+    for (long i = 0; i < q; ++i) {
+        const double t = c;
+        c = -s;
+        s = t;
+    }
+    return CD{c, -s};
+}
+template <int RAD>
+struct TwTab {
+    double re[RAD > 0 ? RAD : 1];
+    double im[RAD > 0 ? RAD : 1];
+};
+template <int RAD>
+constexpr TwTab<RAD> make_twtab() {
+    TwTab<RAD> t{};
+    for (int m = 0; m < RAD; ++m) {
+        const CD w = expm2pi(m, RAD);
+        t.re[m] = w.re;
+        t.im[m] = w.im;
+    }
+    return t;
+}
+template <int RAD>
+struct TwConst {
+    static constexpr TwTab<RAD> tab = make_twtab<RAD>();
+};
+
+template <int SIGN, typename R>
+__device__ __forceinline__ cplx<R> twiddle(const cplx<R>* __restrict__ tw, int idx) {
+    cplx<R> w = tw[idx];
+    if (SIGN > 0) w.y = -w.y;
+    return w;
+}
+
+// Length-RAD DFT in registers.  RAD = R1 * R2 with R1 a base radix:
+//   X[k1 + R1 k2] = sum_n2 W_RAD^{n2 k1} W_R2^{n2 k2} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}.
+template <int RAD, int SIGN, int NT, typename R>
+__device__ __forceinline__ void reg_dft(cplx<R>* v, const cplx<R>* __restrict__ tw) {
+    if constexpr (RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8) {
+        butterfly<RAD, SIGN>(v);
+    } else {
+        constexpr int R1 = (RAD % 8 == 0) ? 8 : (RAD % 4 == 0) ? 4 : (RAD % 2 == 0) ? 2 : 3;
+        constexpr int R2 = RAD / R1;
+        cplx<R> a[R2][R1];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[R2 * n1 + n2];
+            butterfly<R1, SIGN>(a[n2]);
+        }
+#pragma unroll
+        for (int n2 = 1; n2 < R2; ++n2)
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) {
+                const int e = n2 * k1;
+                const cplx<R> w = {(R)TwConst<RAD>::tab.re[e], (R)(-SIGN * TwConst<RAD>::tab.im[e])};
+                a[n2][k1] = cmul(a[n2][k1], w);
+            }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cplx<R> b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
+            reg_dft<R2, SIGN, NT>(b, tw);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ stages
+// LDS functors
+template <typename R, int C>
+struct LdsLoad {
+    const cplx<R>* s;
+    __device__ __forceinline__ cplx<R> operator()(int i, int c) const { return s[i * C + c]; }
+};
+template <typename R, int C>
+struct LdsStore {
+    cplx<R>* s;
+    __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[i * C + c] = v; }
+};
+
+// One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
+template <typename R, int L, int C, int TH, int NT, int SIGN, int NS, int RAD, int... REST, class LD,
+          class ST>
+__device__ __forceinline__ void run_stages(cplx<R>* s, const cplx<R>* __restrict__ tw, LD ld, ST st) {
+    constexpr int NB = L / RAD;
+    constexpr int TOT = NB * C;
+    constexpr int PER = (TOT + TH - 1) / TH;
     cplx<R> v[PER][RAD];
 #pragma unroll
     for (int b = 0; b < PER; ++b) {
-        const int id = threadIdx.x + b * T;
-        if (TOT % T == 0 || id < TOT) {
+        const int id = threadIdx.x + b * TH;
+        if (TOT % TH == 0 || id < TOT) {
             const int c = id % C, j = id / C;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) v[b][r] = s[(j + r * NB) * C + c];
+            for (int r = 0; r < RAD; ++r) v[b][r] = ld(j + r * NB, c);
             if constexpr (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
-                for (int r = 1; r < RAD; ++r) {
-                    cplx<R> w = tw[(L / (NS * RAD)) * r * k * TWS];
-                    if (SIGN > 0) w.y = -w.y;
-                    v[b][r] = cmul(v[b][r], w);
-                }
+                for (int r = 1; r < RAD; ++r)
+                    v[b][r] = cmul(v[b][r], twiddle<SIGN>(tw, (NT / (NS * RAD)) * r * k));
             }
-            butterfly<RAD, SIGN>(v[b]);
+            reg_dft<RAD, SIGN, NT>(v[b], tw);
         }
     }
-    __syncthreads();
+    auto emit = [&](auto&& out) {
 #pragma unroll
-    for (int b = 0; b < PER; ++b) {
-        const int id = threadIdx.x + b * T;
-        if (TOT % T == 0 || id < TOT) {
-            const int c = id % C, j = id / C;
-            const int base = (j / NS) * NS * RAD + (j % NS);
+        for (int b = 0; b < PER; ++b) {
+            const int id = threadIdx.x + b * TH;
+            if (TOT % TH == 0 || id < TOT) {
+                const int c = id % C, j = id / C;
+                const int base = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) s[(base + r * NS) * C + c] = v[b][r];
+                for (int r = 0; r < RAD; ++r) out(base + r * NS, c, v[b][r]);
+            }
         }
+    };
+    if constexpr (sizeof...(REST) == 0) {
+        __syncthreads();  // the store may overwrite LDS this stage (or a caller) read
+        emit(st);
+    } else {
+        __syncthreads();  // every input of this stage has been read
+        emit(LdsStore<R, C>{s});
+        __syncthreads();
+        run_stages<R, L, C, TH, NT, SIGN, NS * RAD, REST...>(s, tw, LdsLoad<R, C>{s}, st);
     }
-    __syncthreads();
 }
 
-// Full length-L transform of the C lines held in s (natural order in and out).
-template <typename R, int L, int C, int T, int SIGN, int TWS, int NS = 1, int REM = L>
-__device__ __forceinline__ void fft_lines(cplx<R>* s, const cplx<R>* __restrict__ tw) {
-    if constexpr (REM > 1) {
-        constexpr int RAD = radix_for(REM);
-        fft_stage<R, L, C, T, RAD, NS, SIGN, TWS>(s, tw);
-        fft_lines<R, L, C, T, SIGN, TWS, NS * RAD, REM / RAD>(s, tw);
-    }
+template <typename R, int L, int C, int TH, int NT, int SIGN, class LD, class ST, int... Rs>
+__device__ __forceinline__ void run_fft(cplx<R>* s, const cplx<R>* __restrict__ tw, LD ld, ST st,
+                                        Radices<Rs...>) {
+    run_stages<R, L, C, TH, NT, SIGN, 1, Rs...>(s, tw, ld, st);
+}
+
+// Threads per block so that the largest radix stage has one butterfly per thread.
+template <int L, int C, int RMAX>
+constexpr int fft_threads() {
+    constexpr int t = C * L / plan_max(make_plan(L, RMAX));
+    return t < 64 ? 64 : (t > 1024 ? 1024 : (t + 63) / 64 * 64);
 }
 
 }  // namespace ibdl

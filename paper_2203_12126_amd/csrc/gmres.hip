@@ -17,9 +17,12 @@
 
 namespace ibdl {
 
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
 constexpr int GT = 256;             // threads per block
-constexpr int GPER = 4;             // elements per thread
+constexpr int GPER = 1;             // elements per thread
 constexpr int GCHUNK = GT * GPER;   // elements per block
+constexpr int FIN_BLOCK = 256;      // points per block of the operator's finishing kernel
 
 enum { ST_DONE = 0, ST_ITERS = 1, ST_STATUS = 2, ST_J = 3 };
 
@@ -35,11 +38,36 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;  // valid in thread 0
 }
 
+// Block sums of nv per-thread values at once: each wave reduces its values with
+// cross-lane shuffles, one LDS write per wave and value, one barrier, then
+// thread i adds the wave totals of value i (fixed order).  out[i] valid in
+// threads i < nv after the call; sh holds GT/64 * nv doubles.
+template <int MAXV>
+__device__ __forceinline__ void block_multi_sum(double (&v)[MAXV], int nv, double* sh, double* out) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        if (i < nv) {
+            double t = v[i];
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (l == 0) sh[w * MAXV + i] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double t = 0.0;
+        for (int ww = 0; ww < GT / 64; ++ww) t += sh[ww * MAXV + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
 struct KArgs {
     double* V;          // [rhs][m+1][M]
     size_t vstride;
     int M, m, nblk;
-    double* part;       // [rhs][nblk][m+2] (two banks: part and part2)
+    int nblk_dots;      // blocks of the operator's fused first inner products
+    double* part;       // [rhs][blocks][m+2] (two banks: part and part2)
     double* part2;
     size_t pstride;     // per rhs
     double* hcol;       // [rhs][m+2]
@@ -111,30 +139,6 @@ __global__ __launch_bounds__(GT) void k_init_cycle(const double* __restrict__ rv
     }
 }
 
-// partial <w, v_i> for i <= j, w = v_{j+1} slot
-__global__ __launch_bounds__(GT) void k_dots(KArgs a, int j) {
-    __shared__ double sh[GT / 64];
-    const int rhs = blockIdx.y;
-    if (a.state[4 * rhs + ST_DONE]) return;
-    const double* V = a.V + (size_t)rhs * a.vstride;
-    const double* w = V + (size_t)(j + 1) * a.M;
-    double wl[GPER];
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        wl[i] = m < (size_t)a.M ? w[m] : 0.0;
-    }
-    for (int vi = 0; vi <= j; ++vi) {
-        const double* v = V + (size_t)vi * a.M;
-        double acc = 0.0;
-        for (int i = 0; i < GPER; ++i) {
-            const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-            if (m < (size_t)a.M) acc += v[m] * wl[i];
-        }
-        const double t = block_sum(acc, sh);
-        if (threadIdx.x == 0) a.part[(size_t)rhs * a.pstride + (size_t)blockIdx.x * (a.m + 2) + vi] = t;
-    }
-}
-
 // h = sum of the block partials of pass `pass`; w -= V h; then the partials of
 // the next quantity: pass 0 -> <w, v_i> again, pass 1 -> ||w||^2
 __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
@@ -144,9 +148,10 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
     if (a.state[4 * rhs + ST_DONE]) return;
     const double* pin = (pass == 0 ? a.part : a.part2) + (size_t)rhs * a.pstride;
     double* pout = (pass == 0 ? a.part2 : a.part) + (size_t)rhs * a.pstride;
+    const int nb_in = pass == 0 ? a.nblk_dots : a.nblk;
     for (int vi = threadIdx.x; vi <= j; vi += GT) {
         double s = 0.0;
-        for (int b = 0; b < a.nblk; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        for (int b = 0; b < nb_in; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
         hs[vi] = s;
     }
     __syncthreads();
@@ -169,15 +174,24 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
         }
     }
     if (pass == 0) {
-        for (int vi = 0; vi <= j; ++vi) {
-            const double* v = V + (size_t)vi * a.M;
-            double acc = 0.0;
+        // <w, v_i> for i <= j, 16 at a time
+        __shared__ double msh[(GT / 64) * 16];
+        __shared__ double mout[16];
+        for (int v0 = 0; v0 <= j; v0 += 16) {
+            const int nv = imin(16, j + 1 - v0);
+            double acc[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[u] = 0.0;
             for (int i = 0; i < GPER; ++i) {
                 const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-                if (m < (size_t)a.M) acc += v[m] * wl[i];
+                if (m < (size_t)a.M) {
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (u < nv) acc[u] += V[(size_t)(v0 + u) * a.M + m] * wl[i];
+                }
             }
-            const double t = block_sum(acc, sh);
-            if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2) + vi] = t;
+            block_multi_sum<16>(acc, nv, msh, mout);
+            if (threadIdx.x < nv) pout[(size_t)blockIdx.x * (a.m + 2) + v0 + threadIdx.x] = mout[threadIdx.x];
         }
     } else {
         double acc = 0.0;
@@ -295,6 +309,7 @@ static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
     if (k.cap_rhs >= nrhs && k.cap_m >= m) return;
     const int M = p->M;
     const int nblk = (M + GCHUNK - 1) / GCHUNK;
+    const int nbmax = std::max(nblk, (M + FIN_BLOCK - 1) / FIN_BLOCK);
     nrhs = std::max(nrhs, k.cap_rhs);
     m = std::max(m, k.cap_m);
     auto A = [&](size_t n) { return reinterpret_cast<double*>(dev_alloc(p, n * sizeof(double))); };
@@ -304,7 +319,7 @@ static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
     k.sn = A((size_t)nrhs * m);
     k.g = A((size_t)nrhs * (m + 1));
     k.y = A((size_t)nrhs * m);
-    k.partial = A((size_t)nrhs * nblk * (m + 2) * 2);
+    k.partial = A((size_t)nrhs * nbmax * (m + 2) * 2);
     k.hcol = A((size_t)nrhs * (m + 2));
     k.bnorm = A(nrhs);
     k.resid = A(nrhs);
@@ -317,7 +332,7 @@ static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
     k.skip = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * sizeof(int32_t)));
     if (k.host_pinned) (void)hipHostFree(k.host_pinned);
     k.host_pinned = nullptr;
-    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * 64));
+    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * 64 + 64));
     k.cap_rhs = nrhs;
     k.cap_m = m;
     k.nblk = nblk;
@@ -380,8 +395,9 @@ static void krylov(ibdl_plan p, int nrhs, const double* b, double* x, bool x_zer
     a.M = M;
     a.m = m;
     a.nblk = nblk;
+    a.nblk_dots = (M + FIN_BLOCK - 1) / FIN_BLOCK;
     a.part = k.partial;
-    a.pstride = (size_t)nblk * (m + 2);
+    a.pstride = (size_t)std::max(nblk, a.nblk_dots) * (m + 2);
     a.part2 = k.partial + (size_t)nrhs * a.pstride;
     a.hcol = k.hcol;
     a.H = k.H;
@@ -420,31 +436,84 @@ static void krylov(ibdl_plan p, int nrhs, const double* b, double* x, bool x_zer
     hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, r0, (size_t)M, a);
 
     int32_t* hstate = reinterpret_cast<int32_t*>(hbuf + 2 * nrhs);
+    double* hres_p = hbuf + 4 * nrhs;
     auto all_done = [&]() {
         IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t),
                                     hipMemcpyDeviceToHost, st));
+        IBDL_HIP_TRY(hipMemcpyAsync(hres_p, k.resid, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
         IBDL_HIP_TRY(hipStreamSynchronize(st));
         for (int r = 0; r < nrhs; ++r)
             if (!hstate[4 * r + ST_DONE]) return false;
         return true;
     };
+    // Arnoldi step j for every rhs still running (kernels skip finished ones)
+    auto iteration = [&](int j) {
+        PipeIn in;
+        in.q_dip = k.V + (size_t)j * M;
+        in.c_dip = 1.0;
+        in.q_stride = a.vstride;
+        in.skip = k.state;
+        PipeOut o;
+        o.out = k.V + (size_t)(j + 1) * M;
+        o.out_stride = a.vstride;
+        o.cA = -1.0;
+        o.in = k.V + (size_t)j * M;
+        o.in_stride = a.vstride;
+        o.cB = p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
+        o.dots_V = k.V;
+        o.dots_vstride = a.vstride;
+        o.dots_nv = j + 1;
+        o.dots = a.part;
+        o.dots_rhs = a.pstride;
+        o.dots_stride = m + 2;
+        run_pipeline(p, nrhs, in, o, st);
+        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 0);
+        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 1);
+        hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st, a, j);
+    };
+    // how many steps to queue before looking at the state again: the steps the
+    // slowest rhs needs at its observed rate of residual reduction (1..8)
+    auto next_chunk = [&](int done_steps, const std::vector<double>& prev) {
+        int need = 3;
+        if (done_steps > 0) {
+            need = 1;
+            for (int r = 0; r < nrhs; ++r) {
+                if (hstate[4 * r + ST_DONE]) continue;
+                const double now = hres_p[r], before = prev[r];
+                int nr = 8;
+                if (now > 0.0 && before > now) {
+                    const double rate = std::pow(now / before, 1.0 / done_steps);
+                    if (rate < 1.0) nr = (int)std::ceil(std::log(tol[r] / now) / std::log(rate));
+                }
+                need = std::max(need, std::min(std::max(nr, 1), 8));
+            }
+        }
+        return need;
+    };
 
     int total = 0;
     bool finished = all_done();
     while (!finished) {
-        for (int j = 0; j < m; ++j) {
-            apply_operator(p, nrhs, k.V + (size_t)j * M, a.vstride, k.V + (size_t)(j + 1) * M, a.vstride, st);
-            hipLaunchKernelGGL(k_dots, vg, dim3(GT), 0, st, a, j);
-            hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 0);
-            hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 1);
-            hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st, a, j);
-            ++total;
-            if (all_done() || total >= maxit) break;
+        int j = 0;
+        int last = 0;
+        std::vector<double> prev(hres_p, hres_p + nrhs);
+        bool stop = false;
+        while (j < m) {
+            const int chunk = std::min({next_chunk(last, prev), m - j, maxit - total});
+            prev.assign(hres_p, hres_p + nrhs);
+            for (int t = 0; t < chunk; ++t) iteration(j + t);
+            j += chunk;
+            total += chunk;
+            last = chunk;
+            if (all_done() || total >= maxit) {
+                stop = true;
+                break;
+            }
         }
         hipLaunchKernelGGL(k_backsolve, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
         hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st, a, x, (size_t)M);
         hipLaunchKernelGGL(k_reset_j, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.state, nrhs);
-        if (all_done() || total >= maxit) break;
+        if (stop) break;
         // restart the rhs still running from their current iterate
         residual(p, nrhs, b, x, k.r, st, false);
         hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);

@@ -19,6 +19,8 @@
 // spectrum rows are zero), and lines no boundary point interpolates from are
 // not transformed back.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "fft.h"
 #include "plan.h"
 
@@ -28,20 +30,58 @@ constexpr int imin(int a, int b) { return a < b ? a : b; }
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int rup64(int x) { return (x + 63) / 64 * 64; }
 
-// Column-group width: C adjacent complex columns are read per row (64 bytes).
+// Tile parameters (compile-time; overridable for tuning builds).
+#ifndef IBDL_RMAX_F32
+#define IBDL_RMAX_F32 16
+#endif
+#ifndef IBDL_RMAX_F64
+#define IBDL_RMAX_F64 16
+#endif
+#ifndef IBDL_COLB_F32
+#define IBDL_COLB_F32 64
+#endif
+#ifndef IBDL_COLB_F64
+#define IBDL_COLB_F64 64
+#endif
+#ifndef IBDL_ROW_ELEMS
+#define IBDL_ROW_ELEMS 2048
+#endif
+
+// Largest in-register DFT per precision (register budget).
 template <typename R>
-struct ColBytes { static constexpr int value = 64; };
+struct RMax { static constexpr int value = sizeof(R) == 4 ? IBDL_RMAX_F32 : IBDL_RMAX_F64; };
+
+// Column-group width: C adjacent complex columns are read per row.
+template <typename R>
+struct ColBytes { static constexpr int value = sizeof(R) == 4 ? IBDL_COLB_F32 : IBDL_COLB_F64; };
 
 template <typename R, int N>
 struct RowCfg {
-    static constexpr int L = N / 2;                            // complex length
-    static constexpr int G = imax(1, imin(64, 2048 / L));       // lines per block
-    static constexpr int T = imax(64, imin(1024, rup64(G * L / 8)));
+    static constexpr int L = N / 2;                                      // complex length
+    static constexpr int G = imax(1, imin(64, IBDL_ROW_ELEMS / L));       // lines per block
+    static constexpr int T = imax(256, fft_threads<L, G, RMax<R>::value>());
 };
 template <typename R, int N>
 struct ColCfg {
-    static constexpr int C = ColBytes<R>::value / (2 * (int)sizeof(R));
-    static constexpr int T = imax(64, imin(1024, rup64(N * C / 8)));
+    // at most 128 KiB of LDS for the block's lines
+    static constexpr int C = imax(1, imin(ColBytes<R>::value / (2 * (int)sizeof(R)),
+                                          131072 / (N * 2 * (int)sizeof(R))));
+    static constexpr int T = fft_threads<N, C, RMax<R>::value>();
+};
+
+// Half-spectrum layout in column tiles (complex elements, one right-hand side):
+// element (line, kx), line = y (2-D) or z*n + y (3-D), kx in [0, n/2], is at
+//   (line / n) * NT*n*C + (kx / C) * n*C + (line % n) * C + kx % C,
+// NT = ceil((n/2+1)/C) tiles of C columns; a tile of one plane is n*C contiguous
+// elements, so a column transform reads and writes contiguous memory.
+template <typename R, int N>
+struct Tiles {
+    static constexpr int C = ColCfg<R, N>::C;
+    static constexpr int NT = (N / 2 + 1 + C - 1) / C;
+    static constexpr size_t PLANE = (size_t)NT * N * C;
+    __device__ __forceinline__ static size_t idx(int line, int kx) {
+        return (size_t)(line / N) * PLANE + (size_t)(kx / C) * (N * C) + (size_t)(line % N) * C + (kx % C);
+    }
 };
 
 // ------------------------------------------------------------ accumulation
@@ -86,6 +126,7 @@ struct CsrView {
 
 template <typename R>
 struct RowFwdArgs {
+    const int32_t* skip;   // per-rhs flags (stride 4) or null: a set flag skips that rhs
     const int32_t* lines;  // line list or null (identity)
     int nproc;
     int M;
@@ -101,12 +142,14 @@ struct RowFwdArgs {
 
 template <typename R>
 struct ColArgs {
+    const int32_t* skip;
     cplx<R>* spec;
     size_t rhs_stride;
     const int32_t* outer_list;
-    size_t outer_stride;
-    size_t elem_stride;
-    int width;
+    size_t tile_stride;   // between tiles
+    size_t outer_stride;  // between outer indices (plane z, or a block of K rows)
+    size_t es;            // between consecutive elements of a line
+    int width;            // n/2 + 1 columns
     const uint8_t* lmask;
     int lm_outer, lm_stride;
     const uint8_t* smask;
@@ -115,11 +158,11 @@ struct ColArgs {
     const R* s2;
     R alpha;
     R norm;
-    int dim3;
 };
 
 template <typename R>
 struct RowInvArgs {
+    const int32_t* skip;
     const int32_t* lines;
     int nproc;
     const cplx<R>* spec;
@@ -173,7 +216,23 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
         const int x = (int)(c.act_node[a] - (uint32_t)line * (uint32_t)N);
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
-        for (int e = c.act_ptr[a]; e < e1; ++e) acc.add(c.w[e], (R)q[c.k[e]]);
+        int e = c.act_ptr[a];
+        // issue the loads of 8 entries before using any of them
+        for (; e + 8 <= e1; e += 8) {
+            uint32_t kk[8];
+            R ww[8];
+            double qq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                kk[u] = c.k[e + u];
+                ww[u] = c.w[e + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qq[u] = q[kk[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc.add(ww[u], (R)qq[u]);
+        }
+        for (; e < e1; ++e) acc.add(c.w[e], (R)q[c.k[e]]);
         sr[2 * ((x >> 1) * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
     __syncthreads();
@@ -186,10 +245,16 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a) 
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
     __shared__ int rs[G + 1];
+    __shared__ int lines_s[G];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = blockIdx.y;
+    if (a.skip && a.skip[4 * rhs]) return;
     const int first = blockIdx.x * G;
     for (int i = threadIdx.x; i < L * G; i += T) s[i] = cplx<R>{R(0), R(0)};
+    if (threadIdx.x < G) {
+        const int li = first + threadIdx.x;
+        lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
+    }
     __syncthreads();
     if (a.grid) {
         const double* gr = a.grid + (size_t)rhs * a.grid_stride;
@@ -206,71 +271,118 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a) 
     if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, a.M, a.lines, first, a.nproc, rs);
     if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, a.M, a.lines, first, a.nproc, rs);
 
-    fft_lines<R, L, G, T, -1, 2>(s, a.tw);
+    run_fft<R, L, G, T, N, -1>(s, a.tw, LdsLoad<R, G>{s}, LdsStore<R, G>{s},
+                               FwdRadices<L, RMax<R>::value>{});
+    __syncthreads();
 
-    // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2
+    // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
+    // written in tile order so that consecutive threads store consecutive addresses
+    using TL = Tiles<R, N>;
+    constexpr int C = TL::C;
     cplx<R>* out = a.spec + (size_t)rhs * a.spec_stride;
-    constexpr int H = L / 2 + 1;
-    for (int id = threadIdx.x; id < G * H; id += T) {
-        const int g = id / H, k = id % H;
-        const int li = first + g;
-        if (li >= a.nproc) continue;
-        const int line = a.lines ? a.lines[li] : li;
-        const cplx<R> zk = s[k * G + g];
+    for (int id = threadIdx.x; id < TL::NT * G * C; id += T) {
+        const int t = id / (G * C), rem = id % (G * C);
+        const int g = rem / C, c = rem % C;
+        const int k = t * C + c;
+        const int line = lines_s[g];
+        if (k > L || line < 0) continue;
+        const cplx<R> zk = s[(k % L) * G + g];
         const cplx<R> zm = s[((L - k) % L) * G + g];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
-        const cplx<R> o = cmul_si<-1>(d);                           // -i d
-        const cplx<R> xk = cadd(e, cmul(a.tw[k], o));
-        const cplx<R> xm = cadd(cconj(e), cmul(a.tw[L - k], cmul_si<-1>(cscale(cconj(d), R(-1)))));
-        cplx<R>* row = out + (size_t)line * a.P;
-        row[k] = xk;
-        if (k != L - k) row[L - k] = xm;
+        out[TL::idx(line, k)] = cadd(e, cmul(a.tw[k], cmul_si<-1>(d)));
     }
 }
 
 // ------------------------------------------------------------ col
+// A block transforms K*C lines of length N: element i of line l at
+// base + i * es + l, with the C columns of tile t (kx = t*C + l % C) and, for
+// K > 1, K consecutive y-rows (ky = o*K + l / C) of the z-transform.
+template <typename R, int LC>
+struct ColLoad {
+    const cplx<R>* base;
+    size_t es;
+    const uint8_t* valid;  // LDS: line holds a real column
+    const uint8_t* m;      // LDS row mask
+    __device__ __forceinline__ cplx<R> operator()(int i, int l) const {
+        if (valid[l] && m[i]) return base[(size_t)i * es + l];
+        return cplx<R>{R(0), R(0)};
+    }
+};
+template <typename R, int LC>
+struct ColStore {
+    cplx<R>* base;
+    size_t es;
+    const uint8_t* valid;
+    const uint8_t* m;
+    __device__ __forceinline__ void operator()(int i, int l, cplx<R> v) const {
+        if (valid[l] && m[i]) base[(size_t)i * es + l] = v;
+    }
+};
+// 1/x: hardware reciprocal (about 1 ulp) in FP32, exact division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+// LDS store that multiplies by norm / lambda(k), lambda = -(sum_d (4/h^2) sin^2(pi k_d/n)) - alpha:
+// srow[i] is the line-axis term, scol[l] the other axes plus alpha (-1: invalid line)
+template <typename R, int LC>
+struct SymStore {
+    cplx<R>* s;
+    const R* srow;
+    const R* scol;
+    R norm;
+    __device__ __forceinline__ void operator()(int i, int l, cplx<R> v) const {
+        const R cc = scol[l];
+        const R lam = srow[i] + cc;
+        const R sig = (cc >= R(0) && lam != R(0)) ? -norm * recip(lam) : R(0);
+        s[i * LC + l] = cscale(v, sig);
+    }
+};
+
+template <typename R, int N, int K>
+struct ColK {
+    static constexpr int C = ColCfg<R, N>::C;
+    static constexpr int LC = K * C;
+    static constexpr int T = fft_threads<N, LC, RMax<R>::value>();
+};
+
 // MODE 0: forward; 1: forward, times inverse symbol, inverse; 2: inverse.
-template <typename R, int N, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N>::T)) void k_col(ColArgs<R> a) {
-    constexpr int C = ColCfg<R, N>::C, T = ColCfg<R, N>::T;
-    __shared__ cplx<R> s[N * C];
-    const int grp = blockIdx.x;
-    const int outer = a.outer_list ? a.outer_list[blockIdx.y] : (int)blockIdx.y;
+template <typename R, int N, int MODE, int K>
+__global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a) {
+    using CK = ColK<R, N, K>;
+    constexpr int C = CK::C, LC = CK::LC, T = CK::T, RM = RMax<R>::value;
+    __shared__ cplx<R> s[N * LC];
+    __shared__ uint8_t lmask[N], smask[N], valid[LC];
+    __shared__ R srow[MODE == 1 ? N : 1];
+    __shared__ R scol[MODE == 1 ? LC : 1];
+    const int t = blockIdx.x;
+    const int o = a.outer_list ? a.outer_list[blockIdx.y] : (int)blockIdx.y;
     const int rhs = blockIdx.z;
-    cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)outer * a.outer_stride + (size_t)grp * C;
-    const int ncol = imin(C, a.width - grp * C);
-    for (int id = threadIdx.x; id < N * C; id += T) {
-        const int c = id % C, i = id / C;
-        cplx<R> v = {R(0), R(0)};
-        if (c < ncol && (!a.lmask || a.lmask[outer * a.lm_outer + i * a.lm_stride]))
-            v = base[(size_t)i * a.elem_stride + c];
-        s[i * C + c] = v;
+    if (a.skip && a.skip[4 * rhs]) return;
+    cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
+    for (int i = threadIdx.x; i < N; i += T) {
+        lmask[i] = a.lmask ? a.lmask[o * a.lm_outer + i * a.lm_stride] : 1;
+        smask[i] = a.smask ? a.smask[o * a.sm_outer + i * a.sm_stride] : 1;
+        if constexpr (MODE == 1) srow[i] = a.s2[i];
+    }
+    for (int l = threadIdx.x; l < LC; l += T) {
+        const int kx = t * C + l % C;
+        const bool ok = kx < a.width;
+        valid[l] = ok;
+        if constexpr (MODE == 1)
+            scol[l] = ok ? a.s2[kx] + (K > 1 ? a.s2[o * K + l / C] : R(0)) + a.alpha : R(-1);
     }
     __syncthreads();
-    if constexpr (MODE == 2) {
-        fft_lines<R, N, C, T, +1, 1>(s, a.tw);
+    const ColLoad<R, LC> ld{base, a.es, valid, lmask};
+    const ColStore<R, LC> st{base, a.es, valid, smask};
+    if constexpr (MODE == 0) {
+        run_fft<R, N, LC, T, N, -1>(s, a.tw, ld, st, FwdRadices<N, RM>{});
+    } else if constexpr (MODE == 2) {
+        run_fft<R, N, LC, T, N, +1>(s, a.tw, ld, st, FwdRadices<N, RM>{});
     } else {
-        fft_lines<R, N, C, T, -1, 1>(s, a.tw);
-    }
-    if constexpr (MODE == 1) {
-        // multiply by norm / lambda(k), lambda = -(sum_d (4/h^2) sin^2(pi k_d/n)) - alpha
-        for (int id = threadIdx.x; id < N * C; id += T) {
-            const int c = id % C, i = id / C;
-            if (c < ncol) {
-                const int kx = grp * C + c;
-                const R lam = a.s2[kx] + a.s2[i] + (a.dim3 ? a.s2[outer] : R(0)) + a.alpha;
-                const R sig = lam != R(0) ? -a.norm / lam : R(0);
-                s[i * C + c] = cscale(s[i * C + c], sig);
-            }
-        }
+        const SymStore<R, LC> sym{s, srow, scol, a.norm};
+        run_fft<R, N, LC, T, N, -1>(s, a.tw, ld, sym, FwdRadices<N, RM>{});
         __syncthreads();
-        fft_lines<R, N, C, T, +1, 1>(s, a.tw);
-    }
-    for (int id = threadIdx.x; id < N * C; id += T) {
-        const int c = id % C, i = id / C;
-        if (c < ncol && (!a.smask || a.smask[outer * a.sm_outer + i * a.sm_stride]))
-            base[(size_t)i * a.elem_stride + c] = s[i * C + c];
+        run_fft<R, N, LC, T, N, +1>(s, a.tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
     }
 }
 
@@ -283,26 +395,37 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a) 
     __shared__ cplx<R> s[L * G];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = blockIdx.y;
+    if (a.skip && a.skip[4 * rhs]) return;
     const int first = blockIdx.x * G;
     const cplx<R>* spec = a.spec + (size_t)rhs * a.spec_stride;
-    // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
-    for (int id = threadIdx.x; id < G * L; id += T) {
-        const int g = id / L, k = id % L;
-        const int li = first + g;
-        cplx<R> z = {R(0), R(0)};
-        if (li < a.nproc) {
-            const int line = a.lines ? a.lines[li] : li;
-            const cplx<R>* row = spec + (size_t)line * a.P;
-            const cplx<R> xk = row[k];
-            const cplx<R> xm = row[L - k];
-            const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
-            const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
-            z = cadd(e, cmul_si<1>(cmul(cconj(a.tw[k]), d)));
-        }
-        s[k * G + g] = z;
+    __shared__ int lines_s[G];
+    if (threadIdx.x < G) {
+        const int li = first + threadIdx.x;
+        lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
     }
     __syncthreads();
-    fft_lines<R, L, G, T, +1, 2>(s, a.tw);
+    // the block's rows X[0..L], read in tile order (consecutive threads, consecutive addresses)
+    using TL = Tiles<R, N>;
+    constexpr int C = TL::C;
+    __shared__ cplx<R> xs[(L + 1) * G];
+    for (int id = threadIdx.x; id < TL::NT * G * C; id += T) {
+        const int t = id / (G * C), rem = id % (G * C);
+        const int g = rem / C, c = rem % C;
+        const int k = t * C + c;
+        const int line = lines_s[g];
+        if (k <= L) xs[g * (L + 1) + k] = line >= 0 ? spec[TL::idx(line, k)] : cplx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
+    auto split = [&](int k, int g) -> cplx<R> {
+        const cplx<R> xk = xs[g * (L + 1) + k];
+        const cplx<R> xm = xs[g * (L + 1) + L - k];
+        const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
+        const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
+        return cadd(e, cmul_si<1>(cmul(cconj(a.tw[k]), d)));
+    };
+    run_fft<R, L, G, T, N, +1>(s, a.tw, split, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
+    __syncthreads();
 
     if constexpr (OUT == 1) {
         double* u = a.u + (size_t)rhs * a.u_stride;
@@ -317,65 +440,87 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a) 
     } else {
         R* part = a.part + (size_t)rhs * a.part_stride;
         const int gpp = a.dim == 3 ? 16 : 4;
-        for (int g = 0; g < G; ++g) {
-            const int li = first + g;
-            if (li >= a.nproc) break;
-            const int line = a.lines ? a.lines[li] : li;
-            const int y = line % N, z = line / N;
-            // sorted-point ranges of the x-lines (cy, cz) with cy in y-2..y+1, cz in z-2..z+1
-            int rb[8], rc[8], nr = 0;
-            const int nz = a.dim == 3 ? 4 : 1;
-            for (int dz = 0; dz < nz; ++dz) {
+        // sorted-point ranges of the x-lines (cy, cz), cy in y-2..y+1, cz in z-2..z+1,
+        // for every line of the block, then one pass over their union
+        __shared__ int rb[G * 8], rc[G * 8], roff[G * 8 + 1];
+        const int nz = a.dim == 3 ? 4 : 1;
+        for (int t = threadIdx.x; t < G * 4; t += T) {
+            const int g = t / 4, dz = t % 4;
+            int b0 = 0, c0 = 0, b1 = 0, c1 = 0;
+            const int line = lines_s[g];
+            if (line >= 0 && dz < nz) {
+                const int y = line % N, z = line / N;
                 const int cz = a.dim == 3 ? (z - 2 + dz + N) % N : 0;
                 const int pz = cz * N;
                 const int lo = y - 2, hi = y + 2;
                 if (lo < 0) {
-                    rb[nr] = a.line_start[pz + lo + N];
-                    rc[nr] = a.line_start[pz + N] - rb[nr]; ++nr;
-                    rb[nr] = a.line_start[pz];
-                    rc[nr] = a.line_start[pz + hi] - rb[nr]; ++nr;
+                    b0 = a.line_start[pz + lo + N];
+                    c0 = a.line_start[pz + N] - b0;
+                    b1 = a.line_start[pz];
+                    c1 = a.line_start[pz + hi] - b1;
                 } else if (hi > N) {
-                    rb[nr] = a.line_start[pz + lo];
-                    rc[nr] = a.line_start[pz + N] - rb[nr]; ++nr;
-                    rb[nr] = a.line_start[pz];
-                    rc[nr] = a.line_start[pz + hi - N] - rb[nr]; ++nr;
+                    b0 = a.line_start[pz + lo];
+                    c0 = a.line_start[pz + N] - b0;
+                    b1 = a.line_start[pz];
+                    c1 = a.line_start[pz + hi - N] - b1;
                 } else {
-                    rb[nr] = a.line_start[pz + lo];
-                    rc[nr] = a.line_start[pz + hi] - rb[nr]; ++nr;
+                    b0 = a.line_start[pz + lo];
+                    c0 = a.line_start[pz + hi] - b0;
                 }
             }
-            int total = 0;
-            for (int r = 0; r < nr; ++r) total += rc[r];
-            for (int f = threadIdx.x; f < total; f += T) {
-                int r = 0, off = f;
-                while (off >= rc[r]) { off -= rc[r]; ++r; }
-                const int sidx = rb[r] + off;
-                const int cx = a.cell[3 * sidx + 0];
-                const int cy = a.cell[3 * sidx + 1];
-                const int oy = (y - cy + 1 + N) % N;
-                const R* tp = a.taps + (size_t)sidx * 12;
-                R acc = R(0);
+            rb[2 * t] = b0;
+            rc[2 * t] = c0;
+            rb[2 * t + 1] = b1;
+            rc[2 * t + 1] = c1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int r = 0; r < G * 8; ++r) {
+                roff[r] = acc;
+                acc += rc[r];
+            }
+            roff[G * 8] = acc;
+        }
+        __syncthreads();
+        const int total = roff[G * 8];
+        for (int f = threadIdx.x; f < total; f += T) {
+            int lo = 0, hi = G * 8;  // range r with roff[r] <= f < roff[r+1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (roff[mid] <= f) lo = mid; else hi = mid;
+            }
+            const int r = lo;
+            const int g = r / 8;
+            const int line = lines_s[g];
+            const int y = line % N, z = line / N;
+            const int sidx = rb[r] + (f - roff[r]);
+            const int cx = a.cell[3 * sidx + 0];
+            const int cy = a.cell[3 * sidx + 1];
+            const int oy = (y - cy + 1 + N) % N;
+            const R* tp = a.taps + (size_t)sidx * 12;
+            R acc = R(0);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int x = (cx - 1 + t + N) % N;
-                    acc += tp[t] * sr[2 * ((x >> 1) * G + g) + (x & 1)];
-                }
-                acc *= tp[4 + oy];
-                int o = oy;
-                if (a.dim == 3) {
-                    const int cz = a.cell[3 * sidx + 2];
-                    const int oz = (z - cz + 1 + N) % N;
-                    acc *= tp[8 + oz];
-                    o += 4 * oz;
-                }
-                part[(size_t)sidx * gpp + o] = acc;
+            for (int t = 0; t < 4; ++t) {
+                const int x = (cx - 1 + t + N) % N;
+                acc += tp[t] * sr[2 * ((x >> 1) * G + g) + (x & 1)];
             }
+            acc *= tp[4 + oy];
+            int o = oy;
+            if (a.dim == 3) {
+                const int cz = a.cell[3 * sidx + 2];
+                const int oz = (z - cz + 1 + N) % N;
+                acc *= tp[8 + oz];
+                o += 4 * oz;
+            }
+            part[(size_t)sidx * gpp + o] = acc;
         }
     }
 }
 
 // ------------------------------------------------------------ finish
 struct FinishArgs {
+    const int32_t* skip;
     const uint32_t* perm;
     int M, gpp;
     size_t part_stride;
@@ -388,21 +533,58 @@ struct FinishArgs {
     const double* in2;
     size_t in2_stride;
     double cC;
+    // optional: partial <out, V_i> for i < nv over each block's points (Arnoldi step)
+    const double* V;
+    size_t vstride_rhs;   // between right-hand sides
+    int nv;               // number of basis vectors (V_i at V + i*M)
+    double* dots;         // [rhs][block][dstride]
+    size_t dots_rhs;
+    int dstride;
 };
 
+constexpr int FIN_T = 256;
+
 template <typename R>
-__global__ void k_finish(const R* __restrict__ part, FinishArgs f) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(FIN_T) void k_finish(const R* __restrict__ part, FinishArgs f) {
+    const int s = blockIdx.x * FIN_T + threadIdx.x;
     const int rhs = blockIdx.y;
-    if (s >= f.M) return;
-    const R* p = part + (size_t)rhs * f.part_stride + (size_t)s * f.gpp;
-    double acc = 0.0;
-    for (int o = 0; o < f.gpp; ++o) acc += (double)p[o];
-    const uint32_t k = f.perm[s];
-    double v = f.cA * acc;
-    if (f.in) v += f.cB * f.in[(size_t)rhs * f.in_stride + k];
-    if (f.in2) v += f.cC * f.in2[(size_t)rhs * f.in2_stride + k];
-    f.out[(size_t)rhs * f.out_stride + k] = v;
+    if (f.skip && f.skip[4 * rhs]) return;
+    double v = 0.0;
+    uint32_t k = 0;
+    if (s < f.M) {
+        const R* p = part + (size_t)rhs * f.part_stride + (size_t)s * f.gpp;
+        double acc = 0.0;
+        for (int o = 0; o < f.gpp; ++o) acc += (double)p[o];
+        k = f.perm[s];
+        v = f.cA * acc;
+        if (f.in) v += f.cB * f.in[(size_t)rhs * f.in_stride + k];
+        if (f.in2) v += f.cC * f.in2[(size_t)rhs * f.in2_stride + k];
+        f.out[(size_t)rhs * f.out_stride + k] = v;
+    }
+    if (!f.V) return;
+    // fixed-order block reductions of v * V_i[k], 16 basis vectors per LDS pass
+    __shared__ double sh[(FIN_T / 64) * 16];
+    const double* Vr = f.V + (size_t)rhs * f.vstride_rhs;
+    double* d = f.dots + (size_t)rhs * f.dots_rhs + (size_t)blockIdx.x * f.dstride;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int v0 = 0; v0 < f.nv; v0 += 16) {
+        const int nv = f.nv - v0 < 16 ? f.nv - v0 : 16;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (u < nv) {
+                double t = s < f.M ? v * Vr[(size_t)(v0 + u) * f.M + k] : 0.0;
+                for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+                if (l == 0) sh[w * 16 + u] = t;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < nv) {
+            double t = 0.0;
+            for (int ww = 0; ww < FIN_T / 64; ++ww) t += sh[ww * 16 + threadIdx.x];
+            d[v0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -429,28 +611,56 @@ inline int col_width(int n) {
 }
 
 template <typename R>
-void launch_row_fwd(int n, dim3 grid, hipStream_t st, const RowFwdArgs<R>& a) {
+void launch_row_fwd(int n, dim3 grid, hipStream_t st, StageEv e, const RowFwdArgs<R>& a) {
     switch (n) {
 #define IBDL_C(NN) \
-    case NN: hipLaunchKernelGGL((k_row_fwd<R, NN>), grid, dim3(RowCfg<R, NN>::T), 0, st, a); break;
+    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN>), grid, dim3(RowCfg<R, NN>::T), 0, st, e.a, e.b, 0, a); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
-template <typename R, int MODE>
-void launch_col(int n, dim3 grid, hipStream_t st, const ColArgs<R>& a) {
+// y-rows per block of the 3-D z transform: up to 4 while the block's lines fit 128 KiB of LDS
+template <typename R, int N>
+struct ZRows {
+    static constexpr int value = imax(1, imin(4, 131072 / (N * ColCfg<R, N>::C * 2 * (int)sizeof(R))));
+};
+template <typename R>
+inline int z_rows(int n) {
     switch (n) {
-#define IBDL_C(NN) \
-    case NN: hipLaunchKernelGGL((k_col<R, NN, MODE>), grid, dim3(ColCfg<R, NN>::T), 0, st, a); break;
+#define IBDL_C(NN) case NN: return ZRows<R, NN>::value;
+        IBDL_SIZES(IBDL_C)
+#undef IBDL_C
+    }
+    return 1;
+}
+
+template <typename R, int MODE, bool ZPASS>
+void launch_col(int n, dim3 grid, hipStream_t st, StageEv e, const ColArgs<R>& a) {
+    switch (n) {
+#define IBDL_C(NN)                                                                                  \
+    case NN: {                                                                                      \
+        constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                          \
+        hipExtLaunchKernelGGL((k_col<R, NN, MODE, K>), grid, dim3(ColK<R, NN, K>::T), 0, st, e.a, e.b, 0, a); \
+    } break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
+template <typename R>
+inline int col_tiles(int n) {
+    switch (n) {
+#define IBDL_C(NN) case NN: return Tiles<R, NN>::NT;
+        IBDL_SIZES(IBDL_C)
+#undef IBDL_C
+    }
+    return 1;
+}
+
 template <typename R, int OUT>
-void launch_row_inv(int n, dim3 grid, hipStream_t st, const RowInvArgs<R>& a) {
+void launch_row_inv(int n, dim3 grid, hipStream_t st, StageEv e, const RowInvArgs<R>& a) {
     switch (n) {
 #define IBDL_C(NN) \
-    case NN: hipLaunchKernelGGL((k_row_inv<R, NN, OUT>), grid, dim3(RowCfg<R, NN>::T), 0, st, a); break;
+    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT>), grid, dim3(RowCfg<R, NN>::T), 0, st, e.a, e.b, 0, a); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
@@ -485,6 +695,7 @@ void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out,
 
     // ---- row_fwd
     RowFwdArgs<R> ra{};
+    ra.skip = in.skip;
     ra.lines = dense_in ? nullptr : p->spread_lines;
     ra.nproc = dense_in ? p->nlines : p->n_spread_lines;
     ra.M = p->M;
@@ -510,13 +721,18 @@ void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out,
     ra.P = p->P;
     ra.tw = PP::tw(p);
     const int G = row_lines_per_block<R>(n);
-    stage_mark(p, stage++, "spread+fft_x", st);
-    if (ra.nproc > 0) launch_row_fwd<R>(n, dim3((ra.nproc + G - 1) / G, nrhs), st, ra);
+    {
+        const StageEv e = stage_events(p, stage++, "spread+fft_x");
+        if (ra.nproc > 0) launch_row_fwd<R>(n, dim3((ra.nproc + G - 1) / G, nrhs), st, e, ra);
+    }
 
     // ---- columns
     const int C = col_width<R>(n);
-    const int ngrp = (p->W + C - 1) / C;
+    const int NT = col_tiles<R>(n);
+    const size_t plane = (size_t)NT * n * C;
+    const int KZ = z_rows<R>(n);  // y-rows per block of the z transform
     ColArgs<R> ca{};
+    ca.skip = in.skip;
     ca.spec = spec;
     ca.rhs_stride = sstride;
     ca.width = p->W;
@@ -524,56 +740,58 @@ void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out,
     ca.s2 = PP::s2(p);
     ca.alpha = (R)p->alpha;
     ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
+    ca.tile_stride = (size_t)n * C;
     if (p->dim == 2) {
         ca.outer_list = nullptr;
         ca.outer_stride = 0;
-        ca.elem_stride = p->P;
+        ca.es = C;
         ca.lmask = dense_in ? nullptr : p->spread_line_mask;
         ca.lm_outer = 0; ca.lm_stride = 1;
         ca.smask = dense_out ? nullptr : p->gather_line_mask;
         ca.sm_outer = 0; ca.sm_stride = 1;
-        ca.dim3 = 0;
-        stage_mark(p, stage++, "fft_y+symbol", st);
-        launch_col<R, 1>(n, dim3(ngrp, 1, nrhs), st, ca);
+        launch_col<R, 1, false>(n, dim3(NT, 1, nrhs), st, stage_events(p, stage++, "fft_y+symbol"), ca);
     } else {
         // y forward over planes that hold forcing
         ColArgs<R> y1 = ca;
         y1.outer_list = dense_in ? nullptr : p->spread_planes;
-        y1.outer_stride = (size_t)n * p->P;
-        y1.elem_stride = p->P;
+        y1.outer_stride = plane;
+        y1.es = C;
         y1.lmask = dense_in ? nullptr : p->spread_line_mask;
         y1.lm_outer = n; y1.lm_stride = 1;
         y1.smask = nullptr;
         const int ny1 = dense_in ? n : p->n_spread_planes;
-        stage_mark(p, stage++, "fft_y", st);
-        if (ny1 > 0) launch_col<R, 0>(n, dim3(ngrp, ny1, nrhs), st, y1);
-        // z forward, symbol, z inverse over every (kx, ky)
+        {
+            const StageEv e = stage_events(p, stage++, "fft_y");
+            if (ny1 > 0) launch_col<R, 0, false>(n, dim3(NT, ny1, nrhs), st, e, y1);
+        }
+        // z forward, symbol, z inverse: blocks of KZ y-rows of one tile
         ColArgs<R> z = ca;
         z.outer_list = nullptr;
-        z.outer_stride = p->P;
-        z.elem_stride = (size_t)n * p->P;
+        z.outer_stride = (size_t)KZ * C;
+        z.es = plane;
         z.lmask = dense_in ? nullptr : p->spread_plane_mask;
         z.lm_outer = 0; z.lm_stride = 1;
         z.smask = dense_out ? nullptr : p->gather_plane_mask;
         z.sm_outer = 0; z.sm_stride = 1;
-        z.dim3 = 1;
-        stage_mark(p, stage++, "fft_z+symbol", st);
-        launch_col<R, 1>(n, dim3(ngrp, n, nrhs), st, z);
+        launch_col<R, 1, true>(n, dim3(NT, n / KZ, nrhs), st, stage_events(p, stage++, "fft_z+symbol"), z);
         // y inverse over planes something is read from
         ColArgs<R> y2 = ca;
         y2.outer_list = dense_out ? nullptr : p->gather_planes;
-        y2.outer_stride = (size_t)n * p->P;
-        y2.elem_stride = p->P;
+        y2.outer_stride = plane;
+        y2.es = C;
         y2.lmask = nullptr;
         y2.smask = dense_out ? nullptr : p->gather_line_mask;
         y2.sm_outer = n; y2.sm_stride = 1;
         const int ny2 = dense_out ? n : p->n_gather_planes;
-        stage_mark(p, stage++, "ifft_y", st);
-        if (ny2 > 0) launch_col<R, 2>(n, dim3(ngrp, ny2, nrhs), st, y2);
+        {
+            const StageEv e = stage_events(p, stage++, "ifft_y");
+            if (ny2 > 0) launch_col<R, 2, false>(n, dim3(NT, ny2, nrhs), st, e, y2);
+        }
     }
 
     // ---- row_inv
     RowInvArgs<R> ia{};
+    ia.skip = in.skip;
     ia.lines = dense_out ? nullptr : p->gather_lines;
     ia.nproc = dense_out ? p->nlines : p->n_gather_lines;
     ia.spec = spec;
@@ -589,12 +807,11 @@ void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out,
     ia.part_stride = (size_t)p->M * p->gpp;
     ia.M = p->M;
     ia.dim = p->dim;
-    stage_mark(p, stage++, dense_out ? "ifft_x" : "ifft_x+interp", st);
     if (dense_out) {
-        launch_row_inv<R, 1>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, ia);
+        launch_row_inv<R, 1>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, stage_events(p, stage++, "ifft_x"), ia);
     } else {
-        if (ia.nproc > 0) launch_row_inv<R, 0>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, ia);
-        stage_mark(p, stage++, "finish", st);
+        const StageEv e = stage_events(p, stage++, "ifft_x+interp");
+        if (ia.nproc > 0) launch_row_inv<R, 0>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, e, ia);
         FinishArgs fa{};
         fa.perm = p->perm;
         fa.M = p->M;
@@ -609,10 +826,17 @@ void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out,
         fa.in2 = out.in2;
         fa.in2_stride = out.in2_stride ? out.in2_stride : (size_t)p->M;
         fa.cC = out.cC;
-        hipLaunchKernelGGL((k_finish<R>), dim3((p->M + 255) / 256, nrhs), dim3(256), 0, st,
-                           reinterpret_cast<const R*>(p->ws.part), fa);
+        fa.skip = in.skip;
+        fa.V = out.dots_V;
+        fa.vstride_rhs = out.dots_vstride;
+        fa.nv = out.dots_nv;
+        fa.dots = out.dots;
+        fa.dots_rhs = out.dots_rhs;
+        fa.dstride = out.dots_stride;
+        const StageEv ef = stage_events(p, stage++, "finish");
+        hipExtLaunchKernelGGL((k_finish<R>), dim3((p->M + FIN_T - 1) / FIN_T, nrhs), dim3(FIN_T), 0, st, ef.a,
+                              ef.b, 0, reinterpret_cast<const R*>(p->ws.part), fa);
     }
-    stage_mark(p, stage++, nullptr, st);
     IBDL_HIP_TRY(hipGetLastError());
 }
 

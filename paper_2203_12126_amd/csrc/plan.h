@@ -59,7 +59,7 @@ struct ibdl_plan_s {
     // description
     int dim = 2, n = 0, bc = 0, delta = 0, prec = 0, M = 0;
     double lo[3] = {0, 0, 0}, length = 1, h = 1, alpha = 0;
-    int P = 0;          // half-spectrum pitch (complex elements)
+    int P = 0;          // complex elements per line of the tiled half spectrum (>= n/2+1)
     int W = 0;          // half-spectrum width n/2+1
     int nlines = 0;     // n^(dim-1) x-lines
     size_t spec_elems = 0;  // nlines * P
@@ -99,13 +99,14 @@ struct ibdl_plan_s {
     ibdl::Workspace ws;
     ibdl::Krylov kr;
 
-    // stage timing: a ring of event sets, one set per pass through the grid
+    // stage timing: a ring of event sets, one set per pass through the grid; each
+    // stage kernel records a start and a stop event in its own dispatch
     static constexpr int RING = 64;
-    static constexpr int MAXST = 9;
+    static constexpr int MAXST = 8;
     int timing = 0;
     int events_made = 0;
     int ring_pos = 0, cur_set = -1;
-    hipEvent_t ev[RING][MAXST + 1] = {};
+    hipEvent_t ev[RING][2 * MAXST] = {};
     const char* set_names[RING][MAXST] = {};
     int set_used[RING] = {};
     const char* acc_names[16] = {};
@@ -127,6 +128,7 @@ struct PipeIn {
     const double* grid = nullptr;    // [nrhs][n^dim] grid forcing
     double c_grid = 0;
     size_t q_stride = 0;             // distance between right-hand sides of q_dip/q_mono (0: M)
+    const int32_t* skip = nullptr;   // per-rhs flags (stride 4): set -> the rhs is not processed
 };
 struct PipeOut {
     // gather: out[k] = cA * (S* u)_k + cB * in[k] + cC * in2[k]   (strides 0: M)
@@ -139,6 +141,13 @@ struct PipeOut {
     const double* in2 = nullptr;
     size_t in2_stride = 0;
     double cC = 0;
+    // gather only: also the block partial sums of <out, V_i>, i < dots_nv
+    const double* dots_V = nullptr;
+    size_t dots_vstride = 0;
+    int dots_nv = 0;
+    double* dots = nullptr;
+    size_t dots_rhs = 0;
+    int dots_stride = 0;
     // grid: u = the full grid field
     double* u = nullptr;
 };
@@ -150,11 +159,17 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
                   bool fp64 = false);
 void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
 void run_pipeline_f32(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+int tile_pitch_f64(int n);
+int tile_pitch_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
 void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
                  double* sol, ibdl_solve_info* info, hipStream_t st, int* overall);
 
-// timing helpers used by the pipeline
-void stage_mark(ibdl_plan p, int idx, const char* name, hipStream_t st);
+// timing helpers used by the pipeline: events to pass to the stage's launch
+// (both null when timing is off); stage 0 opens a new event set
+struct StageEv {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+StageEv stage_events(ibdl_plan p, int idx, const char* name);
 
 }  // namespace ibdl
