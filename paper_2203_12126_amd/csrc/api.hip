@@ -59,13 +59,41 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 namespace ibdl {
 
+std::unique_ptr<PreparedPass> prepare_pass(const std::vector<PassJob>& jobs, bool fp64) {
+    for (const PassJob& j : jobs) ensure_workspace(j.p, j.nrhs);
+    if (fp64 || jobs[0].p->prec == IBDL_PREC_FP64) return prepare_f64(jobs);
+    return prepare_f32(jobs);
+}
+
 void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st,
                   bool fp64) {
-    ensure_workspace(p, nrhs);
-    if (fp64 || p->prec == IBDL_PREC_FP64)
-        run_pipeline_f64(p, nrhs, in, out, st);
-    else
-        run_pipeline_f32(p, nrhs, in, out, st);
+    std::vector<PassJob> jobs{PassJob{p, nrhs, in, out}};
+    prepare_pass(jobs, fp64)->run(0, st);
+}
+
+void* ring_put(JobRing& r, const void* src, size_t bytes, hipStream_t st) {
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (!r.host || need > r.cap) {
+        if (r.host) IBDL_HIP_TRY(hipStreamSynchronize(st));
+        const size_t cap = std::max<size_t>(need, 4u << 20);
+        void* h = nullptr;
+        IBDL_HIP_TRY(hipHostMalloc(&h, cap));
+        if (r.host) (void)hipHostFree(r.host);
+        r.host = reinterpret_cast<char*>(h);
+        r.dev = reinterpret_cast<char*>(dev_alloc(*r.owner, cap));
+        r.cap = cap;
+        r.pos = 0;
+    }
+    if (r.pos + need > r.cap) {
+        // wrap: copies queued earlier must have consumed the host staging area
+        IBDL_HIP_TRY(hipStreamSynchronize(st));
+        r.pos = 0;
+    }
+    std::memcpy(r.host + r.pos, src, bytes);
+    IBDL_HIP_TRY(hipMemcpyAsync(r.dev + r.pos, r.host + r.pos, bytes, hipMemcpyHostToDevice, st));
+    void* d = r.dev + r.pos;
+    r.pos += need;
+    return d;
 }
 
 static void flush_set(ibdl_plan p, int set) {
@@ -154,6 +182,7 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
     if (!why.empty()) return fail(IBDL_ERR_ARG, why);
     ibdl_plan p = new (std::nothrow) ibdl_plan_s();
     if (!p) return fail(IBDL_ERR_OOM, "host allocation failed");
+    p->ring.owner = &p->allocs;
     try {
         p->dim = desc->dim;
         p->n = desc->n;
@@ -188,6 +217,7 @@ ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     (void)hipDeviceSynchronize();
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->kr.host_pinned) (void)hipHostFree(p->kr.host_pinned);
+    if (p->ring.host) (void)hipHostFree(p->ring.host);
     if (p->events_made)
         for (int s = 0; s < ibdl_plan_s::RING; ++s)
             for (int i = 0; i < 2 * ibdl_plan_s::MAXST; ++i) (void)hipEventDestroy(p->ev[s][i]);

@@ -21,6 +21,9 @@
 #pragma once
 #include <hip/hip_ext.h>
 
+#include <memory>
+#include <vector>
+
 #include "fft.h"
 #include "plan.h"
 
@@ -119,8 +122,9 @@ struct CsrView {
     const uint32_t* act_node;
     const uint32_t* k;
     const R* w;
-    const double* q;     // q + rhs * q_stride: strengths of one right-hand side
+    const double* q;     // q + rhs * q_stride + it * q_jstride: strengths of one right-hand side
     size_t q_stride;
+    size_t q_jstride;    // offset per iteration index (Krylov basis vectors), else 0
     double coef;
 };
 
@@ -129,6 +133,7 @@ struct RowFwdArgs {
     const int32_t* skip;   // per-rhs flags (stride 4) or null: a set flag skips that rhs
     const int32_t* lines;  // line list or null (identity)
     int nproc;
+    int nblk;              // line blocks per right-hand side
     int M;
     CsrView<R> dip, mono;
     const double* grid;    // [nrhs][n^dim] or null
@@ -158,6 +163,7 @@ struct ColArgs {
     const R* s2;
     R alpha;
     R norm;
+    int nouter;           // outer indices per right-hand side
 };
 
 template <typename R>
@@ -165,6 +171,7 @@ struct RowInvArgs {
     const int32_t* skip;
     const int32_t* lines;
     int nproc;
+    int nblk;
     const cplx<R>* spec;
     size_t spec_stride;
     int P;
@@ -180,11 +187,36 @@ struct RowInvArgs {
     int dim;
 };
 
+// ------------------------------------------------------------ jobs
+// A launch covers one job (arguments by value) or many jobs of the same size
+// (arguments from a device table; job j owns blocks start[j] .. start[j+1]-1).
+template <class A>
+struct Jobs {
+    const A* list;
+    const int* start;   // n + 1 entries
+    int n;
+};
+__device__ __forceinline__ int job_of(const int* start, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+#define IBDL_JOB_ENTRY(BODY, A, a0, js, it)                          \
+    if constexpr (MULTI) {                                            \
+        const int j_ = job_of(js.start, js.n, (int)blockIdx.x);       \
+        BODY(js.list[j_], (int)blockIdx.x - js.start[j_], it);        \
+    } else {                                                          \
+        BODY(a0, (int)blockIdx.x, it);                                \
+    }
+
 // ------------------------------------------------------------ spread phase
 // Adds coef * (sum_e w_e q[k_e]) into the LDS lines for every active node of
 // the block's lines.  Each node is written by exactly one thread.
 template <typename R, int N, int G, int T>
-__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs, int M,
+__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs, int it, int M,
                                              const int32_t* lines, int first, int nproc,
                                              int* rs) {
     if (threadIdx.x < G) {
@@ -203,7 +235,7 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
         for (int g = 1; g <= G; ++g) rs[g] += rs[g - 1];
     __syncthreads();
     const int total = rs[G];
-    const double* q = c.q + (size_t)rhs * c.q_stride;
+    const double* q = c.q + (size_t)rhs * c.q_stride + (size_t)it * c.q_jstride;
     for (int f = threadIdx.x; f < total; f += T) {
         int lo = 0, hi = G;  // find g with rs[g] <= f < rs[g+1]
         while (hi - lo > 1) {
@@ -240,16 +272,16 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
 
 // ------------------------------------------------------------ row_fwd
 template <typename R, int N>
-__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a) {
+__device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int it) {
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
     __shared__ int rs[G + 1];
     __shared__ int lines_s[G];
     R* sr = reinterpret_cast<R*>(s);
-    const int rhs = blockIdx.y;
+    const int rhs = lb / a.nblk;
     if (a.skip && a.skip[4 * rhs]) return;
-    const int first = blockIdx.x * G;
+    const int first = (lb % a.nblk) * G;
     for (int i = threadIdx.x; i < L * G; i += T) s[i] = cplx<R>{R(0), R(0)};
     if (threadIdx.x < G) {
         const int li = first + threadIdx.x;
@@ -268,8 +300,8 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a) 
         }
         __syncthreads();
     }
-    if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, a.M, a.lines, first, a.nproc, rs);
-    if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, a.M, a.lines, first, a.nproc, rs);
+    if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, it, a.M, a.lines, first, a.nproc, rs);
+    if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, it, a.M, a.lines, first, a.nproc, rs);
 
     run_fft<R, L, G, T, N, -1>(s, a.tw, LdsLoad<R, G>{s}, LdsStore<R, G>{s},
                                FwdRadices<L, RMax<R>::value>{});
@@ -292,6 +324,11 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a) 
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
         out[TL::idx(line, k)] = cadd(e, cmul(a.tw[k], cmul_si<-1>(d)));
     }
+}
+template <typename R, int N, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a0, Jobs<RowFwdArgs<R>> js,
+                                                               int it) {
+    IBDL_JOB_ENTRY((row_fwd_body<R, N>), RowFwdArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ col
@@ -347,16 +384,18 @@ struct ColK {
 
 // MODE 0: forward; 1: forward, times inverse symbol, inverse; 2: inverse.
 template <typename R, int N, int MODE, int K>
-__global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a) {
+__device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     using CK = ColK<R, N, K>;
     constexpr int C = CK::C, LC = CK::LC, T = CK::T, RM = RMax<R>::value;
+    constexpr int NT = (N / 2 + 1 + C - 1) / C;
     __shared__ cplx<R> s[N * LC];
     __shared__ uint8_t lmask[N], smask[N], valid[LC];
     __shared__ R srow[MODE == 1 ? N : 1];
     __shared__ R scol[MODE == 1 ? LC : 1];
-    const int t = blockIdx.x;
-    const int o = a.outer_list ? a.outer_list[blockIdx.y] : (int)blockIdx.y;
-    const int rhs = blockIdx.z;
+    const int t = lb % NT;
+    const int oi = (lb / NT) % a.nouter;
+    const int rhs = lb / NT / a.nouter;
+    const int o = a.outer_list ? a.outer_list[oi] : oi;
     if (a.skip && a.skip[4 * rhs]) return;
     cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
     for (int i = threadIdx.x; i < N; i += T) {
@@ -385,18 +424,22 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a) {
         run_fft<R, N, LC, T, N, +1>(s, a.tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
     }
 }
+template <typename R, int N, int MODE, int K, bool MULTI>
+__global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<ColArgs<R>> js, int it) {
+    IBDL_JOB_ENTRY((col_body<R, N, MODE, K>), ColArgs<R>, a0, js, it)
+}
 
 // ------------------------------------------------------------ row_inv
 // OUT 0: interpolation partial sums; OUT 1: grid output.
 template <typename R, int N, int OUT>
-__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a) {
+__device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
     R* sr = reinterpret_cast<R*>(s);
-    const int rhs = blockIdx.y;
+    const int rhs = lb / a.nblk;
     if (a.skip && a.skip[4 * rhs]) return;
-    const int first = blockIdx.x * G;
+    const int first = (lb % a.nblk) * G;
     const cplx<R>* spec = a.spec + (size_t)rhs * a.spec_stride;
     __shared__ int lines_s[G];
     if (threadIdx.x < G) {
@@ -517,18 +560,25 @@ __global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a) 
         }
     }
 }
+template <typename R, int N, int OUT, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a0, Jobs<RowInvArgs<R>> js,
+                                                               int it) {
+    IBDL_JOB_ENTRY((row_inv_body<R, N, OUT>), RowInvArgs<R>, a0, js, it)
+}
 
 // ------------------------------------------------------------ finish
 struct FinishArgs {
     const int32_t* skip;
     const uint32_t* perm;
     int M, gpp;
+    int nblk;             // point blocks per right-hand side
+    const void* part;     // gather partials of the plan's precision
     size_t part_stride;
-    double* out;
-    size_t out_stride;
+    double* out;          // + rhs * out_stride + it * out_jstride
+    size_t out_stride, out_jstride;
     double cA;
     const double* in;
-    size_t in_stride;
+    size_t in_stride, in_jstride;
     double cB;
     const double* in2;
     size_t in2_stride;
@@ -536,7 +586,7 @@ struct FinishArgs {
     // optional: partial <out, V_i> for i < nv over each block's points (Arnoldi step)
     const double* V;
     size_t vstride_rhs;   // between right-hand sides
-    int nv;               // number of basis vectors (V_i at V + i*M)
+    int nv;               // number of basis vectors (V_i at V + i*M), plus it
     double* dots;         // [rhs][block][dstride]
     size_t dots_rhs;
     int dstride;
@@ -545,30 +595,31 @@ struct FinishArgs {
 constexpr int FIN_T = 256;
 
 template <typename R>
-__global__ __launch_bounds__(FIN_T) void k_finish(const R* __restrict__ part, FinishArgs f) {
-    const int s = blockIdx.x * FIN_T + threadIdx.x;
-    const int rhs = blockIdx.y;
+__device__ __forceinline__ void finish_body(const FinishArgs& f, int lb, int it) {
+    const int rhs = lb / f.nblk;
+    const int s = (lb % f.nblk) * FIN_T + threadIdx.x;
     if (f.skip && f.skip[4 * rhs]) return;
     double v = 0.0;
     uint32_t k = 0;
     if (s < f.M) {
-        const R* p = part + (size_t)rhs * f.part_stride + (size_t)s * f.gpp;
+        const R* p = reinterpret_cast<const R*>(f.part) + (size_t)rhs * f.part_stride + (size_t)s * f.gpp;
         double acc = 0.0;
         for (int o = 0; o < f.gpp; ++o) acc += (double)p[o];
         k = f.perm[s];
         v = f.cA * acc;
-        if (f.in) v += f.cB * f.in[(size_t)rhs * f.in_stride + k];
+        if (f.in) v += f.cB * f.in[(size_t)rhs * f.in_stride + (size_t)it * f.in_jstride + k];
         if (f.in2) v += f.cC * f.in2[(size_t)rhs * f.in2_stride + k];
-        f.out[(size_t)rhs * f.out_stride + k] = v;
+        f.out[(size_t)rhs * f.out_stride + (size_t)it * f.out_jstride + k] = v;
     }
     if (!f.V) return;
     // fixed-order block reductions of v * V_i[k], 16 basis vectors per LDS pass
     __shared__ double sh[(FIN_T / 64) * 16];
     const double* Vr = f.V + (size_t)rhs * f.vstride_rhs;
-    double* d = f.dots + (size_t)rhs * f.dots_rhs + (size_t)blockIdx.x * f.dstride;
+    double* d = f.dots + (size_t)rhs * f.dots_rhs + (size_t)(lb % f.nblk) * f.dstride;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int v0 = 0; v0 < f.nv; v0 += 16) {
-        const int nv = f.nv - v0 < 16 ? f.nv - v0 : 16;
+    const int nvt = f.nv + it;
+    for (int v0 = 0; v0 < nvt; v0 += 16) {
+        const int nv = nvt - v0 < 16 ? nvt - v0 : 16;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             if (u < nv) {
@@ -585,6 +636,10 @@ __global__ __launch_bounds__(FIN_T) void k_finish(const R* __restrict__ part, Fi
         }
         __syncthreads();
     }
+}
+template <typename R, bool MULTI>
+__global__ __launch_bounds__(FIN_T) void k_finish(FinishArgs a0, Jobs<FinishArgs> js, int it) {
+    IBDL_JOB_ENTRY((finish_body<R>), FinishArgs, a0, js, it)
 }
 
 // ------------------------------------------------------------ dispatch
@@ -609,15 +664,14 @@ inline int col_width(int n) {
     }
     return 1;
 }
-
 template <typename R>
-void launch_row_fwd(int n, dim3 grid, hipStream_t st, StageEv e, const RowFwdArgs<R>& a) {
+inline int col_tiles(int n) {
     switch (n) {
-#define IBDL_C(NN) \
-    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN>), grid, dim3(RowCfg<R, NN>::T), 0, st, e.a, e.b, 0, a); break;
+#define IBDL_C(NN) case NN: return Tiles<R, NN>::NT;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
+    return 1;
 }
 // y-rows per block of the 3-D z transform: up to 4 while the block's lines fit 128 KiB of LDS
 template <typename R, int N>
@@ -634,33 +688,59 @@ inline int z_rows(int n) {
     return 1;
 }
 
-template <typename R, int MODE, bool ZPASS>
-void launch_col(int n, dim3 grid, hipStream_t st, StageEv e, const ColArgs<R>& a) {
+template <class A>
+struct StageTable {
+    std::vector<A> args;
+    std::vector<int> start{0};  // block offsets, njobs + 1 entries
+    const A* dargs = nullptr;   // device copies (several jobs)
+    const int* dstart = nullptr;
+    void add(const A& a, int blocks) {
+        args.push_back(a);
+        start.push_back(start.back() + blocks);
+    }
+    int njobs() const { return (int)args.size(); }
+    int blocks() const { return start.back(); }
+    bool multi() const { return njobs() > 1; }
+    Jobs<A> jobs() const { return Jobs<A>{dargs, dstart, njobs()}; }
+    void upload(JobRing& ring, hipStream_t st) {
+        if (!multi()) return;
+        dargs = reinterpret_cast<const A*>(ring_put(ring, args.data(), args.size() * sizeof(A), st));
+        dstart = reinterpret_cast<const int*>(ring_put(ring, start.data(), start.size() * sizeof(int), st));
+    }
+};
+
+template <typename R, bool MULTI>
+void launch_row_fwd_t(int n, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
+                      Jobs<RowFwdArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                  \
-    case NN: {                                                                                      \
-        constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                          \
-        hipExtLaunchKernelGGL((k_col<R, NN, MODE, K>), grid, dim3(ColK<R, NN, K>::T), 0, st, e.a, e.b, 0, a); \
+#define IBDL_C(NN)                                                                                       \
+    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN, MULTI>), dim3(blocks), dim3(RowCfg<R, NN>::T), 0, st, \
+                                   e.a, e.b, 0, a, js, it); break;
+        IBDL_SIZES(IBDL_C)
+#undef IBDL_C
+    }
+}
+template <typename R, int MODE, bool ZPASS, bool MULTI>
+void launch_col_t(int n, int blocks, hipStream_t st, StageEv e, const ColArgs<R>& a, Jobs<ColArgs<R>> js,
+                  int it) {
+    switch (n) {
+#define IBDL_C(NN)                                                                                    \
+    case NN: {                                                                                        \
+        constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                            \
+        hipExtLaunchKernelGGL((k_col<R, NN, MODE, K, MULTI>), dim3(blocks), dim3(ColK<R, NN, K>::T), 0, st, \
+                              e.a, e.b, 0, a, js, it);                                                \
     } break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
-template <typename R>
-inline int col_tiles(int n) {
+template <typename R, int OUT, bool MULTI>
+void launch_row_inv_t(int n, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
+                      Jobs<RowInvArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN) case NN: return Tiles<R, NN>::NT;
-        IBDL_SIZES(IBDL_C)
-#undef IBDL_C
-    }
-    return 1;
-}
-
-template <typename R, int OUT>
-void launch_row_inv(int n, dim3 grid, hipStream_t st, StageEv e, const RowInvArgs<R>& a) {
-    switch (n) {
-#define IBDL_C(NN) \
-    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT>), grid, dim3(RowCfg<R, NN>::T), 0, st, e.a, e.b, 0, a); break;
+#define IBDL_C(NN)                                                                                        \
+    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT, MULTI>), dim3(blocks), dim3(RowCfg<R, NN>::T), 0, \
+                                   st, e.a, e.b, 0, a, js, it); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
@@ -683,161 +763,247 @@ struct PlanPrec<float> {
     static const float* s2(ibdl_plan p) { return p->s2_32; }
 };
 
+// One pass of L^-1 for one or more jobs of the same dimension, grid size and
+// precision: per stage a table of per-job arguments.
 template <typename R>
-void run_pipeline_t(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
-    using PP = PlanPrec<R>;
-    const int n = p->n;
-    const bool dense_in = in.grid != nullptr;
-    const bool dense_out = out.u != nullptr;
-    cplx<R>* spec = reinterpret_cast<cplx<R>*>(p->ws.spec);
-    const size_t sstride = p->spec_elems;
-    int stage = 0;
+struct PreparedT : PreparedPass {
+    int n = 0, dim = 2;
+    bool dense_out = false;
+    ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
+    StageTable<RowFwdArgs<R>> rf;
+    StageTable<ColArgs<R>> col[3];
+    StageTable<RowInvArgs<R>> ri;
+    StageTable<FinishArgs> fi;
 
-    // ---- row_fwd
-    RowFwdArgs<R> ra{};
-    ra.skip = in.skip;
-    ra.lines = dense_in ? nullptr : p->spread_lines;
-    ra.nproc = dense_in ? p->nlines : p->n_spread_lines;
-    ra.M = p->M;
-    auto view = [&](const Csr& c, const double* q, double coef) {
-        CsrView<R> v{};
-        v.q_stride = in.q_stride ? in.q_stride : (size_t)p->M;
-        v.line_act = c.line_act;
-        v.act_ptr = c.act_ptr;
-        v.act_node = c.act_node;
-        v.k = c.k;
-        v.w = PP::w(c);
-        v.q = q;
-        v.coef = coef;
-        return v;
-    };
-    ra.dip = view(p->dip, in.q_dip, in.c_dip);
-    ra.mono = view(p->mono, in.q_mono, in.c_mono);
-    ra.grid = in.grid;
-    ra.cg = in.c_grid;
-    ra.grid_stride = (size_t)p->nlines * n;
-    ra.spec = spec;
-    ra.spec_stride = sstride;
-    ra.P = p->P;
-    ra.tw = PP::tw(p);
-    const int G = row_lines_per_block<R>(n);
-    {
-        const StageEv e = stage_events(p, stage++, "spread+fft_x");
-        if (ra.nproc > 0) launch_row_fwd<R>(n, dim3((ra.nproc + G - 1) / G, nrhs), st, e, ra);
+    void upload(JobRing& ring, hipStream_t st) override {
+        rf.upload(ring, st);
+        for (auto& c : col) c.upload(ring, st);
+        ri.upload(ring, st);
+        fi.upload(ring, st);
     }
+    template <class T, class F>
+    static void go(const StageTable<T>& tb, F&& f) {
+        if (tb.blocks() == 0) return;
+        f(tb.multi());
+    }
+    void run(int it, hipStream_t st) override {
+        int stage = 0;
+        {
+            const StageEv e = stage_events(tplan, stage++, "spread+fft_x");
+            go(rf, [&](bool m) {
+                if (m) launch_row_fwd_t<R, true>(n, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
+                else launch_row_fwd_t<R, false>(n, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
+            });
+        }
+        if (dim == 2) {
+            const StageEv e = stage_events(tplan, stage++, "fft_y+symbol");
+            go(col[0], [&](bool m) {
+                if (m) launch_col_t<R, 1, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+                else launch_col_t<R, 1, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+            });
+        } else {
+            StageEv e = stage_events(tplan, stage++, "fft_y");
+            go(col[0], [&](bool m) {
+                if (m) launch_col_t<R, 0, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+                else launch_col_t<R, 0, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+            });
+            e = stage_events(tplan, stage++, "fft_z+symbol");
+            go(col[1], [&](bool m) {
+                if (m) launch_col_t<R, 1, true, true>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(), it);
+                else launch_col_t<R, 1, true, false>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(), it);
+            });
+            e = stage_events(tplan, stage++, "ifft_y");
+            go(col[2], [&](bool m) {
+                if (m) launch_col_t<R, 2, false, true>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(), it);
+                else launch_col_t<R, 2, false, false>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(), it);
+            });
+        }
+        if (dense_out) {
+            const StageEv e = stage_events(tplan, stage++, "ifft_x");
+            go(ri, [&](bool m) {
+                if (m) launch_row_inv_t<R, 1, true>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                else launch_row_inv_t<R, 1, false>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+            });
+        } else {
+            StageEv e = stage_events(tplan, stage++, "ifft_x+interp");
+            go(ri, [&](bool m) {
+                if (m) launch_row_inv_t<R, 0, true>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                else launch_row_inv_t<R, 0, false>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+            });
+            e = stage_events(tplan, stage++, "finish");
+            go(fi, [&](bool m) {
+                if (m)
+                    hipExtLaunchKernelGGL((k_finish<R, true>), dim3(fi.blocks()), dim3(FIN_T), 0, st, e.a, e.b, 0,
+                                          fi.args[0], fi.jobs(), it);
+                else
+                    hipExtLaunchKernelGGL((k_finish<R, false>), dim3(fi.blocks()), dim3(FIN_T), 0, st, e.a, e.b,
+                                          0, fi.args[0], fi.jobs(), it);
+            });
+        }
+        IBDL_HIP_TRY(hipGetLastError());
+    }
+};
 
-    // ---- columns
+template <typename R>
+std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
+    using PP = PlanPrec<R>;
+    auto P = std::make_unique<PreparedT<R>>();
+    const ibdl_plan p0 = jobs[0].p;
+    const int n = p0->n;
+    P->n = n;
+    P->dim = p0->dim;
+    P->dense_out = jobs[0].out.u != nullptr;
+    P->tplan = p0;
+    const int G = row_lines_per_block<R>(n);
     const int C = col_width<R>(n);
     const int NT = col_tiles<R>(n);
     const size_t plane = (size_t)NT * n * C;
-    const int KZ = z_rows<R>(n);  // y-rows per block of the z transform
-    ColArgs<R> ca{};
-    ca.skip = in.skip;
-    ca.spec = spec;
-    ca.rhs_stride = sstride;
-    ca.width = p->W;
-    ca.tw = PP::tw(p);
-    ca.s2 = PP::s2(p);
-    ca.alpha = (R)p->alpha;
-    ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
-    ca.tile_stride = (size_t)n * C;
-    if (p->dim == 2) {
-        ca.outer_list = nullptr;
-        ca.outer_stride = 0;
-        ca.es = C;
-        ca.lmask = dense_in ? nullptr : p->spread_line_mask;
-        ca.lm_outer = 0; ca.lm_stride = 1;
-        ca.smask = dense_out ? nullptr : p->gather_line_mask;
-        ca.sm_outer = 0; ca.sm_stride = 1;
-        launch_col<R, 1, false>(n, dim3(NT, 1, nrhs), st, stage_events(p, stage++, "fft_y+symbol"), ca);
-    } else {
-        // y forward over planes that hold forcing
-        ColArgs<R> y1 = ca;
-        y1.outer_list = dense_in ? nullptr : p->spread_planes;
-        y1.outer_stride = plane;
-        y1.es = C;
-        y1.lmask = dense_in ? nullptr : p->spread_line_mask;
-        y1.lm_outer = n; y1.lm_stride = 1;
-        y1.smask = nullptr;
-        const int ny1 = dense_in ? n : p->n_spread_planes;
-        {
-            const StageEv e = stage_events(p, stage++, "fft_y");
-            if (ny1 > 0) launch_col<R, 0, false>(n, dim3(NT, ny1, nrhs), st, e, y1);
-        }
-        // z forward, symbol, z inverse: blocks of KZ y-rows of one tile
-        ColArgs<R> z = ca;
-        z.outer_list = nullptr;
-        z.outer_stride = (size_t)KZ * C;
-        z.es = plane;
-        z.lmask = dense_in ? nullptr : p->spread_plane_mask;
-        z.lm_outer = 0; z.lm_stride = 1;
-        z.smask = dense_out ? nullptr : p->gather_plane_mask;
-        z.sm_outer = 0; z.sm_stride = 1;
-        launch_col<R, 1, true>(n, dim3(NT, n / KZ, nrhs), st, stage_events(p, stage++, "fft_z+symbol"), z);
-        // y inverse over planes something is read from
-        ColArgs<R> y2 = ca;
-        y2.outer_list = dense_out ? nullptr : p->gather_planes;
-        y2.outer_stride = plane;
-        y2.es = C;
-        y2.lmask = nullptr;
-        y2.smask = dense_out ? nullptr : p->gather_line_mask;
-        y2.sm_outer = n; y2.sm_stride = 1;
-        const int ny2 = dense_out ? n : p->n_gather_planes;
-        {
-            const StageEv e = stage_events(p, stage++, "ifft_y");
-            if (ny2 > 0) launch_col<R, 2, false>(n, dim3(NT, ny2, nrhs), st, e, y2);
-        }
-    }
+    const int KZ = z_rows<R>(n);
+    for (const PassJob& jb : jobs) {
+        const ibdl_plan p = jb.p;
+        const PipeIn& in = jb.in;
+        const PipeOut& out = jb.out;
+        const int nrhs = jb.nrhs;
+        const bool dense_in = in.grid != nullptr;
+        const bool dense_out = out.u != nullptr;
+        cplx<R>* spec = reinterpret_cast<cplx<R>*>(p->ws.spec);
+        const size_t sstride = p->spec_elems;
 
-    // ---- row_inv
-    RowInvArgs<R> ia{};
-    ia.skip = in.skip;
-    ia.lines = dense_out ? nullptr : p->gather_lines;
-    ia.nproc = dense_out ? p->nlines : p->n_gather_lines;
-    ia.spec = spec;
-    ia.spec_stride = sstride;
-    ia.P = p->P;
-    ia.tw = PP::tw(p);
-    ia.u = out.u;
-    ia.u_stride = (size_t)p->nlines * n;
-    ia.line_start = p->line_start;
-    ia.cell = p->cell;
-    ia.taps = PP::taps(p);
-    ia.part = reinterpret_cast<R*>(p->ws.part);
-    ia.part_stride = (size_t)p->M * p->gpp;
-    ia.M = p->M;
-    ia.dim = p->dim;
-    if (dense_out) {
-        launch_row_inv<R, 1>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, stage_events(p, stage++, "ifft_x"), ia);
-    } else {
-        const StageEv e = stage_events(p, stage++, "ifft_x+interp");
-        if (ia.nproc > 0) launch_row_inv<R, 0>(n, dim3((ia.nproc + G - 1) / G, nrhs), st, e, ia);
-        FinishArgs fa{};
-        fa.perm = p->perm;
-        fa.M = p->M;
-        fa.gpp = p->gpp;
-        fa.part_stride = ia.part_stride;
-        fa.out = out.out;
-        fa.out_stride = out.out_stride ? out.out_stride : (size_t)p->M;
-        fa.cA = out.cA;
-        fa.in = out.in;
-        fa.in_stride = out.in_stride ? out.in_stride : (size_t)p->M;
-        fa.cB = out.cB;
-        fa.in2 = out.in2;
-        fa.in2_stride = out.in2_stride ? out.in2_stride : (size_t)p->M;
-        fa.cC = out.cC;
-        fa.skip = in.skip;
-        fa.V = out.dots_V;
-        fa.vstride_rhs = out.dots_vstride;
-        fa.nv = out.dots_nv;
-        fa.dots = out.dots;
-        fa.dots_rhs = out.dots_rhs;
-        fa.dstride = out.dots_stride;
-        const StageEv ef = stage_events(p, stage++, "finish");
-        hipExtLaunchKernelGGL((k_finish<R>), dim3((p->M + FIN_T - 1) / FIN_T, nrhs), dim3(FIN_T), 0, st, ef.a,
-                              ef.b, 0, reinterpret_cast<const R*>(p->ws.part), fa);
+        // ---- row_fwd
+        RowFwdArgs<R> ra{};
+        ra.skip = in.skip;
+        ra.lines = dense_in ? nullptr : p->spread_lines;
+        ra.nproc = dense_in ? p->nlines : p->n_spread_lines;
+        ra.nblk = (ra.nproc + G - 1) / G;
+        ra.M = p->M;
+        auto view = [&](const Csr& c, const double* q, double coef) {
+            CsrView<R> v{};
+            v.q_stride = in.q_stride ? in.q_stride : (size_t)p->M;
+            v.q_jstride = in.q_jstride;
+            v.line_act = c.line_act;
+            v.act_ptr = c.act_ptr;
+            v.act_node = c.act_node;
+            v.k = c.k;
+            v.w = PP::w(c);
+            v.q = q;
+            v.coef = coef;
+            return v;
+        };
+        ra.dip = view(p->dip, in.q_dip, in.c_dip);
+        ra.mono = view(p->mono, in.q_mono, in.c_mono);
+        ra.grid = in.grid;
+        ra.cg = in.c_grid;
+        ra.grid_stride = (size_t)p->nlines * n;
+        ra.spec = spec;
+        ra.spec_stride = sstride;
+        ra.P = p->P;
+        ra.tw = PP::tw(p);
+        P->rf.add(ra, ra.nblk * nrhs);
+
+        // ---- columns
+        ColArgs<R> ca{};
+        ca.skip = in.skip;
+        ca.spec = spec;
+        ca.rhs_stride = sstride;
+        ca.width = p->W;
+        ca.tw = PP::tw(p);
+        ca.s2 = PP::s2(p);
+        ca.alpha = (R)p->alpha;
+        ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
+        ca.tile_stride = (size_t)n * C;
+        if (p->dim == 2) {
+            ca.outer_list = nullptr;
+            ca.outer_stride = 0;
+            ca.es = C;
+            ca.lmask = dense_in ? nullptr : p->spread_line_mask;
+            ca.lm_outer = 0; ca.lm_stride = 1;
+            ca.smask = dense_out ? nullptr : p->gather_line_mask;
+            ca.sm_outer = 0; ca.sm_stride = 1;
+            ca.nouter = 1;
+            P->col[0].add(ca, NT * nrhs);
+        } else {
+            ColArgs<R> y1 = ca;  // y forward over planes that hold forcing
+            y1.outer_list = dense_in ? nullptr : p->spread_planes;
+            y1.outer_stride = plane;
+            y1.es = C;
+            y1.lmask = dense_in ? nullptr : p->spread_line_mask;
+            y1.lm_outer = n; y1.lm_stride = 1;
+            y1.smask = nullptr;
+            y1.nouter = dense_in ? n : p->n_spread_planes;
+            P->col[0].add(y1, NT * y1.nouter * nrhs);
+            ColArgs<R> z = ca;   // z forward, symbol, z inverse: blocks of KZ y-rows of one tile
+            z.outer_list = nullptr;
+            z.outer_stride = (size_t)KZ * C;
+            z.es = plane;
+            z.lmask = dense_in ? nullptr : p->spread_plane_mask;
+            z.lm_outer = 0; z.lm_stride = 1;
+            z.smask = dense_out ? nullptr : p->gather_plane_mask;
+            z.sm_outer = 0; z.sm_stride = 1;
+            z.nouter = n / KZ;
+            P->col[1].add(z, NT * z.nouter * nrhs);
+            ColArgs<R> y2 = ca;  // y inverse over planes something is read from
+            y2.outer_list = dense_out ? nullptr : p->gather_planes;
+            y2.outer_stride = plane;
+            y2.es = C;
+            y2.lmask = nullptr;
+            y2.smask = dense_out ? nullptr : p->gather_line_mask;
+            y2.sm_outer = n; y2.sm_stride = 1;
+            y2.nouter = dense_out ? n : p->n_gather_planes;
+            P->col[2].add(y2, NT * y2.nouter * nrhs);
+        }
+
+        // ---- row_inv
+        RowInvArgs<R> ia{};
+        ia.skip = in.skip;
+        ia.lines = dense_out ? nullptr : p->gather_lines;
+        ia.nproc = dense_out ? p->nlines : p->n_gather_lines;
+        ia.nblk = (ia.nproc + G - 1) / G;
+        ia.spec = spec;
+        ia.spec_stride = sstride;
+        ia.P = p->P;
+        ia.tw = PP::tw(p);
+        ia.u = out.u;
+        ia.u_stride = (size_t)p->nlines * n;
+        ia.line_start = p->line_start;
+        ia.cell = p->cell;
+        ia.taps = PP::taps(p);
+        ia.part = reinterpret_cast<R*>(p->ws.part);
+        ia.part_stride = (size_t)p->M * p->gpp;
+        ia.M = p->M;
+        ia.dim = p->dim;
+        P->ri.add(ia, ia.nblk * nrhs);
+
+        // ---- finish
+        if (!dense_out) {
+            FinishArgs fa{};
+            fa.skip = in.skip;
+            fa.perm = p->perm;
+            fa.M = p->M;
+            fa.gpp = p->gpp;
+            fa.nblk = (p->M + FIN_T - 1) / FIN_T;
+            fa.part = p->ws.part;
+            fa.part_stride = ia.part_stride;
+            fa.out = out.out;
+            fa.out_stride = out.out_stride ? out.out_stride : (size_t)p->M;
+            fa.out_jstride = out.out_jstride;
+            fa.cA = out.cA;
+            fa.in = out.in;
+            fa.in_stride = out.in_stride ? out.in_stride : (size_t)p->M;
+            fa.in_jstride = out.in_jstride;
+            fa.cB = out.cB;
+            fa.in2 = out.in2;
+            fa.in2_stride = out.in2_stride ? out.in2_stride : (size_t)p->M;
+            fa.cC = out.cC;
+            fa.V = out.dots_V;
+            fa.vstride_rhs = out.dots_vstride;
+            fa.nv = out.dots_nv;
+            fa.dots = out.dots;
+            fa.dots_rhs = out.dots_rhs;
+            fa.dstride = out.dots_stride;
+            P->fi.add(fa, fa.nblk * nrhs);
+        }
     }
-    IBDL_HIP_TRY(hipGetLastError());
+    return P;
 }
 
 }  // namespace ibdl

@@ -2,9 +2,7 @@
 #include "pipeline.h"
 
 namespace ibdl {
-void run_pipeline_f32(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
-    run_pipeline_t<float>(p, nrhs, in, out, st);
-}
+std::unique_ptr<PreparedPass> prepare_f32(const std::vector<PassJob>& jobs) { return prepare_t<float>(jobs); }
 // complex elements per line of the tiled half spectrum: tiles x columns per tile
 int tile_pitch_f32(int n) { return col_tiles<float>(n) * col_width<float>(n); }
 }  // namespace ibdl

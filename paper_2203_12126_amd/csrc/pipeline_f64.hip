@@ -2,9 +2,7 @@
 #include "pipeline.h"
 
 namespace ibdl {
-void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st) {
-    run_pipeline_t<double>(p, nrhs, in, out, st);
-}
+std::unique_ptr<PreparedPass> prepare_f64(const std::vector<PassJob>& jobs) { return prepare_t<double>(jobs); }
 // complex elements per line of the tiled half spectrum: tiles x columns per tile
 int tile_pitch_f64(int n) { return col_tiles<double>(n) * col_width<double>(n); }
 }  // namespace ibdl

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <vector>
 
 #include "../../include/ibdl.h"
@@ -51,7 +52,12 @@ struct Krylov {
     void* host_pinned = nullptr;
 };
 
-struct ibdl_plan_impl;
+struct JobRing {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0, pos = 0;
+    std::vector<void*>* owner = nullptr;
+};
 
 }  // namespace ibdl
 
@@ -115,6 +121,7 @@ struct ibdl_plan_s {
     int n_acc = 0;
 
     std::vector<void*> allocs;  // everything to free
+    ibdl::JobRing ring;
 };
 
 namespace ibdl {
@@ -128,20 +135,23 @@ struct PipeIn {
     const double* grid = nullptr;    // [nrhs][n^dim] grid forcing
     double c_grid = 0;
     size_t q_stride = 0;             // distance between right-hand sides of q_dip/q_mono (0: M)
+    size_t q_jstride = 0;            // added per iteration index (Krylov basis)
     const int32_t* skip = nullptr;   // per-rhs flags (stride 4): set -> the rhs is not processed
 };
 struct PipeOut {
     // gather: out[k] = cA * (S* u)_k + cB * in[k] + cC * in2[k]   (strides 0: M)
     double* out = nullptr;
     size_t out_stride = 0;
+    size_t out_jstride = 0;          // added per iteration index
     double cA = 0;
     const double* in = nullptr;
     size_t in_stride = 0;
+    size_t in_jstride = 0;
     double cB = 0;
     const double* in2 = nullptr;
     size_t in2_stride = 0;
     double cC = 0;
-    // gather only: also the block partial sums of <out, V_i>, i < dots_nv
+    // gather only: also the block partial sums of <out, V_i>, i < dots_nv + iteration index
     const double* dots_V = nullptr;
     size_t dots_vstride = 0;
     int dots_nv = 0;
@@ -152,13 +162,32 @@ struct PipeOut {
     double* u = nullptr;
 };
 
+void* dev_alloc(std::vector<void*>& owner, size_t bytes);
 void* dev_alloc(ibdl_plan p, size_t bytes);
 void ensure_workspace(ibdl_plan p, int nrhs);
+
+// One job of a grid pass: a plan, its right-hand sides, inputs and outputs.
+struct PassJob {
+    ibdl_plan p;
+    int nrhs;
+    PipeIn in;
+    PipeOut out;
+};
+// A grid pass prepared for one or more jobs of the same dimension, grid size and
+// precision; run() launches every stage once for all jobs.
+struct PreparedPass {
+    virtual ~PreparedPass() {}
+    virtual void upload(JobRing& ring, hipStream_t st) = 0;  // only needed for several jobs
+    virtual void run(int it, hipStream_t st) = 0;            // it: iteration index
+};
+std::unique_ptr<PreparedPass> prepare_f64(const std::vector<PassJob>& jobs);
+std::unique_ptr<PreparedPass> prepare_f32(const std::vector<PassJob>& jobs);
 // fp64 forces the FP64 pipeline on a mixed plan (right-hand sides, residuals, grid solutions)
+std::unique_ptr<PreparedPass> prepare_pass(const std::vector<PassJob>& jobs, bool fp64);
 void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st,
                   bool fp64 = false);
-void run_pipeline_f64(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
-void run_pipeline_f32(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st);
+// staging area for argument tables: pinned host copy, device copy, wraps after a stream sync
+void* ring_put(JobRing& r, const void* src, size_t bytes, hipStream_t st);
 int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);

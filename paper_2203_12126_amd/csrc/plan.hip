@@ -22,7 +22,7 @@
 namespace ibdl {
 
 // ------------------------------------------------------------------ alloc
-void* dev_alloc(ibdl_plan p, size_t bytes) {
+void* dev_alloc(std::vector<void*>& owner, size_t bytes) {
     void* ptr = nullptr;
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(&ptr, bytes);
@@ -30,9 +30,10 @@ void* dev_alloc(ibdl_plan p, size_t bytes) {
         (void)hipGetLastError();
         throw Error{IBDL_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     }
-    p->allocs.push_back(ptr);
+    owner.push_back(ptr);
     return ptr;
 }
+void* dev_alloc(ibdl_plan p, size_t bytes) { return dev_alloc(p->allocs, bytes); }
 
 template <typename T>
 static T* alloc_n(ibdl_plan p, size_t n) {
