@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 typedef struct ibdl_plan_s* ibdl_plan;
+typedef struct ibdl_batch_s* ibdl_batch;
 
 typedef enum {
     IBDL_OK = 0,
@@ -177,6 +178,62 @@ typedef struct {
 } ibdl_plan_stats;
 
 ibdl_status ibdl_plan_get_stats(ibdl_plan plan, ibdl_plan_stats* out_host);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems (each its own geometry, grid size, alpha,
+ * boundary condition, precision and number of right-hand sides) carried through
+ * the method together.  Every grid pass launches each stage once per group of
+ * instances with the same dimension, grid size and precision (a per-instance
+ * argument table maps each workgroup to its instance), and every GMRES kernel
+ * launches once over all right-hand sides of the batch.  The arithmetic of an
+ * instance is the same as in a solve through its own plan: results are
+ * bit-identical to ibdl_solve / ibdl_apply / ibdl_eval_grid on that instance.
+ * Per-instance array arguments are HOST arrays of `count` DEVICE pointers, each
+ * laid out as for the single-plan entry point ([nrhs_i][M_i] or [nrhs_i][n_i^dim]).
+ * A batch is not thread-safe; its entry points wait for work already queued on
+ * `stream` before they start.
+ * ------------------------------------------------------------------------- */
+
+/* Build one plan per instance (as ibdl_plan_create) and the batch's workspace.
+ * descs: host [count]; nrhs: host [count], each >= 1.  Synchronises `stream`.
+ * Errors: IBDL_ERR_ARG (the message names the first bad instance), IBDL_ERR_NUMERIC,
+ * IBDL_ERR_OOM, IBDL_ERR_HIP.  *out is set only on success. */
+ibdl_status ibdl_batch_create(const ibdl_desc* descs, int32_t count, const int32_t* nrhs, void* stream,
+                              ibdl_batch* out);
+
+/* Free the batch, its plans and workspace (waits for the device). */
+ibdl_status ibdl_batch_destroy(ibdl_batch batch);
+
+/* Number of instances and of right-hand sides over all instances (either may be NULL). */
+ibdl_status ibdl_batch_size(ibdl_batch batch, int32_t* count, int32_t* total_rhs);
+
+/* ibdl_plan_get_stats of instance i (0 <= i < count). */
+ibdl_status ibdl_batch_get_stats(ibdl_batch batch, int32_t i, ibdl_plan_stats* out_host);
+
+/* Aq_i = A_i q_i for every instance (Sec. 5.3 / Sec. 4.3 operators; async after the wait). */
+ibdl_status ibdl_batch_apply(ibdl_batch batch, const double* const* q, double* const* Aq, void* stream);
+
+/* ibdl_solve for every instance (Sec. 4.1, Sec. 5.3): right-hand sides, GMRES
+ * with the instances' own stopping tests, FP64 refinement of MIXED instances.
+ * data, sol: per instance; g: NULL (no forcing anywhere) or per instance with
+ * NULL entries allowed.  opts as for ibdl_solve except that opts->x0 must be NULL.
+ * info: HOST [total_rhs] in instance order.  Blocks until done.  Returns
+ * IBDL_ERR_NOCONV / IBDL_ERR_NUMERIC if any right-hand side ended so (every
+ * other solution is still written). */
+ibdl_status ibdl_batch_solve(ibdl_batch batch, const double* const* data, const double* const* g,
+                             const ibdl_solve_opts* opts, double* const* sol, ibdl_solve_info* info,
+                             void* stream);
+
+/* ibdl_eval_grid for every instance (FP64; async after the wait).  vb: per
+ * instance, required for Neumann instances (may be NULL when none is Neumann);
+ * g: NULL or per instance with NULL entries allowed. */
+ibdl_status ibdl_batch_eval_grid(ibdl_batch batch, const double* const* sol, const double* const* vb,
+                                 const double* const* g, double* const* u, void* stream);
+
+/* Stage timing of the batch's grid passes, as ibdl_plan_set_timing / ibdl_plan_stage_times. */
+ibdl_status ibdl_batch_set_timing(ibdl_batch batch, int32_t enable);
+ibdl_status ibdl_batch_stage_times(ibdl_batch batch, double* ms_host, const char** names,
+                                   int64_t* calls, int32_t cap, int32_t* count);
 
 /* Message for the last failing call on this host thread ("" if none). */
 const char* ibdl_last_error(void);

@@ -7,7 +7,7 @@
 #include <new>
 #include <string>
 
-#include "plan.h"
+#include "solve.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -71,77 +71,122 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
     prepare_pass(jobs, fp64)->run(0, st);
 }
 
-void* ring_put(JobRing& r, const void* src, size_t bytes, hipStream_t st) {
+void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st) {
     const size_t need = (bytes + 255) / 256 * 256;
-    if (!r.host || need > r.cap) {
-        if (r.host) IBDL_HIP_TRY(hipStreamSynchronize(st));
-        const size_t cap = std::max<size_t>(need, 4u << 20);
+    while (a.cur < (int)a.blocks.size() && a.pos + need > a.blocks[a.cur].cap) {
+        ++a.cur;
+        a.pos = 0;
+    }
+    if (a.cur == (int)a.blocks.size()) {
+        Arena::Block blk;
+        blk.cap = std::max<size_t>(need, 4u << 20);
         void* h = nullptr;
-        IBDL_HIP_TRY(hipHostMalloc(&h, cap));
-        if (r.host) (void)hipHostFree(r.host);
-        r.host = reinterpret_cast<char*>(h);
-        r.dev = reinterpret_cast<char*>(dev_alloc(*r.owner, cap));
-        r.cap = cap;
-        r.pos = 0;
+        IBDL_HIP_TRY(hipHostMalloc(&h, blk.cap));
+        blk.host = reinterpret_cast<char*>(h);
+        void* d = nullptr;
+        if (hipMalloc(&d, blk.cap) != hipSuccess) {
+            (void)hipHostFree(h);
+            throw Error{IBDL_ERR_OOM, "device allocation failed (argument tables)"};
+        }
+        blk.dev = reinterpret_cast<char*>(d);
+        a.blocks.push_back(blk);
+        a.pos = 0;
     }
-    if (r.pos + need > r.cap) {
-        // wrap: copies queued earlier must have consumed the host staging area
-        IBDL_HIP_TRY(hipStreamSynchronize(st));
-        r.pos = 0;
-    }
-    std::memcpy(r.host + r.pos, src, bytes);
-    IBDL_HIP_TRY(hipMemcpyAsync(r.dev + r.pos, r.host + r.pos, bytes, hipMemcpyHostToDevice, st));
-    void* d = r.dev + r.pos;
-    r.pos += need;
+    Arena::Block& blk = a.blocks[a.cur];
+    std::memcpy(blk.host + a.pos, src, bytes);
+    IBDL_HIP_TRY(hipMemcpyAsync(blk.dev + a.pos, blk.host + a.pos, bytes, hipMemcpyHostToDevice, st));
+    void* d = blk.dev + a.pos;
+    a.pos += need;
     return d;
 }
 
-static void flush_set(ibdl_plan p, int set) {
-    const int n = p->set_used[set];
+void arena_reset(Arena& a) {
+    a.cur = 0;
+    a.pos = 0;
+}
+
+void arena_free(Arena& a) {
+    for (auto& b : a.blocks) {
+        (void)hipFree(b.dev);
+        (void)hipHostFree(b.host);
+    }
+    a.blocks.clear();
+    a.cur = 0;
+    a.pos = 0;
+}
+
+static void flush_set(Timing& t, int set) {
+    const int n = t.set_used[set];
     if (n <= 0) return;
-    IBDL_HIP_TRY(hipEventSynchronize(p->ev[set][2 * n - 1]));
+    IBDL_HIP_TRY(hipEventSynchronize(t.ev[set][2 * n - 1]));
     for (int i = 0; i < n; ++i) {
         float ms = 0.f;
-        IBDL_HIP_TRY(hipEventElapsedTime(&ms, p->ev[set][2 * i], p->ev[set][2 * i + 1]));
-        const char* nm = p->set_names[set][i];
+        IBDL_HIP_TRY(hipEventElapsedTime(&ms, t.ev[set][2 * i], t.ev[set][2 * i + 1]));
+        const char* nm = t.set_names[set][i];
         int slot = -1;
-        for (int k = 0; k < p->n_acc; ++k)
-            if (std::strcmp(p->acc_names[k], nm) == 0) slot = k;
-        if (slot < 0 && p->n_acc < 16) {
-            slot = p->n_acc++;
-            p->acc_names[slot] = nm;
-            p->acc_ms[slot] = 0.0;
-            p->acc_n[slot] = 0;
+        for (int k = 0; k < t.n_acc; ++k)
+            if (std::strcmp(t.acc_names[k], nm) == 0) slot = k;
+        if (slot < 0 && t.n_acc < 16) {
+            slot = t.n_acc++;
+            t.acc_names[slot] = nm;
+            t.acc_ms[slot] = 0.0;
+            t.acc_n[slot] = 0;
         }
         if (slot >= 0) {
-            p->acc_ms[slot] += ms;
-            p->acc_n[slot] += 1;
+            t.acc_ms[slot] += ms;
+            t.acc_n[slot] += 1;
         }
     }
-    p->set_used[set] = 0;
+    t.set_used[set] = 0;
 }
 
 // Stage names must be string literals.
 StageEv stage_events(ibdl_plan p, int idx, const char* name) {
     StageEv e;
-    if (!p->timing || idx >= ibdl_plan_s::MAXST) return e;
-    if (!p->events_made) {
-        for (int s = 0; s < ibdl_plan_s::RING; ++s)
-            for (int i = 0; i < 2 * ibdl_plan_s::MAXST; ++i) IBDL_HIP_TRY(hipEventCreate(&p->ev[s][i]));
-        p->events_made = 1;
+    Timing& t = *p->tm;
+    if (!t.enabled || idx >= Timing::MAXST) return e;
+    if (!t.events_made) {
+        for (int s = 0; s < Timing::RING; ++s)
+            for (int i = 0; i < 2 * Timing::MAXST; ++i) IBDL_HIP_TRY(hipEventCreate(&t.ev[s][i]));
+        t.events_made = 1;
     }
     if (idx == 0) {
-        const int set = p->ring_pos;
-        flush_set(p, set);
-        p->cur_set = set;
-        p->ring_pos = (set + 1) % ibdl_plan_s::RING;
+        const int set = t.ring_pos;
+        flush_set(t, set);
+        t.cur_set = set;
+        t.ring_pos = (set + 1) % Timing::RING;
     }
-    if (p->cur_set < 0) return e;
-    p->set_names[p->cur_set][idx] = name;
-    p->set_used[p->cur_set] = idx + 1;
-    e.a = p->ev[p->cur_set][2 * idx];
-    e.b = p->ev[p->cur_set][2 * idx + 1];
+    if (t.cur_set < 0) return e;
+    t.set_names[t.cur_set][idx] = name;
+    t.set_used[t.cur_set] = idx + 1;
+    e.a = t.ev[t.cur_set][2 * idx];
+    e.b = t.ev[t.cur_set][2 * idx + 1];
     return e;
+}
+
+void timing_reset(Timing& t, int enable) {
+    for (int s = 0; s < Timing::RING; ++s) t.set_used[s] = 0;
+    t.n_acc = 0;
+    t.cur_set = -1;
+    t.ring_pos = 0;
+    t.enabled = enable ? 1 : 0;
+}
+
+void timing_free(Timing& t) {
+    if (t.events_made)
+        for (int s = 0; s < Timing::RING; ++s)
+            for (int i = 0; i < 2 * Timing::MAXST; ++i) (void)hipEventDestroy(t.ev[s][i]);
+    t.events_made = 0;
+}
+
+int timing_read(Timing& t, double* ms, const char** names, int64_t* calls, int cap) {
+    for (int s = 0; s < Timing::RING; ++s) flush_set(t, s);
+    for (int i = 0; i < t.n_acc && i < cap; ++i) {
+        if (ms) ms[i] = t.acc_n[i] ? t.acc_ms[i] / (double)t.acc_n[i] : 0.0;
+        if (names) names[i] = t.acc_names[i];
+        if (calls) calls[i] = t.acc_n[i];
+    }
+    return t.n_acc;
 }
 
 void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out, size_t ostride,
@@ -182,7 +227,7 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
     if (!why.empty()) return fail(IBDL_ERR_ARG, why);
     ibdl_plan p = new (std::nothrow) ibdl_plan_s();
     if (!p) return fail(IBDL_ERR_OOM, "host allocation failed");
-    p->ring.owner = &p->allocs;
+    p->ks.arena = &p->arena;
     try {
         p->dim = desc->dim;
         p->n = desc->n;
@@ -216,11 +261,9 @@ ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
     (void)hipDeviceSynchronize();
     for (void* a : p->allocs) (void)hipFree(a);
-    if (p->kr.host_pinned) (void)hipHostFree(p->kr.host_pinned);
-    if (p->ring.host) (void)hipHostFree(p->ring.host);
-    if (p->events_made)
-        for (int s = 0; s < ibdl_plan_s::RING; ++s)
-            for (int i = 0; i < 2 * ibdl_plan_s::MAXST; ++i) (void)hipEventDestroy(p->ev[s][i]);
+    free_krylov(p->ks.w);
+    arena_free(p->arena);
+    timing_free(p->own_timing);
     delete p;
     return IBDL_OK;
 }
@@ -300,7 +343,9 @@ ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const doub
     if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
     IBDL_GUARD_BEGIN
     int overall = IBDL_OK;
-    gmres_solve(p, nrhs, data, g, o, sol, info, S(stream), &overall);
+    p->ks.inst.assign(1, Inst{p, nrhs, 0});
+    p->ks.R = nrhs;
+    solve_set(p->ks, {data}, {g}, {o.x0}, o, {sol}, info, S(stream), &overall);
     if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
     if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
     g_last_error.clear();
@@ -358,11 +403,7 @@ ibdl_status ibdl_plan_get_stats(ibdl_plan p, ibdl_plan_stats* o) {
 ibdl_status ibdl_plan_set_timing(ibdl_plan p, int32_t enable) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
     IBDL_GUARD_BEGIN
-    for (int s = 0; s < ibdl_plan_s::RING; ++s) p->set_used[s] = 0;
-    p->n_acc = 0;
-    p->cur_set = -1;
-    p->ring_pos = 0;
-    p->timing = enable ? 1 : 0;
+    timing_reset(*p->tm, enable);
     return IBDL_OK;
     IBDL_GUARD_END
 }
@@ -371,13 +412,191 @@ ibdl_status ibdl_plan_stage_times(ibdl_plan p, double* ms_host, const char** nam
                                   int32_t cap, int32_t* count) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
     IBDL_GUARD_BEGIN
-    for (int s = 0; s < ibdl_plan_s::RING; ++s) flush_set(p, s);
-    for (int i = 0; i < p->n_acc && i < cap; ++i) {
-        if (ms_host) ms_host[i] = p->acc_n[i] ? p->acc_ms[i] / (double)p->acc_n[i] : 0.0;
-        if (names) names[i] = p->acc_names[i];
-        if (calls) calls[i] = p->acc_n[i];
+    const int n = timing_read(*p->tm, ms_host, names, calls, cap);
+    if (count) *count = n;
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+// ------------------------------------------------------------------ batches
+static bool ptr_array_ok(const void* const* a, int n) {
+    if (!a) return false;
+    for (int i = 0; i < n; ++i)
+        if (!a[i]) return false;
+    return true;
+}
+
+ibdl_status ibdl_batch_create(const ibdl_desc* descs, int32_t count, const int32_t* nrhs, void* stream,
+                              ibdl_batch* out) {
+    if (!out) return fail(IBDL_ERR_ARG, "out is NULL");
+    if (!descs || !nrhs || count < 1) return fail(IBDL_ERR_ARG, "descs and nrhs must hold count >= 1 entries");
+    long long R = 0;
+    for (int i = 0; i < count; ++i) {
+        const std::string why = check_desc(&descs[i]);
+        if (!why.empty()) return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": " + why);
+        if (nrhs[i] < 1) return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": nrhs must be >= 1");
+        R += nrhs[i];
     }
-    if (count) *count = p->n_acc;
+    if (R >= (1LL << 24)) return fail(IBDL_ERR_ARG, "too many right-hand sides in one batch");
+    ibdl_batch b = new (std::nothrow) ibdl_batch_s();
+    if (!b) return fail(IBDL_ERR_OOM, "host allocation failed");
+    b->ks.arena = &b->arena;
+    int r0 = 0;
+    for (int i = 0; i < count; ++i) {
+        ibdl_plan p = nullptr;
+        const ibdl_status st = ibdl_plan_create(&descs[i], stream, &p);
+        if (st != IBDL_OK) {
+            const std::string msg = "instance " + std::to_string(i) + ": " + g_last_error;
+            ibdl_batch_destroy(b);
+            return fail(st, msg);
+        }
+        p->tm = &b->timing;
+        b->plans.push_back(p);
+        b->ks.inst.push_back(Inst{p, nrhs[i], r0});
+        r0 += nrhs[i];
+    }
+    b->ks.R = r0;
+    try {
+        for (const Inst& in : b->ks.inst) ensure_workspace(in.p, in.nrhs);
+    } catch (const ibdl::Error& e) {
+        ibdl_batch_destroy(b);
+        return fail(e.status, e.msg);
+    }
+    *out = b;
+    g_last_error.clear();
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_batch_destroy(ibdl_batch b) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    (void)hipDeviceSynchronize();
+    free_krylov(b->ks.w);
+    for (ibdl_plan p : b->plans) ibdl_plan_destroy(p);
+    arena_free(b->arena);
+    timing_free(b->timing);
+    delete b;
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_batch_size(ibdl_batch b, int32_t* count, int32_t* total_rhs) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    if (count) *count = (int32_t)b->plans.size();
+    if (total_rhs) *total_rhs = b->ks.R;
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_batch_get_stats(ibdl_batch b, int32_t i, ibdl_plan_stats* out_host) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    if (i < 0 || i >= (int32_t)b->plans.size()) return fail(IBDL_ERR_ARG, "instance index out of range");
+    return ibdl_plan_get_stats(b->plans[i], out_host);
+}
+
+ibdl_status ibdl_batch_apply(ibdl_batch b, const double* const* q, double* const* Aq, void* stream) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    const int n = (int)b->plans.size();
+    if (!ptr_array_ok((const void* const*)q, n) || !ptr_array_ok((const void* const*)Aq, n))
+        return fail(IBDL_ERR_ARG, "q and Aq must hold a device pointer per instance");
+    for (int i = 0; i < n; ++i)
+        if ((const void*)q[i] == (const void*)Aq[i]) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
+    IBDL_GUARD_BEGIN
+    IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    arena_reset(b->arena);
+    auto make = [&](size_t i) {
+        const Inst& in = b->ks.inst[i];
+        PipeIn pi;
+        pi.q_dip = q[i];
+        pi.c_dip = 1.0;
+        PipeOut po;
+        po.out = Aq[i];
+        po.cA = -1.0;
+        po.in = q[i];
+        po.cB = in.p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
+        return PassJob{in.p, in.nrhs, pi, po};
+    };
+    std::vector<size_t> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    prepare_grouped(b->ks, all, make, false, S(stream)).run(0, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const double* const* g,
+                             const ibdl_solve_opts* opts, double* const* sol, ibdl_solve_info* info,
+                             void* stream) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    const int n = (int)b->plans.size();
+    if (!ptr_array_ok((const void* const*)data, n) || !ptr_array_ok((const void* const*)sol, n))
+        return fail(IBDL_ERR_ARG, "data and sol must hold a device pointer per instance");
+    ibdl_solve_opts o{1e-8, 50, 500, nullptr, 0};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(IBDL_ERR_ARG, "tol must be positive");
+    if (o.restart < 1 || o.restart > 200) return fail(IBDL_ERR_ARG, "restart must be in 1..200");
+    if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
+    if (o.x0) return fail(IBDL_ERR_ARG, "opts->x0 must be NULL for a batch (solves start from 0)");
+    IBDL_GUARD_BEGIN
+    IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    SolveIO io;
+    io.data.assign(data, data + n);
+    io.g.assign(n, nullptr);
+    if (g) io.g.assign(g, g + n);
+    io.sol.assign(sol, sol + n);
+    SolveTask t(b->ks, std::move(io), o, S(stream));
+    t.run_to_end();
+    int overall = IBDL_OK;
+    t.results(info, &overall);
+    if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
+    if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
+    g_last_error.clear();
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_batch_eval_grid(ibdl_batch b, const double* const* sol, const double* const* vb,
+                                 const double* const* g, double* const* u, void* stream) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    const int n = (int)b->plans.size();
+    if (!ptr_array_ok((const void* const*)sol, n) || !ptr_array_ok((const void* const*)u, n))
+        return fail(IBDL_ERR_ARG, "sol and u must hold a device pointer per instance");
+    for (int i = 0; i < n; ++i)
+        if (b->plans[i]->bc == IBDL_NEUMANN && (!vb || !vb[i]))
+            return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": Neumann instances need V_b");
+    IBDL_GUARD_BEGIN
+    IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    arena_reset(b->arena);
+    auto make = [&](size_t i) {
+        const Inst& in = b->ks.inst[i];
+        PipeIn pi;
+        pi.q_dip = sol[i];
+        pi.c_dip = -1.0;
+        if (in.p->bc == IBDL_NEUMANN) {
+            pi.q_mono = vb[i];
+            pi.c_mono = -1.0;
+        }
+        pi.grid = g ? g[i] : nullptr;
+        pi.c_grid = 1.0;
+        PipeOut po;
+        po.u = u[i];
+        return PassJob{in.p, in.nrhs, pi, po};
+    };
+    std::vector<size_t> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    prepare_grouped(b->ks, all, make, true, S(stream)).run(0, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_batch_set_timing(ibdl_batch b, int32_t enable) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    timing_reset(b->timing, enable);
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_batch_stage_times(ibdl_batch b, double* ms_host, const char** names, int64_t* calls,
+                                   int32_t cap, int32_t* count) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    IBDL_GUARD_BEGIN
+    const int n = timing_read(b->timing, ms_host, names, calls, cap);
+    if (count) *count = n;
     return IBDL_OK;
     IBDL_GUARD_END
 }

@@ -1,47 +1,64 @@
 // Unpreconditioned restarted GMRES on the boundary density (Sec. 5.3), FP64 on
-// the device for every right-hand side at once.
+// the device, for a set of right-hand sides that may belong to different plans
+// (different boundary sizes M, grids, boundary conditions, precisions).
 //
-// Arnoldi step j of right-hand side r:  w = A v_j (one pass of the operator),
-// h_ij = <w, v_i> and w -= sum_i h_ij v_i done twice (classical Gram-Schmidt
-// applied twice), h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the previous Givens
-// rotations are applied to column j, a new rotation zeroes h_{j+1,j}, and the
-// rotated right-hand side g gives the residual estimate |g_{j+1}|.  All inner
-// products are two-level block reductions in a fixed order (deterministic).
+// Arnoldi step j of right-hand side r:  w = A v_j (one pass of the operator, whose
+// finishing kernel also forms the block partial sums of <w, v_i>), then
+// h_ij = <w, v_i> and w -= sum_i h_ij v_i twice (classical Gram-Schmidt applied
+// twice), h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the previous Givens rotations
+// are applied to column j, a new rotation zeroes h_{j+1,j}, and the rotated
+// right-hand side g gives the residual estimate |g_{j+1}|.  Every inner product is
+// a two-level block reduction in a fixed order over the rhs's own blocks, so a
+// right-hand side's arithmetic does not depend on which others share the launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <map>
+#include <tuple>
 #include <vector>
 
-#include "plan.h"
+#include "solve.h"
 
 namespace ibdl {
 
-__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int imin_d(int a, int b) { return a < b ? a : b; }
 
-constexpr int GT = 256;             // threads per block
-constexpr int GPER = 1;             // elements per thread
-constexpr int GCHUNK = GT * GPER;   // elements per block
-constexpr int FIN_BLOCK = 256;      // points per block of the operator's finishing kernel
+constexpr int GT = 256;  // threads per block = vector elements per block (= points per finishing block)
 
 enum { ST_DONE = 0, ST_ITERS = 1, ST_STATUS = 2, ST_J = 3 };
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < GT / 64; ++i) t += sh[i];
-    return t;  // valid in thread 0
-}
+// Device view of the Krylov state of R right-hand sides.
+struct KArgs {
+    int R, m;
+    const int32_t* Mr;
+    const size_t* voff;
+    const size_t* xoff;
+    double* V;
+    double* part;       // [R][nblk][m+2] (two banks: part and part2)
+    double* part2;
+    size_t pstride;     // per rhs
+    double* hcol;       // [R][m+2]
+    double* H;          // [R][m][m+1]: column j at H + j*(m+1)
+    double* cs;         // [R][m]
+    double* sn;
+    double* g;          // [R][m+1]
+    double* y;          // [R][m]
+    double* bnorm;      // [R]
+    double* resid;      // [R]
+    double* nrm;        // [R]
+    const double* tolv; // [R] tolerance relative to ||b_r||
+    int32_t* state;     // [R][4]
+    const int32_t* skip;
+};
+
+__device__ __forceinline__ int nblocks_of(int M) { return (M + GT - 1) / GT; }
 
 // Block sums of nv per-thread values at once: each wave reduces its values with
 // cross-lane shuffles, one LDS write per wave and value, one barrier, then
 // thread i adds the wave totals of value i (fixed order).  out[i] valid in
-// threads i < nv after the call; sh holds GT/64 * nv doubles.
+// threads i < nv after the call.
 template <int MAXV>
 __device__ __forceinline__ void block_multi_sum(double (&v)[MAXV], int nv, double* sh, double* out) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -54,7 +71,7 @@ __device__ __forceinline__ void block_multi_sum(double (&v)[MAXV], int nv, doubl
         }
     }
     __syncthreads();
-    if (threadIdx.x < nv) {
+    if ((int)threadIdx.x < nv) {
         double t = 0.0;
         for (int ww = 0; ww < GT / 64; ++ww) t += sh[ww * MAXV + threadIdx.x];
         out[threadIdx.x] = t;
@@ -62,77 +79,64 @@ __device__ __forceinline__ void block_multi_sum(double (&v)[MAXV], int nv, doubl
     __syncthreads();
 }
 
-struct KArgs {
-    double* V;          // [rhs][m+1][M]
-    size_t vstride;
-    int M, m, nblk;
-    int nblk_dots;      // blocks of the operator's fused first inner products
-    double* part;       // [rhs][blocks][m+2] (two banks: part and part2)
-    double* part2;
-    size_t pstride;     // per rhs
-    double* hcol;       // [rhs][m+2]
-    double* H;          // [rhs][m][m+1] column j at H + j*(m+1)
-    double* cs;         // [rhs][m]
-    double* sn;
-    double* g;          // [rhs][m+1]
-    double* y;          // [rhs][m]
-    double* bnorm;      // [rhs]
-    double* resid;      // [rhs]
-    int32_t* state;     // [rhs][4]
-    const double* tolv; // [rhs] tolerance relative to ||b_r||
-};
-
-// sum of squares of x over each block's chunk
-__global__ __launch_bounds__(GT) void k_sumsq(const double* __restrict__ x, size_t xstride, int M,
-                                              double* part, size_t pstride) {
+// block partial sums of x^2 (pool vectors) into part[r][b]
+__global__ __launch_bounds__(GT) void k_sumsq(KArgs a, const double* __restrict__ pool) {
     __shared__ double sh[GT / 64];
-    const int rhs = blockIdx.y;
-    const double* xr = x + (size_t)rhs * xstride;
-    double acc = 0.0;
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (m < (size_t)M) acc += xr[m] * xr[m];
+    __shared__ double o1[1];
+    const int r = blockIdx.y, M = a.Mr[r];
+    if ((int)blockIdx.x >= nblocks_of(M)) return;
+    const int m = blockIdx.x * GT + threadIdx.x;
+    double v[1] = {0.0};
+    if (m < M) {
+        const double x = pool[a.xoff[r] + m];
+        v[0] = x * x;
     }
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[(size_t)rhs * pstride + blockIdx.x] = t;
+    block_multi_sum<1>(v, 1, sh, o1);
+    if (threadIdx.x == 0) a.part[(size_t)r * a.pstride + blockIdx.x] = o1[0];
 }
 
-__global__ void k_set_bnorm(const double* __restrict__ part, size_t pstride, int nblk,
-                            double* bnorm, int32_t* state, const int32_t* skip, int nrhs) {
+// nrm[r] = sqrt of the summed block partials of k_sumsq
+__global__ void k_norms(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+    if (r >= a.R) return;
+    const int nb = nblocks_of(a.Mr[r]);
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)r * pstride + b];
-    bnorm[r] = sqrt(s);
-    state[4 * r + ST_DONE] = skip[r];
-    state[4 * r + ST_ITERS] = 0;
-    state[4 * r + ST_STATUS] = isfinite(s) ? IBDL_OK : IBDL_ERR_NUMERIC;
-    state[4 * r + ST_J] = 0;
+    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
+    a.nrm[r] = sqrt(s);
+}
+
+__global__ void k_set_bnorm(KArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    const int nb = nblocks_of(a.Mr[r]);
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
+    a.bnorm[r] = sqrt(s);
+    a.state[4 * r + ST_DONE] = a.skip[r];
+    a.state[4 * r + ST_ITERS] = 0;
+    a.state[4 * r + ST_STATUS] = isfinite(s) ? IBDL_OK : IBDL_ERR_NUMERIC;
+    a.state[4 * r + ST_J] = 0;
 }
 
 // start a cycle: v_0 = r / ||r||, g = (||r||, 0, ...); rhs already done are left alone
-__global__ __launch_bounds__(GT) void k_init_cycle(const double* __restrict__ rv, size_t rstride,
-                                                   KArgs a) {
-    const int rhs = blockIdx.y;
-    int32_t* st = a.state + 4 * rhs;
-    if (st[ST_DONE]) return;
+__global__ __launch_bounds__(GT) void k_init_cycle(KArgs a, const double* __restrict__ rpool) {
+    const int r = blockIdx.y, M = a.Mr[r];
+    const int nb = nblocks_of(M);
+    int32_t* st = a.state + 4 * r;
+    if (st[ST_DONE] || (int)blockIdx.x >= nb) return;
     double s = 0.0;
-    for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)rhs * a.pstride + b];
+    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
     const double beta = sqrt(s);
-    const double bn = a.bnorm[rhs];
-    const bool done = !(bn > 0.0) || beta <= a.tolv[rhs] * bn || !(beta > 0.0);
+    const double bn = a.bnorm[r];
+    const bool done = !(bn > 0.0) || beta <= a.tolv[r] * bn || !(beta > 0.0);
     const double inv = (beta > 0.0) ? 1.0 / beta : 0.0;
-    double* v0 = a.V + (size_t)rhs * a.vstride;
-    const double* r = rv + (size_t)rhs * rstride;
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (m < (size_t)a.M) v0[m] = r[m] * inv;
-    }
+    const int m = blockIdx.x * GT + threadIdx.x;
+    if (m < M) a.V[a.voff[r] + m] = rpool[a.xoff[r] + m] * inv;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double* g = a.g + (size_t)rhs * (a.m + 1);
+        double* g = a.g + (size_t)r * (a.m + 1);
         g[0] = beta;
         for (int i = 1; i <= a.m; ++i) g[i] = 0.0;
-        a.resid[rhs] = bn > 0.0 ? beta / bn : 0.0;
+        a.resid[r] = bn > 0.0 ? beta / bn : 0.0;
         st[ST_J] = 0;
         if (!isfinite(s)) st[ST_STATUS] = IBDL_ERR_NUMERIC;
         if (done || !isfinite(s)) st[ST_DONE] = 1;
@@ -142,86 +146,71 @@ __global__ __launch_bounds__(GT) void k_init_cycle(const double* __restrict__ rv
 // h = sum of the block partials of pass `pass`; w -= V h; then the partials of
 // the next quantity: pass 0 -> <w, v_i> again, pass 1 -> ||w||^2
 __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
-    __shared__ double sh[GT / 64];
     __shared__ double hs[256];
-    const int rhs = blockIdx.y;
-    if (a.state[4 * rhs + ST_DONE]) return;
-    const double* pin = (pass == 0 ? a.part : a.part2) + (size_t)rhs * a.pstride;
-    double* pout = (pass == 0 ? a.part2 : a.part) + (size_t)rhs * a.pstride;
-    const int nb_in = pass == 0 ? a.nblk_dots : a.nblk;
+    __shared__ double msh[(GT / 64) * 16];
+    __shared__ double mout[16];
+    const int r = blockIdx.y, M = a.Mr[r];
+    const int nb = nblocks_of(M);
+    if (a.state[4 * r + ST_DONE] || (int)blockIdx.x >= nb) return;
+    const double* pin = (pass == 0 ? a.part : a.part2) + (size_t)r * a.pstride;
+    double* pout = (pass == 0 ? a.part2 : a.part) + (size_t)r * a.pstride;
     for (int vi = threadIdx.x; vi <= j; vi += GT) {
         double s = 0.0;
-        for (int b = 0; b < nb_in; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
         hs[vi] = s;
     }
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double* hc = a.hcol + (size_t)rhs * (a.m + 2);
+        double* hc = a.hcol + (size_t)r * (a.m + 2);
         for (int vi = 0; vi <= j; ++vi) hc[vi] = (pass == 0 ? 0.0 : hc[vi]) + hs[vi];
     }
-    double* V = a.V + (size_t)rhs * a.vstride;
-    double* w = V + (size_t)(j + 1) * a.M;
-    double wl[GPER];
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (m < (size_t)a.M) {
-            double acc = w[m];
-            for (int vi = 0; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * a.M + m];
-            wl[i] = acc;
-            w[m] = acc;
-        } else {
-            wl[i] = 0.0;
-        }
+    double* V = a.V + a.voff[r];
+    double* w = V + (size_t)(j + 1) * M;
+    const int m = blockIdx.x * GT + threadIdx.x;
+    double wl = 0.0;
+    if (m < M) {
+        double acc = w[m];
+        for (int vi = 0; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
+        wl = acc;
+        w[m] = acc;
     }
     if (pass == 0) {
         // <w, v_i> for i <= j, 16 at a time
-        __shared__ double msh[(GT / 64) * 16];
-        __shared__ double mout[16];
         for (int v0 = 0; v0 <= j; v0 += 16) {
-            const int nv = imin(16, j + 1 - v0);
+            const int nv = imin_d(16, j + 1 - v0);
             double acc[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-            for (int i = 0; i < GPER; ++i) {
-                const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-                if (m < (size_t)a.M) {
-#pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        if (u < nv) acc[u] += V[(size_t)(v0 + u) * a.M + m] * wl[i];
-                }
-            }
+            for (int u = 0; u < 16; ++u) acc[u] = (u < nv && m < M) ? V[(size_t)(v0 + u) * M + m] * wl : 0.0;
             block_multi_sum<16>(acc, nv, msh, mout);
-            if (threadIdx.x < nv) pout[(size_t)blockIdx.x * (a.m + 2) + v0 + threadIdx.x] = mout[threadIdx.x];
+            if ((int)threadIdx.x < nv) pout[(size_t)blockIdx.x * (a.m + 2) + v0 + threadIdx.x] = mout[threadIdx.x];
         }
     } else {
-        double acc = 0.0;
-        for (int i = 0; i < GPER; ++i) acc += wl[i] * wl[i];
-        const double t = block_sum(acc, sh);
-        if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2)] = t;
+        double acc[1] = {wl * wl};
+        block_multi_sum<1>(acc, 1, msh, mout);
+        if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2)] = mout[0];
     }
 }
 
 // v_{j+1} = w / ||w||; block 0 applies the Givens rotations and updates the state
 __global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
-    const int rhs = blockIdx.y;
-    int32_t* st = a.state + 4 * rhs;
-    if (st[ST_DONE]) return;
-    const double* pin = a.part + (size_t)rhs * a.pstride;
+    const int r = blockIdx.y, M = a.Mr[r];
+    const int nb = nblocks_of(M);
+    int32_t* st = a.state + 4 * r;
+    if (st[ST_DONE] || (int)blockIdx.x >= nb) return;
+    const double* pin = a.part + (size_t)r * a.pstride;
     double s = 0.0;
-    for (int b = 0; b < a.nblk; ++b) s += pin[(size_t)b * (a.m + 2)];
+    for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2)];
     const double hn = sqrt(s);
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-    double* w = a.V + (size_t)rhs * a.vstride + (size_t)(j + 1) * a.M;
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (m < (size_t)a.M) w[m] *= inv;
-    }
+    double* w = a.V + a.voff[r] + (size_t)(j + 1) * M;
+    const int m = blockIdx.x * GT + threadIdx.x;
+    if (m < M) w[m] *= inv;
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const double* hc = a.hcol + (size_t)rhs * (a.m + 2);
-    double* Hj = a.H + (size_t)rhs * a.m * (a.m + 1) + (size_t)j * (a.m + 1);
-    double* cs = a.cs + (size_t)rhs * a.m;
-    double* sn = a.sn + (size_t)rhs * a.m;
-    double* g = a.g + (size_t)rhs * (a.m + 1);
+    const double* hc = a.hcol + (size_t)r * (a.m + 2);
+    double* Hj = a.H + (size_t)r * a.m * (a.m + 1) + (size_t)j * (a.m + 1);
+    double* cs = a.cs + (size_t)r * a.m;
+    double* sn = a.sn + (size_t)r * a.m;
+    double* g = a.g + (size_t)r * (a.m + 1);
     for (int i = 0; i <= j; ++i) Hj[i] = hc[i];
     Hj[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
@@ -238,26 +227,26 @@ __global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
     Hj[j + 1] = 0.0;
     g[j + 1] = -sv * g[j];
     g[j] = c * g[j];
-    const double res = fabs(g[j + 1]) / a.bnorm[rhs];
-    a.resid[rhs] = res;
+    const double res = fabs(g[j + 1]) / a.bnorm[r];
+    a.resid[r] = res;
     st[ST_ITERS] += 1;
     st[ST_J] = j + 1;
     if (!isfinite(res) || !isfinite(s)) {
         st[ST_STATUS] = IBDL_ERR_NUMERIC;
         st[ST_DONE] = 1;
-    } else if (res <= a.tolv[rhs] || !(hn > 0.0)) {
+    } else if (res <= a.tolv[r] || !(hn > 0.0)) {
         st[ST_DONE] = 1;
     }
 }
 
-// y = R^-1 g over the steps of the current cycle, then mark the cycle as consumed
-__global__ void k_backsolve(KArgs a, int nrhs) {
-    const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rhs >= nrhs) return;
-    const int jr = a.state[4 * rhs + ST_J];
-    const double* H = a.H + (size_t)rhs * a.m * (a.m + 1);
-    const double* g = a.g + (size_t)rhs * (a.m + 1);
-    double* y = a.y + (size_t)rhs * a.m;
+// y = R^-1 g over the steps of the current cycle
+__global__ void k_backsolve(KArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    const int jr = a.state[4 * r + ST_J];
+    const double* H = a.H + (size_t)r * a.m * (a.m + 1);
+    const double* g = a.g + (size_t)r * (a.m + 1);
+    double* y = a.y + (size_t)r * a.m;
     for (int i = jr - 1; i >= 0; --i) {
         double t = g[i];
         for (int k = i + 1; k < jr; ++k) t -= H[(size_t)k * (a.m + 1) + i] * y[k];
@@ -266,139 +255,116 @@ __global__ void k_backsolve(KArgs a, int nrhs) {
     }
 }
 
-// x += V[0..jr) y ; then the cycle position is reset
-__global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* x, size_t xstride) {
-    const int rhs = blockIdx.y;
-    const int jr = a.state[4 * rhs + ST_J];
-    if (jr == 0) return;
-    const double* V = a.V + (size_t)rhs * a.vstride;
-    const double* y = a.y + (size_t)rhs * a.m;
-    double* xr = x + (size_t)rhs * xstride;
-    for (int i = 0; i < GPER; ++i) {
-        const size_t m = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (m < (size_t)a.M) {
-            double acc = xr[m];
-            for (int vi = 0; vi < jr; ++vi) acc += y[vi] * V[(size_t)vi * a.M + m];
-            xr[m] = acc;
-        }
-    }
+// x += V[0..jr) y
+__global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* xpool) {
+    const int r = blockIdx.y, M = a.Mr[r];
+    const int jr = a.state[4 * r + ST_J];
+    const int m = blockIdx.x * GT + threadIdx.x;
+    if (jr == 0 || m >= M) return;
+    const double* V = a.V + a.voff[r];
+    const double* y = a.y + (size_t)r * a.m;
+    double acc = xpool[a.xoff[r] + m];
+    for (int vi = 0; vi < jr; ++vi) acc += y[vi] * V[(size_t)vi * M + m];
+    xpool[a.xoff[r] + m] = acc;
 }
 
-__global__ void k_reset_j(int32_t* state, int nrhs) {
+__global__ void k_reset_j(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrhs) state[4 * r + ST_J] = 0;
+    if (r < a.R) a.state[4 * r + ST_J] = 0;
 }
 
-__global__ void k_fill0_masked(double* x, size_t stride, int M, const int32_t* skip) {
-    const int rhs = blockIdx.y;
-    if (skip[rhs]) return;
-    for (int i = 0; i < GPER; ++i) {
-        const size_t mm = (size_t)blockIdx.x * GCHUNK + i * GT + threadIdx.x;
-        if (mm < (size_t)M) x[(size_t)rhs * stride + mm] = 0.0;
-    }
-}
-
-__global__ void k_copy(double* dst, const double* src, size_t n) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+// pool vectors of the rhs not skipped: op 0: dst = 0, op 1: dst += src
+__global__ __launch_bounds__(GT) void k_pool_op(KArgs a, int op, double* dst, const double* src) {
+    const int r = blockIdx.y, M = a.Mr[r];
+    const int m = blockIdx.x * GT + threadIdx.x;
+    if (m >= M || a.skip[r]) return;
+    const size_t i = a.xoff[r] + m;
+    if (op == 0) dst[i] = 0.0;
+    else dst[i] += src[i];
 }
 
 // ------------------------------------------------------------------ host
-static void ensure_krylov(ibdl_plan p, int nrhs, int m) {
-    Krylov& k = p->kr;
-    if (k.cap_rhs >= nrhs && k.cap_m >= m) return;
-    const int M = p->M;
-    const int nblk = (M + GCHUNK - 1) / GCHUNK;
-    const int nbmax = std::max(nblk, (M + FIN_BLOCK - 1) / FIN_BLOCK);
-    nrhs = std::max(nrhs, k.cap_rhs);
-    m = std::max(m, k.cap_m);
-    auto A = [&](size_t n) { return reinterpret_cast<double*>(dev_alloc(p, n * sizeof(double))); };
-    k.V = A((size_t)nrhs * (m + 1) * M);
-    k.H = A((size_t)nrhs * m * (m + 1));
-    k.cs = A((size_t)nrhs * m);
-    k.sn = A((size_t)nrhs * m);
-    k.g = A((size_t)nrhs * (m + 1));
-    k.y = A((size_t)nrhs * m);
-    k.partial = A((size_t)nrhs * nbmax * (m + 2) * 2);
-    k.hcol = A((size_t)nrhs * (m + 2));
-    k.bnorm = A(nrhs);
-    k.resid = A(nrhs);
-    k.tolv = A(nrhs);
-    k.b = A((size_t)nrhs * M);
-    k.r = A((size_t)nrhs * M);
-    k.rr = A((size_t)nrhs * M);
-    k.d = A((size_t)nrhs * M);
-    k.state = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * 4 * sizeof(int32_t)));
-    k.skip = reinterpret_cast<int32_t*>(dev_alloc(p, (size_t)nrhs * sizeof(int32_t)));
+void free_krylov(KWork& k) {
+    for (void* p : k.mem) (void)hipFree(p);
+    k.mem.clear();
     if (k.host_pinned) (void)hipHostFree(k.host_pinned);
     k.host_pinned = nullptr;
-    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)nrhs * 64 + 64));
-    k.cap_rhs = nrhs;
+    k.cap_m = 0;
+    k.R = 0;
+    k.layout.clear();
+}
+
+static void ensure_krylov(KrylovSet& ks, int m) {
+    KWork& k = ks.w;
+    std::vector<std::pair<ibdl_plan, int>> layout;
+    for (const Inst& in : ks.inst) layout.emplace_back(in.p, in.nrhs);
+    if (k.cap_m >= m && layout == k.layout) return;
+    m = std::max(m, k.layout == layout ? k.cap_m : 0);
+    free_krylov(k);
+    const int R = ks.R;
+    size_t vtot = 0, xtot = 0;
+    int maxM = 1;
+    std::vector<int32_t> Mr(R);
+    std::vector<size_t> voff(R), xoff(R);
+    for (const Inst& in : ks.inst)
+        for (int q = 0; q < in.nrhs; ++q) {
+            const int r = in.r0 + q;
+            Mr[r] = in.p->M;
+            voff[r] = vtot;
+            xoff[r] = xtot;
+            vtot += (size_t)(m + 1) * in.p->M;
+            xtot += (size_t)in.p->M;
+            maxM = std::max(maxM, in.p->M);
+        }
+    const int nblk = (maxM + GT - 1) / GT;
+    auto A = [&](size_t n) { return reinterpret_cast<double*>(dev_alloc(k.mem, std::max<size_t>(n, 1) * 8)); };
+    k.V = A(vtot);
+    k.H = A((size_t)R * m * (m + 1));
+    k.cs = A((size_t)R * m);
+    k.sn = A((size_t)R * m);
+    k.g = A((size_t)R * (m + 1));
+    k.y = A((size_t)R * m);
+    k.partial = A((size_t)R * nblk * (m + 2) * 2);
+    k.hcol = A((size_t)R * (m + 2));
+    k.bnorm = A(R);
+    k.resid = A(R);
+    k.tolv = A(R);
+    k.nrm = A(R);
+    k.b = A(xtot);
+    k.x = A(xtot);
+    k.r = A(xtot);
+    k.rr = A(xtot);
+    k.d = A(xtot);
+    k.state = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * 4 * sizeof(int32_t)));
+    k.skip = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
+    k.Mr = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
+    k.voff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
+    k.xoff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
+    IBDL_HIP_TRY(hipMemcpy(k.Mr, Mr.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
+    IBDL_HIP_TRY(hipMemcpy(k.voff, voff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
+    IBDL_HIP_TRY(hipMemcpy(k.xoff, xoff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
+    // host staging: tolerances, skip flags, state, residuals, norms
+    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)R * 48 + 64));
     k.cap_m = m;
+    k.R = R;
     k.nblk = nblk;
+    k.hvoff = voff;
+    k.hxoff = xoff;
+    k.layout = layout;
 }
 
-void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out,
-                    size_t ostride, hipStream_t st);
-
-// r = b - A x for every rhs (operator in FP64 when fp64, else the plan's precision)
-static void residual(ibdl_plan p, int nrhs, const double* b, const double* x, double* r,
-                     hipStream_t st, bool fp64) {
-    // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
-    PipeIn in;
-    in.q_dip = x;
-    in.c_dip = 1.0;
-    PipeOut out;
-    out.out = r;
-    out.cA = 1.0;
-    out.in = x;
-    out.cB = p->bc == IBDL_DIRICHLET ? -0.5 : 0.5;
-    out.in2 = b;
-    out.cC = 1.0;
-    run_pipeline(p, nrhs, in, out, st, fp64);
-}
-
-// host copies of per-rhs norms: sqrt of the summed block partials of k_sumsq
-static void norms(ibdl_plan p, int nrhs, const double* x, hipStream_t st, std::vector<double>& out) {
-    Krylov& k = p->kr;
-    const size_t pstride = (size_t)k.nblk;
-    hipLaunchKernelGGL(k_sumsq, dim3(k.nblk, nrhs), dim3(GT), 0, st, x, (size_t)p->M, p->M, k.partial,
-                       pstride);
-    std::vector<double> hp((size_t)nrhs * pstride);
-    IBDL_HIP_TRY(hipMemcpyAsync(hp.data(), k.partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    IBDL_HIP_TRY(hipStreamSynchronize(st));
-    out.assign(nrhs, 0.0);
-    for (int r = 0; r < nrhs; ++r) {
-        double s = 0.0;
-        for (int b = 0; b < k.nblk; ++b) s += hp[(size_t)r * pstride + b];
-        out[r] = std::sqrt(s);
-    }
-}
-
-struct KrylovResult {
-    std::vector<int> iters, status;
-    std::vector<double> est;
-};
-
-// Restarted GMRES on A x = b with the operator in the plan's precision, for every
-// rhs not marked in skip.  x holds the initial iterate (x_zero: it is set to 0).
-// tol[r] is relative to ||b_r||.  Iterations add to res.iters.
-static void krylov(ibdl_plan p, int nrhs, const double* b, double* x, bool x_zero,
-                   const std::vector<double>& tol, int m, int maxit, const std::vector<int>& skip,
-                   hipStream_t st, KrylovResult& res) {
-    const int M = p->M;
-    Krylov& k = p->kr;
-    const int nblk = k.nblk;
+static KArgs kargs(KrylovSet& ks, int m) {
+    KWork& k = ks.w;
     KArgs a{};
-    a.V = k.V;
-    a.vstride = (size_t)(m + 1) * M;
-    a.M = M;
+    a.R = ks.R;
     a.m = m;
-    a.nblk = nblk;
-    a.nblk_dots = (M + FIN_BLOCK - 1) / FIN_BLOCK;
+    a.Mr = k.Mr;
+    a.voff = k.voff;
+    a.xoff = k.xoff;
+    a.V = k.V;
     a.part = k.partial;
-    a.pstride = (size_t)std::max(nblk, a.nblk_dots) * (m + 2);
-    a.part2 = k.partial + (size_t)nrhs * a.pstride;
+    a.pstride = (size_t)k.nblk * (m + 2);
+    a.part2 = k.partial + (size_t)ks.R * a.pstride;
     a.hcol = k.hcol;
     a.H = k.H;
     a.cs = k.cs;
@@ -407,262 +373,522 @@ static void krylov(ibdl_plan p, int nrhs, const double* b, double* x, bool x_zer
     a.y = k.y;
     a.bnorm = k.bnorm;
     a.resid = k.resid;
-    a.state = k.state;
+    a.nrm = k.nrm;
     a.tolv = k.tolv;
-    const dim3 vg(nblk, nrhs);
-    const size_t tot = (size_t)nrhs * M;
+    a.state = k.state;
+    a.skip = k.skip;
+    return a;
+}
 
-    // per-rhs tolerances and skip flags
-    double* hbuf = reinterpret_cast<double*>(k.host_pinned);
-    int32_t* hint = reinterpret_cast<int32_t*>(hbuf + nrhs);
-    for (int r = 0; r < nrhs; ++r) {
-        hbuf[r] = tol[r];
-        hint[r] = skip[r];
+// host staging slices
+struct Staging {
+    double* tol;
+    int32_t* skip;
+    int32_t* state;
+    double* resid;
+    double* nrm;
+};
+static Staging staging(KWork& k, int R) {
+    char* base = reinterpret_cast<char*>(k.host_pinned);
+    Staging s;
+    s.tol = reinterpret_cast<double*>(base);
+    s.resid = s.tol + R;
+    s.nrm = s.resid + R;
+    s.state = reinterpret_cast<int32_t*>(s.nrm + R);
+    s.skip = s.state + 4 * R;
+    return s;
+}
+
+GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, const JobMaker& make, bool fp64,
+                            hipStream_t st) {
+    std::map<std::tuple<int, int, int>, std::vector<PassJob>> groups;
+    for (size_t i : which) {
+        const Inst& in = ks.inst[i];
+        const int pr = (fp64 || in.p->prec == IBDL_PREC_FP64) ? 0 : 1;
+        groups[std::make_tuple(in.p->dim, in.p->n, pr)].push_back(make(i));
     }
-    IBDL_HIP_TRY(hipMemcpyAsync(k.tolv, hbuf, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
-    IBDL_HIP_TRY(hipMemcpyAsync(k.skip, hint, nrhs * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GroupedPass gp;
+    for (auto& kv : groups) {
+        auto pp = prepare_pass(kv.second, fp64);
+        pp->upload(*ks.arena, st);
+        gp.parts.push_back(std::move(pp));
+    }
+    return gp;
+}
 
-    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, b, (size_t)M, M, k.partial, a.pstride);
-    hipLaunchKernelGGL(k_set_bnorm, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.partial, a.pstride, nblk,
-                       k.bnorm, k.state, k.skip, nrhs);
+static std::vector<size_t> all_of(const KrylovSet& ks) {
+    std::vector<size_t> w(ks.inst.size());
+    for (size_t i = 0; i < w.size(); ++i) w[i] = i;
+    return w;
+}
+
+// ------------------------------------------------------------------ solve task
+SolveTask::SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st)
+    : ks_(ks), io_(std::move(io)), o_(o), st_(st) {
+    m_ = o.restart;
+    R_ = ks.R;
+    IBDL_HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+}
+
+SolveTask::~SolveTask() {
+    if (ev_) (void)hipEventDestroy(ev_);
+}
+
+bool SolveTask::ready() {
+    if (phase_ == DONE) return true;
+    const hipError_t e = hipEventQuery(ev_);
+    if (e == hipSuccess) return true;
+    if (e == hipErrorNotReady) return false;
+    (void)hipGetLastError();
+    throw Error{IBDL_ERR_HIP, std::string("device work of a solve failed: ") + hipGetErrorString(e)};
+}
+
+void SolveTask::wait() {
+    if (phase_ != DONE) IBDL_HIP_TRY(hipEventSynchronize(ev_));
+}
+
+void SolveTask::run_to_end() {
+    while (!done()) {
+        wait();
+        advance();
+    }
+}
+
+void SolveTask::mark() {
+    IBDL_HIP_TRY(hipGetLastError());
+    IBDL_HIP_TRY(hipEventRecord(ev_, st_));
+}
+
+// r = b - A x for every instance (operator in FP64 when fp64, else the plans' precision)
+void SolveTask::residual(const double* b, const double* x, double* r, bool fp64) {
+    KWork& k = ks_.w;
+    auto make = [&](size_t i) {
+        // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
+        const Inst& in = ks_.inst[i];
+        const size_t off = k.hxoff[in.r0];
+        PipeIn pi;
+        pi.q_dip = x + off;
+        pi.c_dip = 1.0;
+        PipeOut po;
+        po.out = r + off;
+        po.cA = 1.0;
+        po.in = x + off;
+        po.cB = in.p->bc == IBDL_DIRICHLET ? -0.5 : 0.5;
+        po.in2 = b + off;
+        po.cC = 1.0;
+        return PassJob{in.p, in.nrhs, pi, po};
+    };
+    prepare_grouped(ks_, all_of(ks_), make, fp64, st_).run(0, st_);
+}
+
+// per-rhs 2-norms of a pool into the host staging area (read after the next wait point)
+void SolveTask::norms_async(const double* pool) {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    Staging hs = staging(k, R_);
+    hipLaunchKernelGGL(k_sumsq, dim3(k.nblk, R_), dim3(GT), 0, st_, a, pool);
+    hipLaunchKernelGGL(k_norms, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.nrm, k.nrm, R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+}
+
+// Restarted GMRES on A x = b (pool vectors) with each plan's operator in its own
+// precision, for every rhs not marked in skip_, to the tolerances tol_ (relative
+// to ||b_r||); x_zero: start from x = 0, else from the iterate in x.
+void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    const dim3 vg(k.nblk, R_);
+    Staging hs = staging(k, R_);
+    kb_ = b;
+    kx_ = x;
+    kmaxit_ = maxit;
+    ktotal_ = kj_ = klast_ = 0;
+    for (int r = 0; r < R_; ++r) {
+        hs.tol[r] = tol_[r];
+        hs.skip[r] = skip_[r];
+    }
+    IBDL_HIP_TRY(hipMemcpyAsync(k.tolv, hs.tol, R_ * sizeof(double), hipMemcpyHostToDevice, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(k.skip, hs.skip, R_ * sizeof(int32_t), hipMemcpyHostToDevice, st_));
+    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, b);
+    hipLaunchKernelGGL(k_set_bnorm, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
     const double* r0 = b;
     if (x_zero) {
-        hipLaunchKernelGGL(k_fill0_masked, vg, dim3(GT), 0, st, x, (size_t)M, M, k.skip);
+        hipLaunchKernelGGL(k_pool_op, vg, dim3(GT), 0, st_, a, 0, x, (const double*)nullptr);
     } else {
-        residual(p, nrhs, b, x, k.r, st, false);
+        residual(b, x, k.r, false);
         r0 = k.r;
     }
-    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, r0, (size_t)M, M, k.partial, a.pstride);
-    hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, r0, (size_t)M, a);
+    hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, r0);
+    hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st_, a, r0);
 
-    int32_t* hstate = reinterpret_cast<int32_t*>(hbuf + 2 * nrhs);
-    double* hres_p = hbuf + 4 * nrhs;
-    auto all_done = [&]() {
-        IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, st));
-        IBDL_HIP_TRY(hipMemcpyAsync(hres_p, k.resid, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-        IBDL_HIP_TRY(hipStreamSynchronize(st));
-        for (int r = 0; r < nrhs; ++r)
-            if (!hstate[4 * r + ST_DONE]) return false;
-        return true;
+    // the operator step of an Arnoldi iteration, prepared once: the iteration
+    // index selects the basis vectors on the device
+    auto make = [&](size_t i) {
+        const Inst& in = ks_.inst[i];
+        const int M = in.p->M;
+        const size_t vb = k.hvoff[in.r0];
+        const size_t vs = (size_t)(k.cap_m + 1) * M;
+        PipeIn pi;
+        pi.q_dip = k.V + vb;
+        pi.c_dip = 1.0;
+        pi.q_stride = vs;
+        pi.q_jstride = M;
+        pi.skip = k.state + 4 * in.r0;
+        PipeOut po;
+        po.out = k.V + vb + M;
+        po.out_stride = vs;
+        po.out_jstride = M;
+        po.cA = -1.0;
+        po.in = k.V + vb;
+        po.in_stride = vs;
+        po.in_jstride = M;
+        po.cB = in.p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
+        po.dots_V = k.V + vb;
+        po.dots_vstride = vs;
+        po.dots_nv = 1;
+        po.dots = a.part + (size_t)in.r0 * a.pstride;
+        po.dots_rhs = a.pstride;
+        po.dots_stride = m_ + 2;
+        return PassJob{in.p, in.nrhs, pi, po};
     };
-    // Arnoldi step j for every rhs still running (kernels skip finished ones)
-    auto iteration = [&](int j) {
-        PipeIn in;
-        in.q_dip = k.V + (size_t)j * M;
-        in.c_dip = 1.0;
-        in.q_stride = a.vstride;
-        in.skip = k.state;
-        PipeOut o;
-        o.out = k.V + (size_t)(j + 1) * M;
-        o.out_stride = a.vstride;
-        o.cA = -1.0;
-        o.in = k.V + (size_t)j * M;
-        o.in_stride = a.vstride;
-        o.cB = p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
-        o.dots_V = k.V;
-        o.dots_vstride = a.vstride;
-        o.dots_nv = j + 1;
-        o.dots = a.part;
-        o.dots_rhs = a.pstride;
-        o.dots_stride = m + 2;
-        run_pipeline(p, nrhs, in, o, st);
-        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 0);
-        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st, a, j, 1);
-        hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st, a, j);
-    };
-    // how many steps to queue before looking at the state again: the steps the
-    // slowest rhs needs at its observed rate of residual reduction (1..8)
-    auto next_chunk = [&](int done_steps, const std::vector<double>& prev) {
-        int need = 3;
-        if (done_steps > 0) {
-            need = 1;
-            for (int r = 0; r < nrhs; ++r) {
-                if (hstate[4 * r + ST_DONE]) continue;
-                const double now = hres_p[r], before = prev[r];
-                int nr = 8;
-                if (now > 0.0 && before > now) {
-                    const double rate = std::pow(now / before, 1.0 / done_steps);
-                    if (rate < 1.0) nr = (int)std::ceil(std::log(tol[r] / now) / std::log(rate));
-                }
-                need = std::max(need, std::min(std::max(nr, 1), 8));
-            }
-        }
-        return need;
-    };
+    op_ = prepare_grouped(ks_, all_of(ks_), make, false, st_);
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+    mark();
+    phase_ = ITER;
+}
 
-    int total = 0;
-    bool finished = all_done();
-    while (!finished) {
-        int j = 0;
-        int last = 0;
-        std::vector<double> prev(hres_p, hres_p + nrhs);
-        bool stop = false;
-        while (j < m) {
-            const int chunk = std::min({next_chunk(last, prev), m - j, maxit - total});
-            prev.assign(hres_p, hres_p + nrhs);
-            for (int t = 0; t < chunk; ++t) iteration(j + t);
-            j += chunk;
-            total += chunk;
-            last = chunk;
-            if (all_done() || total >= maxit) {
-                stop = true;
-                break;
-            }
-        }
-        hipLaunchKernelGGL(k_backsolve, dim3((nrhs + 63) / 64), dim3(64), 0, st, a, nrhs);
-        hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st, a, x, (size_t)M);
-        hipLaunchKernelGGL(k_reset_j, dim3((nrhs + 63) / 64), dim3(64), 0, st, k.state, nrhs);
-        if (stop) break;
-        // restart the rhs still running from their current iterate
-        residual(p, nrhs, b, x, k.r, st, false);
-        hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st, k.r, (size_t)M, M, k.partial, a.pstride);
-        hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st, k.r, (size_t)M, a);
-        finished = all_done();
-    }
-    IBDL_HIP_TRY(hipGetLastError());
-    std::vector<double> hres(nrhs);
-    IBDL_HIP_TRY(hipMemcpyAsync(hres.data(), k.resid, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    IBDL_HIP_TRY(hipMemcpyAsync(hstate, k.state, (size_t)nrhs * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    IBDL_HIP_TRY(hipStreamSynchronize(st));
-    for (int r = 0; r < nrhs; ++r) {
-        if (skip[r]) continue;
-        res.iters[r] += hstate[4 * r + ST_ITERS];
-        res.est[r] = hres[r];
-        int s = hstate[4 * r + ST_STATUS];
-        if (s == IBDL_OK && !(hres[r] <= tol[r])) s = IBDL_ERR_NOCONV;
-        res.status[r] = s;
+void SolveTask::kend() {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    Staging hs = staging(k, R_);
+    const dim3 sg((R_ + 63) / 64);
+    hipLaunchKernelGGL(k_backsolve, sg, dim3(64), 0, st_, a);
+    hipLaunchKernelGGL(k_update_x, dim3(k.nblk, R_), dim3(GT), 0, st_, a, kx_);
+    hipLaunchKernelGGL(k_reset_j, sg, dim3(64), 0, st_, a);
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    mark();
+    phase_ = KEND;
+}
+
+void SolveTask::collect() {
+    Staging hs = staging(ks_.w, R_);
+    for (int r = 0; r < R_; ++r) {
+        if (skip_[r]) continue;
+        iters_[r] += hs.state[4 * r + ST_ITERS];
+        est_[r] = hs.resid[r];
+        int s = hs.state[4 * r + ST_STATUS];
+        if (s == IBDL_OK && !(hs.resid[r] <= tol_[r])) s = IBDL_ERR_NOCONV;
+        status_[r] = s;
     }
 }
 
-__global__ void k_axpy_masked(double* x, const double* d, size_t stride, int M, const int32_t* skip) {
-    const int rhs = blockIdx.y;
-    if (skip[rhs]) return;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (size_t)M) x[(size_t)rhs * stride + i] += d[(size_t)rhs * stride + i];
+// FP64 residual of the mixed instances, for the next refinement decision
+void SolveTask::refine_check() {
+    KWork& k = ks_.w;
+    residual(k.b, k.x, k.rr, true);
+    norms_async(k.rr);
+    mark();
+    phase_ = REFINE;
 }
 
-void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
-                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall) {
-    const int M = p->M;
-    const int m = o.restart;
-    ensure_krylov(p, nrhs, m);
-    Krylov& k = p->kr;
-    const size_t tot = (size_t)nrhs * M;
+void SolveTask::true_check() {
+    bool any = false;
+    for (int r = 0; r < R_; ++r) any |= truer_[r] < 0.0;
+    if (o_.true_residual && any) {
+        KWork& k = ks_.w;
+        residual(k.b, k.x, k.rr, true);
+        norms_async(k.rr);
+        mark();
+        phase_ = TRUE_RES;
+    } else {
+        output();
+    }
+}
 
-    // right-hand side b in FP64 (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~))
-    {
-        PipeIn in;
-        PipeOut out;
-        out.out = k.b;
-        if (p->bc == IBDL_DIRICHLET) {
-            if (g) {
-                in.grid = g;
-                in.c_grid = 1.0;
-                out.cA = -1.0;
-                out.in = data;
-                out.cB = 1.0;
-                run_pipeline(p, nrhs, in, out, st, true);
-            } else {
-                hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, k.b, data, tot);
+void SolveTask::output() {
+    KWork& k = ks_.w;
+    const size_t NI = ks_.inst.size();
+    std::vector<size_t> grid;
+    for (size_t i = 0; i < NI; ++i) {
+        const Inst& in = ks_.inst[i];
+        IBDL_HIP_TRY(hipMemcpyAsync(io_.sol[i], k.x + k.hxoff[in.r0], (size_t)in.nrhs * in.p->M * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st_));
+        if (i < io_.u.size() && io_.u[i]) grid.push_back(i);
+    }
+    if (!grid.empty()) {
+        // the grid solution (FP64): u = L^-1 (g~ - S~ Q) or L^-1 (g~ - S~ U_b - S V_b)
+        auto make = [&](size_t i) {
+            const Inst& in = ks_.inst[i];
+            PipeIn pi;
+            pi.q_dip = k.x + k.hxoff[in.r0];
+            pi.c_dip = -1.0;
+            if (in.p->bc == IBDL_NEUMANN) {
+                pi.q_mono = io_.vb[i];
+                pi.c_mono = -1.0;
             }
-        } else {
-            in.q_mono = data;
-            in.c_mono = 1.0;
-            if (g) {
-                in.grid = g;
-                in.c_grid = -1.0;
-            }
-            out.cA = 1.0;
-            run_pipeline(p, nrhs, in, out, st, true);
+            pi.grid = io_.g[i];
+            pi.c_grid = 1.0;
+            PipeOut po;
+            po.u = io_.u[i];
+            return PassJob{in.p, in.nrhs, pi, po};
+        };
+        prepare_grouped(ks_, grid, make, true, st_).run(0, st_);
+    }
+    mark();
+    phase_ = OUT;
+}
+
+void SolveTask::advance() {
+    KWork& k = ks_.w;
+    switch (phase_) {
+    case BEGIN: {
+        arena_reset(*ks_.arena);
+        ensure_krylov(ks_, m_);
+        const size_t NI = ks_.inst.size();
+        iters_.assign(R_, 0);
+        status_.assign(R_, IBDL_OK);
+        est_.assign(R_, 0.0);
+        tol_.assign(R_, o_.tol);
+        skip_.assign(R_, 0);
+        truer_.assign(R_, -1.0);
+        fp64_.assign(R_, 0);
+        any_mixed_ = false;
+        for (const Inst& in : ks_.inst) any_mixed_ |= in.p->prec == IBDL_PREC_MIXED;
+        refining_ = false;
+        round_ = 0;
+        auto bytes_of = [&](const Inst& in) { return (size_t)in.nrhs * in.p->M * sizeof(double); };
+        // right-hand sides in FP64 (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~));
+        // Dirichlet instances without forcing need no pass: b = U_b
+        std::vector<size_t> need_pass;
+        for (size_t i = 0; i < NI; ++i) {
+            const Inst& in = ks_.inst[i];
+            if (in.p->bc == IBDL_DIRICHLET && !io_.g[i])
+                IBDL_HIP_TRY(hipMemcpyAsync(k.b + k.hxoff[in.r0], io_.data[i], bytes_of(in), hipMemcpyDeviceToDevice,
+                                            st_));
+            else
+                need_pass.push_back(i);
         }
-    }
-    std::vector<double> bn;
-    norms(p, nrhs, k.b, st, bn);
-
-    KrylovResult res;
-    res.iters.assign(nrhs, 0);
-    res.status.assign(nrhs, IBDL_OK);
-    res.est.assign(nrhs, 0.0);
-    std::vector<double> tol(nrhs, o.tol);
-    std::vector<int> skip(nrhs, 0);
-    std::vector<double> truer(nrhs, -1.0);
-    std::vector<int> fp64_applies(nrhs, 0);
-
-    if (o.x0) {
-        hipLaunchKernelGGL(k_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, sol, o.x0, tot);
-    }
-    krylov(p, nrhs, k.b, sol, o.x0 == nullptr, tol, m, o.maxit, skip, st, res);
-
-    if (p->prec == IBDL_PREC_MIXED) {
-        // FP64 iterative refinement: r = b - A x with the FP64 operator, correct
-        // with the FP32-operator Krylov solve of A d = r, x += d.
-        for (int round = 0; round < 5; ++round) {
-            residual(p, nrhs, k.b, sol, k.rr, st, true);
-            std::vector<double> rn;
-            norms(p, nrhs, k.rr, st, rn);
-            bool all = true;
-            for (int r = 0; r < nrhs; ++r) {
-                fp64_applies[r] += skip[r] ? 0 : 1;
-                const double rel = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
-                if (!skip[r]) {
-                    truer[r] = rel;
-                    res.est[r] = rel;
-                }
-                if (!std::isfinite(rel)) {
-                    res.status[r] = IBDL_ERR_NUMERIC;
-                    skip[r] = 1;
-                } else if (rel <= o.tol || res.status[r] == IBDL_ERR_NUMERIC) {
-                    if (res.status[r] == IBDL_ERR_NOCONV) res.status[r] = IBDL_OK;
-                    skip[r] = 1;
+        if (!need_pass.empty()) {
+            auto make = [&](size_t i) {
+                const Inst& in = ks_.inst[i];
+                PipeIn pi;
+                PipeOut po;
+                po.out = k.b + k.hxoff[in.r0];
+                if (in.p->bc == IBDL_DIRICHLET) {
+                    pi.grid = io_.g[i];
+                    pi.c_grid = 1.0;
+                    po.cA = -1.0;
+                    po.in = io_.data[i];
+                    po.cB = 1.0;
                 } else {
-                    all = false;
-                    // reduce the correction's residual to the target, no further than the FP32 floor
-                    tol[r] = std::max(o.tol * bn[r] / rn[r], 1e-6);
+                    pi.q_mono = io_.data[i];
+                    pi.c_mono = 1.0;
+                    if (io_.g[i]) {
+                        pi.grid = io_.g[i];
+                        pi.c_grid = -1.0;
+                    }
+                    po.cA = 1.0;
+                }
+                return PassJob{in.p, in.nrhs, pi, po};
+            };
+            prepare_grouped(ks_, need_pass, make, true, st_).run(0, st_);
+        }
+        bool any_x0 = false;
+        for (size_t i = 0; i < io_.x0.size(); ++i) any_x0 |= io_.x0[i] != nullptr;
+        if (any_x0) {
+            for (size_t i = 0; i < NI; ++i) {
+                const Inst& in = ks_.inst[i];
+                double* dst = k.x + k.hxoff[in.r0];
+                if (i < io_.x0.size() && io_.x0[i])
+                    IBDL_HIP_TRY(hipMemcpyAsync(dst, io_.x0[i], bytes_of(in), hipMemcpyDeviceToDevice, st_));
+                else
+                    IBDL_HIP_TRY(hipMemsetAsync(dst, 0, bytes_of(in), st_));
+            }
+        }
+        x_zero_ = !any_x0;
+        norms_async(k.b);
+        mark();
+        phase_ = RHS_NORM;
+        return;
+    }
+    case RHS_NORM: {
+        Staging hs = staging(k, R_);
+        bn_.assign(hs.nrm, hs.nrm + R_);
+        kstart(k.b, k.x, x_zero_, o_.maxit);
+        return;
+    }
+    case ITER: {
+        Staging hs = staging(k, R_);
+        bool all = true;
+        for (int r = 0; r < R_ && all; ++r) all = hs.state[4 * r + ST_DONE] != 0;
+        if (all || ktotal_ >= kmaxit_) {
+            kend();
+            return;
+        }
+        KArgs a = kargs(ks_, m_);
+        const dim3 vg(k.nblk, R_);
+        if (kj_ >= m_) {
+            // restart the rhs still running from their current iterate
+            const dim3 sg((R_ + 63) / 64);
+            hipLaunchKernelGGL(k_backsolve, sg, dim3(64), 0, st_, a);
+            hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st_, a, kx_);
+            hipLaunchKernelGGL(k_reset_j, sg, dim3(64), 0, st_, a);
+            residual(kb_, kx_, k.r, false);
+            hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, k.r);
+            hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st_, a, k.r);
+            kj_ = 0;
+            klast_ = 0;
+        } else {
+            // steps to queue before looking at the state again: what the slowest
+            // rhs needs at its observed rate of residual reduction (1..8)
+            int need = 3;
+            if (klast_ > 0) {
+                need = 1;
+                for (int r = 0; r < R_; ++r) {
+                    if (hs.state[4 * r + ST_DONE]) continue;
+                    const double now = hs.resid[r], before = prev_[r];
+                    int nr = 8;
+                    if (now > 0.0 && before > now) {
+                        const double rate = std::pow(now / before, 1.0 / klast_);
+                        if (rate < 1.0) nr = (int)std::ceil(std::log(tol_[r] / now) / std::log(rate));
+                    }
+                    need = std::max(need, std::min(std::max(nr, 1), 8));
                 }
             }
-            if (all || round == 4) {
-                for (int r = 0; r < nrhs; ++r)
-                    if (!(truer[r] <= o.tol) && res.status[r] == IBDL_OK) res.status[r] = IBDL_ERR_NOCONV;
-                break;
+            const int chunk = std::min({need, m_ - kj_, kmaxit_ - ktotal_});
+            prev_.assign(hs.resid, hs.resid + R_);
+            for (int t = 0; t < chunk; ++t) {
+                const int j = kj_ + t;
+                op_.run(j, st_);
+                hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j, 0);
+                hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j, 1);
+                hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st_, a, j);
             }
-            int used = 0;
-            for (int r = 0; r < nrhs; ++r) used = std::max(used, res.iters[r]);
-            const int left = o.maxit - used;
-            if (left <= 0) {
-                for (int r = 0; r < nrhs; ++r)
-                    if (!skip[r]) res.status[r] = IBDL_ERR_NOCONV;
-                break;
-            }
-            krylov(p, nrhs, k.rr, k.d, true, tol, m, left, skip, st, res);
-            hipLaunchKernelGGL(k_axpy_masked, dim3((M + 255) / 256, nrhs), dim3(256), 0, st, sol, k.d,
-                               (size_t)M, M, k.skip);
+            kj_ += chunk;
+            ktotal_ += chunk;
+            klast_ = chunk;
         }
-    } else if (o.true_residual) {
-        residual(p, nrhs, k.b, sol, k.rr, st, true);
-        std::vector<double> rn;
-        norms(p, nrhs, k.rr, st, rn);
-        for (int r = 0; r < nrhs; ++r) {
-            truer[r] = bn[r] > 0.0 ? rn[r] / bn[r] : 0.0;
-            fp64_applies[r] = 1;
-        }
+        IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+        IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+        mark();
+        return;
     }
-    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    case KEND: {
+        collect();
+        if (refining_) {
+            KArgs a = kargs(ks_, m_);
+            hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
+            ++round_;
+            refine_check();
+        } else if (any_mixed_) {
+            // FP64 iterative refinement of the mixed instances: r = b - A x with the
+            // FP64 operator, correct with the FP32-operator solve of A d = r, x += d
+            for (const Inst& in : ks_.inst)
+                if (in.p->prec != IBDL_PREC_MIXED)
+                    for (int q = 0; q < in.nrhs; ++q) skip_[in.r0 + q] = 1;
+            refining_ = true;
+            round_ = 0;
+            refine_check();
+        } else {
+            true_check();
+        }
+        return;
+    }
+    case REFINE: {
+        Staging hs = staging(k, R_);
+        bool all = true;
+        for (int r = 0; r < R_; ++r) {
+            if (skip_[r]) continue;
+            fp64_[r] += 1;
+            const double rn = hs.nrm[r];
+            const double rel = bn_[r] > 0.0 ? rn / bn_[r] : 0.0;
+            truer_[r] = rel;
+            est_[r] = rel;
+            if (!std::isfinite(rel)) {
+                status_[r] = IBDL_ERR_NUMERIC;
+                skip_[r] = 1;
+            } else if (rel <= o_.tol || status_[r] == IBDL_ERR_NUMERIC) {
+                if (status_[r] == IBDL_ERR_NOCONV) status_[r] = IBDL_OK;
+                skip_[r] = 1;
+            } else {
+                all = false;
+                // reduce the correction's residual to the target, no further than the FP32 floor
+                tol_[r] = std::max(o_.tol * bn_[r] / rn, 1e-6);
+            }
+        }
+        if (all) {
+            true_check();
+            return;
+        }
+        int used = 0;
+        for (int r = 0; r < R_; ++r)
+            if (!skip_[r]) used = std::max(used, iters_[r]);
+        const int left = o_.maxit - used;
+        if (round_ >= 4 || left <= 0) {
+            for (int r = 0; r < R_; ++r)
+                if (!skip_[r] && status_[r] != IBDL_ERR_NUMERIC) status_[r] = IBDL_ERR_NOCONV;
+            true_check();
+            return;
+        }
+        kstart(k.rr, k.d, true, left);
+        return;
+    }
+    case TRUE_RES: {
+        Staging hs = staging(k, R_);
+        for (int r = 0; r < R_; ++r)
+            if (truer_[r] < 0.0) {
+                truer_[r] = bn_[r] > 0.0 ? hs.nrm[r] / bn_[r] : 0.0;
+                fp64_[r] += 1;
+            }
+        output();
+        return;
+    }
+    case OUT:
+        phase_ = DONE;
+        return;
+    case DONE:
+        return;
+    }
+}
 
+int SolveTask::total_iters() const {
+    int t = 0;
+    for (int v : iters_) t += v;
+    return t;
+}
+
+void SolveTask::results(ibdl_solve_info* info, int* overall) const {
     int worst = IBDL_OK;
-    for (int r = 0; r < nrhs; ++r) {
-        const int s = res.status[r];
+    for (int r = 0; r < R_; ++r) {
+        const int s = status_[r];
         if (info) {
-            info[r].iters = res.iters[r];
-            info[r].rel_resid_est = res.est[r];
-            info[r].rel_resid_true = truer[r];
+            info[r].iters = iters_[r];
+            info[r].rel_resid_est = est_[r];
+            info[r].rel_resid_true = truer_[r];
             info[r].status = s;
-            info[r].fp64_applies = fp64_applies[r];
+            info[r].fp64_applies = fp64_[r];
         }
         if (s == IBDL_ERR_NUMERIC) worst = IBDL_ERR_NUMERIC;
         else if (s == IBDL_ERR_NOCONV && worst == IBDL_OK) worst = IBDL_ERR_NOCONV;
     }
-    *overall = worst;
+    if (overall) *overall = worst;
+}
+
+void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std::vector<const double*>& g,
+               const std::vector<const double*>& x0, const ibdl_solve_opts& o, const std::vector<double*>& sol,
+               ibdl_solve_info* info, hipStream_t st, int* overall) {
+    // nothing queued earlier reads argument tables any more once the stream is idle
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    SolveIO io;
+    io.data = data;
+    io.g = g;
+    io.x0 = x0;
+    io.sol = sol;
+    SolveTask t(ks, std::move(io), o, st);
+    t.run_to_end();
+    t.results(info, overall);
 }
 
 }  // namespace ibdl

@@ -702,10 +702,10 @@ struct StageTable {
     int blocks() const { return start.back(); }
     bool multi() const { return njobs() > 1; }
     Jobs<A> jobs() const { return Jobs<A>{dargs, dstart, njobs()}; }
-    void upload(JobRing& ring, hipStream_t st) {
+    void upload(Arena& ar, hipStream_t st) {
         if (!multi()) return;
-        dargs = reinterpret_cast<const A*>(ring_put(ring, args.data(), args.size() * sizeof(A), st));
-        dstart = reinterpret_cast<const int*>(ring_put(ring, start.data(), start.size() * sizeof(int), st));
+        dargs = reinterpret_cast<const A*>(arena_put(ar, args.data(), args.size() * sizeof(A), st));
+        dstart = reinterpret_cast<const int*>(arena_put(ar, start.data(), start.size() * sizeof(int), st));
     }
 };
 
@@ -775,11 +775,11 @@ struct PreparedT : PreparedPass {
     StageTable<RowInvArgs<R>> ri;
     StageTable<FinishArgs> fi;
 
-    void upload(JobRing& ring, hipStream_t st) override {
-        rf.upload(ring, st);
-        for (auto& c : col) c.upload(ring, st);
-        ri.upload(ring, st);
-        fi.upload(ring, st);
+    void upload(Arena& ar, hipStream_t st) override {
+        rf.upload(ar, st);
+        for (auto& c : col) c.upload(ar, st);
+        ri.upload(ar, st);
+        fi.upload(ar, st);
     }
     template <class T, class F>
     static void go(const StageTable<T>& tb, F&& f) {

@@ -30,33 +30,90 @@ struct Workspace {
     void* part = nullptr;       // [cap][M][4^(dim-1)] gather partial sums
 };
 
-struct Krylov {
-    int cap_rhs = 0, cap_m = 0, nblk = 0;
-    double* V = nullptr;        // [rhs][m+1][M]
-    double* H = nullptr;        // [rhs][m+1][m]  (column-major by j: H[j*(m+1) + i])
-    double* cs = nullptr;       // [rhs][m]
-    double* sn = nullptr;       // [rhs][m]
-    double* g = nullptr;        // [rhs][m+1]
-    double* y = nullptr;        // [rhs][m]
-    double* partial = nullptr;  // [rhs][nblk][m+2]
-    double* hcol = nullptr;     // [rhs][m+2]
-    double* bnorm = nullptr;    // [rhs]
-    double* resid = nullptr;    // [rhs]
-    double* tolv = nullptr;     // [rhs]
-    int32_t* state = nullptr;   // [rhs][4]: done flag, iterations, status, j
-    int32_t* skip = nullptr;    // [rhs]
-    double* b = nullptr;        // [rhs][M] right-hand side
-    double* r = nullptr;        // [rhs][M] restart residual
-    double* rr = nullptr;       // [rhs][M] refinement residual
-    double* d = nullptr;        // [rhs][M] refinement correction
-    void* host_pinned = nullptr;
+// Staging of per-job argument tables: pinned host blocks with device twins.
+// Space is handed out in order and only reclaimed by arena_reset, which the
+// caller issues when nothing queued on the stream still reads the tables.
+struct Arena {
+    struct Block {
+        char* host = nullptr;
+        char* dev = nullptr;
+        size_t cap = 0;
+    };
+    std::vector<Block> blocks;
+    int cur = 0;
+    size_t pos = 0;
+};
+void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st);
+void arena_reset(Arena& a);
+void arena_free(Arena& a);
+
+// One instance of a Krylov set: a plan and its right-hand sides r0 .. r0+nrhs-1.
+struct Inst {
+    ibdl_plan p = nullptr;
+    int nrhs = 0;
+    int r0 = 0;
 };
 
-struct JobRing {
-    char* host = nullptr;
-    char* dev = nullptr;
-    size_t cap = 0, pos = 0;
-    std::vector<void*>* owner = nullptr;
+// Device state of restarted GMRES for R right-hand sides of possibly different
+// lengths: rhs r has M_r unknowns, basis block voff[r] in V (cap_m+1 vectors),
+// vectors xoff[r] in the pools b, x, r, rr, d.
+struct KWork {
+    int cap_m = 0, R = 0, nblk = 0;
+    std::vector<std::pair<ibdl_plan, int>> layout;  // (plan, nrhs) per instance
+    double* V = nullptr;
+    double* H = nullptr;        // [R][m][m+1] (column j at j*(m+1))
+    double* cs = nullptr;       // [R][m]
+    double* sn = nullptr;
+    double* g = nullptr;        // [R][m+1]
+    double* y = nullptr;        // [R][m]
+    double* partial = nullptr;  // two banks of [R][nblk][m+2]
+    double* hcol = nullptr;     // [R][m+2]
+    double* bnorm = nullptr;    // [R]
+    double* resid = nullptr;    // [R]
+    double* tolv = nullptr;     // [R]
+    double* nrm = nullptr;      // [R] norms handed to the host
+    int32_t* state = nullptr;   // [R][4]: done flag, iterations, status, j
+    int32_t* skip = nullptr;    // [R]
+    int32_t* Mr = nullptr;      // [R]
+    size_t* voff = nullptr;     // [R]
+    size_t* xoff = nullptr;     // [R]
+    double* b = nullptr;        // pools: right-hand side, iterate, restart residual,
+    double* x = nullptr;        // refinement residual and correction
+    double* r = nullptr;
+    double* rr = nullptr;
+    double* d = nullptr;
+    void* host_pinned = nullptr;
+    std::vector<size_t> hvoff, hxoff;
+    std::vector<void*> mem;
+};
+void free_krylov(KWork& k);
+
+// Stage timing: a ring of event sets, one set per pass through the grid; each
+// stage kernel records a start and a stop event in its own dispatch.
+struct Timing {
+    static constexpr int RING = 64;
+    static constexpr int MAXST = 8;
+    int enabled = 0;
+    int events_made = 0;
+    int ring_pos = 0, cur_set = -1;
+    hipEvent_t ev[RING][2 * MAXST] = {};
+    const char* set_names[RING][MAXST] = {};
+    int set_used[RING] = {};
+    const char* acc_names[16] = {};
+    double acc_ms[16] = {};
+    long long acc_n[16] = {};
+    int n_acc = 0;
+};
+void timing_reset(Timing& t, int enable);
+void timing_free(Timing& t);
+// mean ms and call count per stage name since the last reset
+int timing_read(Timing& t, double* ms, const char** names, int64_t* calls, int cap);
+
+struct KrylovSet {
+    std::vector<Inst> inst;
+    int R = 0;
+    KWork w;
+    Arena* arena = nullptr;
 };
 
 }  // namespace ibdl
@@ -103,25 +160,22 @@ struct ibdl_plan_s {
     float* s2_32 = nullptr;
 
     ibdl::Workspace ws;
-    ibdl::Krylov kr;
+    ibdl::KrylovSet ks;     // Krylov state of solves through this plan alone
+    ibdl::Arena arena;
 
-    // stage timing: a ring of event sets, one set per pass through the grid; each
-    // stage kernel records a start and a stop event in its own dispatch
-    static constexpr int RING = 64;
-    static constexpr int MAXST = 8;
-    int timing = 0;
-    int events_made = 0;
-    int ring_pos = 0, cur_set = -1;
-    hipEvent_t ev[RING][2 * MAXST] = {};
-    const char* set_names[RING][MAXST] = {};
-    int set_used[RING] = {};
-    const char* acc_names[16] = {};
-    double acc_ms[16] = {};
-    long long acc_n[16] = {};
-    int n_acc = 0;
+    // stage timing (the plan's own record, or one shared by the plans of a batch)
+    ibdl::Timing own_timing;
+    ibdl::Timing* tm = &own_timing;
 
     std::vector<void*> allocs;  // everything to free
-    ibdl::JobRing ring;
+};
+
+// Many independent instances solved together (one plan per instance).
+struct ibdl_batch_s {
+    std::vector<ibdl_plan> plans;
+    ibdl::KrylovSet ks;
+    ibdl::Arena arena;
+    ibdl::Timing timing;
 };
 
 namespace ibdl {
@@ -177,7 +231,7 @@ struct PassJob {
 // precision; run() launches every stage once for all jobs.
 struct PreparedPass {
     virtual ~PreparedPass() {}
-    virtual void upload(JobRing& ring, hipStream_t st) = 0;  // only needed for several jobs
+    virtual void upload(Arena& arena, hipStream_t st) = 0;  // only needed for several jobs
     virtual void run(int it, hipStream_t st) = 0;            // it: iteration index
 };
 std::unique_ptr<PreparedPass> prepare_f64(const std::vector<PassJob>& jobs);
@@ -186,13 +240,15 @@ std::unique_ptr<PreparedPass> prepare_f32(const std::vector<PassJob>& jobs);
 std::unique_ptr<PreparedPass> prepare_pass(const std::vector<PassJob>& jobs, bool fp64);
 void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, hipStream_t st,
                   bool fp64 = false);
-// staging area for argument tables: pinned host copy, device copy, wraps after a stream sync
-void* ring_put(JobRing& r, const void* src, size_t bytes, hipStream_t st);
 int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
-void gmres_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
-                 double* sol, ibdl_solve_info* info, hipStream_t st, int* overall);
+// GMRES (with FP64 refinement for mixed plans) for every instance of the set:
+// per instance i the data, forcing (or null), initial iterate (or null) and
+// solution buffers, [nrhs_i][M_i] / [nrhs_i][n^d].  info: host [R].
+void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std::vector<const double*>& g,
+               const std::vector<const double*>& x0, const ibdl_solve_opts& o, const std::vector<double*>& sol,
+               ibdl_solve_info* info, hipStream_t st, int* overall);
 
 // timing helpers used by the pipeline: events to pass to the stage's launch
 // (both null when timing is off); stage 0 opens a new event set

@@ -578,7 +578,14 @@ void ensure_workspace(ibdl_plan p, int nrhs) {
     // sized for FP64: mixed plans run their once-per-solve passes in FP64
     const size_t cs = 16;
     const size_t rs = 8;
-    // grow: the old buffers stay owned by the plan until it is destroyed
+    // grow: hipFree waits for the device to finish work that may still use the old buffers
+    for (void* old : {p->ws.spec, p->ws.part}) {
+        if (!old) continue;
+        p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), old), p->allocs.end());
+        (void)hipFree(old);
+    }
+    p->ws.spec = p->ws.part = nullptr;
+    p->ws.cap_rhs = 0;
     p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
     p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);
     p->ws.cap_rhs = nrhs;

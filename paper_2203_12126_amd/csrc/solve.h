@@ -1,0 +1,82 @@
+// A solve of a Krylov set (one or more plans with their right-hand sides) as a
+// resumable sequence of device work: the right-hand side, restarted GMRES, FP64
+// refinement of mixed plans, optional true residuals, the solution copy-out and
+// optionally the grid solution.  advance() does the host logic for the last
+// wait point and enqueues the work up to the next one; ready() polls that wait
+// point without blocking, so a scheduler can interleave many tasks on their own
+// streams.
+#pragma once
+#include <functional>
+#include <memory>
+#include <vector>
+
+#include "plan.h"
+
+namespace ibdl {
+
+// per-instance device buffers of a solve
+struct SolveIO {
+    std::vector<const double*> data, g, x0;   // x0 entries may be null
+    std::vector<double*> sol;
+    std::vector<double*> u;                   // grid solutions (empty or null entries: none)
+    std::vector<const double*> vb;            // Neumann V_b for the grid solution
+};
+
+// A grid pass over chosen instances of a set, one prepared pass per
+// (dimension, grid size, precision) group.
+using JobMaker = std::function<PassJob(size_t)>;
+struct GroupedPass {
+    std::vector<std::unique_ptr<PreparedPass>> parts;
+    void run(int it, hipStream_t st) {
+        for (auto& p : parts) p->run(it, st);
+    }
+};
+GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, const JobMaker& make, bool fp64,
+                            hipStream_t st);
+
+class SolveTask {
+public:
+    SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st);
+    ~SolveTask();
+    bool done() const { return phase_ == DONE; }
+    bool ready();          // the last wait point has been reached (non-blocking)
+    void wait();           // block until it has
+    void advance();        // requires ready(); enqueues the next stretch of work
+    void run_to_end();     // wait/advance until done
+    // per-rhs results (host [R]) and the worst status
+    void results(ibdl_solve_info* info, int* overall) const;
+    int total_iters() const;
+
+private:
+    enum Phase { BEGIN, RHS_NORM, ITER, KEND, REFINE, TRUE_RES, OUT, DONE };
+    void mark();                                  // record the wait point
+    void kstart(const double* b, double* x, bool x_zero, int maxit);
+    void kend();
+    void collect();
+    void refine_check();
+    void true_check();
+    void output();
+    void residual(const double* b, const double* x, double* r, bool fp64);
+    void norms_async(const double* pool);
+
+    KrylovSet& ks_;
+    SolveIO io_;
+    ibdl_solve_opts o_;
+    hipStream_t st_;
+    hipEvent_t ev_ = nullptr;
+    Phase phase_ = BEGIN;
+    int m_ = 0, R_ = 0;
+    // current Krylov run
+    const double* kb_ = nullptr;
+    double* kx_ = nullptr;
+    int kmaxit_ = 0, ktotal_ = 0, kj_ = 0, klast_ = 0;
+    std::vector<double> prev_;
+    GroupedPass op_;
+    // solve state
+    bool any_mixed_ = false, refining_ = false, x_zero_ = true;
+    int round_ = 0;
+    std::vector<double> bn_, tol_, est_, truer_;
+    std::vector<int> skip_, iters_, status_, fp64_;
+};
+
+}  // namespace ibdl

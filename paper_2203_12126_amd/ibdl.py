@@ -81,6 +81,15 @@ def lib():
         "ibdl_plan_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
         "ibdl_plan_get_stats": ([P, ctypes.POINTER(PlanStats)], st),
         "ibdl_last_error": ([], ctypes.c_char_p),
+        "ibdl_batch_create": ([ctypes.POINTER(Desc), I, P, P, ctypes.POINTER(P)], st),
+        "ibdl_batch_destroy": ([P], st),
+        "ibdl_batch_size": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], st),
+        "ibdl_batch_apply": ([P, P, P, P], st),
+        "ibdl_batch_get_stats": ([P, I, ctypes.POINTER(PlanStats)], st),
+        "ibdl_batch_solve": ([P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P], st),
+        "ibdl_batch_eval_grid": ([P, P, P, P, P, P], st),
+        "ibdl_batch_set_timing": ([P, I], st),
+        "ibdl_batch_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -246,6 +255,137 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ibdl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _info_dicts(info):
+    return [dict(iters=i.iters, rel_resid_est=i.rel_resid_est, rel_resid_true=i.rel_resid_true,
+                 status=i.status, fp64_applies=i.fp64_applies) for i in info]
+
+
+def _ptr_array(tensors, name, sizes, allow_none=False):
+    """Host array of device pointers, one per instance (None entries -> NULL)."""
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        if t is None:
+            if not allow_none:
+                raise ValueError(f"{name}[{i}] is required")
+            arr[i] = None
+        else:
+            arr[i] = _dptr(t, f"{name}[{i}]", sizes[i] if sizes is not None else None).value
+    return arr
+
+
+class Batch:
+    """Many independent instances solved together (``ibdl_batch``).
+
+    ``instances``: list of dicts with keys dim, n, lo, length, alpha, X, normal,
+    weight (float64 CUDA tensors), bc, prec, nrhs and optionally delta."""
+
+    def __init__(self, instances, stream=None):
+        import torch
+        self._torch = torch
+        keep = []
+        descs = (Desc * len(instances))()
+        nrhs = (ctypes.c_int32 * len(instances))()
+        self.meta = []
+        for i, ins in enumerate(instances):
+            X, nrm, w = (ins[k].contiguous() for k in ("X", "normal", "weight"))
+            keep += [X, nrm, w]
+            m = int(w.numel())
+            dim, n = ins["dim"], ins["n"]
+            _dptr(X, "X", m * dim)
+            _dptr(nrm, "normal", m * dim)
+            _dptr(w, "weight", m)
+            descs[i] = make_desc(dim, n, ins.get("lo", (0.0, 0.0, 0.0)), ins.get("length", 1.0),
+                                 ins["alpha"], ins.get("bc", DIRICHLET), ins.get("delta", PESKIN4),
+                                 ins.get("prec", MIXED), m, X, nrm, w)
+            nrhs[i] = int(ins["nrhs"])
+            self.meta.append(dict(dim=dim, n=n, m=m, nrhs=int(ins["nrhs"]), bc=ins.get("bc", DIRICHLET)))
+        h = ctypes.c_void_p()
+        _check(lib().ibdl_batch_create(descs, len(instances), nrhs, _stream(stream), ctypes.byref(h)),
+               "ibdl_batch_create")
+        self._h = h
+        self.count = len(instances)
+        self.total_rhs = sum(mt["nrhs"] for mt in self.meta)
+
+    @classmethod
+    def from_problems(cls, items, prec=MIXED, delta=PESKIN4, device="cuda"):
+        """items: list of (Problem, nrhs); geometry, grid, alpha and bc come from the Problem."""
+        import torch
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
+        inst = []
+        for prob, nrhs in items:
+            g = prob.grid
+            inst.append(dict(dim=g.dim, n=g.n, lo=tuple(g.lo), length=g.length, alpha=prob.alpha,
+                             X=t(prob.geom.X), normal=t(prob.geom.normal), weight=t(prob.geom.weight),
+                             bc=prob.bc, prec=prec, delta=delta, nrhs=nrhs))
+        return cls(inst)
+
+    def _sizes(self, grid=False):
+        return [mt["nrhs"] * (mt["n"] ** mt["dim"] if grid else mt["m"]) for mt in self.meta]
+
+    def _empty_like_sizes(self, grid=False):
+        out = []
+        for mt in self.meta:
+            shape = (mt["nrhs"], *([mt["n"]] * mt["dim"])) if grid else (mt["nrhs"], mt["m"])
+            out.append(self._torch.empty(*shape, dtype=self._torch.float64, device="cuda"))
+        return out
+
+    def apply(self, q, out=None, stream=None):
+        out = self._empty_like_sizes() if out is None else out
+        _check(lib().ibdl_batch_apply(self._h, _ptr_array(q, "q", self._sizes()),
+                                      _ptr_array(out, "Aq", self._sizes()), _stream(stream)),
+               "ibdl_batch_apply")
+        return out
+
+    def solve(self, data, g=None, tol=1e-8, restart=50, maxit=500, true_residual=False, out=None,
+              stream=None, raise_on_noconv=True):
+        out = self._empty_like_sizes() if out is None else out
+        o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
+        info = (SolveInfo * self.total_rhs)()
+        garr = None if g is None else _ptr_array(g, "g", self._sizes(grid=True), allow_none=True)
+        st = lib().ibdl_batch_solve(self._h, _ptr_array(data, "data", self._sizes()), garr, ctypes.byref(o),
+                                    _ptr_array(out, "sol", self._sizes()), info, _stream(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            _check(st, "ibdl_batch_solve")
+        return out, _info_dicts(info)
+
+    def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
+        out = self._empty_like_sizes(grid=True) if out is None else out
+        vbarr = None if vb is None else _ptr_array(vb, "vb", self._sizes(), allow_none=True)
+        garr = None if g is None else _ptr_array(g, "g", self._sizes(grid=True), allow_none=True)
+        _check(lib().ibdl_batch_eval_grid(self._h, _ptr_array(sol, "sol", self._sizes()), vbarr, garr,
+                                          _ptr_array(out, "u", self._sizes(grid=True)), _stream(stream)),
+               "ibdl_batch_eval_grid")
+        return out
+
+    def stats(self, i) -> dict:
+        s = PlanStats()
+        _check(lib().ibdl_batch_get_stats(self._h, i, ctypes.byref(s)), "ibdl_batch_get_stats")
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
+    def set_timing(self, on=True):
+        _check(lib().ibdl_batch_set_timing(self._h, 1 if on else 0), "ibdl_batch_set_timing")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 16)()
+        calls = (ctypes.c_int64 * 16)()
+        cnt = ctypes.c_int32()
+        _check(lib().ibdl_batch_stage_times(self._h, ms, names, calls, 16, ctypes.byref(cnt)),
+               "ibdl_batch_stage_times")
+        return [(names[i].decode(), ms[i], calls[i]) for i in range(cnt.value)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ibdl_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

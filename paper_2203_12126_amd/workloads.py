@@ -312,6 +312,24 @@ def sol_random_fourier(dim: int, seed: int, kmax: int = 4, length: float = 1.0) 
     return Solution(u, grad, lap)
 
 
+def random_fourier_grid_2d(seed: int, grid: "Grid", kmax: int = 4):
+    """u and Lap u of sol_random_fourier(2, seed, kmax, grid.length) at the grid
+    nodes, by separable evaluation: u[iy, ix] = Re sum_ab C_ab e^{i kx_a x} e^{i ky_b y}
+    with C = a - i b (same draws as sol_random_fourier)."""
+    rng = np.random.default_rng(seed)
+    K = 2 * kmax + 1
+    a = rng.standard_normal(K * K).reshape(K, K)
+    b = rng.standard_normal(K * K).reshape(K, K)
+    kk = 2 * np.pi * np.arange(-kmax, kmax + 1) / grid.length
+    C = a - 1j * b
+    Ex = np.exp(1j * np.outer(grid.axis_coords(0), kk))     # (n, K): [ix, mx]
+    Ey = np.exp(1j * np.outer(grid.axis_coords(1), kk))     # (n, K): [iy, my]
+    k2 = kk[:, None] ** 2 + kk[None, :] ** 2
+    u = np.real(Ey @ C.T @ Ex.T)
+    lap = np.real(Ey @ (-(k2 * C)).T @ Ex.T)
+    return u, lap
+
+
 # ----------------------------------------------------------------------------
 # problems
 # ----------------------------------------------------------------------------
@@ -418,14 +436,30 @@ def config_batch(count: int = 512, seed: int = 12126, sizes=(128, 192, 256, 384,
     return out
 
 
-def batch_instance(spec: dict):
-    """Materialise one batch instance: (grid, geom, alpha, bc, [Problem per rhs])."""
+def batch_instance(spec: dict, fast: bool = True):
+    """Materialise one batch instance: (grid, geom, alpha, bc, [Problem per rhs]).
+    fast: grid forcing by separable evaluation (same values as make_problem up
+    to rounding)."""
     grid = Grid(2, spec["n"], (0.0, 0.0), 1.0)
     geom = ellipse((0.5, 0.5), spec["a"], spec["b"], spec["rot"], spec["m"])
     probs = []
+    inside = None
     for r in range(spec["nrhs"]):
         sol = sol_random_fourier(2, spec["seed"] + r)
-        probs.append(make_problem(grid, geom, spec["alpha"], spec["bc"], sol))
+        if not fast:
+            probs.append(make_problem(grid, geom, spec["alpha"], spec["bc"], sol))
+            continue
+        if inside is None:
+            pts = np.stack([c.ravel() for c in grid.nodes()], axis=1)
+            inside = geom.inside(pts).reshape(grid.n, grid.n)
+        u, lap = random_fourier_grid_2d(spec["seed"] + r, grid)
+        g = np.where(inside, lap - spec["alpha"] * u, 0.0)
+        if spec["bc"] == DIRICHLET:
+            data = sol.u(geom.X)
+        else:
+            data = np.sum(sol.grad(geom.X) * geom.normal, axis=1)
+        probs.append(Problem(grid, geom, spec["alpha"], spec["bc"], np.ascontiguousarray(data),
+                             np.ascontiguousarray(g), sol, f"batch_n{grid.n}"))
     return grid, geom, probs
 
 
