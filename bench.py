@@ -15,6 +15,13 @@ of both against the FP64 oracle, the roofline of the dominant kernel (timed with
 HIP events on the library's stream) and the oracle's own throughput on the
 host.
 
+With --workload serve the line reports the served stream instead: 2000
+requests (80% 2-D, 20% 3-D, sizes 256^2..2048^2 and 64^3..256^3, alpha
+log-uniform in [1, 1000], mixed precision, grid solution included) cycling
+through a set of materialised request templates; first the saturation
+throughput with a bounded number of requests outstanding, then seeded Poisson
+arrivals at 0.5x and 0.8x of it, with p50/p99 of submission-to-result latency.
+
 With --workload batch512 a step is one batched solve of the 512-instance
 ellipse batch (grid sizes 128..512, 2..8 right-hand sides each, Dirichlet and
 Neumann, alpha log-uniform in [1, 1000], mixed precision) followed by the grid
@@ -22,7 +29,7 @@ solutions of every instance; the roofline is that of one batched operator
 application over all instances.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs R]
-                       [--workload star1024|sphere256|batch512]
+                       [--workload star1024|sphere256|batch512|serve]
 """
 import argparse
 import json
@@ -205,6 +212,115 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args):
+    import torch
+    from paper_2203_12126_amd import ibdl
+    from paper_2203_12126_amd import workloads as W
+
+    count = args.serve_requests
+    specs = W.config_serve(count=count)
+    ntpl = min(args.serve_templates, count)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    tpl = []
+    for sp in specs[:ntpl]:
+        p = W.serve_instance(sp)
+        g = p.grid
+        tpl.append(dict(dim=g.dim, n=g.n, lo=tuple(g.lo), length=g.length, alpha=p.alpha, bc=p.bc,
+                        X=t(p.geom.X), normal=t(p.geom.normal), weight=t(p.geom.weight),
+                        data=t(p.data).reshape(1, -1), g=t(p.g_tilde).reshape(1, -1), m=p.geom.m))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    srv = ibdl.Server(max_slots=64, streams=4)
+
+    def submit(i):
+        q = tpl[i % ntpl]
+        return srv.submit(q["dim"], q["n"], q["lo"], q["length"], q["alpha"], q["X"], q["normal"], q["weight"],
+                          q["data"], q["g"], bc=q["bc"], prec=ibdl.MIXED, tol=1e-8, grid=True)
+
+    # warm-up: every template once
+    for tk in [submit(i) for i in range(ntpl)]:
+        srv.wait(tk)
+
+    def closed_loop(n, window):
+        out, live, i = [], [], 0
+        c0 = time.perf_counter()
+        while i < n or live:
+            while i < n and len(live) < window:
+                live.append(submit(i))
+                i += 1
+            keep = []
+            for tk in live:
+                r = srv.poll(tk)
+                if r is None:
+                    keep.append(tk)
+                else:
+                    out.append(r)
+            live = keep
+            if live:
+                time.sleep(0.0002)
+        return out, time.perf_counter() - c0
+
+    def open_loop(n, qps, cap=512):
+        out, live = [], []
+        arr = np.array([s["arrival"] for s in specs[:n]]) / qps
+        c0 = time.perf_counter()
+        i = 0
+        while i < n or live:
+            now = time.perf_counter() - c0
+            while i < n and arr[i] <= now and len(live) < cap:
+                live.append(submit(i))
+                i += 1
+            keep = []
+            for tk in live:
+                r = srv.poll(tk)
+                if r is None:
+                    keep.append(tk)
+                else:
+                    out.append(r)
+            live = keep
+            time.sleep(0.0002)
+        return out, time.perf_counter() - c0
+
+    sat_res, sat_el = closed_loop(count, args.serve_window)
+    sat = count / sat_el
+    runs = {}
+    for f in (0.5, 0.8):
+        res, el = open_loop(count, f * sat)
+        lat = np.array([r["times"]["total_ms"] for r in res])
+        runs[f"{f}x"] = {"qps": round(f * sat, 2), "solves_per_s": round(len(res) / el, 2),
+                         "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                         "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                         "queue_ms_p50": round(float(np.percentile([r["times"]["queue_ms"] for r in res], 50)), 3),
+                         "mean_cohort": round(float(np.mean([r["times"]["cohort_size"] for r in res])), 2),
+                         "bad_status": int(sum(r["status"] != 0 for r in res))}
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["times"]["total_ms"] for r in sat_res])
+    iters = sum(r["info"][0]["iters"] for r in sat_res)
+    line = {
+        "metric": METRIC, "value": round(sat, 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": count, "warmup": ntpl, "ms_per_step": round(sat_el / count * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 grid + f64 krylov", "data": "synthetic",
+        "config": {"workload": "serve", "requests": count, "templates": ntpl, "window": args.serve_window,
+                   "description": "served stream: 80% 2-D (256^2..2048^2, circle/star, 1k..16k points, D/N), "
+                                  "20% 3-D (64^3..256^3, sphere/ellipsoid, 5k..40k points), alpha logU[1,1000], "
+                                  "tol 1e-8, grid solution included", "precision": "mixed"},
+        "saturation": {"solves_per_s": round(sat, 2), "applies_per_s": round(iters / sat_el, 1),
+                       "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                       "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)},
+        "open_loop": runs,
+        "server": {"peak_active": st["peak_active"], "cohorts": st["cohorts"],
+                   "peak_in_use_GB": round(st["peak_in_use_bytes"] / 1e9, 3),
+                   "budget_GB": round(st["budget_bytes"] / 1e9, 1)},
+        "setup_s": round(t_gen, 2),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +329,9 @@ def main():
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--workload", default="star1024")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-templates", type=int, default=48)
+    ap.add_argument("--serve-window", type=int, default=64)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration runs)")
     args = ap.parse_args()
@@ -227,6 +346,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch512":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     probs, desc, tol = make_workload(args.workload, args.nrhs)
     p0 = probs[0]

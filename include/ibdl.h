@@ -41,6 +41,7 @@ extern "C" {
 
 typedef struct ibdl_plan_s* ibdl_plan;
 typedef struct ibdl_batch_s* ibdl_batch;
+typedef struct ibdl_server_s* ibdl_server;
 
 typedef enum {
     IBDL_OK = 0,
@@ -234,6 +235,71 @@ ibdl_status ibdl_batch_eval_grid(ibdl_batch batch, const double* const* sol, con
 ibdl_status ibdl_batch_set_timing(ibdl_batch batch, int32_t enable);
 ibdl_status ibdl_batch_stage_times(ibdl_batch batch, double* ms_host, const char** names,
                                    int64_t* calls, int32_t cap, int32_t* count);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a worker thread admits solve requests (any dimension, grid size,
+ * geometry, boundary condition, precision) first come first served while the
+ * sum of the admitted requests' footprints (ibdl_server_footprint) stays within
+ * the memory budget and fewer than max_slots are on the device.  Requests
+ * admitted at the same scheduling step form a cohort whose solve runs as one
+ * batched task on one of the server's streams; cohorts on different streams
+ * overlap on the device, and new requests are admitted while others run.
+ * Each request gets its own plan (built on admission), device Krylov state and
+ * results; these are the same as ibdl_solve + ibdl_eval_grid through a plan of
+ * its own (bit-identical: a right-hand side's arithmetic does not depend on its
+ * cohort).  Entry points may be called from any host thread.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double queue_ms;       /* submission -> admission                                  */
+    double run_ms;         /* admission -> results complete on the device              */
+    double total_ms;       /* submission -> results complete                           */
+    int32_t cohort_size;   /* requests admitted together with this one (itself included) */
+} ibdl_request_times;
+
+typedef struct {
+    int64_t submitted, completed, cohorts;
+    int32_t pending, active, peak_active;
+    size_t in_use_bytes, peak_in_use_bytes, budget_bytes;
+} ibdl_server_stats;
+
+/* Start a server on the current device.  hbm_budget_bytes: admission budget
+ * (0: 90% of the device memory free now; more than is free: IBDL_ERR_OOM);
+ * max_slots >= 1: requests on the device at once; streams in 1..16: cohorts in
+ * flight at once. */
+ibdl_status ibdl_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t streams, ibdl_server* out);
+
+/* Wait for every submitted request to finish, stop the worker, free the server. */
+ibdl_status ibdl_server_destroy(ibdl_server server);
+
+/* Bytes a request is charged at admission: ibdl_plan_footprint plus its share of
+ * its cohort's argument tables (host-only). */
+ibdl_status ibdl_server_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart, size_t* bytes);
+
+/* Queue a solve (non-blocking): the right-hand side, GMRES (Sec. 5.3) with FP64
+ * refinement for MIXED, and, when u is not NULL, the grid solution (Sec. 4.1).
+ * desc, data [nrhs][M], g [nrhs][n^dim] or NULL, sol [nrhs][M], u [nrhs][n^dim]
+ * or NULL: as for ibdl_plan_create / ibdl_solve / ibdl_eval_grid (Neumann
+ * requests use data as V_b for the grid solution).  The geometry, data and g are
+ * read after the work queued on `stream` so far; every buffer must stay valid
+ * until the request completes.  opts->x0 must be NULL.  Errors: IBDL_ERR_ARG,
+ * IBDL_ERR_OOM (footprint above the budget), IBDL_ERR_STATE (shutting down). */
+ibdl_status ibdl_server_submit(ibdl_server server, const ibdl_desc* desc, int32_t nrhs, const double* data,
+                               const double* g, const ibdl_solve_opts* opts, double* sol, double* u,
+                               void* stream, uint64_t* ticket);
+
+/* IBDL_ERR_STATE while the request is pending or running.  Once complete,
+ * fills info (HOST [nrhs]) and times (either may be NULL), forgets the ticket
+ * and returns the request's status (IBDL_OK, IBDL_ERR_NOCONV, IBDL_ERR_NUMERIC,
+ * or the plan construction error).  Unknown tickets: IBDL_ERR_ARG. */
+ibdl_status ibdl_server_poll(ibdl_server server, uint64_t ticket, ibdl_solve_info* info,
+                             ibdl_request_times* times);
+
+/* As ibdl_server_poll, but blocks until the request is complete. */
+ibdl_status ibdl_server_wait(ibdl_server server, uint64_t ticket, ibdl_solve_info* info,
+                             ibdl_request_times* times);
+
+ibdl_status ibdl_server_get_stats(ibdl_server server, ibdl_server_stats* out_host);
 
 /* Message for the last failing call on this host thread ("" if none). */
 const char* ibdl_last_error(void);

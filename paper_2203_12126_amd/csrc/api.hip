@@ -59,6 +59,8 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 namespace ibdl {
 
+ibdl_status set_error(int status, const std::string& msg) { return fail(status, msg); }
+
 std::unique_ptr<PreparedPass> prepare_pass(const std::vector<PassJob>& jobs, bool fp64) {
     for (const PassJob& j : jobs) ensure_workspace(j.p, j.nrhs);
     if (fp64 || jobs[0].p->prec == IBDL_PREC_FP64) return prepare_f64(jobs);
@@ -260,6 +262,7 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
 ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
     (void)hipDeviceSynchronize();
+    free_build_tmp(p);
     for (void* a : p->allocs) (void)hipFree(a);
     free_krylov(p->ks.w);
     arena_free(p->arena);
@@ -270,21 +273,33 @@ ibdl_status ibdl_plan_destroy(ibdl_plan p) {
 
 size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     if (!check_desc(d).empty() || nrhs < 1 || restart < 1) return 0;
-    const size_t n = d->n, M = d->npts, dim = d->dim;
+    const size_t n = d->n, M = d->npts, dim = d->dim, R = nrhs, m = restart;
     const size_t nlines = dim == 2 ? n : n * n;
-    const size_t P = (n / 2 + 1 + 15) / 16 * 16;
-    const size_t cs = d->prec == IBDL_PREC_FP64 ? 16 : 8;
-    const size_t npp = dim == 2 ? 32 : 160;
+    const size_t P = (size_t)std::max(tile_pitch_f64(d->n), tile_pitch_f32(d->n));
+    const size_t gpp = dim == 3 ? 16 : 4;
+    auto pow2 = [](size_t v) {
+        size_t t = 2048;
+        while (t < v) t <<= 1;
+        return t;
+    };
     size_t b = 0;
-    b += (size_t)nrhs * nlines * P * cs;                 // spectra
-    b += (size_t)nrhs * M * (dim == 3 ? 16 : 4) * 8;     // partial sums
-    const size_t nnz = M * npp;
-    size_t n2 = 2048;
-    while (n2 < nnz) n2 <<= 1;
-    b += n2 * 8 + nnz * (4 + 8 + 4 + 4 + 4);             // sorted keys, weights, scan buffers
-    if (d->bc == IBDL_NEUMANN) b += nnz / 2 * 24;
-    b += M * (4 * 6 + 12 * 12 + 8 * 4) + nlines * 24;   // geometry, taps, tables, lists
-    b += (size_t)nrhs * ((restart + 1) * M * 8 + 3 * M * 8 + (restart + 2) * (restart + 8) * 8);
+    // workspace, FP64-sized: half spectra and gather partial sums
+    b += R * nlines * P * 16 + R * M * gpp * 8;
+    // sorted geometry: key, perm, skey, invperm, cell, normals, weights, taps (FP64 + FP32)
+    b += M * (16 + 12 + 24 + 8 + 96 + 48);
+    // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
+    const size_t nd = M * (dim == 2 ? 32 : 160);
+    const size_t nm = d->bc == IBDL_NEUMANN ? M * (dim == 2 ? 16 : 64) : 0;
+    b += (nd + nm) * 24 + 2 * (nlines + 2) * 4;
+    // line and plane masks, lists, line starts, FFT and symbol tables
+    b += nlines * 18 + n * 64;
+    // construction temporaries (sort keys, scan buffers), alive together at most
+    b += M * 36 + pow2(M) * 8 + pow2(nd) * 8 + nd * 9 + pow2(nm) * 8 + nm * 9 + nlines * 12;
+    // Krylov state: basis, five pools, two banks of block partial sums, Hessenberg and rotations
+    const size_t nblk = (M + 255) / 256;
+    b += R * ((m + 1) * M * 8 + 5 * M * 8 + 2 * nblk * (m + 2) * 8 + (m * (m + 1) + 4 * m + 3 * (m + 2)) * 8 + 64);
+    // allocation granularity
+    b += 96 * 4096;
     return b;
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "../../include/ibdl.h"
@@ -167,7 +168,8 @@ struct ibdl_plan_s {
     ibdl::Timing own_timing;
     ibdl::Timing* tm = &own_timing;
 
-    std::vector<void*> allocs;  // everything to free
+    std::vector<void*> allocs;     // everything to free
+    std::vector<void*> build_tmp;  // construction temporaries
 };
 
 // Many independent instances solved together (one plan per instance).
@@ -216,6 +218,9 @@ struct PipeOut {
     double* u = nullptr;
 };
 
+// records msg as this host thread's last error and returns status
+ibdl_status set_error(int status, const std::string& msg);
+
 void* dev_alloc(std::vector<void*>& owner, size_t bytes);
 void* dev_alloc(ibdl_plan p, size_t bytes);
 void ensure_workspace(ibdl_plan p, int nrhs);
@@ -243,6 +248,7 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
 int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
+void free_build_tmp(ibdl_plan p);
 // GMRES (with FP64 refinement for mixed plans) for every instance of the set:
 // per instance i the data, forcing (or null), initial iterate (or null) and
 // solution buffers, [nrhs_i][M_i] / [nrhs_i][n^d].  info: host [R].

@@ -39,6 +39,11 @@ template <typename T>
 static T* alloc_n(ibdl_plan p, size_t n) {
     return reinterpret_cast<T*>(dev_alloc(p, n * sizeof(T)));
 }
+// construction temporaries, freed when the plan is built
+template <typename T>
+static T* tmp_n(ibdl_plan p, size_t n) {
+    return reinterpret_cast<T*>(dev_alloc(p->build_tmp, n * sizeof(T)));
+}
 
 static inline int nblocks(size_t n, int t) { return (int)((n + t - 1) / t); }
 
@@ -212,8 +217,8 @@ static void scan_excl(ibdl_plan p, const int32_t* in, int32_t* out, size_t n, hi
         hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (int32_t*)nullptr);
         return;
     }
-    int32_t* sums = alloc_n<int32_t>(p, nt);
-    int32_t* soff = alloc_n<int32_t>(p, nt);
+    int32_t* sums = tmp_n<int32_t>(p, nt);
+    int32_t* soff = tmp_n<int32_t>(p, nt);
     hipLaunchKernelGGL(k_scan_tile, dim3((int)nt), dim3(SCAN_T), 0, st, in, out, n, sums);
     scan_excl(p, sums, soff, nt, st);
     hipLaunchKernelGGL(k_scan_add, dim3(nblocks(n, 256)), dim3(256), 0, st, out, n, soff);
@@ -448,7 +453,7 @@ __global__ void k_tables(int n, double h, double* tw64, float* tw32, double* s26
 
 // ------------------------------------------------------------------ host
 static int compact(ibdl_plan p, const int32_t* flag, int n, int32_t** list, hipStream_t st) {
-    int32_t* idx = alloc_n<int32_t>(p, (size_t)n + 1);
+    int32_t* idx = tmp_n<int32_t>(p, (size_t)n + 1);
     scan_excl(p, flag, idx, (size_t)n, st);
     const int cnt = read_i32(idx + n - 1, st) + read_i32(flag + n - 1, st);
     *list = alloc_n<int32_t>(p, (size_t)std::max(cnt, 1));
@@ -462,7 +467,7 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
     const size_t nnz = (size_t)M * npp;
     if (nnz >= (size_t)INT32_MAX) throw Error{IBDL_ERR_ARG, "too many spread entries"};
     const size_t n2 = pow2_at_least(nnz, BIT_BLOCK);
-    uint64_t* keys = alloc_n<uint64_t>(p, n2);
+    uint64_t* keys = tmp_n<uint64_t>(p, n2);
     hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, (const uint32_t*)nullptr,
                        0, n2, keys);  // fill with padding
     hipLaunchKernelGGL(k_emit, dim3(nblocks(nnz, 256)), dim3(256), 0, st, p->cell, p->perm, M, dim, n,
@@ -472,8 +477,8 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
     c.k = alloc_n<uint32_t>(p, nnz);
     c.w64 = alloc_n<double>(p, nnz);
     c.w32 = alloc_n<float>(p, nnz);
-    int32_t* head = alloc_n<int32_t>(p, nnz);
-    int32_t* idx = alloc_n<int32_t>(p, nnz);
+    int32_t* head = tmp_n<int32_t>(p, nnz);
+    int32_t* idx = tmp_n<int32_t>(p, nnz);
     hipLaunchKernelGGL(k_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, p->invperm,
                        p->cell, p->taps64, p->nrm, p->wgt, dim, n, p->h, dipole ? 1 : 0, c.k, c.w64,
                        c.w32, head);
@@ -492,11 +497,11 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
 
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     const int dim = p->dim, n = p->n, M = p->M;
-    int32_t* bad = alloc_n<int32_t>(p, 4);
+    int32_t* bad = tmp_n<int32_t>(p, 4);
     IBDL_HIP_TRY(hipMemsetAsync(bad, 0, 4 * sizeof(int32_t), st));
     p->key = alloc_n<uint32_t>(p, M);
-    int32_t* cell_c = alloc_n<int32_t>(p, 3 * (size_t)M);
-    double* frac = alloc_n<double>(p, 3 * (size_t)M);
+    int32_t* cell_c = tmp_n<int32_t>(p, 3 * (size_t)M);
+    double* frac = tmp_n<double>(p, 3 * (size_t)M);
     hipLaunchKernelGGL(k_bin, dim3(nblocks(M, 256)), dim3(256), 0, st, d->X, M, dim, n, p->lo[0],
                        p->lo[1], p->lo[2], p->h, p->key, cell_c, frac, bad);
     hipLaunchKernelGGL(k_check_geom, dim3(nblocks(M, 256)), dim3(256), 0, st, d->normal, d->weight, M,
@@ -515,7 +520,7 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
 
     // stable order of (key, index)
     const size_t n2 = pow2_at_least((size_t)M, BIT_BLOCK);
-    uint64_t* comp = alloc_n<uint64_t>(p, n2);
+    uint64_t* comp = tmp_n<uint64_t>(p, n2);
     hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, p->key, M, n2, comp);
     bitonic_sort(comp, n2, st);
     p->perm = alloc_n<uint32_t>(p, M);
@@ -537,7 +542,7 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     if (p->bc == IBDL_NEUMANN) build_csr(p, p->mono, false, st);
 
     // line and plane sets
-    int32_t* flag = alloc_n<int32_t>(p, (size_t)std::max(p->nlines, n));
+    int32_t* flag = tmp_n<int32_t>(p, (size_t)std::max(p->nlines, n));
     p->spread_line_mask = alloc_n<uint8_t>(p, p->nlines);
     hipLaunchKernelGGL(k_spread_mask, dim3(nblocks(p->nlines, 256)), dim3(256), 0, st, p->dip.line_act,
                        p->nlines, p->spread_line_mask, flag);
@@ -571,6 +576,12 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
                        p->s2_64, p->s2_32);
     IBDL_HIP_TRY(hipGetLastError());
     IBDL_HIP_TRY(hipStreamSynchronize(st));
+    free_build_tmp(p);
+}
+
+void free_build_tmp(ibdl_plan p) {
+    for (void* t : p->build_tmp) (void)hipFree(t);
+    p->build_tmp.clear();
 }
 
 void ensure_workspace(ibdl_plan p, int nrhs) {

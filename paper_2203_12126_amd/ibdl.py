@@ -54,6 +54,18 @@ class SolveInfo(ctypes.Structure):
                 ("fp64_applies", ctypes.c_int32)]
 
 
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("cohort_size", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cohorts", ctypes.c_int64),
+                ("pending", ctypes.c_int32), ("active", ctypes.c_int32), ("peak_active", ctypes.c_int32),
+                ("in_use_bytes", ctypes.c_size_t), ("peak_in_use_bytes", ctypes.c_size_t),
+                ("budget_bytes", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -90,6 +102,14 @@ def lib():
         "ibdl_batch_eval_grid": ([P, P, P, P, P, P], st),
         "ibdl_batch_set_timing": ([P, I], st),
         "ibdl_batch_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
+        "ibdl_server_create": ([ctypes.c_size_t, I, I, ctypes.POINTER(P)], st),
+        "ibdl_server_destroy": ([P], st),
+        "ibdl_server_footprint": ([ctypes.POINTER(Desc), I, I, ctypes.POINTER(ctypes.c_size_t)], st),
+        "ibdl_server_submit": ([P, ctypes.POINTER(Desc), I, P, P, ctypes.POINTER(SolveOpts), P, P, P,
+                                ctypes.POINTER(ctypes.c_uint64)], st),
+        "ibdl_server_poll": ([P, ctypes.c_uint64, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)], st),
+        "ibdl_server_wait": ([P, ctypes.c_uint64, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)], st),
+        "ibdl_server_get_stats": ([P, ctypes.POINTER(ServerStats)], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -386,6 +406,97 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ibdl_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (``ibdl_server``): submit solves, poll or wait for results.
+
+    A request is a Problem-like set of tensors; the server keeps references to
+    every tensor of a request until its result has been taken."""
+
+    def __init__(self, budget_bytes=0, max_slots=64, streams=4):
+        h = ctypes.c_void_p()
+        _check(lib().ibdl_server_create(int(budget_bytes), int(max_slots), int(streams), ctypes.byref(h)),
+               "ibdl_server_create")
+        self._h = h
+        self._req = {}
+
+    @staticmethod
+    def footprint(dim, n, npts, bc=DIRICHLET, prec=MIXED, nrhs=1, restart=50) -> int:
+        d = make_desc(dim, n, (0, 0, 0), 1.0, 1.0, bc, PESKIN4, prec, npts)
+        d.X = d.normal = d.weight = 1  # placeholders: the estimate never dereferences them
+        out = ctypes.c_size_t()
+        _check(lib().ibdl_server_footprint(ctypes.byref(d), nrhs, restart, ctypes.byref(out)),
+               "ibdl_server_footprint")
+        return int(out.value)
+
+    def submit(self, dim, n, lo, length, alpha, X, normal, weight, data, g=None, bc=DIRICHLET,
+               delta=PESKIN4, prec=MIXED, tol=1e-8, restart=50, maxit=500, grid=True, true_residual=False,
+               stream=None):
+        """Queue one solve; returns a ticket.  data: (nrhs, M); g: (nrhs, n^dim) or None."""
+        import torch
+        m = int(weight.numel())
+        nrhs = data.numel() // m
+        _dptr(X, "X", m * dim)
+        _dptr(normal, "normal", m * dim)
+        _dptr(weight, "weight", m)
+        sol = torch.empty(nrhs, m, dtype=torch.float64, device="cuda")
+        u = torch.empty(nrhs, *([n] * dim), dtype=torch.float64, device="cuda") if grid else None
+        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight)
+        o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
+        t = ctypes.c_uint64()
+        _check(lib().ibdl_server_submit(self._h, ctypes.byref(d), nrhs, _dptr(data, "data", nrhs * m),
+                                        _dptr(g, "g", nrhs * n ** dim), ctypes.byref(o), _dptr(sol, "sol"),
+                                        _dptr(u, "u") if u is not None else None, _stream(stream),
+                                        ctypes.byref(t)), "ibdl_server_submit")
+        self._req[t.value] = dict(keep=(X, normal, weight, data, g), sol=sol, u=u, nrhs=nrhs)
+        return t.value
+
+    def submit_problem(self, prob, nrhs_data=None, prec=MIXED, **kw):
+        import torch
+        g = prob.grid
+        T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+        data = T(prob.data).reshape(1, -1) if nrhs_data is None else T(nrhs_data[0])
+        gt = T(prob.g_tilde).reshape(1, -1) if nrhs_data is None else T(nrhs_data[1])
+        return self.submit(g.dim, g.n, tuple(g.lo), g.length, prob.alpha, T(prob.geom.X), T(prob.geom.normal),
+                           T(prob.geom.weight), data, gt, bc=prob.bc, prec=prec, **kw)
+
+    def _result(self, fn, ticket, raise_on_error):
+        rq = self._req[ticket]
+        info = (SolveInfo * rq["nrhs"])()
+        tm = RequestTimes()
+        st = fn(self._h, ticket, info, ctypes.byref(tm))
+        if st == ERR_STATE:
+            return None
+        del self._req[ticket]
+        if st != OK and raise_on_error and st != ERR_NOCONV:
+            _check(st, "request")
+        return dict(status=st, sol=rq["sol"], u=rq["u"], info=_info_dicts(info),
+                    times=dict(queue_ms=tm.queue_ms, run_ms=tm.run_ms, total_ms=tm.total_ms,
+                               cohort_size=tm.cohort_size))
+
+    def poll(self, ticket, raise_on_error=True):
+        """None while pending, else dict(status, sol, u, info, times)."""
+        return self._result(lib().ibdl_server_poll, ticket, raise_on_error)
+
+    def wait(self, ticket, raise_on_error=True):
+        return self._result(lib().ibdl_server_wait, ticket, raise_on_error)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().ibdl_server_get_stats(self._h, ctypes.byref(s)), "ibdl_server_get_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ibdl_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

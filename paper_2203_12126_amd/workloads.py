@@ -463,6 +463,94 @@ def batch_instance(spec: dict, fast: bool = True):
     return grid, geom, probs
 
 
+SERVE_SIZES_2D = (256, 384, 512, 768, 1024, 1536, 2048)
+SERVE_SIZES_3D = (64, 96, 128, 192, 256)
+
+
+def config_serve(count: int = 2000, seed: int = 355, sizes2=SERVE_SIZES_2D, sizes3=SERVE_SIZES_3D,
+                 frac3d: float = 0.2):
+    """A stream of solve requests: 80% 2-D (circle or star 50/50, Dirichlet or
+    Neumann 50/50, M = clip(round(L / (c h)), 1000, 16000) with c ~ U(0.5, 2)),
+    20% 3-D (sphere or ellipsoid, Dirichlet, M = clip(round(A / (c h)^2), 5000,
+    40000)); alpha log-uniform in [1, 1000]; unit-rate exponential gaps between
+    arrivals (scale by 1/QPS).  Returns a list of dicts."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(count):
+        t += float(rng.exponential(1.0))
+        alpha = float(math.exp(rng.uniform(0.0, math.log(1000.0))))
+        c = float(rng.uniform(0.5, 2.0))
+        sd = int(rng.integers(0, 2**31 - 1))
+        if rng.uniform() >= frac3d:
+            n = int(rng.choice(sizes2))
+            shape = "circle" if rng.uniform() < 0.5 else "star"
+            bc = int(rng.integers(0, 2))
+            radius = float(rng.uniform(0.15, 0.35))
+            per = 2 * math.pi * radius if shape == "circle" else star_perimeter(STAR_R0, STAR_AMP, STAR_LOBES)
+            m = int(min(max(round(per / (c / n)), 1000), 16000))
+            out.append(dict(dim=2, n=n, shape=shape, radius=radius, bc=bc, alpha=alpha, m=m, c=c,
+                            seed=sd, arrival=t))
+        else:
+            n = int(rng.choice(sizes3))
+            shape = "sphere" if rng.uniform() < 0.5 else "ellipsoid"
+            axes = tuple(float(v) for v in rng.uniform(0.2, 0.35, size=3))
+            if shape == "sphere":
+                axes = (axes[0],) * 3
+            area = ellipsoid_area(axes)
+            m = int(min(max(round(area / (c / n) ** 2), 5000), 40000))
+            out.append(dict(dim=3, n=n, shape=shape, axes=axes, bc=DIRICHLET, alpha=alpha, m=m, c=c,
+                            seed=sd, arrival=t))
+    return out
+
+
+def ellipsoid_area(axes) -> float:
+    """Surface area of an ellipsoid (Knud Thomsen's formula, p = 1.6075; exact for spheres)."""
+    a, b, c = axes
+    p = 1.6075
+    return 4 * math.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3.0) ** (1.0 / p)
+
+
+def serve_instance(spec: dict) -> Problem:
+    """Materialise one request of config_serve: 2-D data from sol_random_fourier
+    (separable grid evaluation), 3-D data from exp(x+y) cos(sqrt2 z - 0.3)."""
+    n, dim = spec["n"], spec["dim"]
+    grid = Grid(dim, n, (0.0,) * dim, 1.0)
+    alpha = spec["alpha"]
+    if dim == 2:
+        if spec["shape"] == "circle":
+            geom = circle((0.5, 0.5), spec["radius"], spec["m"])
+        else:
+            geom = star((0.5, 0.5), STAR_R0, STAR_AMP, STAR_LOBES, spec["m"])
+        sol = sol_random_fourier(2, spec["seed"])
+        pts = np.stack([c.ravel() for c in grid.nodes()], axis=1)
+        inside = geom.inside(pts).reshape(n, n)
+        u, lap = random_fourier_grid_2d(spec["seed"], grid)
+        g = np.where(inside, lap - alpha * u, 0.0)
+    else:
+        if spec["shape"] == "sphere":
+            geom = fibonacci_sphere((0.5, 0.5, 0.5), spec["axes"][0], spec["m"])
+        else:
+            geom = fibonacci_ellipsoid((0.5, 0.5, 0.5), spec["axes"], spec["m"])
+        sol = sol_exp_cos3d()
+        x = grid.axis_coords(0)
+        # u = e^x e^y cos(sqrt2 z - 0.3) is harmonic: g = -alpha u inside
+        u = (np.cos(math.sqrt(2.0) * x - 0.3)[:, None, None] * np.exp(x)[None, :, None] *
+             np.exp(x)[None, None, :])
+        a, b, c = spec["axes"]
+        dz = (x - 0.5)[:, None, None] / c
+        dy = (x - 0.5)[None, :, None] / b
+        dx = (x - 0.5)[None, None, :] / a
+        inside = dx * dx + dy * dy + dz * dz < 1.0
+        g = np.where(inside, -alpha * u, 0.0)
+    if spec["bc"] == DIRICHLET:
+        data = sol.u(geom.X)
+    else:
+        data = np.sum(sol.grad(geom.X) * geom.normal, axis=1)
+    return Problem(grid, geom, alpha, spec["bc"], np.ascontiguousarray(data), np.ascontiguousarray(g), sol,
+                   f"serve{dim}d_n{n}")
+
+
 def table1_problem(n: int, c: float, k: float = 1.0) -> Problem:
     """Sec. 6.1: Lap u - u = 0 in the disc R=0.25 at the origin, U_b = sin(2 theta),
     periodic box [-1/2,1/2]^2, points equispaced with Delta s ~ c Delta x."""

@@ -25,3 +25,32 @@ def test_batch_config_recipe():
     for s in specs[:20]:
         per = W.ellipse_perimeter(s["a"], s["b"])
         assert abs(per / s["m"] - 0.75 / s["n"]) < 0.01 / s["n"]
+
+
+def test_serve_instances_match_direct_evaluation():
+    specs = W.config_serve(count=60, sizes2=(64, 96), sizes3=(16, 24))
+    two = [s for s in specs if s["dim"] == 2][:2]
+    three = [s for s in specs if s["dim"] == 3][:2]
+    assert two and three
+    for sp in two + three:
+        p = W.serve_instance(sp)
+        sol = p.sol
+        pts = np.stack([c.ravel() for c in p.grid.nodes()], axis=1)
+        g = np.where(p.geom.inside(pts), sol.lap(pts) - p.alpha * sol.u(pts), 0.0).reshape(p.g_tilde.shape)
+        assert np.max(np.abs(g - p.g_tilde)) <= 1e-11 * max(1.0, np.max(np.abs(g)))
+
+
+def test_serve_config_recipe():
+    specs = W.config_serve()
+    assert len(specs) == 2000
+    frac3 = np.mean([s["dim"] == 3 for s in specs])
+    assert 0.17 < frac3 < 0.23
+    for s in specs:
+        lo, hi = (1000, 16000) if s["dim"] == 2 else (5000, 40000)
+        assert lo <= s["m"] <= hi
+        assert 1.0 <= s["alpha"] <= 1000.0
+        if s["dim"] == 3:
+            assert s["bc"] == W.DIRICHLET
+    arr = np.array([s["arrival"] for s in specs])
+    assert np.all(np.diff(arr) > 0)
+    assert abs(np.mean(np.diff(arr)) - 1.0) < 0.1
