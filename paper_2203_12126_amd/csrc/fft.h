@@ -194,17 +194,49 @@ struct TwConst {
     static constexpr TwTab<RAD> tab = make_twtab<RAD>();
 };
 
+// Stage twiddles W^idx (W = exp(-2 pi i / NT)) from two small LDS tables:
+// lo[i] = W^i for i < 64 and hi[j] = W^(64 j), W^idx = lo[idx % 64] hi[idx / 64].
+template <typename R>
+struct Tw2 {
+    const cplx<R>* lo;
+    const cplx<R>* hi;
+    __device__ __forceinline__ cplx<R> get(int idx) const { return cmul(lo[idx & 63], hi[idx >> 6]); }
+};
+template <int NT>
+struct Tw2Size {
+    static constexpr int LO = NT < 64 ? NT : 64;
+    static constexpr int HI = (NT + 63) / 64;
+    static constexpr int ALL = LO + HI;
+};
+// fills the tables from the full table tw[0..NT) (call before a barrier)
+template <typename R, int NT, int T>
+__device__ __forceinline__ Tw2<R> load_tw2(cplx<R>* lds, const cplx<R>* __restrict__ tw) {
+    using S = Tw2Size<NT>;
+    cplx<R> v[(S::ALL + T - 1) / T];
+#pragma unroll
+    for (int u = 0; u < (S::ALL + T - 1) / T; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < S::ALL) v[u] = tw[i < S::LO ? i : 64 * (i - S::LO)];
+    }
+#pragma unroll
+    for (int u = 0; u < (S::ALL + T - 1) / T; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < S::ALL) lds[i] = v[u];
+    }
+    return Tw2<R>{lds, lds + S::LO};
+}
+
 template <int SIGN, typename R>
-__device__ __forceinline__ cplx<R> twiddle(const cplx<R>* __restrict__ tw, int idx) {
-    cplx<R> w = tw[idx];
+__device__ __forceinline__ cplx<R> twiddle(const Tw2<R>& tw, int idx) {
+    cplx<R> w = tw.get(idx);
     if (SIGN > 0) w.y = -w.y;
     return w;
 }
 
 // Length-RAD DFT in registers.  RAD = R1 * R2 with R1 a base radix:
 //   X[k1 + R1 k2] = sum_n2 W_RAD^{n2 k1} W_R2^{n2 k2} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}.
-template <int RAD, int SIGN, int NT, typename R>
-__device__ __forceinline__ void reg_dft(cplx<R>* v, const cplx<R>* __restrict__ tw) {
+template <int RAD, int SIGN, typename R>
+__device__ __forceinline__ void reg_dft(cplx<R>* v) {
     if constexpr (RAD == 2 || RAD == 3 || RAD == 4 || RAD == 8) {
         butterfly<RAD, SIGN>(v);
     } else {
@@ -230,7 +262,7 @@ __device__ __forceinline__ void reg_dft(cplx<R>* v, const cplx<R>* __restrict__ 
             cplx<R> b[R2];
 #pragma unroll
             for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
-            reg_dft<R2, SIGN, NT>(b, tw);
+            reg_dft<R2, SIGN>(b);
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
         }
@@ -253,7 +285,7 @@ struct LdsStore {
 // One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
 template <typename R, int L, int C, int TH, int NT, int SIGN, int NS, int RAD, int... REST, class LD,
           class ST>
-__device__ __forceinline__ void run_stages(cplx<R>* s, const cplx<R>* __restrict__ tw, LD ld, ST st) {
+__device__ __forceinline__ void run_stages(cplx<R>* s, const Tw2<R>& tw, LD ld, ST st) {
     constexpr int NB = L / RAD;
     constexpr int TOT = NB * C;
     constexpr int PER = (TOT + TH - 1) / TH;
@@ -271,7 +303,7 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const cplx<R>* __restrict
                 for (int r = 1; r < RAD; ++r)
                     v[b][r] = cmul(v[b][r], twiddle<SIGN>(tw, (NT / (NS * RAD)) * r * k));
             }
-            reg_dft<RAD, SIGN, NT>(v[b], tw);
+            reg_dft<RAD, SIGN>(v[b]);
         }
     }
     auto emit = [&](auto&& out) {
@@ -298,8 +330,7 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const cplx<R>* __restrict
 }
 
 template <typename R, int L, int C, int TH, int NT, int SIGN, class LD, class ST, int... Rs>
-__device__ __forceinline__ void run_fft(cplx<R>* s, const cplx<R>* __restrict__ tw, LD ld, ST st,
-                                        Radices<Rs...>) {
+__device__ __forceinline__ void run_fft(cplx<R>* s, const Tw2<R>& tw, LD ld, ST st, Radices<Rs...>) {
     run_stages<R, L, C, TH, NT, SIGN, 1, Rs...>(s, tw, ld, st);
 }
 

@@ -5,7 +5,8 @@
 // Arnoldi step j of right-hand side r:  w = A v_j (one pass of the operator, whose
 // finishing kernel also forms the block partial sums of <w, v_i>), then
 // h_ij = <w, v_i> and w -= sum_i h_ij v_i twice (classical Gram-Schmidt applied
-// twice), h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the previous Givens rotations
+// twice; the first pass also sums ||w||^2 so that h_{j+1,j} needs no further
+// reduction), v_{j+1} = w / h_{j+1,j}; the previous Givens rotations
 // are applied to column j, a new rotation zeroes h_{j+1,j}, and the rotated
 // right-hand side g gives the residual estimate |g_{j+1}|.  Every inner product is
 // a two-level block reduction in a fixed order over the rhs's own blocks, so a
@@ -28,6 +29,9 @@ __device__ __forceinline__ int imin_d(int a, int b) { return a < b ? a : b; }
 constexpr int GT = 256;  // threads per block = vector elements per block (= points per finishing block)
 
 enum { ST_DONE = 0, ST_ITERS = 1, ST_STATUS = 2, ST_J = 3 };
+
+// relative residual at which the first FP32-operator solve of a mixed instance stops
+constexpr double kMixedFirstTol = 1e-6;
 
 // Device view of the Krylov state of R right-hand sides.
 struct KArgs {
@@ -143,95 +147,144 @@ __global__ __launch_bounds__(GT) void k_init_cycle(KArgs a, const double* __rest
     }
 }
 
-// h = sum of the block partials of pass `pass`; w -= V h; then the partials of
-// the next quantity: pass 0 -> <w, v_i> again, pass 1 -> ||w||^2
-__global__ __launch_bounds__(GT) void k_orth(KArgs a, int j, int pass) {
+// First Gram-Schmidt pass of Arnoldi step j: h1 = sum of the block partials of
+// <w, v_i> (left by the operator's finishing kernel), w' = w - V h1, and the
+// block partials of <w', v_i> (i <= j) and of ||w'||^2 (slot j+1).
+__global__ __launch_bounds__(GT) void k_orth(KArgs a, int j) {
     __shared__ double hs[256];
     __shared__ double msh[(GT / 64) * 16];
     __shared__ double mout[16];
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     if (a.state[4 * r + ST_DONE] || (int)blockIdx.x >= nb) return;
-    const double* pin = (pass == 0 ? a.part : a.part2) + (size_t)r * a.pstride;
-    double* pout = (pass == 0 ? a.part2 : a.part) + (size_t)r * a.pstride;
+    const double* pin = a.part + (size_t)r * a.pstride;
+    double* pout = a.part2 + (size_t)r * a.pstride;
     for (int vi = threadIdx.x; vi <= j; vi += GT) {
         double s = 0.0;
         for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
         hs[vi] = s;
     }
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double* hc = a.hcol + (size_t)r * (a.m + 2);
-        for (int vi = 0; vi <= j; ++vi) hc[vi] = (pass == 0 ? 0.0 : hc[vi]) + hs[vi];
-    }
+    if (blockIdx.x == 0)
+        for (int vi = threadIdx.x; vi <= j; vi += GT) a.hcol[(size_t)r * (a.m + 2) + vi] = hs[vi];
     double* V = a.V + a.voff[r];
     double* w = V + (size_t)(j + 1) * M;
     const int m = blockIdx.x * GT + threadIdx.x;
     double wl = 0.0;
     if (m < M) {
+        // w -= sum_i h_i v_i in index order, loads issued 8 at a time
         double acc = w[m];
-        for (int vi = 0; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
+        int vi = 0;
+        for (; vi + 8 <= j + 1; vi += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc -= hs[vi + u] * t[u];
+        }
+        for (; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
         wl = acc;
         w[m] = acc;
     }
-    if (pass == 0) {
-        // <w, v_i> for i <= j, 16 at a time
-        for (int v0 = 0; v0 <= j; v0 += 16) {
-            const int nv = imin_d(16, j + 1 - v0);
-            double acc[16];
+    // <w', v_i> for i <= j and ||w'||^2, 16 at a time
+    const int nvt = j + 2;
+    for (int v0 = 0; v0 < nvt; v0 += 16) {
+        const int nv = imin_d(16, nvt - v0);
+        double acc[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = (u < nv && m < M) ? V[(size_t)(v0 + u) * M + m] * wl : 0.0;
-            block_multi_sum<16>(acc, nv, msh, mout);
-            if ((int)threadIdx.x < nv) pout[(size_t)blockIdx.x * (a.m + 2) + v0 + threadIdx.x] = mout[threadIdx.x];
+        for (int u = 0; u < 16; ++u) {
+            const int vi = v0 + u;
+            acc[u] = (u < nv && m < M) ? (vi <= j ? V[(size_t)vi * M + m] : wl) * wl : 0.0;
         }
-    } else {
-        double acc[1] = {wl * wl};
-        block_multi_sum<1>(acc, 1, msh, mout);
-        if (threadIdx.x == 0) pout[(size_t)blockIdx.x * (a.m + 2)] = mout[0];
+        block_multi_sum<16>(acc, nv, msh, mout);
+        if ((int)threadIdx.x < nv) pout[(size_t)blockIdx.x * (a.m + 2) + v0 + threadIdx.x] = mout[threadIdx.x];
     }
 }
 
-// v_{j+1} = w / ||w||; block 0 applies the Givens rotations and updates the state
-__global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
+// Second Gram-Schmidt pass and normalisation of Arnoldi step j: h2 = sum of the
+// partials of <w', v_i>, h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2) (= ||w' - V h2||
+// for orthonormal V), v_{j+1} = (w' - V h2) / h_{j+1,j}; block 0 applies the
+// previous Givens rotations to the column h1 + h2, forms the new one and updates
+// the residual estimate and the state.
+__global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
+    __shared__ double hs[256];
+    __shared__ double hn_s[2];
+    __shared__ double hc_s[256], cs_s[256], sn_s[256];
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     int32_t* st = a.state + 4 * r;
     if (st[ST_DONE] || (int)blockIdx.x >= nb) return;
-    const double* pin = a.part + (size_t)r * a.pstride;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2)];
-    const double hn = sqrt(s);
+    const double* pin = a.part2 + (size_t)r * a.pstride;
+    for (int vi = threadIdx.x; vi <= j + 1; vi += GT) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        hs[vi] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double q = 0.0;
+        for (int vi = 0; vi <= j; ++vi) q += hs[vi] * hs[vi];
+        const double d = hs[j + 1] - q;
+        hn_s[0] = d > 0.0 ? sqrt(d) : 0.0;
+        hn_s[1] = hs[j + 1];
+    }
+    __syncthreads();
+    const double hn = hn_s[0];
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-    double* w = a.V + a.voff[r] + (size_t)(j + 1) * M;
+    double* V = a.V + a.voff[r];
+    double* w = V + (size_t)(j + 1) * M;
     const int m = blockIdx.x * GT + threadIdx.x;
-    if (m < M) w[m] *= inv;
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (m < M) {
+        double acc = w[m];
+        int vi = 0;
+        for (; vi + 8 <= j + 1; vi += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc -= hs[vi + u] * t[u];
+        }
+        for (; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
+        w[m] = acc * inv;
+    }
+    if (blockIdx.x != 0) return;
+    // the column h1 + h2 and the previous rotations, loaded in parallel
     const double* hc = a.hcol + (size_t)r * (a.m + 2);
-    double* Hj = a.H + (size_t)r * a.m * (a.m + 1) + (size_t)j * (a.m + 1);
     double* cs = a.cs + (size_t)r * a.m;
     double* sn = a.sn + (size_t)r * a.m;
-    double* g = a.g + (size_t)r * (a.m + 1);
-    for (int i = 0; i <= j; ++i) Hj[i] = hc[i];
-    Hj[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
-        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
-        Hj[i] = t;
+    for (int i = threadIdx.x; i <= j; i += GT) {
+        hc_s[i] = hc[i] + hs[i];
+        if (i < j) {
+            cs_s[i] = cs[i];
+            sn_s[i] = sn[i];
+        }
     }
-    const double den = hypot(Hj[j], Hj[j + 1]);
-    const double c = den > 0.0 ? Hj[j] / den : 1.0;
-    const double sv = den > 0.0 ? Hj[j + 1] / den : 0.0;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* Hj = a.H + (size_t)r * a.m * (a.m + 1) + (size_t)j * (a.m + 1);
+    double* g = a.g + (size_t)r * (a.m + 1);
+    hc_s[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs_s[i] * hc_s[i] + sn_s[i] * hc_s[i + 1];
+        hc_s[i + 1] = -sn_s[i] * hc_s[i] + cs_s[i] * hc_s[i + 1];
+        hc_s[i] = t;
+    }
+    const double den = hypot(hc_s[j], hc_s[j + 1]);
+    const double c = den > 0.0 ? hc_s[j] / den : 1.0;
+    const double sv = den > 0.0 ? hc_s[j + 1] / den : 0.0;
     cs[j] = c;
     sn[j] = sv;
+    for (int i = 0; i < j; ++i) Hj[i] = hc_s[i];
     Hj[j] = den;
     Hj[j + 1] = 0.0;
-    g[j + 1] = -sv * g[j];
-    g[j] = c * g[j];
-    const double res = fabs(g[j + 1]) / a.bnorm[r];
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    const double res = fabs(sv * gj) / a.bnorm[r];
     a.resid[r] = res;
     st[ST_ITERS] += 1;
     st[ST_J] = j + 1;
-    if (!isfinite(res) || !isfinite(s)) {
+    if (!isfinite(res) || !isfinite(hn_s[1])) {
         st[ST_STATUS] = IBDL_ERR_NUMERIC;
         st[ST_DONE] = 1;
     } else if (res <= a.tolv[r] || !(hn > 0.0)) {
@@ -239,32 +292,59 @@ __global__ __launch_bounds__(GT) void k_normalize_givens(KArgs a, int j) {
     }
 }
 
-// y = R^-1 g over the steps of the current cycle
-__global__ void k_backsolve(KArgs a) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.R) return;
+// y = R^-1 g over the steps of the current cycle (one block per rhs; the
+// triangle is staged in LDS when it fits)
+constexpr int BS_T = 64;
+constexpr int BS_LDS = 4096;  // doubles
+__global__ __launch_bounds__(BS_T) void k_backsolve(KArgs a) {
+    __shared__ double Rs[BS_LDS];
+    __shared__ double gs[256], ys[256];
+    const int r = blockIdx.x;
     const int jr = a.state[4 * r + ST_J];
     const double* H = a.H + (size_t)r * a.m * (a.m + 1);
     const double* g = a.g + (size_t)r * (a.m + 1);
     double* y = a.y + (size_t)r * a.m;
-    for (int i = jr - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int k = i + 1; k < jr; ++k) t -= H[(size_t)k * (a.m + 1) + i] * y[k];
-        const double d = H[(size_t)i * (a.m + 1) + i];
-        y[i] = d != 0.0 ? t / d : 0.0;
+    const bool lds = jr * jr <= BS_LDS;
+    for (int i = threadIdx.x; i < jr; i += BS_T) gs[i] = g[i];
+    if (lds)
+        for (int e = threadIdx.x; e < jr * jr; e += BS_T) {
+            const int k = e / jr, i = e % jr;  // column k, row i
+            Rs[e] = i <= k ? H[(size_t)k * (a.m + 1) + i] : 0.0;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = jr - 1; i >= 0; --i) {
+            double t = gs[i];
+            for (int k = i + 1; k < jr; ++k) t -= (lds ? Rs[k * jr + i] : H[(size_t)k * (a.m + 1) + i]) * ys[k];
+            const double d = lds ? Rs[i * jr + i] : H[(size_t)i * (a.m + 1) + i];
+            ys[i] = d != 0.0 ? t / d : 0.0;
+        }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < jr; i += BS_T) y[i] = ys[i];
 }
 
 // x += V[0..jr) y
 __global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* xpool) {
+    __shared__ double ys[256];
     const int r = blockIdx.y, M = a.Mr[r];
     const int jr = a.state[4 * r + ST_J];
+    if (jr == 0 || (int)blockIdx.x * GT >= M) return;
+    for (int i = threadIdx.x; i < jr; i += GT) ys[i] = a.y[(size_t)r * a.m + i];
+    __syncthreads();
     const int m = blockIdx.x * GT + threadIdx.x;
-    if (jr == 0 || m >= M) return;
+    if (m >= M) return;
     const double* V = a.V + a.voff[r];
-    const double* y = a.y + (size_t)r * a.m;
     double acc = xpool[a.xoff[r] + m];
-    for (int vi = 0; vi < jr; ++vi) acc += y[vi] * V[(size_t)vi * M + m];
+    int vi = 0;
+    for (; vi + 8 <= jr; vi += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += ys[vi + u] * t[u];
+    }
+    for (; vi < jr; ++vi) acc += ys[vi] * V[(size_t)vi * M + m];
     xpool[a.xoff[r] + m] = acc;
 }
 
@@ -344,7 +424,7 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     IBDL_HIP_TRY(hipMemcpy(k.voff, voff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
     IBDL_HIP_TRY(hipMemcpy(k.xoff, xoff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
     // host staging: tolerances, skip flags, state, residuals, norms
-    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)R * 48 + 64));
+    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)R * (5 * 8 + 9 * 4) + 64));  // the Staging layout
     k.cap_m = m;
     k.R = R;
     k.nblk = nblk;
@@ -380,22 +460,28 @@ static KArgs kargs(KrylovSet& ks, int m) {
     return a;
 }
 
-// host staging slices
+// host staging: tolerances, skip flags, norms of b, norms of other pools, and two
+// alternating snapshots of the per-rhs state and residual estimates
 struct Staging {
     double* tol;
-    int32_t* skip;
-    int32_t* state;
-    double* resid;
+    double* bn;
     double* nrm;
+    double* resid[2];
+    int32_t* state[2];
+    int32_t* skip;
 };
 static Staging staging(KWork& k, int R) {
-    char* base = reinterpret_cast<char*>(k.host_pinned);
+    double* d = reinterpret_cast<double*>(k.host_pinned);
     Staging s;
-    s.tol = reinterpret_cast<double*>(base);
-    s.resid = s.tol + R;
-    s.nrm = s.resid + R;
-    s.state = reinterpret_cast<int32_t*>(s.nrm + R);
-    s.skip = s.state + 4 * R;
+    s.tol = d;
+    s.bn = d + R;
+    s.nrm = d + 2 * R;
+    s.resid[0] = d + 3 * R;
+    s.resid[1] = d + 4 * R;
+    int32_t* i = reinterpret_cast<int32_t*>(d + 5 * R);
+    s.state[0] = i;
+    s.state[1] = i + 4 * R;
+    s.skip = i + 8 * R;
     return s;
 }
 
@@ -481,14 +567,50 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64)
     prepare_grouped(ks_, all_of(ks_), make, fp64, st_).run(0, st_);
 }
 
-// per-rhs 2-norms of a pool into the host staging area (read after the next wait point)
-void SolveTask::norms_async(const double* pool) {
+// per-rhs 2-norms of a pool into a host staging array (read after the next wait point)
+void SolveTask::norms_async(const double* pool, double* host) {
     KWork& k = ks_.w;
     KArgs a = kargs(ks_, m_);
-    Staging hs = staging(k, R_);
     hipLaunchKernelGGL(k_sumsq, dim3(k.nblk, R_), dim3(GT), 0, st_, a, pool);
     hipLaunchKernelGGL(k_norms, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.nrm, k.nrm, R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(host, k.nrm, R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+}
+
+void SolveTask::snapshot(int buf) {
+    KWork& k = ks_.w;
+    Staging hs = staging(k, R_);
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.state[buf], k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid[buf], k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+}
+
+void SolveTask::enqueue_iters(int j0, int c) {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    const dim3 vg(k.nblk, R_);
+    for (int t = 0; t < c; ++t) {
+        const int j = j0 + t;
+        op_.run(j, st_);
+        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j);
+        hipLaunchKernelGGL(k_orth_final, vg, dim3(GT), 0, st_, a, j);
+    }
+}
+
+// c Arnoldi steps: the state is looked at before the last one, which keeps the
+// device busy during the host's decision
+void SolveTask::enqueue_chunk(int c) {
+    const int c1 = c > 1 ? c - 1 : 1;
+    enqueue_iters(kj_, c1);
+    kj_ += c1;
+    ktotal_ += c1;
+    snap_buf_ ^= 1;
+    snapshot(snap_buf_);
+    mark();
+    snap_iter_ = kj_;
+    enqueue_iters(kj_, c - c1);
+    kj_ += c - c1;
+    ktotal_ += c - c1;
+    queued_after_ = c - c1;
 }
 
 // Restarted GMRES on A x = b (pool vectors) with each plan's operator in its own
@@ -502,7 +624,8 @@ void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
     kb_ = b;
     kx_ = x;
     kmaxit_ = maxit;
-    ktotal_ = kj_ = klast_ = 0;
+    ktotal_ = kj_ = 0;
+    prev_iter_ = -1;
     for (int r = 0; r < R_; ++r) {
         hs.tol[r] = tol_[r];
         hs.skip[r] = skip_[r];
@@ -552,59 +675,65 @@ void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
         return PassJob{in.p, in.nrhs, pi, po};
     };
     op_ = prepare_grouped(ks_, all_of(ks_), make, false, st_);
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
-    mark();
+    // rhs already converged at the start skip every step on the device
+    enqueue_chunk(std::min({3, m_, kmaxit_}));
     phase_ = ITER;
 }
 
-void SolveTask::kend() {
+// end of a Krylov run: x += V y, then what follows it without a host decision
+// (the FP64 residual of a refinement, or the outputs), up to one wait point
+void SolveTask::after_krylov() {
     KWork& k = ks_.w;
     KArgs a = kargs(ks_, m_);
     Staging hs = staging(k, R_);
-    const dim3 sg((R_ + 63) / 64);
-    hipLaunchKernelGGL(k_backsolve, sg, dim3(64), 0, st_, a);
+    hipLaunchKernelGGL(k_backsolve, dim3(R_), dim3(BS_T), 0, st_, a);
     hipLaunchKernelGGL(k_update_x, dim3(k.nblk, R_), dim3(GT), 0, st_, a, kx_);
-    hipLaunchKernelGGL(k_reset_j, sg, dim3(64), 0, st_, a);
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    hipLaunchKernelGGL(k_reset_j, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
+    snap_buf_ ^= 1;
+    snapshot(snap_buf_);
+    if (refining_) hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
+    if (any_mixed_) {
+        residual(k.b, k.x, k.rr, true);
+        norms_async(k.rr, hs.nrm);
+    } else {
+        if (o_.true_residual) {
+            residual(k.b, k.x, k.rr, true);
+            norms_async(k.rr, hs.nrm);
+        }
+        output();
+    }
     mark();
     phase_ = KEND;
 }
 
 void SolveTask::collect() {
     Staging hs = staging(ks_.w, R_);
+    const int32_t* state = hs.state[snap_buf_];
+    const double* resid = hs.resid[snap_buf_];
     for (int r = 0; r < R_; ++r) {
         if (skip_[r]) continue;
-        iters_[r] += hs.state[4 * r + ST_ITERS];
-        est_[r] = hs.resid[r];
-        int s = hs.state[4 * r + ST_STATUS];
-        if (s == IBDL_OK && !(hs.resid[r] <= tol_[r])) s = IBDL_ERR_NOCONV;
+        iters_[r] += state[4 * r + ST_ITERS];
+        est_[r] = resid[r];
+        int s = state[4 * r + ST_STATUS];
+        if (s == IBDL_OK && !(resid[r] <= tol_[r])) s = IBDL_ERR_NOCONV;
         status_[r] = s;
     }
 }
 
-// FP64 residual of the mixed instances, for the next refinement decision
-void SolveTask::refine_check() {
-    KWork& k = ks_.w;
-    residual(k.b, k.x, k.rr, true);
-    norms_async(k.rr);
-    mark();
-    phase_ = REFINE;
-}
-
-void SolveTask::true_check() {
+// outputs after a mixed solve: the FP64 residual of rhs that have none yet
+// (when asked for), the solution copies and the grid solutions
+void SolveTask::finish_mixed() {
     bool any = false;
     for (int r = 0; r < R_; ++r) any |= truer_[r] < 0.0;
-    if (o_.true_residual && any) {
+    fill_true_ = o_.true_residual && any;
+    if (fill_true_) {
         KWork& k = ks_.w;
         residual(k.b, k.x, k.rr, true);
-        norms_async(k.rr);
-        mark();
-        phase_ = TRUE_RES;
-    } else {
-        output();
+        norms_async(k.rr, staging(k, R_).nrm);
     }
+    output();
+    mark();
+    phase_ = OUT;
 }
 
 void SolveTask::output() {
@@ -636,8 +765,6 @@ void SolveTask::output() {
         };
         prepare_grouped(ks_, grid, make, true, st_).run(0, st_);
     }
-    mark();
-    phase_ = OUT;
 }
 
 void SolveTask::advance() {
@@ -651,12 +778,18 @@ void SolveTask::advance() {
         status_.assign(R_, IBDL_OK);
         est_.assign(R_, 0.0);
         tol_.assign(R_, o_.tol);
+        // mixed instances: the first FP32-operator solve stops near the FP32
+        // operator's own accuracy; the FP64 refinement takes it to tol
+        for (const Inst& in : ks_.inst)
+            if (in.p->prec == IBDL_PREC_MIXED)
+                for (int q = 0; q < in.nrhs; ++q) tol_[in.r0 + q] = std::max(o_.tol, kMixedFirstTol);
         skip_.assign(R_, 0);
         truer_.assign(R_, -1.0);
         fp64_.assign(R_, 0);
         any_mixed_ = false;
         for (const Inst& in : ks_.inst) any_mixed_ |= in.p->prec == IBDL_PREC_MIXED;
         refining_ = false;
+        fill_true_ = false;
         round_ = 0;
         auto bytes_of = [&](const Inst& in) { return (size_t)in.nrhs * in.p->M * sizeof(double); };
         // right-hand sides in FP64 (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~));
@@ -707,97 +840,86 @@ void SolveTask::advance() {
                     IBDL_HIP_TRY(hipMemsetAsync(dst, 0, bytes_of(in), st_));
             }
         }
-        x_zero_ = !any_x0;
-        norms_async(k.b);
-        mark();
-        phase_ = RHS_NORM;
-        return;
-    }
-    case RHS_NORM: {
-        Staging hs = staging(k, R_);
-        bn_.assign(hs.nrm, hs.nrm + R_);
-        kstart(k.b, k.x, x_zero_, o_.maxit);
+        norms_async(k.b, staging(k, R_).bn);
+        kstart(k.b, k.x, !any_x0, o_.maxit);
         return;
     }
     case ITER: {
         Staging hs = staging(k, R_);
+        const int32_t* state = hs.state[snap_buf_];
+        const double* resid = hs.resid[snap_buf_];
         bool all = true;
-        for (int r = 0; r < R_ && all; ++r) all = hs.state[4 * r + ST_DONE] != 0;
+        for (int r = 0; r < R_ && all; ++r) all = state[4 * r + ST_DONE] != 0;
         if (all || ktotal_ >= kmaxit_) {
-            kend();
+            after_krylov();
             return;
         }
-        KArgs a = kargs(ks_, m_);
-        const dim3 vg(k.nblk, R_);
+        // steps still needed by the slowest rhs at its observed rate of residual
+        // reduction, less those already queued behind the snapshot (1..8)
+        int need = 3;
+        if (prev_iter_ >= 0 && snap_iter_ > prev_iter_) {
+            need = 1;
+            const int d = snap_iter_ - prev_iter_;
+            for (int r = 0; r < R_; ++r) {
+                if (state[4 * r + ST_DONE]) continue;
+                const double now = resid[r], before = prev_[r];
+                int nr = 8;
+                if (now > 0.0 && before > now) {
+                    const double rate = std::pow(now / before, 1.0 / d);
+                    if (rate < 1.0) nr = (int)std::ceil(std::log(tol_[r] / now) / std::log(rate));
+                }
+                need = std::max(need, std::min(std::max(nr, 1), 8));
+            }
+        }
+        prev_.assign(resid, resid + R_);
+        prev_iter_ = snap_iter_;
+        int c = std::max(1, std::min(8, need - queued_after_));
         if (kj_ >= m_) {
-            // restart the rhs still running from their current iterate
-            const dim3 sg((R_ + 63) / 64);
-            hipLaunchKernelGGL(k_backsolve, sg, dim3(64), 0, st_, a);
+            // cycle end: restart the rhs still running from their current iterate
+            KArgs a = kargs(ks_, m_);
+            const dim3 vg(k.nblk, R_);
+            hipLaunchKernelGGL(k_backsolve, dim3(R_), dim3(BS_T), 0, st_, a);
             hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st_, a, kx_);
-            hipLaunchKernelGGL(k_reset_j, sg, dim3(64), 0, st_, a);
+            hipLaunchKernelGGL(k_reset_j, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
             residual(kb_, kx_, k.r, false);
             hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, k.r);
             hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st_, a, k.r);
             kj_ = 0;
-            klast_ = 0;
-        } else {
-            // steps to queue before looking at the state again: what the slowest
-            // rhs needs at its observed rate of residual reduction (1..8)
-            int need = 3;
-            if (klast_ > 0) {
-                need = 1;
-                for (int r = 0; r < R_; ++r) {
-                    if (hs.state[4 * r + ST_DONE]) continue;
-                    const double now = hs.resid[r], before = prev_[r];
-                    int nr = 8;
-                    if (now > 0.0 && before > now) {
-                        const double rate = std::pow(now / before, 1.0 / klast_);
-                        if (rate < 1.0) nr = (int)std::ceil(std::log(tol_[r] / now) / std::log(rate));
-                    }
-                    need = std::max(need, std::min(std::max(nr, 1), 8));
-                }
-            }
-            const int chunk = std::min({need, m_ - kj_, kmaxit_ - ktotal_});
-            prev_.assign(hs.resid, hs.resid + R_);
-            for (int t = 0; t < chunk; ++t) {
-                const int j = kj_ + t;
-                op_.run(j, st_);
-                hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j, 0);
-                hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j, 1);
-                hipLaunchKernelGGL(k_normalize_givens, vg, dim3(GT), 0, st_, a, j);
-            }
-            kj_ += chunk;
-            ktotal_ += chunk;
-            klast_ = chunk;
+            prev_iter_ = -1;
+            c = 3;
         }
-        IBDL_HIP_TRY(hipMemcpyAsync(hs.state, k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-        IBDL_HIP_TRY(hipMemcpyAsync(hs.resid, k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
-        mark();
+        c = std::min({c, m_ - kj_, kmaxit_ - ktotal_});
+        if (c <= 0) {
+            after_krylov();
+            return;
+        }
+        enqueue_chunk(c);
         return;
     }
     case KEND: {
         collect();
-        if (refining_) {
-            KArgs a = kargs(ks_, m_);
-            hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
-            ++round_;
-            refine_check();
-        } else if (any_mixed_) {
-            // FP64 iterative refinement of the mixed instances: r = b - A x with the
-            // FP64 operator, correct with the FP32-operator solve of A d = r, x += d
+        Staging hs = staging(k, R_);
+        bn_.assign(hs.bn, hs.bn + R_);
+        if (!any_mixed_) {
+            if (o_.true_residual)
+                for (int r = 0; r < R_; ++r) {
+                    truer_[r] = bn_[r] > 0.0 ? hs.nrm[r] / bn_[r] : 0.0;
+                    fp64_[r] += 1;
+                }
+            phase_ = DONE;
+            return;
+        }
+        if (!refining_) {
+            // FP64 iterative refinement of the mixed instances: r = b - A x with
+            // the FP64 operator, correct with the FP32-operator solve of A d = r, x += d
             for (const Inst& in : ks_.inst)
                 if (in.p->prec != IBDL_PREC_MIXED)
                     for (int q = 0; q < in.nrhs; ++q) skip_[in.r0 + q] = 1;
             refining_ = true;
             round_ = 0;
-            refine_check();
         } else {
-            true_check();
+            ++round_;
         }
-        return;
-    }
-    case REFINE: {
-        Staging hs = staging(k, R_);
         bool all = true;
         for (int r = 0; r < R_; ++r) {
             if (skip_[r]) continue;
@@ -819,7 +941,7 @@ void SolveTask::advance() {
             }
         }
         if (all) {
-            true_check();
+            finish_mixed();
             return;
         }
         int used = 0;
@@ -829,25 +951,24 @@ void SolveTask::advance() {
         if (round_ >= 4 || left <= 0) {
             for (int r = 0; r < R_; ++r)
                 if (!skip_[r] && status_[r] != IBDL_ERR_NUMERIC) status_[r] = IBDL_ERR_NOCONV;
-            true_check();
+            finish_mixed();
             return;
         }
         kstart(k.rr, k.d, true, left);
         return;
     }
-    case TRUE_RES: {
-        Staging hs = staging(k, R_);
-        for (int r = 0; r < R_; ++r)
-            if (truer_[r] < 0.0) {
-                truer_[r] = bn_[r] > 0.0 ? hs.nrm[r] / bn_[r] : 0.0;
-                fp64_[r] += 1;
-            }
-        output();
-        return;
-    }
-    case OUT:
+    case OUT: {
+        if (fill_true_) {
+            Staging hs = staging(k, R_);
+            for (int r = 0; r < R_; ++r)
+                if (truer_[r] < 0.0) {
+                    truer_[r] = bn_[r] > 0.0 ? hs.nrm[r] / bn_[r] : 0.0;
+                    fp64_[r] += 1;
+                }
+        }
         phase_ = DONE;
         return;
+    }
     case DONE:
         return;
     }

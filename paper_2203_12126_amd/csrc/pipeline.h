@@ -214,26 +214,12 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
 
 // ------------------------------------------------------------ spread phase
 // Adds coef * (sum_e w_e q[k_e]) into the LDS lines for every active node of
-// the block's lines.  Each node is written by exactly one thread.
+// the block's lines.  Each node is written by exactly one thread.  la[g] is the
+// first active node of line g of the block and rs the prefix sums of the lines'
+// active-node counts (both in LDS).
 template <typename R, int N, int G, int T>
-__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs, int it, int M,
-                                             const int32_t* lines, int first, int nproc,
-                                             int* rs) {
-    if (threadIdx.x < G) {
-        const int g = threadIdx.x;
-        int cnt = 0;
-        const int li = first + g;
-        if (li < nproc) {
-            const int line = lines ? lines[li] : li;
-            cnt = c.line_act[line + 1] - c.line_act[line];
-        }
-        rs[g + 1] = cnt;
-    }
-    if (threadIdx.x == 0) rs[0] = 0;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int g = 1; g <= G; ++g) rs[g] += rs[g - 1];
-    __syncthreads();
+__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs, int it, const int* la,
+                                             const int* rs) {
     const int total = rs[G];
     const double* q = c.q + (size_t)rhs * c.q_stride + (size_t)it * c.q_jstride;
     for (int f = threadIdx.x; f < total; f += T) {
@@ -243,9 +229,8 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
             if (rs[mid] <= f) lo = mid; else hi = mid;
         }
         const int g = lo;
-        const int line = lines ? lines[first + g] : first + g;
-        const int a = c.line_act[line] + (f - rs[g]);
-        const int x = (int)(c.act_node[a] - (uint32_t)line * (uint32_t)N);
+        const int a = la[g] + (f - rs[g]);
+        const int x = (int)(c.act_node[a] % (uint32_t)N);
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
         int e = c.act_ptr[a];
@@ -276,35 +261,58 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
-    __shared__ int rs[G + 1];
+    __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G];
+    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = lb / a.nblk;
-    if (a.skip && a.skip[4 * rhs]) return;
     const int first = (lb % a.nblk) * G;
-    for (int i = threadIdx.x; i < L * G; i += T) s[i] = cplx<R>{R(0), R(0)};
+    // every table load of the block at once: skip flag, twiddles, line ids and
+    // the lines' active-node ranges of both spread matrices
+    const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
+    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
     if (threadIdx.x < G) {
-        const int li = first + threadIdx.x;
-        lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
+        const int g = threadIdx.x;
+        const int li = first + g;
+        int line = -1, c0 = 0, c1 = 0, m0 = 0, m1 = 0;
+        if (li < a.nproc) {
+            line = a.lines ? a.lines[li] : li;
+            if (a.dip.q) {
+                c0 = a.dip.line_act[line];
+                c1 = a.dip.line_act[line + 1];
+            }
+            if (a.mono.q) {
+                m0 = a.mono.line_act[line];
+                m1 = a.mono.line_act[line + 1];
+            }
+        }
+        lines_s[g] = line;
+        la[0][g] = c0;
+        rs[0][g + 1] = c1 - c0;
+        la[1][g] = m0;
+        rs[1][g + 1] = m1 - m0;
     }
+    if (skipv) return;
+    for (int i = threadIdx.x; i < L * G; i += T) s[i] = cplx<R>{R(0), R(0)};
     __syncthreads();
+    if (threadIdx.x < 2) {
+        int* r = rs[threadIdx.x];
+        r[0] = 0;
+        for (int g = 1; g <= G; ++g) r[g] += r[g - 1];
+    }
     if (a.grid) {
         const double* gr = a.grid + (size_t)rhs * a.grid_stride;
         for (int id = threadIdx.x; id < N * G; id += T) {
             const int g = id / N, x = id % N;
-            const int li = first + g;
-            if (li < a.nproc) {
-                const int line = a.lines ? a.lines[li] : li;
-                sr[2 * ((x >> 1) * G + g) + (x & 1)] = (R)(a.cg * gr[(size_t)line * N + x]);
-            }
+            const int line = lines_s[g];
+            if (line >= 0) sr[2 * ((x >> 1) * G + g) + (x & 1)] = (R)(a.cg * gr[(size_t)line * N + x]);
         }
-        __syncthreads();
     }
-    if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, it, a.M, a.lines, first, a.nproc, rs);
-    if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, it, a.M, a.lines, first, a.nproc, rs);
+    __syncthreads();
+    if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, it, la[0], rs[0]);
+    if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, it, la[1], rs[1]);
 
-    run_fft<R, L, G, T, N, -1>(s, a.tw, LdsLoad<R, G>{s}, LdsStore<R, G>{s},
-                               FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, G, T, N, -1>(s, tw, LdsLoad<R, G>{s}, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
@@ -322,7 +330,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         const cplx<R> zm = s[((L - k) % L) * G + g];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
-        out[TL::idx(line, k)] = cadd(e, cmul(a.tw[k], cmul_si<-1>(d)));
+        out[TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
     }
 }
 template <typename R, int N, bool MULTI>
@@ -392,36 +400,67 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     __shared__ uint8_t lmask[N], smask[N], valid[LC];
     __shared__ R srow[MODE == 1 ? N : 1];
     __shared__ R scol[MODE == 1 ? LC : 1];
+    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
     const int t = lb % NT;
     const int oi = (lb / NT) % a.nouter;
     const int rhs = lb / NT / a.nouter;
     const int o = a.outer_list ? a.outer_list[oi] : oi;
-    if (a.skip && a.skip[4 * rhs]) return;
-    cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
-    for (int i = threadIdx.x; i < N; i += T) {
-        lmask[i] = a.lmask ? a.lmask[o * a.lm_outer + i * a.lm_stride] : 1;
-        smask[i] = a.smask ? a.smask[o * a.sm_outer + i * a.sm_stride] : 1;
-        if constexpr (MODE == 1) srow[i] = a.s2[i];
+    // every table load of the block at once: skip flag, twiddles, row masks, symbol terms
+    const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
+    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
+    constexpr int PN = (N + T - 1) / T, PL = (LC + T - 1) / T;
+    uint8_t lmv[PN], smv[PN];
+    R s2v[PN];
+#pragma unroll
+    for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < N) {
+            lmv[u] = a.lmask ? a.lmask[o * a.lm_outer + i * a.lm_stride] : 1;
+            smv[u] = a.smask ? a.smask[o * a.sm_outer + i * a.sm_stride] : 1;
+            if constexpr (MODE == 1) s2v[u] = a.s2[i];
+        }
     }
-    for (int l = threadIdx.x; l < LC; l += T) {
-        const int kx = t * C + l % C;
-        const bool ok = kx < a.width;
-        valid[l] = ok;
-        if constexpr (MODE == 1)
-            scol[l] = ok ? a.s2[kx] + (K > 1 ? a.s2[o * K + l / C] : R(0)) + a.alpha : R(-1);
+    R scv[PL];
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+        const int l = threadIdx.x + u * T;
+        if (l < LC) {
+            const int kx = t * C + l % C;
+            if constexpr (MODE == 1)
+                scv[u] = kx < a.width ? a.s2[kx] + (K > 1 ? a.s2[o * K + l / C] : R(0)) + a.alpha : R(-1);
+        }
+    }
+    if (skipv) return;
+    cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
+#pragma unroll
+    for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < N) {
+            lmask[i] = lmv[u];
+            smask[i] = smv[u];
+            if constexpr (MODE == 1) srow[i] = s2v[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+        const int l = threadIdx.x + u * T;
+        if (l < LC) {
+            valid[l] = t * C + l % C < a.width;
+            if constexpr (MODE == 1) scol[l] = scv[u];
+        }
     }
     __syncthreads();
     const ColLoad<R, LC> ld{base, a.es, valid, lmask};
     const ColStore<R, LC> st{base, a.es, valid, smask};
     if constexpr (MODE == 0) {
-        run_fft<R, N, LC, T, N, -1>(s, a.tw, ld, st, FwdRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, -1>(s, tw, ld, st, FwdRadices<N, RM>{});
     } else if constexpr (MODE == 2) {
-        run_fft<R, N, LC, T, N, +1>(s, a.tw, ld, st, FwdRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, +1>(s, tw, ld, st, FwdRadices<N, RM>{});
     } else {
         const SymStore<R, LC> sym{s, srow, scol, a.norm};
-        run_fft<R, N, LC, T, N, -1>(s, a.tw, ld, sym, FwdRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, -1>(s, tw, ld, sym, FwdRadices<N, RM>{});
         __syncthreads();
-        run_fft<R, N, LC, T, N, +1>(s, a.tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
     }
 }
 template <typename R, int N, int MODE, int K, bool MULTI>
@@ -436,21 +475,27 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
+    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
+    __shared__ int lines_s[G];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = lb / a.nblk;
-    if (a.skip && a.skip[4 * rhs]) return;
     const int first = (lb % a.nblk) * G;
-    const cplx<R>* spec = a.spec + (size_t)rhs * a.spec_stride;
-    __shared__ int lines_s[G];
+    const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
+    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
     if (threadIdx.x < G) {
         const int li = first + threadIdx.x;
         lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
     }
+    if (skipv) return;
     __syncthreads();
-    // the block's rows X[0..L], read in tile order (consecutive threads, consecutive addresses)
+    const cplx<R>* spec = a.spec + (size_t)rhs * a.spec_stride;
+    // the block's rows X[0..L], read in tile order (consecutive threads, consecutive addresses),
+    // and (interpolation) the sorted-point ranges of the x-lines (cy, cz), cy in y-2..y+1,
+    // cz in z-2..z+1, of every line of the block
     using TL = Tiles<R, N>;
     constexpr int C = TL::C;
     __shared__ cplx<R> xs[(L + 1) * G];
+    __shared__ int rb[OUT == 0 ? G * 8 : 1], rc[OUT == 0 ? G * 8 : 1], roff[OUT == 0 ? G * 8 + 1 : 1];
     for (int id = threadIdx.x; id < TL::NT * G * C; id += T) {
         const int t = id / (G * C), rem = id % (G * C);
         const int g = rem / C, c = rem % C;
@@ -458,34 +503,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
         const int line = lines_s[g];
         if (k <= L) xs[g * (L + 1) + k] = line >= 0 ? spec[TL::idx(line, k)] : cplx<R>{R(0), R(0)};
     }
-    __syncthreads();
-    // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
-    auto split = [&](int k, int g) -> cplx<R> {
-        const cplx<R> xk = xs[g * (L + 1) + k];
-        const cplx<R> xm = xs[g * (L + 1) + L - k];
-        const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
-        const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
-        return cadd(e, cmul_si<1>(cmul(cconj(a.tw[k]), d)));
-    };
-    run_fft<R, L, G, T, N, +1>(s, a.tw, split, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
-    __syncthreads();
-
-    if constexpr (OUT == 1) {
-        double* u = a.u + (size_t)rhs * a.u_stride;
-        for (int id = threadIdx.x; id < G * N; id += T) {
-            const int g = id / N, x = id % N;
-            const int li = first + g;
-            if (li < a.nproc) {
-                const int line = a.lines ? a.lines[li] : li;
-                u[(size_t)line * N + x] = (double)sr[2 * ((x >> 1) * G + g) + (x & 1)];
-            }
-        }
-    } else {
-        R* part = a.part + (size_t)rhs * a.part_stride;
-        const int gpp = a.dim == 3 ? 16 : 4;
-        // sorted-point ranges of the x-lines (cy, cz), cy in y-2..y+1, cz in z-2..z+1,
-        // for every line of the block, then one pass over their union
-        __shared__ int rb[G * 8], rc[G * 8], roff[G * 8 + 1];
+    if constexpr (OUT == 0) {
         const int nz = a.dim == 3 ? 4 : 1;
         for (int t = threadIdx.x; t < G * 4; t += T) {
             const int g = t / 4, dz = t % 4;
@@ -516,7 +534,13 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             rb[2 * t + 1] = b1;
             rc[2 * t + 1] = c1;
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    // interpolation: the first point of every thread, fetched before the transform
+    int pf_s = -1, pf_r = 0;
+    int pf_cell[3] = {0, 0, 0};
+    R pf_tp[12];
+    if constexpr (OUT == 0) {
         if (threadIdx.x == 0) {
             int acc = 0;
             for (int r = 0; r < G * 8; ++r) {
@@ -526,22 +550,48 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             roff[G * 8] = acc;
         }
         __syncthreads();
-        const int total = roff[G * 8];
-        for (int f = threadIdx.x; f < total; f += T) {
-            int lo = 0, hi = G * 8;  // range r with roff[r] <= f < roff[r+1]
+        const int f = threadIdx.x;
+        if (f < roff[G * 8]) {
+            int lo = 0, hi = G * 8;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
                 if (roff[mid] <= f) lo = mid; else hi = mid;
             }
-            const int r = lo;
+            pf_r = lo;
+            pf_s = rb[lo] + (f - roff[lo]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pf_cell[d] = a.cell[3 * pf_s + d];
+#pragma unroll
+            for (int u = 0; u < 12; ++u) pf_tp[u] = a.taps[(size_t)pf_s * 12 + u];
+        }
+    }
+    // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
+    auto split = [&](int k, int g) -> cplx<R> {
+        const cplx<R> xk = xs[g * (L + 1) + k];
+        const cplx<R> xm = xs[g * (L + 1) + L - k];
+        const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
+        const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
+        return cadd(e, cmul_si<1>(cmul(cconj(tw.get(k)), d)));
+    };
+    run_fft<R, L, G, T, N, +1>(s, tw, split, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
+    __syncthreads();
+
+    if constexpr (OUT == 1) {
+        double* u = a.u + (size_t)rhs * a.u_stride;
+        for (int id = threadIdx.x; id < G * N; id += T) {
+            const int g = id / N, x = id % N;
+            const int line = lines_s[g];
+            if (line >= 0) u[(size_t)line * N + x] = (double)sr[2 * ((x >> 1) * G + g) + (x & 1)];
+        }
+    } else {
+        R* part = a.part + (size_t)rhs * a.part_stride;
+        const int gpp = a.dim == 3 ? 16 : 4;
+        auto gather = [&](int r, int sidx, const int* cell, const R* tp) {
             const int g = r / 8;
             const int line = lines_s[g];
             const int y = line % N, z = line / N;
-            const int sidx = rb[r] + (f - roff[r]);
-            const int cx = a.cell[3 * sidx + 0];
-            const int cy = a.cell[3 * sidx + 1];
+            const int cx = cell[0], cy = cell[1];
             const int oy = (y - cy + 1 + N) % N;
-            const R* tp = a.taps + (size_t)sidx * 12;
             R acc = R(0);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -551,12 +601,28 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             acc *= tp[4 + oy];
             int o = oy;
             if (a.dim == 3) {
-                const int cz = a.cell[3 * sidx + 2];
-                const int oz = (z - cz + 1 + N) % N;
+                const int oz = (z - cell[2] + 1 + N) % N;
                 acc *= tp[8 + oz];
                 o += 4 * oz;
             }
             part[(size_t)sidx * gpp + o] = acc;
+        };
+        if (pf_s >= 0) gather(pf_r, pf_s, pf_cell, pf_tp);
+        const int total = roff[G * 8];
+        for (int f = threadIdx.x + T; f < total; f += T) {
+            int lo = 0, hi = G * 8;  // range r with roff[r] <= f < roff[r+1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (roff[mid] <= f) lo = mid; else hi = mid;
+            }
+            const int sidx = rb[lo] + (f - roff[lo]);
+            int cell[3];
+            R tp[12];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cell[d] = a.cell[3 * sidx + d];
+#pragma unroll
+            for (int u = 0; u < 12; ++u) tp[u] = a.taps[(size_t)sidx * 12 + u];
+            gather(lo, sidx, cell, tp);
         }
     }
 }
@@ -598,14 +664,30 @@ template <typename R>
 __device__ __forceinline__ void finish_body(const FinishArgs& f, int lb, int it) {
     const int rhs = lb / f.nblk;
     const int s = (lb % f.nblk) * FIN_T + threadIdx.x;
-    if (f.skip && f.skip[4 * rhs]) return;
+    // skip flag, point index and partials are loaded together
+    const int32_t skipv = f.skip ? f.skip[4 * rhs] : 0;
     double v = 0.0;
     uint32_t k = 0;
+    double acc = 0.0;
     if (s < f.M) {
         const R* p = reinterpret_cast<const R*>(f.part) + (size_t)rhs * f.part_stride + (size_t)s * f.gpp;
-        double acc = 0.0;
-        for (int o = 0; o < f.gpp; ++o) acc += (double)p[o];
         k = f.perm[s];
+        if (f.gpp == 4) {
+            R pv[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) pv[o] = p[o];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) acc += (double)pv[o];
+        } else {
+            R pv[16];
+#pragma unroll
+            for (int o = 0; o < 16; ++o) pv[o] = p[o];
+#pragma unroll
+            for (int o = 0; o < 16; ++o) acc += (double)pv[o];
+        }
+    }
+    if (skipv) return;
+    if (s < f.M) {
         v = f.cA * acc;
         if (f.in) v += f.cB * f.in[(size_t)rhs * f.in_stride + (size_t)it * f.in_jstride + k];
         if (f.in2) v += f.cC * f.in2[(size_t)rhs * f.in2_stride + k];

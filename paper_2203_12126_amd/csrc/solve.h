@@ -48,16 +48,18 @@ public:
     int total_iters() const;
 
 private:
-    enum Phase { BEGIN, RHS_NORM, ITER, KEND, REFINE, TRUE_RES, OUT, DONE };
+    enum Phase { BEGIN, ITER, KEND, OUT, DONE };
     void mark();                                  // record the wait point
     void kstart(const double* b, double* x, bool x_zero, int maxit);
-    void kend();
+    void enqueue_iters(int j0, int c);
+    void enqueue_chunk(int c);
+    void snapshot(int buf);
+    void after_krylov();
     void collect();
-    void refine_check();
-    void true_check();
+    void finish_mixed();
     void output();
     void residual(const double* b, const double* x, double* r, bool fp64);
-    void norms_async(const double* pool);
+    void norms_async(const double* pool, double* host);
 
     KrylovSet& ks_;
     SolveIO io_;
@@ -69,11 +71,15 @@ private:
     // current Krylov run
     const double* kb_ = nullptr;
     double* kx_ = nullptr;
-    int kmaxit_ = 0, ktotal_ = 0, kj_ = 0, klast_ = 0;
+    int kmaxit_ = 0, ktotal_ = 0, kj_ = 0;
+    int snap_buf_ = 0;      // staging buffer of the last snapshot
+    int snap_iter_ = 0;     // cycle steps enqueued before it
+    int queued_after_ = 0;  // steps enqueued after it
+    int prev_iter_ = -1;    // cycle steps before the previous snapshot (-1: none this cycle)
     std::vector<double> prev_;
     GroupedPass op_;
     // solve state
-    bool any_mixed_ = false, refining_ = false, x_zero_ = true;
+    bool any_mixed_ = false, refining_ = false, fill_true_ = false;
     int round_ = 0;
     std::vector<double> bn_, tol_, est_, truer_;
     std::vector<int> skip_, iters_, status_, fp64_;
