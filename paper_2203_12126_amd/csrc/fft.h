@@ -226,9 +226,49 @@ __device__ __forceinline__ Tw2<R> load_tw2(cplx<R>* lds, const cplx<R>* __restri
     return Tw2<R>{lds, lds + S::LO};
 }
 
-template <int SIGN, typename R>
-__device__ __forceinline__ cplx<R> twiddle(const Tw2<R>& tw, int idx) {
-    cplx<R> w = tw.get(idx);
+// The full table W^idx, idx < NT, in LDS (when it fits the kernel's LDS budget).
+template <typename R>
+struct TwFull {
+    const cplx<R>* tab;
+    __device__ __forceinline__ cplx<R> get(int idx) const { return tab[idx]; }
+};
+template <typename R, int NT, int T>
+__device__ __forceinline__ TwFull<R> load_twfull(cplx<R>* lds, const cplx<R>* __restrict__ tw) {
+    constexpr int P = (NT + T - 1) / T;
+    cplx<R> v[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < NT) v[u] = tw[i];
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const int i = threadIdx.x + u * T;
+        if (i < NT) lds[i] = v[u];
+    }
+    return TwFull<R>{lds};
+}
+// LDS twiddle storage: the full table or the two small ones
+template <typename R, int NT, bool FULL>
+struct TwLds;
+template <typename R, int NT>
+struct TwLds<R, NT, true> {
+    using type = TwFull<R>;
+    static constexpr int SIZE = NT;
+    template <int T>
+    __device__ __forceinline__ static type load(cplx<R>* lds, const cplx<R>* tw) { return load_twfull<R, NT, T>(lds, tw); }
+};
+template <typename R, int NT>
+struct TwLds<R, NT, false> {
+    using type = Tw2<R>;
+    static constexpr int SIZE = Tw2Size<NT>::ALL;
+    template <int T>
+    __device__ __forceinline__ static type load(cplx<R>* lds, const cplx<R>* tw) { return load_tw2<R, NT, T>(lds, tw); }
+};
+
+template <int SIGN, class TW>
+__device__ __forceinline__ auto twiddle(const TW& tw, int idx) {
+    auto w = tw.get(idx);
     if (SIGN > 0) w.y = -w.y;
     return w;
 }
@@ -283,9 +323,9 @@ struct LdsStore {
 };
 
 // One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
-template <typename R, int L, int C, int TH, int NT, int SIGN, int NS, int RAD, int... REST, class LD,
+template <typename R, int L, int C, int TH, int NT, int SIGN, int NS, int RAD, int... REST, class TW, class LD,
           class ST>
-__device__ __forceinline__ void run_stages(cplx<R>* s, const Tw2<R>& tw, LD ld, ST st) {
+__device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST st) {
     constexpr int NB = L / RAD;
     constexpr int TOT = NB * C;
     constexpr int PER = (TOT + TH - 1) / TH;
@@ -329,8 +369,8 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const Tw2<R>& tw, LD ld, 
     }
 }
 
-template <typename R, int L, int C, int TH, int NT, int SIGN, class LD, class ST, int... Rs>
-__device__ __forceinline__ void run_fft(cplx<R>* s, const Tw2<R>& tw, LD ld, ST st, Radices<Rs...>) {
+template <typename R, int L, int C, int TH, int NT, int SIGN, class TW, class LD, class ST, int... Rs>
+__device__ __forceinline__ void run_fft(cplx<R>* s, const TW& tw, LD ld, ST st, Radices<Rs...>) {
     run_stages<R, L, C, TH, NT, SIGN, 1, Rs...>(s, tw, ld, st);
 }
 

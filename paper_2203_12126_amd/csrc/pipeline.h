@@ -164,6 +164,7 @@ struct ColArgs {
     R alpha;
     R norm;
     int nouter;           // outer indices per right-hand side
+    int nrhs;
 };
 
 template <typename R>
@@ -263,14 +264,15 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     __shared__ cplx<R> s[L * G];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G];
-    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    __shared__ cplx<R> twl[TWL::SIZE];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = lb / a.nblk;
     const int first = (lb % a.nblk) * G;
     // every table load of the block at once: skip flag, twiddles, line ids and
     // the lines' active-node ranges of both spread matrices
     const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
-    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
+    const auto tw = TWL::template load<T>(twl, a.tw);
     if (threadIdx.x < G) {
         const int g = threadIdx.x;
         const int li = first + g;
@@ -400,14 +402,29 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     __shared__ uint8_t lmask[N], smask[N], valid[LC];
     __shared__ R srow[MODE == 1 ? N : 1];
     __shared__ R scol[MODE == 1 ? LC : 1];
-    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
-    const int t = lb % NT;
-    const int oi = (lb / NT) % a.nouter;
-    const int rhs = lb / NT / a.nouter;
+    // the full twiddle table in LDS where it keeps two blocks per compute unit
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    __shared__ cplx<R> twl[TWL::SIZE];
+    // A last tile that holds only the column kx = n/2 is transformed alone (below),
+    // and its blocks come after all full tiles so that the full tiles spread
+    // evenly over the compute units.
+    constexpr bool NYQ = K == 1 && (N / 2) % C == 0;
+    constexpr int NTF = NYQ ? NT - 1 : NT;
+    const int pairs = a.nouter * a.nrhs;
+    int t, pr;
+    if (lb < NTF * pairs) {
+        t = lb % NTF;
+        pr = lb / NTF;
+    } else {
+        t = NT - 1;
+        pr = lb - NTF * pairs;
+    }
+    const int oi = pr % a.nouter;
+    const int rhs = pr / a.nouter;
     const int o = a.outer_list ? a.outer_list[oi] : oi;
     // every table load of the block at once: skip flag, twiddles, row masks, symbol terms
     const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
-    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
+    const auto tw = TWL::template load<T>(twl, a.tw);
     constexpr int PN = (N + T - 1) / T, PL = (LC + T - 1) / T;
     uint8_t lmv[PN], smv[PN];
     R s2v[PN];
@@ -450,6 +467,24 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
         }
     }
     __syncthreads();
+    if constexpr (NYQ) {
+        if (t == NT - 1) {
+            // the last tile holds only the column kx = n/2: transform it alone
+            const ColLoad<R, 1> ld1{base, a.es, valid, lmask};
+            const ColStore<R, 1> st1{base, a.es, valid, smask};
+            if constexpr (MODE == 0) {
+                run_fft<R, N, 1, T, N, -1>(s, tw, ld1, st1, FwdRadices<N, RM>{});
+            } else if constexpr (MODE == 2) {
+                run_fft<R, N, 1, T, N, +1>(s, tw, ld1, st1, FwdRadices<N, RM>{});
+            } else {
+                const SymStore<R, 1> sym1{s, srow, scol, a.norm};
+                run_fft<R, N, 1, T, N, -1>(s, tw, ld1, sym1, FwdRadices<N, RM>{});
+                __syncthreads();
+                run_fft<R, N, 1, T, N, +1>(s, tw, LdsLoad<R, 1>{s}, st1, RevRadices<N, RM>{});
+            }
+            return;
+        }
+    }
     const ColLoad<R, LC> ld{base, a.es, valid, lmask};
     const ColStore<R, LC> st{base, a.es, valid, smask};
     if constexpr (MODE == 0) {
@@ -475,13 +510,14 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
     __shared__ cplx<R> s[L * G];
-    __shared__ cplx<R> twl[Tw2Size<N>::ALL];
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    __shared__ cplx<R> twl[TWL::SIZE];
     __shared__ int lines_s[G];
     R* sr = reinterpret_cast<R*>(s);
     const int rhs = lb / a.nblk;
     const int first = (lb % a.nblk) * G;
     const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
-    const Tw2<R> tw = load_tw2<R, N, T>(twl, a.tw);
+    const auto tw = TWL::template load<T>(twl, a.tw);
     if (threadIdx.x < G) {
         const int li = first + threadIdx.x;
         lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
@@ -993,6 +1029,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ca.alpha = (R)p->alpha;
         ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
         ca.tile_stride = (size_t)n * C;
+        ca.nrhs = nrhs;
         if (p->dim == 2) {
             ca.outer_list = nullptr;
             ca.outer_stride = 0;
