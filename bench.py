@@ -1,6 +1,7 @@
 """Benchmark of the IBDL hot path on one MI355X.
 
-A step is one complete IBDL solve of a batch of right-hand sides on the 2-D
+A step is one complete IBDL solve of a batch of right-hand sides (32 by
+default: enough column tiles to give every compute unit eight blocks) on the 2-D
 star workload (periodic unit square, 1024^2 grid, star r = 0.3 + 0.05 cos 5t
 with 4096 boundary points, alpha = 1, Dirichlet, random-Fourier manufactured
 data): the right-hand side, unpreconditioned GMRES on the device to tol 1e-8,
@@ -69,6 +70,50 @@ def stage_bytes(st, dim, n, m, prec, nrhs):
     out["ifft_x+interp"] = nrhs * (G * W * bc + m * gpp * br) + pts
     out["finish"] = nrhs * (m * gpp * br + m * 16) + m * 4
     return out
+
+
+ROOF_APPLIES = 50
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "star1024_nrhs32_traffic.md")
+KERNEL_SOURCES = ["paper_2203_12126_amd/csrc/pipeline.h", "paper_2203_12126_amd/csrc/fft.h",
+                  "paper_2203_12126_amd/csrc/common.h"]
+
+
+def stage_kernel(stage, dim, n):
+    """Kernel (FP32 instantiation) behind a stage name of a mixed 2-D apply."""
+    if dim != 2:
+        return stage
+    return {"spread+fft_x": f"k_row_fwd<float, {n}, false>",
+            "fft_y+symbol": f"k_col<float, {n}, 1, 1, false>",
+            "ifft_x+interp": f"k_row_inv<float, {n}, 0, false>",
+            "finish": "k_finish<float, false>"}.get(stage, stage)
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(workload, nrhs, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary
+    is for another configuration or the kernel sources changed since."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("traffic:"):
+            continue
+        kv = dict(x.strip().split("=", 1) for x in ln[len("traffic:"):].split(";") if "=" in x)
+        if (kv.get("workload") == workload and int(kv.get("nrhs", -1)) == nrhs and kv.get("kernel") == kernel
+                and kv.get("sources_sha1") == kernel_sources_sha1()):
+            return int(kv["bytes_per_launch"])
+    return None
 
 
 def full_grid_bytes_per_apply(dim, n, m, prec):
@@ -326,9 +371,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--nrhs", type=int, default=4)
+    ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--workload", default="star1024")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="length of the oracle CPU sample")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-templates", type=int, default=48)
     ap.add_argument("--serve-window", type=int, default=64)
@@ -399,18 +445,28 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # accuracy against the FP64 oracle (outside the timed region)
+    # accuracy against the FP64 oracle (outside the timed region), and the
+    # oracle's own throughput on a bounded sample of the same right-hand sides
     from oracle import ibdl_oracle as O
+    from threadpoolctl import threadpool_limits
     st = O.setup_from_problem(p0)
-    t_cpu0 = time.perf_counter()
-    res, _ = O.solve(st, p0.data, p0.g_tilde, tol=tol)
-    uo = O.eval_grid(st, res.x, g_tilde=p0.g_tilde)
-    t_cpu = time.perf_counter() - t_cpu0
     tight, _ = O.solve(st, p0.data, p0.g_tilde, tol=1e-13)
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     err_mixed = rel(mixed["sol"][0], tight.x)
     err_fp64 = rel(fp64["sol"][0], tight.x)
     err_u_mixed = rel(mixed["u"][0], O.eval_grid(st, tight.x, g_tilde=p0.g_tilde))
+    cpu_iters, cpu_solves, t_cpu = 0, 0, 0.0
+    if not args.no_cpu:
+        with threadpool_limits(limits=1):
+            for pr in probs:
+                c0 = time.perf_counter()
+                res, _ = O.solve(st, pr.data, pr.g_tilde, tol=tol)
+                O.eval_grid(st, res.x, g_tilde=pr.g_tilde)
+                t_cpu += time.perf_counter() - c0
+                cpu_iters += res.iters
+                cpu_solves += 1
+                if t_cpu >= args.cpu_seconds:
+                    break
 
     K = args.steps
     el = mixed["elapsed"]
@@ -418,22 +474,40 @@ def main():
     solves_s = K * args.nrhs / el
     lat_ms = np.array(mixed["lat"]) * 1e3
 
-    # roofline of the dominant stage
-    sb = stage_bytes(mixed["stats"], dim, n, m, 1, args.nrhs)
-    tot = {name: ms * calls for name, ms, calls in mixed["stages"]}
-    dom = max(tot, key=tot.get)
-    dom_ms = dict((nm, ms) for nm, ms, _ in mixed["stages"])[dom]
-    achieved = sb.get(dom, 0) / (dom_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": int(sb.get(dom, 0)), "ms_per_launch": round(dom_ms, 5)}
+    # roofline of the dominant kernel: a dedicated loop of mixed operator
+    # applications with every right-hand side active and the stage events on
+    rplan = ibdl.Plan.from_problem(p0, prec=ibdl.MIXED)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    q = torch.randn(args.nrhs, m, dtype=torch.float64, device="cuda", generator=gen)
+    out = rplan.apply(q)
+    for _ in range(5):
+        rplan.apply(q, out=out)
+    torch.cuda.synchronize()
+    rplan.set_timing(True)
+    for _ in range(ROOF_APPLIES):
+        rplan.apply(q, out=out)
+    stages = rplan.stage_times()
+    rplan.set_timing(False)
+    rstats = rplan.stats()
+    rplan.close()
+    sb = stage_bytes(rstats, dim, n, m, 1, args.nrhs)
+    dom_ms = {nm: ms for nm, ms, _ in stages}
+    dom = max(dom_ms, key=dom_ms.get)
+    achieved = sb.get(dom, 0) / (dom_ms[dom] * 1e-3) / 1e9
+    kname = stage_kernel(dom, dim, n)
+    roof = {"bound": "hbm", "kernel": kname, "stage": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(args.workload, args.nrhs, kname),
+            "bytes_per_launch": int(sb.get(dom, 0)), "ms_per_launch": round(dom_ms[dom], 5),
+            "launches": ROOF_APPLIES}
 
     cpu = None
     if not args.no_cpu:
-        cpu = {"value": round(res.iters / t_cpu, 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
-               "sample": f"one FP64 oracle solve of the first right-hand side (rhs, {res.iters} GMRES "
-                         f"applies, grid solution) = {t_cpu:.1f} s",
-               "host_cpus": os.cpu_count()}
+        cpu = {"value": round(cpu_iters / t_cpu, 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle solves (rhs, GMRES to tol {tol:g}, grid solution) of the first "
+                         f"{cpu_solves} right-hand sides of the workload: {cpu_iters} applies in {t_cpu:.1f} s, "
+                         f"one thread (numpy FFT; BLAS pools limited to 1)",
+               "solves_per_s": round(cpu_solves / t_cpu, 4), "host_cpus": os.cpu_count()}
 
     line = {
         "metric": METRIC, "value": round(applies_s, 2), "unit": "applies/s", "n_gpus": 1,
@@ -451,7 +525,8 @@ def main():
         "fp64_path": {"applies_per_s": round(fp64["iters"] / fp64["elapsed"], 2),
                       "solves_per_s": round(len(fp64["lat"]) * args.nrhs / fp64["elapsed"], 3),
                       "latency_ms_p50": round(float(np.percentile(np.array(fp64["lat"]) * 1e3, 50)), 4)},
-        "stages_ms": {nm: round(ms, 5) for nm, ms, _ in mixed["stages"]},
+        "stages_ms_in_solves": {nm: round(ms, 5) for nm, ms, _ in mixed["stages"]},
+        "stages_ms_apply": {nm: round(ms, 5) for nm, ms in dom_ms.items()},
         "full_grid_bytes_per_apply": full_grid_bytes_per_apply(dim, n, m, 1),
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -234,23 +234,25 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
         const int x = (int)(c.act_node[a] % (uint32_t)N);
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
-        int e = c.act_ptr[a];
-        // issue the loads of 8 entries before using any of them
-        for (; e + 8 <= e1; e += 8) {
+        // entries in groups of 8: every load of a group is issued before any is used
+        for (int e = c.act_ptr[a]; e < e1; e += 8) {
+            const int cnt = e1 - e;
             uint32_t kk[8];
             R ww[8];
             double qq[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                kk[u] = c.k[e + u];
-                ww[u] = c.w[e + u];
-            }
+            for (int u = 0; u < 8; ++u)
+                if (u < cnt) {
+                    kk[u] = c.k[e + u];
+                    ww[u] = c.w[e + u];
+                }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) qq[u] = q[kk[u]];
+            for (int u = 0; u < 8; ++u)
+                if (u < cnt) qq[u] = q[kk[u]];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc.add(ww[u], (R)qq[u]);
+            for (int u = 0; u < 8; ++u)
+                if (u < cnt) acc.add(ww[u], (R)qq[u]);
         }
-        for (; e < e1; ++e) acc.add(c.w[e], (R)q[c.k[e]]);
         sr[2 * ((x >> 1) * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
     __syncthreads();

@@ -402,9 +402,30 @@ def config_star1024(m: int = 4096, alpha: float = 1.0, bc: int = DIRICHLET,
     """2-D star r = 0.3 + 0.05 cos(5 theta) at (0.5,0.5) on a periodic unit
     square, random-Fourier manufactured solution (modes |m_i| <= 4, N(0,1))."""
     grid = Grid(2, n, (0.0, 0.0), 1.0)
-    geom = star((0.5, 0.5), STAR_R0, STAR_AMP, STAR_LOBES, m)
+    geom = _star_geometry(m)
     sol = sol_random_fourier(2, seed)
-    return make_problem(grid, geom, alpha, bc, sol, name=f"star{n}_m{m}")
+    # forcing by separable evaluation (same values as make_problem up to rounding)
+    key = (m, n)
+    if key not in _STAR_INSIDE:
+        pts = np.stack([c.ravel() for c in grid.nodes()], axis=1)
+        _STAR_INSIDE[key] = geom.inside(pts).reshape(n, n)
+    inside = _STAR_INSIDE[key]
+    u, lap = random_fourier_grid_2d(seed, grid)
+    g = np.where(inside, lap - alpha * u, 0.0)
+    data = sol.u(geom.X) if bc == DIRICHLET else np.sum(sol.grad(geom.X) * geom.normal, axis=1)
+    return Problem(grid, geom, alpha, bc, np.ascontiguousarray(data), np.ascontiguousarray(g), sol,
+                   f"star{n}_m{m}")
+
+
+_STAR_CACHE: dict = {}
+_STAR_INSIDE: dict = {}
+
+
+def _star_geometry(m: int) -> Geometry:
+    """The star's points (cached: every right-hand side of a workload shares them)."""
+    if m not in _STAR_CACHE:
+        _STAR_CACHE[m] = star((0.5, 0.5), STAR_R0, STAR_AMP, STAR_LOBES, m)
+    return _STAR_CACHE[m]
 
 
 def config_sphere256(n: int = 256, m: int = 40000, alpha: float = 10.0) -> Problem:

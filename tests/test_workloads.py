@@ -54,3 +54,12 @@ def test_serve_config_recipe():
     arr = np.array([s["arrival"] for s in specs])
     assert np.all(np.diff(arr) > 0)
     assert abs(np.mean(np.diff(arr)) - 1.0) < 0.1
+
+
+def test_star_forcing_matches_direct_evaluation():
+    p = W.config_star1024(m=300, n=64, alpha=3.0, seed=5)
+    pts = np.stack([c.ravel() for c in p.grid.nodes()], axis=1)
+    g = np.where(p.geom.inside(pts), p.sol.lap(pts) - 3.0 * p.sol.u(pts), 0.0).reshape(p.g_tilde.shape)
+    assert np.max(np.abs(g - p.g_tilde)) <= 1e-11 * np.max(np.abs(g))
+    pn = W.config_star1024(m=300, n=64, alpha=3.0, seed=5, bc=W.NEUMANN)
+    assert np.allclose(pn.data, np.sum(pn.sol.grad(pn.geom.X) * pn.geom.normal, axis=1), rtol=0, atol=1e-13)
