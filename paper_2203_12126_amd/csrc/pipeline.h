@@ -305,11 +305,22 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         for (int g = 1; g <= G; ++g) r[g] += r[g - 1];
     }
     if (a.grid) {
+        // every load of the block's grid rows is issued before the first is stored
         const double* gr = a.grid + (size_t)rhs * a.grid_stride;
-        for (int id = threadIdx.x; id < N * G; id += T) {
+        constexpr int PER = (N * G + T - 1) / T;
+        double v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int id = threadIdx.x + u * T;
             const int g = id / N, x = id % N;
-            const int line = lines_s[g];
-            if (line >= 0) sr[2 * ((x >> 1) * G + g) + (x & 1)] = (R)(a.cg * gr[(size_t)line * N + x]);
+            const int line = id < N * G ? lines_s[g] : -1;
+            v[u] = line >= 0 ? gr[(size_t)line * N + x] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int id = threadIdx.x + u * T;
+            const int g = id / N, x = id % N;
+            if (id < N * G && lines_s[g] >= 0) sr[2 * ((x >> 1) * G + g) + (x & 1)] = (R)(a.cg * v[u]);
         }
     }
     __syncthreads();
@@ -511,7 +522,10 @@ template <typename R, int N, int OUT>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
     using CF = RowCfg<R, N>;
     constexpr int L = CF::L, G = CF::G, T = CF::T;
-    __shared__ cplx<R> s[L * G];
+    // the block's spectrum rows X[0..L] (line-major, xs) are only read by the
+    // first stage of the inverse transform, whose outputs (s) therefore share the storage
+    __shared__ cplx<R> s[(L + 1) * G];
+    cplx<R>* xs = s;
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     __shared__ int lines_s[G];
@@ -532,14 +546,29 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     // cz in z-2..z+1, of every line of the block
     using TL = Tiles<R, N>;
     constexpr int C = TL::C;
-    __shared__ cplx<R> xs[(L + 1) * G];
     __shared__ int rb[OUT == 0 ? G * 8 : 1], rc[OUT == 0 ? G * 8 : 1], roff[OUT == 0 ? G * 8 + 1 : 1];
-    for (int id = threadIdx.x; id < TL::NT * G * C; id += T) {
-        const int t = id / (G * C), rem = id % (G * C);
-        const int g = rem / C, c = rem % C;
-        const int k = t * C + c;
-        const int line = lines_s[g];
-        if (k <= L) xs[g * (L + 1) + k] = line >= 0 ? spec[TL::idx(line, k)] : cplx<R>{R(0), R(0)};
+    {
+        // every load of the block's rows is issued before the first is stored
+        constexpr int TOT = TL::NT * G * C;
+        constexpr int PER = (TOT + T - 1) / T;
+        cplx<R> v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int id = threadIdx.x + u * T;
+            const int t = id / (G * C), rem = id % (G * C);
+            const int g = rem / C, c = rem % C;
+            const int k = t * C + c;
+            const int line = id < TOT ? lines_s[g] : -1;
+            v[u] = (line >= 0 && k <= L) ? spec[TL::idx(line, k)] : cplx<R>{R(0), R(0)};
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int id = threadIdx.x + u * T;
+            const int t = id / (G * C), rem = id % (G * C);
+            const int g = rem / C, c = rem % C;
+            const int k = t * C + c;
+            if (id < TOT && k <= L) xs[g * (L + 1) + k] = v[u];
+        }
     }
     if constexpr (OUT == 0) {
         const int nz = a.dim == 3 ? 4 : 1;
