@@ -82,15 +82,14 @@ void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st) {
     if (a.cur == (int)a.blocks.size()) {
         Arena::Block blk;
         blk.cap = std::max<size_t>(need, 4u << 20);
-        void* h = nullptr;
-        IBDL_HIP_TRY(hipHostMalloc(&h, blk.cap));
-        blk.host = reinterpret_cast<char*>(h);
-        void* d = nullptr;
-        if (hipMalloc(&d, blk.cap) != hipSuccess) {
-            (void)hipHostFree(h);
-            throw Error{IBDL_ERR_OOM, "device allocation failed (argument tables)"};
+        blk.host = reinterpret_cast<char*>(pinned_get(blk.cap));
+        std::vector<void*> own;
+        try {
+            blk.dev = reinterpret_cast<char*>(dev_alloc(own, blk.cap));
+        } catch (...) {
+            pinned_put(blk.host);
+            throw;
         }
-        blk.dev = reinterpret_cast<char*>(d);
         a.blocks.push_back(blk);
         a.pos = 0;
     }
@@ -109,8 +108,8 @@ void arena_reset(Arena& a) {
 
 void arena_free(Arena& a) {
     for (auto& b : a.blocks) {
-        (void)hipFree(b.dev);
-        (void)hipHostFree(b.host);
+        dev_free(b.dev);
+        pinned_put(b.host);
     }
     a.blocks.clear();
     a.cur = 0;
@@ -208,6 +207,17 @@ void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, doub
     run_pipeline(p, nrhs, in, o, st);
 }
 
+void release_plan(ibdl_plan p, hipStream_t st) {
+    AllocStream as(st);
+    free_build_tmp(p);
+    for (void* a : p->allocs) dev_free(a);
+    p->allocs.clear();
+    free_krylov(p->ks.w);
+    arena_free(p->arena);
+    timing_free(p->own_timing);
+    delete p;
+}
+
 }  // namespace ibdl
 
 using namespace ibdl;
@@ -229,6 +239,8 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
     if (!why.empty()) return fail(IBDL_ERR_ARG, why);
     ibdl_plan p = new (std::nothrow) ibdl_plan_s();
     if (!p) return fail(IBDL_ERR_OOM, "host allocation failed");
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
     p->ks.arena = &p->arena;
     try {
         p->dim = desc->dim;
@@ -261,13 +273,9 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
 
 ibdl_status ibdl_plan_destroy(ibdl_plan p) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    // the plan may have been used on several streams: wait for the device, then free
     (void)hipDeviceSynchronize();
-    free_build_tmp(p);
-    for (void* a : p->allocs) (void)hipFree(a);
-    free_krylov(p->ks.w);
-    arena_free(p->arena);
-    timing_free(p->own_timing);
-    delete p;
+    release_plan(p, nullptr);
     return IBDL_OK;
 }
 
@@ -309,6 +317,8 @@ ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, v
     if (!q || !Aq) return fail(IBDL_ERR_ARG, "q and Aq must be device pointers");
     if (q == Aq) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
     IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
     apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
     return IBDL_OK;
     IBDL_GUARD_END
@@ -320,6 +330,8 @@ ibdl_status ibdl_rhs(ibdl_plan p, int32_t nrhs, const double* data, const double
     if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
     if (!data || !b) return fail(IBDL_ERR_ARG, "data and b must be device pointers");
     IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
     PipeIn in;
     PipeOut out;
     out.out = b;
@@ -357,6 +369,8 @@ ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const doub
     if (o.restart < 1 || o.restart > 200) return fail(IBDL_ERR_ARG, "restart must be in 1..200");
     if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
     IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
     int overall = IBDL_OK;
     p->ks.inst.assign(1, Inst{p, nrhs, 0});
     p->ks.R = nrhs;
@@ -375,6 +389,8 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     if (!sol || !u) return fail(IBDL_ERR_ARG, "sol and u must be device pointers");
     if (p->bc == IBDL_NEUMANN && !vb) return fail(IBDL_ERR_ARG, "Neumann plans need V_b");
     IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
     PipeIn in;
     in.q_dip = sol;
     in.c_dip = -1.0;
@@ -456,6 +472,8 @@ ibdl_status ibdl_batch_create(const ibdl_desc* descs, int32_t count, const int32
     ibdl_batch b = new (std::nothrow) ibdl_batch_s();
     if (!b) return fail(IBDL_ERR_OOM, "host allocation failed");
     b->ks.arena = &b->arena;
+    b->last_stream = S(stream);
+    AllocStream as(S(stream));
     int r0 = 0;
     for (int i = 0; i < count; ++i) {
         ibdl_plan p = nullptr;
@@ -485,8 +503,9 @@ ibdl_status ibdl_batch_create(const ibdl_desc* descs, int32_t count, const int32
 ibdl_status ibdl_batch_destroy(ibdl_batch b) {
     if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
     (void)hipDeviceSynchronize();
+    AllocStream as(nullptr);
     free_krylov(b->ks.w);
-    for (ibdl_plan p : b->plans) ibdl_plan_destroy(p);
+    for (ibdl_plan p : b->plans) release_plan(p, nullptr);
     arena_free(b->arena);
     timing_free(b->timing);
     delete b;
@@ -515,6 +534,8 @@ ibdl_status ibdl_batch_apply(ibdl_batch b, const double* const* q, double* const
         if ((const void*)q[i] == (const void*)Aq[i]) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
     IBDL_GUARD_BEGIN
     IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    AllocStream as(S(stream));
+    b->last_stream = S(stream);
     arena_reset(b->arena);
     auto make = [&](size_t i) {
         const Inst& in = b->ks.inst[i];
@@ -550,6 +571,8 @@ ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const doub
     if (o.x0) return fail(IBDL_ERR_ARG, "opts->x0 must be NULL for a batch (solves start from 0)");
     IBDL_GUARD_BEGIN
     IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    AllocStream as(S(stream));
+    b->last_stream = S(stream);
     SolveIO io;
     io.data.assign(data, data + n);
     io.g.assign(n, nullptr);
@@ -577,6 +600,8 @@ ibdl_status ibdl_batch_eval_grid(ibdl_batch b, const double* const* sol, const d
             return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": Neumann instances need V_b");
     IBDL_GUARD_BEGIN
     IBDL_HIP_TRY(hipStreamSynchronize(S(stream)));
+    AllocStream as(S(stream));
+    b->last_stream = S(stream);
     arena_reset(b->arena);
     auto make = [&](size_t i) {
         const Inst& in = b->ks.inst[i];

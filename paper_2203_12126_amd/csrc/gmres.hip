@@ -365,9 +365,9 @@ __global__ __launch_bounds__(GT) void k_pool_op(KArgs a, int op, double* dst, co
 
 // ------------------------------------------------------------------ host
 void free_krylov(KWork& k) {
-    for (void* p : k.mem) (void)hipFree(p);
+    for (void* p : k.mem) dev_free(p);
     k.mem.clear();
-    if (k.host_pinned) (void)hipHostFree(k.host_pinned);
+    pinned_put(k.host_pinned);
     k.host_pinned = nullptr;
     k.cap_m = 0;
     k.R = 0;
@@ -420,11 +420,15 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     k.Mr = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
     k.voff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
     k.xoff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
-    IBDL_HIP_TRY(hipMemcpy(k.Mr, Mr.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
-    IBDL_HIP_TRY(hipMemcpy(k.voff, voff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
-    IBDL_HIP_TRY(hipMemcpy(k.xoff, xoff.data(), R * sizeof(size_t), hipMemcpyHostToDevice));
+    // stream-ordered allocations: fill them on the same stream, from host memory
+    // that stays valid until the copies are done
+    const hipStream_t ast = alloc_stream();
+    IBDL_HIP_TRY(hipMemcpyAsync(k.Mr, Mr.data(), R * sizeof(int32_t), hipMemcpyHostToDevice, ast));
+    IBDL_HIP_TRY(hipMemcpyAsync(k.voff, voff.data(), R * sizeof(size_t), hipMemcpyHostToDevice, ast));
+    IBDL_HIP_TRY(hipMemcpyAsync(k.xoff, xoff.data(), R * sizeof(size_t), hipMemcpyHostToDevice, ast));
+    IBDL_HIP_TRY(hipStreamSynchronize(ast));
     // host staging: tolerances, skip flags, state, residuals, norms
-    IBDL_HIP_TRY(hipHostMalloc(&k.host_pinned, (size_t)R * (5 * 8 + 9 * 4) + 64));  // the Staging layout
+    k.host_pinned = pinned_get((size_t)R * (5 * 8 + 9 * 4) + 64);  // the Staging layout
     k.cap_m = m;
     k.R = R;
     k.nblk = nblk;
@@ -768,6 +772,7 @@ void SolveTask::output() {
 }
 
 void SolveTask::advance() {
+    AllocStream as(st_);
     KWork& k = ks_.w;
     switch (phase_) {
     case BEGIN: {

@@ -21,6 +21,8 @@
 #pragma once
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include <memory>
 #include <vector>
 
@@ -58,12 +60,17 @@ struct RMax { static constexpr int value = sizeof(R) == 4 ? IBDL_RMAX_F32 : IBDL
 template <typename R>
 struct ColBytes { static constexpr int value = sizeof(R) == 4 ? IBDL_COLB_F32 : IBDL_COLB_F64; };
 
-template <typename R, int N>
+// Row passes: a block transforms G lines of each of RB right-hand sides (GB lines
+// in all); the right-hand sides of a block share the spread and interpolation tables.
+template <typename R, int N, int RB = 1>
 struct RowCfg {
-    static constexpr int L = N / 2;                                      // complex length
-    static constexpr int G = imax(1, imin(64, IBDL_ROW_ELEMS / L));       // lines per block
-    static constexpr int T = imax(256, fft_threads<L, G, RMax<R>::value>());
+    static constexpr int L = N / 2;                                           // complex length
+    static constexpr int G = imax(1, imin(64, IBDL_ROW_ELEMS / L) / RB);      // lines per rhs
+    static constexpr int GB = G * RB;                                         // lines per block
+    static constexpr int T = imax(256, fft_threads<L, GB, RMax<R>::value>());
 };
+// right-hand sides per row block the library is built for
+#define IBDL_ROW_RBS(X) X(1) X(2) X(4)
 template <typename R, int N>
 struct ColCfg {
     // at most 128 KiB of LDS for the block's lines
@@ -143,6 +150,7 @@ struct RowFwdArgs {
     size_t spec_stride;
     int P;
     const cplx<R>* tw;
+    int nrhs;
 };
 
 template <typename R>
@@ -186,6 +194,7 @@ struct RowInvArgs {
     size_t part_stride;
     int M;
     int dim;
+    int nrhs;
 };
 
 // ------------------------------------------------------------ jobs
@@ -215,23 +224,30 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
 
 // ------------------------------------------------------------ spread phase
 // Adds coef * (sum_e w_e q[k_e]) into the LDS lines for every active node of
-// the block's lines.  Each node is written by exactly one thread.  la[g] is the
-// first active node of line g of the block and rs the prefix sums of the lines'
-// active-node counts (both in LDS).
-template <typename R, int N, int G, int T>
-__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs, int it, const int* la,
-                                             const int* rs) {
+// the block's lines, for each of the block's right-hand sides (rhs_s[rr] >= 0):
+// the entries of a node are loaded once for all of them.  Each node is written
+// by exactly one thread, its entries summed in their stored order.  la[g] is the
+// first active node of line g and rs the prefix sums of the lines' node counts.
+template <typename R, int N, int G, int RB, int T>
+__device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it, const int* la, const int* rs,
+                                             const int* rhs_s) {
+    constexpr int GB = G * RB;
     const int total = rs[G];
-    const double* q = c.q + (size_t)rhs * c.q_stride + (size_t)it * c.q_jstride;
-    for (int f = threadIdx.x; f < total; f += T) {
-        int lo = 0, hi = G;  // find g with rs[g] <= f < rs[g+1]
+    // work item f: node f / RB for the block's right-hand side f % RB; the RB items of
+    // a node sit in adjacent lanes, so their entry loads are one request per wavefront
+    for (int f = threadIdx.x; f < total * RB; f += T) {
+        const int rr = f % RB, nf = f / RB;
+        const int r = rhs_s[rr];
+        if (r < 0) continue;
+        int lo = 0, hi = G;  // find g with rs[g] <= nf < rs[g+1]
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (rs[mid] <= f) lo = mid; else hi = mid;
+            if (rs[mid] <= nf) lo = mid; else hi = mid;
         }
         const int g = lo;
-        const int a = la[g] + (f - rs[g]);
+        const int a = la[g] + (nf - rs[g]);
         const int x = (int)(c.act_node[a] % (uint32_t)N);
+        const double* q = c.q + (size_t)r * c.q_stride + (size_t)it * c.q_jstride;
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
         // entries in groups of 8: every load of a group is issued before any is used
@@ -253,27 +269,36 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int rhs
             for (int u = 0; u < 8; ++u)
                 if (u < cnt) acc.add(ww[u], (R)qq[u]);
         }
-        sr[2 * ((x >> 1) * G + g) + (x & 1)] += (R)c.coef * acc.value();
+        sr[2 * ((x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
     __syncthreads();
 }
 
 // ------------------------------------------------------------ row_fwd
-template <typename R, int N>
+// Block lb covers lines [b G, b G + G) of the line list for the right-hand sides
+// rg RB .. rg RB + RB - 1 (b = lb % nblk, rg = lb / nblk); LDS line rr G + g holds
+// line g of the rr-th of them.
+template <typename R, int N, int RB>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int it) {
-    using CF = RowCfg<R, N>;
-    constexpr int L = CF::L, G = CF::G, T = CF::T;
-    __shared__ cplx<R> s[L * G];
+    using CF = RowCfg<R, N, RB>;
+    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
+    __shared__ cplx<R> s[L * GB];
     __shared__ int rs[2][G + 1], la[2][G];
-    __shared__ int lines_s[G];
+    __shared__ int lines_s[G], rhs_s[RB];
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     R* sr = reinterpret_cast<R*>(s);
-    const int rhs = lb / a.nblk;
+    const int rg = lb / a.nblk;
     const int first = (lb % a.nblk) * G;
-    // every table load of the block at once: skip flag, twiddles, line ids and
+    // every table load of the block at once: skip flags, twiddles, line ids and
     // the lines' active-node ranges of both spread matrices
-    const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
+    int live = 0, rv[RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+        const int r = rg * RB + rr;
+        rv[rr] = (r < a.nrhs && !(a.skip && a.skip[4 * r])) ? r : -1;
+        live |= rv[rr] >= 0;
+    }
     const auto tw = TWL::template load<T>(twl, a.tw);
     if (threadIdx.x < G) {
         const int g = threadIdx.x;
@@ -296,8 +321,9 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         la[1][g] = m0;
         rs[1][g + 1] = m1 - m0;
     }
-    if (skipv) return;
-    for (int i = threadIdx.x; i < L * G; i += T) s[i] = cplx<R>{R(0), R(0)};
+    if (!live) return;
+    if (threadIdx.x < RB) rhs_s[threadIdx.x] = rv[threadIdx.x];
+    for (int i = threadIdx.x; i < L * GB; i += T) s[i] = cplx<R>{R(0), R(0)};
     __syncthreads();
     if (threadIdx.x < 2) {
         int* r = rs[threadIdx.x];
@@ -306,52 +332,52 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     }
     if (a.grid) {
         // every load of the block's grid rows is issued before the first is stored
-        const double* gr = a.grid + (size_t)rhs * a.grid_stride;
-        constexpr int PER = (N * G + T - 1) / T;
+        constexpr int PER = (N * GB + T - 1) / T;
         double v[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
-            const int g = id / N, x = id % N;
-            const int line = id < N * G ? lines_s[g] : -1;
-            v[u] = line >= 0 ? gr[(size_t)line * N + x] : 0.0;
+            const int l = id / N, x = id % N;
+            const int line = id < N * GB ? lines_s[l % G] : -1;
+            const int r = id < N * GB ? rhs_s[l / G] : -1;
+            v[u] = (line >= 0 && r >= 0) ? a.grid[(size_t)r * a.grid_stride + (size_t)line * N + x] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
-            const int g = id / N, x = id % N;
-            if (id < N * G && lines_s[g] >= 0) sr[2 * ((x >> 1) * G + g) + (x & 1)] = (R)(a.cg * v[u]);
+            const int l = id / N, x = id % N;
+            if (id < N * GB) sr[2 * ((x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
         }
     }
     __syncthreads();
-    if (a.dip.q) spread_phase<R, N, G, T>(sr, a.dip, rhs, it, la[0], rs[0]);
-    if (a.mono.q) spread_phase<R, N, G, T>(sr, a.mono, rhs, it, la[1], rs[1]);
+    if (a.dip.q) spread_phase<R, N, G, RB, T>(sr, a.dip, it, la[0], rs[0], rhs_s);
+    if (a.mono.q) spread_phase<R, N, G, RB, T>(sr, a.mono, it, la[1], rs[1], rhs_s);
 
-    run_fft<R, L, G, T, N, -1>(s, tw, LdsLoad<R, G>{s}, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, GB, T, N, -1>(s, tw, LdsLoad<R, GB>{s}, LdsStore<R, GB>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
     // written in tile order so that consecutive threads store consecutive addresses
     using TL = Tiles<R, N>;
     constexpr int C = TL::C;
-    cplx<R>* out = a.spec + (size_t)rhs * a.spec_stride;
-    for (int id = threadIdx.x; id < TL::NT * G * C; id += T) {
-        const int t = id / (G * C), rem = id % (G * C);
-        const int g = rem / C, c = rem % C;
+    for (int id = threadIdx.x; id < TL::NT * GB * C; id += T) {
+        const int t = id / (GB * C), rem = id % (GB * C);
+        const int l = rem / C, c = rem % C;
         const int k = t * C + c;
-        const int line = lines_s[g];
-        if (k > L || line < 0) continue;
-        const cplx<R> zk = s[(k % L) * G + g];
-        const cplx<R> zm = s[((L - k) % L) * G + g];
+        const int line = lines_s[l % G];
+        const int r = rhs_s[l / G];
+        if (k > L || line < 0 || r < 0) continue;
+        const cplx<R> zk = s[(k % L) * GB + l];
+        const cplx<R> zm = s[((L - k) % L) * GB + l];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
-        out[TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
+        a.spec[(size_t)r * a.spec_stride + TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
     }
 }
-template <typename R, int N, bool MULTI>
-__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_fwd(RowFwdArgs<R> a0, Jobs<RowFwdArgs<R>> js,
-                                                               int it) {
-    IBDL_JOB_ENTRY((row_fwd_body<R, N>), RowFwdArgs<R>, a0, js, it)
+template <typename R, int N, int RB, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N, RB>::T)) void k_row_fwd(RowFwdArgs<R> a0, Jobs<RowFwdArgs<R>> js,
+                                                                   int it) {
+    IBDL_JOB_ENTRY((row_fwd_body<R, N, RB>), RowFwdArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ col
@@ -517,31 +543,38 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<
 }
 
 // ------------------------------------------------------------ row_inv
-// OUT 0: interpolation partial sums; OUT 1: grid output.
-template <typename R, int N, int OUT>
+// OUT 0: interpolation partial sums; OUT 1: grid output.  Blocks map to lines
+// and right-hand sides as in row_fwd.
+template <typename R, int N, int OUT, int RB>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
-    using CF = RowCfg<R, N>;
-    constexpr int L = CF::L, G = CF::G, T = CF::T;
+    using CF = RowCfg<R, N, RB>;
+    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
     // the block's spectrum rows X[0..L] (line-major, xs) are only read by the
     // first stage of the inverse transform, whose outputs (s) therefore share the storage
-    __shared__ cplx<R> s[(L + 1) * G];
+    __shared__ cplx<R> s[(L + 1) * GB];
     cplx<R>* xs = s;
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
     __shared__ cplx<R> twl[TWL::SIZE];
-    __shared__ int lines_s[G];
+    __shared__ int lines_s[G], rhs_s[RB];
     R* sr = reinterpret_cast<R*>(s);
-    const int rhs = lb / a.nblk;
+    const int rg = lb / a.nblk;
     const int first = (lb % a.nblk) * G;
-    const int32_t skipv = a.skip ? a.skip[4 * rhs] : 0;
+    int live = 0, rv[RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+        const int r = rg * RB + rr;
+        rv[rr] = (r < a.nrhs && !(a.skip && a.skip[4 * r])) ? r : -1;
+        live |= rv[rr] >= 0;
+    }
     const auto tw = TWL::template load<T>(twl, a.tw);
     if (threadIdx.x < G) {
         const int li = first + threadIdx.x;
         lines_s[threadIdx.x] = li < a.nproc ? (a.lines ? a.lines[li] : li) : -1;
     }
-    if (skipv) return;
+    if (!live) return;
+    if (threadIdx.x < RB) rhs_s[threadIdx.x] = rv[threadIdx.x];
     __syncthreads();
-    const cplx<R>* spec = a.spec + (size_t)rhs * a.spec_stride;
-    // the block's rows X[0..L], read in tile order (consecutive threads, consecutive addresses),
+    // the block's rows, read in tile order (consecutive threads, consecutive addresses),
     // and (interpolation) the sorted-point ranges of the x-lines (cy, cz), cy in y-2..y+1,
     // cz in z-2..z+1, of every line of the block
     using TL = Tiles<R, N>;
@@ -549,25 +582,27 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     __shared__ int rb[OUT == 0 ? G * 8 : 1], rc[OUT == 0 ? G * 8 : 1], roff[OUT == 0 ? G * 8 + 1 : 1];
     {
         // every load of the block's rows is issued before the first is stored
-        constexpr int TOT = TL::NT * G * C;
+        constexpr int TOT = TL::NT * GB * C;
         constexpr int PER = (TOT + T - 1) / T;
         cplx<R> v[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
-            const int t = id / (G * C), rem = id % (G * C);
-            const int g = rem / C, c = rem % C;
+            const int t = id / (GB * C), rem = id % (GB * C);
+            const int l = rem / C, c = rem % C;
             const int k = t * C + c;
-            const int line = id < TOT ? lines_s[g] : -1;
-            v[u] = (line >= 0 && k <= L) ? spec[TL::idx(line, k)] : cplx<R>{R(0), R(0)};
+            const int line = id < TOT ? lines_s[l % G] : -1;
+            const int r = id < TOT ? rhs_s[l / G] : -1;
+            v[u] = (line >= 0 && r >= 0 && k <= L) ? a.spec[(size_t)r * a.spec_stride + TL::idx(line, k)]
+                                                   : cplx<R>{R(0), R(0)};
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
-            const int t = id / (G * C), rem = id % (G * C);
-            const int g = rem / C, c = rem % C;
+            const int t = id / (GB * C), rem = id % (GB * C);
+            const int l = rem / C, c = rem % C;
             const int k = t * C + c;
-            if (id < TOT && k <= L) xs[g * (L + 1) + k] = v[u];
+            if (id < TOT && k <= L) xs[l * (L + 1) + k] = v[u];
         }
     }
     if constexpr (OUT == 0) {
@@ -603,8 +638,8 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
         }
     }
     __syncthreads();
-    // interpolation: the first point of every thread, fetched before the transform
-    int pf_s = -1, pf_r = 0;
+    // interpolation: the first work item of every thread, fetched before the transform
+    int pf_s = -1, pf_r = 0, pf_rr = 0;
     int pf_cell[3] = {0, 0, 0};
     R pf_tp[12];
     if constexpr (OUT == 0) {
@@ -617,8 +652,9 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             roff[G * 8] = acc;
         }
         __syncthreads();
-        const int f = threadIdx.x;
-        if (f < roff[G * 8]) {
+        const int f = threadIdx.x / RB;
+        pf_rr = threadIdx.x % RB;
+        if ((int)threadIdx.x < roff[G * 8] * RB) {
             int lo = 0, hi = G * 8;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -633,37 +669,42 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
         }
     }
     // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
-    auto split = [&](int k, int g) -> cplx<R> {
-        const cplx<R> xk = xs[g * (L + 1) + k];
-        const cplx<R> xm = xs[g * (L + 1) + L - k];
+    auto split = [&](int k, int l) -> cplx<R> {
+        const cplx<R> xk = xs[l * (L + 1) + k];
+        const cplx<R> xm = xs[l * (L + 1) + L - k];
         const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
         const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
         return cadd(e, cmul_si<1>(cmul(cconj(tw.get(k)), d)));
     };
-    run_fft<R, L, G, T, N, +1>(s, tw, split, LdsStore<R, G>{s}, FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, GB, T, N, +1>(s, tw, split, LdsStore<R, GB>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     if constexpr (OUT == 1) {
-        double* u = a.u + (size_t)rhs * a.u_stride;
-        for (int id = threadIdx.x; id < G * N; id += T) {
-            const int g = id / N, x = id % N;
-            const int line = lines_s[g];
-            if (line >= 0) u[(size_t)line * N + x] = (double)sr[2 * ((x >> 1) * G + g) + (x & 1)];
+        for (int id = threadIdx.x; id < GB * N; id += T) {
+            const int l = id / N, x = id % N;
+            const int line = lines_s[l % G];
+            const int r = rhs_s[l / G];
+            if (line >= 0 && r >= 0)
+                a.u[(size_t)r * a.u_stride + (size_t)line * N + x] = (double)sr[2 * ((x >> 1) * GB + l) + (x & 1)];
         }
     } else {
-        R* part = a.part + (size_t)rhs * a.part_stride;
         const int gpp = a.dim == 3 ? 16 : 4;
-        auto gather = [&](int r, int sidx, const int* cell, const R* tp) {
-            const int g = r / 8;
+        // work item f: point f / RB for the block's right-hand side f % RB (adjacent
+        // lanes share the point's cell and taps)
+        auto gather = [&](int rr8, int rr, int sidx, const int* cell, const R* tp) {
+            const int r = rhs_s[rr];
+            if (r < 0) return;
+            const int g = rr8 / 8;
             const int line = lines_s[g];
             const int y = line % N, z = line / N;
             const int cx = cell[0], cy = cell[1];
             const int oy = (y - cy + 1 + N) % N;
+            const int l = rr * G + g;
             R acc = R(0);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int x = (cx - 1 + t + N) % N;
-                acc += tp[t] * sr[2 * ((x >> 1) * G + g) + (x & 1)];
+                acc += tp[t] * sr[2 * ((x >> 1) * GB + l) + (x & 1)];
             }
             acc *= tp[4 + oy];
             int o = oy;
@@ -672,31 +713,32 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
                 acc *= tp[8 + oz];
                 o += 4 * oz;
             }
-            part[(size_t)sidx * gpp + o] = acc;
+            a.part[(size_t)r * a.part_stride + (size_t)sidx * gpp + o] = acc;
         };
-        if (pf_s >= 0) gather(pf_r, pf_s, pf_cell, pf_tp);
-        const int total = roff[G * 8];
+        if (pf_s >= 0) gather(pf_r, pf_rr, pf_s, pf_cell, pf_tp);
+        const int total = roff[G * 8] * RB;
         for (int f = threadIdx.x + T; f < total; f += T) {
-            int lo = 0, hi = G * 8;  // range r with roff[r] <= f < roff[r+1]
+            const int rr = f % RB, pf = f / RB;
+            int lo = 0, hi = G * 8;  // range r with roff[r] <= pf < roff[r+1]
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (roff[mid] <= f) lo = mid; else hi = mid;
+                if (roff[mid] <= pf) lo = mid; else hi = mid;
             }
-            const int sidx = rb[lo] + (f - roff[lo]);
+            const int sidx = rb[lo] + (pf - roff[lo]);
             int cell[3];
             R tp[12];
 #pragma unroll
             for (int d = 0; d < 3; ++d) cell[d] = a.cell[3 * sidx + d];
 #pragma unroll
             for (int u = 0; u < 12; ++u) tp[u] = a.taps[(size_t)sidx * 12 + u];
-            gather(lo, sidx, cell, tp);
+            gather(lo, rr, sidx, cell, tp);
         }
     }
 }
-template <typename R, int N, int OUT, bool MULTI>
-__global__ __launch_bounds__((RowCfg<R, N>::T)) void k_row_inv(RowInvArgs<R> a0, Jobs<RowInvArgs<R>> js,
-                                                               int it) {
-    IBDL_JOB_ENTRY((row_inv_body<R, N, OUT>), RowInvArgs<R>, a0, js, it)
+template <typename R, int N, int OUT, int RB, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N, RB>::T)) void k_row_inv(RowInvArgs<R> a0, Jobs<RowInvArgs<R>> js,
+                                                                   int it) {
+    IBDL_JOB_ENTRY((row_inv_body<R, N, OUT, RB>), RowInvArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ finish
@@ -796,9 +838,10 @@ __global__ __launch_bounds__(FIN_T) void k_finish(FinishArgs a0, Jobs<FinishArgs
     X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 template <typename R>
-inline int row_lines_per_block(int n) {
+inline int row_lines_per_block(int n, int rb) {
     switch (n) {
-#define IBDL_C(NN) case NN: return RowCfg<R, NN>::G;
+#define IBDL_C(NN) \
+    case NN: return rb == 4 ? RowCfg<R, NN, 4>::G : rb == 2 ? RowCfg<R, NN, 2>::G : RowCfg<R, NN, 1>::G;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
@@ -858,16 +901,23 @@ struct StageTable {
     }
 };
 
-template <typename R, bool MULTI>
-void launch_row_fwd_t(int n, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
-                      Jobs<RowFwdArgs<R>> js, int it) {
+template <typename R, int RB, bool MULTI>
+void launch_row_fwd_rb(int n, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
+                       Jobs<RowFwdArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                       \
-    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN, MULTI>), dim3(blocks), dim3(RowCfg<R, NN>::T), 0, st, \
-                                   e.a, e.b, 0, a, js, it); break;
+#define IBDL_C(NN)                                                                                          \
+    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN, RB, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, RB>::T), 0, \
+                                   st, e.a, e.b, 0, a, js, it); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
+}
+template <typename R, bool MULTI>
+void launch_row_fwd_t(int n, int rb, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
+                      Jobs<RowFwdArgs<R>> js, int it) {
+    if (rb == 4) launch_row_fwd_rb<R, 4, MULTI>(n, blocks, st, e, a, js, it);
+    else if (rb == 2) launch_row_fwd_rb<R, 2, MULTI>(n, blocks, st, e, a, js, it);
+    else launch_row_fwd_rb<R, 1, MULTI>(n, blocks, st, e, a, js, it);
 }
 template <typename R, int MODE, bool ZPASS, bool MULTI>
 void launch_col_t(int n, int blocks, hipStream_t st, StageEv e, const ColArgs<R>& a, Jobs<ColArgs<R>> js,
@@ -883,16 +933,23 @@ void launch_col_t(int n, int blocks, hipStream_t st, StageEv e, const ColArgs<R>
 #undef IBDL_C
     }
 }
-template <typename R, int OUT, bool MULTI>
-void launch_row_inv_t(int n, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
-                      Jobs<RowInvArgs<R>> js, int it) {
+template <typename R, int OUT, int RB, bool MULTI>
+void launch_row_inv_rb(int n, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
+                       Jobs<RowInvArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                        \
-    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT, MULTI>), dim3(blocks), dim3(RowCfg<R, NN>::T), 0, \
-                                   st, e.a, e.b, 0, a, js, it); break;
+#define IBDL_C(NN)                                                                                           \
+    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT, RB, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, RB>::T), \
+                                   0, st, e.a, e.b, 0, a, js, it); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
+}
+template <typename R, int OUT, bool MULTI>
+void launch_row_inv_t(int n, int rb, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
+                      Jobs<RowInvArgs<R>> js, int it) {
+    if (rb == 4) launch_row_inv_rb<R, OUT, 4, MULTI>(n, blocks, st, e, a, js, it);
+    else if (rb == 2) launch_row_inv_rb<R, OUT, 2, MULTI>(n, blocks, st, e, a, js, it);
+    else launch_row_inv_rb<R, OUT, 1, MULTI>(n, blocks, st, e, a, js, it);
 }
 
 template <typename R>
@@ -917,6 +974,7 @@ struct PlanPrec<float> {
 template <typename R>
 struct PreparedT : PreparedPass {
     int n = 0, dim = 2;
+    int rb = 1;  // right-hand sides per row block
     bool dense_out = false;
     ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
     StageTable<RowFwdArgs<R>> rf;
@@ -940,8 +998,8 @@ struct PreparedT : PreparedPass {
         {
             const StageEv e = stage_events(tplan, stage++, "spread+fft_x");
             go(rf, [&](bool m) {
-                if (m) launch_row_fwd_t<R, true>(n, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
-                else launch_row_fwd_t<R, false>(n, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
+                if (m) launch_row_fwd_t<R, true>(n, rb, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
+                else launch_row_fwd_t<R, false>(n, rb, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
             });
         }
         if (dim == 2) {
@@ -970,14 +1028,14 @@ struct PreparedT : PreparedPass {
         if (dense_out) {
             const StageEv e = stage_events(tplan, stage++, "ifft_x");
             go(ri, [&](bool m) {
-                if (m) launch_row_inv_t<R, 1, true>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-                else launch_row_inv_t<R, 1, false>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                if (m) launch_row_inv_t<R, 1, true>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                else launch_row_inv_t<R, 1, false>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
             });
         } else {
             StageEv e = stage_events(tplan, stage++, "ifft_x+interp");
             go(ri, [&](bool m) {
-                if (m) launch_row_inv_t<R, 0, true>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-                else launch_row_inv_t<R, 0, false>(n, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                if (m) launch_row_inv_t<R, 0, true>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
+                else launch_row_inv_t<R, 0, false>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
             });
             e = stage_events(tplan, stage++, "finish");
             go(fi, [&](bool m) {
@@ -1003,7 +1061,13 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
     P->dim = p0->dim;
     P->dense_out = jobs[0].out.u != nullptr;
     P->tplan = p0;
-    const int G = row_lines_per_block<R>(n);
+    // right-hand sides per row block: the largest of 4, 2, 1 that no job of the
+    // pass leaves partly empty
+    int minr = 1 << 30;
+    for (const PassJob& jb : jobs) minr = std::min(minr, jb.nrhs);
+    P->rb = minr >= 4 ? 4 : minr >= 2 ? 2 : 1;
+    const int RBv = P->rb;
+    const int G = row_lines_per_block<R>(n, RBv);
     const int C = col_width<R>(n);
     const int NT = col_tiles<R>(n);
     const size_t plane = (size_t)NT * n * C;
@@ -1047,7 +1111,8 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ra.spec_stride = sstride;
         ra.P = p->P;
         ra.tw = PP::tw(p);
-        P->rf.add(ra, ra.nblk * nrhs);
+        ra.nrhs = nrhs;
+        P->rf.add(ra, ra.nblk * ((nrhs + RBv - 1) / RBv));
 
         // ---- columns
         ColArgs<R> ca{};
@@ -1121,7 +1186,8 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ia.part_stride = (size_t)p->M * p->gpp;
         ia.M = p->M;
         ia.dim = p->dim;
-        P->ri.add(ia, ia.nblk * nrhs);
+        ia.nrhs = nrhs;
+        P->ri.add(ia, ia.nblk * ((nrhs + RBv - 1) / RBv));
 
         // ---- finish
         if (!dense_out) {

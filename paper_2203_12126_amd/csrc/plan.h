@@ -170,10 +170,12 @@ struct ibdl_plan_s {
 
     std::vector<void*> allocs;     // everything to free
     std::vector<void*> build_tmp;  // construction temporaries
+    hipStream_t last_stream = nullptr;  // stream of the latest call
 };
 
 // Many independent instances solved together (one plan per instance).
 struct ibdl_batch_s {
+    hipStream_t last_stream = nullptr;
     std::vector<ibdl_plan> plans;
     ibdl::KrylovSet ks;
     ibdl::Arena arena;
@@ -221,8 +223,22 @@ struct PipeOut {
 // records msg as this host thread's last error and returns status
 ibdl_status set_error(int status, const std::string& msg);
 
+// Device memory is stream ordered (the device's default memory pool, which keeps
+// freed memory for reuse): allocations and frees are placed on the calling
+// thread's current allocation stream, set by AllocStream for the duration of a call.
 void* dev_alloc(std::vector<void*>& owner, size_t bytes);
 void* dev_alloc(ibdl_plan p, size_t bytes);
+void dev_free(void* ptr);
+hipStream_t alloc_stream();
+struct AllocStream {
+    hipStream_t prev;
+    explicit AllocStream(hipStream_t s);
+    ~AllocStream();
+};
+// Pinned host staging blocks, kept for reuse until the process ends (releasing
+// pinned memory can wait for the whole device).
+void* pinned_get(size_t bytes);
+void pinned_put(void* ptr);
 void ensure_workspace(ibdl_plan p, int nrhs);
 
 // One job of a grid pass: a plan, its right-hand sides, inputs and outputs.
@@ -249,6 +265,8 @@ int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
 void free_build_tmp(ibdl_plan p);
+// frees every device allocation of a plan in stream order on st (no wait) and the plan
+void release_plan(ibdl_plan p, hipStream_t st);
 // GMRES (with FP64 refinement for mixed plans) for every instance of the set:
 // per instance i the data, forcing (or null), initial iterate (or null) and
 // solution buffers, [nrhs_i][M_i] / [nrhs_i][n^d].  info: host [R].

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 
@@ -22,16 +24,84 @@
 namespace ibdl {
 
 // ------------------------------------------------------------------ alloc
+static thread_local hipStream_t t_alloc_stream = nullptr;
+
+hipStream_t alloc_stream() { return t_alloc_stream; }
+AllocStream::AllocStream(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
+AllocStream::~AllocStream() { t_alloc_stream = prev; }
+
+// the default pool of the current device keeps freed memory instead of returning it
+static void keep_pool_memory() {
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done.push_back(dev);
+}
+
 void* dev_alloc(std::vector<void*>& owner, size_t bytes) {
+    keep_pool_memory();
     void* ptr = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&ptr, bytes);
+    hipError_t e = hipMallocAsync(&ptr, bytes, t_alloc_stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw Error{IBDL_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        throw Error{IBDL_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     }
     owner.push_back(ptr);
     return ptr;
+}
+
+void dev_free(void* ptr) {
+    if (ptr) (void)hipFreeAsync(ptr, t_alloc_stream);
+}
+
+static std::mutex g_pinned_mu;
+static std::vector<std::pair<void*, size_t>> g_pinned_free;
+static std::vector<std::pair<void*, size_t>> g_pinned_used;
+
+void* pinned_get(size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    size_t best = SIZE_MAX;
+    int bi = -1;
+    for (size_t i = 0; i < g_pinned_free.size(); ++i)
+        if (g_pinned_free[i].second >= bytes && g_pinned_free[i].second < best) {
+            best = g_pinned_free[i].second;
+            bi = (int)i;
+        }
+    if (bi >= 0) {
+        auto blk = g_pinned_free[bi];
+        g_pinned_free.erase(g_pinned_free.begin() + bi);
+        g_pinned_used.push_back(blk);
+        return blk.first;
+    }
+    const size_t cap = std::max<size_t>((bytes + 4095) / 4096 * 4096, 4096);
+    void* h = nullptr;
+    if (hipHostMalloc(&h, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{IBDL_ERR_OOM, "pinned host allocation failed"};
+    }
+    g_pinned_used.emplace_back(h, cap);
+    return h;
+}
+
+void pinned_put(void* ptr) {
+    if (!ptr) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    for (size_t i = 0; i < g_pinned_used.size(); ++i)
+        if (g_pinned_used[i].first == ptr) {
+            g_pinned_free.push_back(g_pinned_used[i]);
+            g_pinned_used.erase(g_pinned_used.begin() + i);
+            return;
+        }
 }
 void* dev_alloc(ibdl_plan p, size_t bytes) { return dev_alloc(p->allocs, bytes); }
 
@@ -580,7 +650,7 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
 }
 
 void free_build_tmp(ibdl_plan p) {
-    for (void* t : p->build_tmp) (void)hipFree(t);
+    for (void* t : p->build_tmp) dev_free(t);
     p->build_tmp.clear();
 }
 
@@ -589,11 +659,13 @@ void ensure_workspace(ibdl_plan p, int nrhs) {
     // sized for FP64: mixed plans run their once-per-solve passes in FP64
     const size_t cs = 16;
     const size_t rs = 8;
-    // grow: hipFree waits for the device to finish work that may still use the old buffers
+    // grow: the old buffers are freed in stream order after the work already queued
+    // on the plan's stream (a switch of stream waits for the old one first)
+    if (p->ws.spec && p->last_stream != alloc_stream()) IBDL_HIP_TRY(hipStreamSynchronize(p->last_stream));
     for (void* old : {p->ws.spec, p->ws.part}) {
         if (!old) continue;
         p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), old), p->allocs.end());
-        (void)hipFree(old);
+        dev_free(old);
     }
     p->ws.spec = p->ws.part = nullptr;
     p->ws.cap_rhs = 0;

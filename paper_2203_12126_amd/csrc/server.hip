@@ -106,14 +106,16 @@ static void complete(ibdl_server s, const std::shared_ptr<Request>& r, bool admi
     s->cv_done.notify_all();
 }
 
+// frees in stream order on the cohort's stream: no wait for other cohorts
 static void release_cohort(ibdl_server s, Cohort& c) {
     const hipStream_t st = s->streams[c.slot];
     (void)hipStreamSynchronize(st);
+    AllocStream as(st);
     c.task.reset();
     free_krylov(c.ks.w);
     arena_free(c.arena);
     for (auto& r : c.reqs) {
-        if (r->plan) ibdl_plan_destroy(r->plan);
+        if (r->plan) release_plan(r->plan, st);
         r->plan = nullptr;
     }
 }
@@ -175,9 +177,10 @@ static std::unique_ptr<Cohort> start_cohort(ibdl_server s, std::vector<std::shar
         }
         if (status == IBDL_OK) {
             try {
+                AllocStream as(st);
                 ensure_workspace(p, r->nrhs);
             } catch (const Error& e) {
-                ibdl_plan_destroy(p);
+                release_plan(p, st);
                 p = nullptr;
                 status = (ibdl_status)e.status;
             }
