@@ -2,8 +2,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -206,6 +209,24 @@ void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, doub
     o.cB = p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
     run_pipeline(p, nrhs, in, o, st);
 }
+
+// ------------------------------------------------------------------ tile autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, float>> g_tune;
+std::atomic<int> g_tune_on{1};
+}  // namespace
+
+int tune_lookup(const TuneKey& k) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(k);
+    return it == g_tune.end() ? -1 : it->second.first;
+}
+void tune_store(const TuneKey& k, int variant, float ms) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[k] = {variant, ms};
+}
+bool tune_enabled() { return g_tune_on.load() != 0; }
 
 void release_plan(ibdl_plan p, hipStream_t st) {
     AllocStream as(st);
@@ -639,6 +660,37 @@ ibdl_status ibdl_batch_stage_times(ibdl_batch b, double* ms_host, const char** n
     if (count) *count = n;
     return IBDL_OK;
     IBDL_GUARD_END
+}
+
+// ------------------------------------------------------------------ tuning
+ibdl_status ibdl_set_autotune(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_on.store(enable ? 1 : 0);
+    return IBDL_OK;
+}
+
+int32_t ibdl_autotune_report(char* buf, size_t cap) {
+    std::string out;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto& kv : g_tune) {
+            const TuneKey& k = kv.first;
+            char line[200];
+            std::snprintf(line, sizeof(line),
+                          "%s dim=%d n=%d stage=%s out=%s min_rhs_bucket=%d total_rhs_bucket=%d jobs=%s -> rhs_per_block=%d (%.4f ms)\n",
+                          k.rbytes == 8 ? "fp64" : "fp32", k.dim, k.n, k.stage == 0 ? "row_fwd" : "row_inv",
+                          k.dense ? "grid" : "points", k.minr, k.totr, k.multi ? "many" : "one",
+                          1 << kv.second.first, kv.second.second);
+            out += line;
+        }
+    }
+    if (buf && cap) {
+        const size_t n = std::min(cap - 1, out.size());
+        std::memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return (int32_t)out.size();
 }
 
 }  // extern "C"

@@ -971,23 +971,80 @@ struct PlanPrec<float> {
 
 // One pass of L^-1 for one or more jobs of the same dimension, grid size and
 // precision: per stage a table of per-job arguments.
+// right-hand sides per row block of the variants built: index 0, 1, 2 -> 1, 2, 4
+constexpr int kRowRB[3] = {1, 2, 4};
+
 template <typename R>
 struct PreparedT : PreparedPass {
     int n = 0, dim = 2;
-    int rb = 1;  // right-hand sides per row block
     bool dense_out = false;
+    int min_nrhs = 1, total_rhs = 1, njobs = 1;
     ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
-    StageTable<RowFwdArgs<R>> rf;
+    StageTable<RowFwdArgs<R>> rf[3];  // one table per row-block variant
     StageTable<ColArgs<R>> col[3];
-    StageTable<RowInvArgs<R>> ri;
+    StageTable<RowInvArgs<R>> ri[3];
     StageTable<FinishArgs> fi;
 
     void upload(Arena& ar, hipStream_t st) override {
-        rf.upload(ar, st);
+        for (auto& t : rf) t.upload(ar, st);
         for (auto& c : col) c.upload(ar, st);
-        ri.upload(ar, st);
+        for (auto& t : ri) t.upload(ar, st);
         fi.upload(ar, st);
     }
+    TuneKey key(int stage) const {
+        return TuneKey{(int)sizeof(R), dim, n, stage, dense_out ? 1 : 0, tune_bucket(min_nrhs),
+                       tune_bucket(total_rhs), njobs > 1 ? 1 : 0};
+    }
+    void fwd(int v, int it, hipStream_t st, StageEv e) {
+        const auto& t = rf[v];
+        go(t, [&](bool m) {
+            if (m) launch_row_fwd_t<R, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+            else launch_row_fwd_t<R, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+        });
+    }
+    void inv(int v, int it, hipStream_t st, StageEv e) {
+        const auto& t = ri[v];
+        go(t, [&](bool m) {
+            if (dense_out) {
+                if (m) launch_row_inv_t<R, 1, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+                else launch_row_inv_t<R, 1, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+            } else {
+                if (m) launch_row_inv_t<R, 0, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+                else launch_row_inv_t<R, 0, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+            }
+        });
+    }
+    // The row-block variant of a stage: the tuned choice for this pass's key; with no
+    // choice yet, every variant runs (each produces the same output, since the
+    // arithmetic of a line and of a point does not depend on the grouping), is timed
+    // on its second run, and the fastest is kept.
+    template <class F>
+    int pick(int stage, int it, hipStream_t st, F&& launch) {
+        int v = tune_lookup(key(stage));
+        if (v >= 0) return v;
+        if (!tune_enabled()) return heuristic();
+        float best = 1e30f;
+        int bv = heuristic();
+        hipEvent_t e0, e1;
+        IBDL_HIP_TRY(hipEventCreate(&e0));
+        IBDL_HIP_TRY(hipEventCreate(&e1));
+        for (int c = 0; c < 3; ++c) {
+            launch(c, StageEv{});
+            launch(c, StageEv{e0, e1});
+            IBDL_HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            IBDL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bv = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        tune_store(key(stage), bv, best);
+        return -1 - bv;  // already run
+    }
+    int heuristic() const { return min_nrhs >= 4 ? 2 : min_nrhs >= 2 ? 1 : 0; }
     template <class T, class F>
     static void go(const StageTable<T>& tb, F&& f) {
         if (tb.blocks() == 0) return;
@@ -996,11 +1053,9 @@ struct PreparedT : PreparedPass {
     void run(int it, hipStream_t st) override {
         int stage = 0;
         {
+            const int v = pick(0, it, st, [&](int c, StageEv e) { fwd(c, it, st, e); });
             const StageEv e = stage_events(tplan, stage++, "spread+fft_x");
-            go(rf, [&](bool m) {
-                if (m) launch_row_fwd_t<R, true>(n, rb, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
-                else launch_row_fwd_t<R, false>(n, rb, rf.blocks(), st, e, rf.args[0], rf.jobs(), it);
-            });
+            if (v >= 0) fwd(v, it, st, e);
         }
         if (dim == 2) {
             const StageEv e = stage_events(tplan, stage++, "fft_y+symbol");
@@ -1025,18 +1080,13 @@ struct PreparedT : PreparedPass {
                 else launch_col_t<R, 2, false, false>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(), it);
             });
         }
-        if (dense_out) {
-            const StageEv e = stage_events(tplan, stage++, "ifft_x");
-            go(ri, [&](bool m) {
-                if (m) launch_row_inv_t<R, 1, true>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-                else launch_row_inv_t<R, 1, false>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-            });
-        } else {
-            StageEv e = stage_events(tplan, stage++, "ifft_x+interp");
-            go(ri, [&](bool m) {
-                if (m) launch_row_inv_t<R, 0, true>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-                else launch_row_inv_t<R, 0, false>(n, rb, ri.blocks(), st, e, ri.args[0], ri.jobs(), it);
-            });
+        {
+            const int v = pick(1, it, st, [&](int c, StageEv e) { inv(c, it, st, e); });
+            const StageEv e = stage_events(tplan, stage++, dense_out ? "ifft_x" : "ifft_x+interp");
+            if (v >= 0) inv(v, it, st, e);
+        }
+        if (!dense_out) {
+            StageEv e;
             e = stage_events(tplan, stage++, "finish");
             go(fi, [&](bool m) {
                 if (m)
@@ -1061,13 +1111,14 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
     P->dim = p0->dim;
     P->dense_out = jobs[0].out.u != nullptr;
     P->tplan = p0;
-    // right-hand sides per row block: the largest of 4, 2, 1 that no job of the
-    // pass leaves partly empty
-    int minr = 1 << 30;
-    for (const PassJob& jb : jobs) minr = std::min(minr, jb.nrhs);
-    P->rb = minr >= 4 ? 4 : minr >= 2 ? 2 : 1;
-    const int RBv = P->rb;
-    const int G = row_lines_per_block<R>(n, RBv);
+    int minr = 1 << 30, tot = 0;
+    for (const PassJob& jb : jobs) {
+        minr = std::min(minr, jb.nrhs);
+        tot += jb.nrhs;
+    }
+    P->min_nrhs = minr;
+    P->total_rhs = tot;
+    P->njobs = (int)jobs.size();
     const int C = col_width<R>(n);
     const int NT = col_tiles<R>(n);
     const size_t plane = (size_t)NT * n * C;
@@ -1087,7 +1138,6 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ra.skip = in.skip;
         ra.lines = dense_in ? nullptr : p->spread_lines;
         ra.nproc = dense_in ? p->nlines : p->n_spread_lines;
-        ra.nblk = (ra.nproc + G - 1) / G;
         ra.M = p->M;
         auto view = [&](const Csr& c, const double* q, double coef) {
             CsrView<R> v{};
@@ -1112,7 +1162,11 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ra.P = p->P;
         ra.tw = PP::tw(p);
         ra.nrhs = nrhs;
-        P->rf.add(ra, ra.nblk * ((nrhs + RBv - 1) / RBv));
+        for (int v = 0; v < 3; ++v) {
+            const int G = row_lines_per_block<R>(n, kRowRB[v]);
+            ra.nblk = (ra.nproc + G - 1) / G;
+            P->rf[v].add(ra, ra.nblk * ((nrhs + kRowRB[v] - 1) / kRowRB[v]));
+        }
 
         // ---- columns
         ColArgs<R> ca{};
@@ -1172,7 +1226,6 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ia.skip = in.skip;
         ia.lines = dense_out ? nullptr : p->gather_lines;
         ia.nproc = dense_out ? p->nlines : p->n_gather_lines;
-        ia.nblk = (ia.nproc + G - 1) / G;
         ia.spec = spec;
         ia.spec_stride = sstride;
         ia.P = p->P;
@@ -1187,7 +1240,11 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ia.M = p->M;
         ia.dim = p->dim;
         ia.nrhs = nrhs;
-        P->ri.add(ia, ia.nblk * ((nrhs + RBv - 1) / RBv));
+        for (int v = 0; v < 3; ++v) {
+            const int G = row_lines_per_block<R>(n, kRowRB[v]);
+            ia.nblk = (ia.nproc + G - 1) / G;
+            P->ri[v].add(ia, ia.nblk * ((nrhs + kRowRB[v] - 1) / kRowRB[v]));
+        }
 
         // ---- finish
         if (!dense_out) {

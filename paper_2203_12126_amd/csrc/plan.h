@@ -274,6 +274,26 @@ void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std:
                const std::vector<const double*>& x0, const ibdl_solve_opts& o, const std::vector<double*>& sol,
                ibdl_solve_info* info, hipStream_t st, int* overall);
 
+// Tile autotuner: per pass configuration, the row-block variant measured fastest.
+struct TuneKey {
+    int rbytes, dim, n, stage, dense, minr, totr, multi;
+    bool operator<(const TuneKey& o) const {
+        const int a[8] = {rbytes, dim, n, stage, dense, minr, totr, multi};
+        const int b[8] = {o.rbytes, o.dim, o.n, o.stage, o.dense, o.minr, o.totr, o.multi};
+        for (int i = 0; i < 8; ++i)
+            if (a[i] != b[i]) return a[i] < b[i];
+        return false;
+    }
+};
+inline int tune_bucket(int v) {  // 1, 2-3, 4-7, ... -> 0, 1, 2, ...
+    int b = 0;
+    while ((2 << b) <= v) ++b;
+    return b;
+}
+int tune_lookup(const TuneKey& k);                      // variant or -1
+void tune_store(const TuneKey& k, int variant, float ms);
+bool tune_enabled();
+
 // timing helpers used by the pipeline: events to pass to the stage's launch
 // (both null when timing is off); stage 0 opens a new event set
 struct StageEv {

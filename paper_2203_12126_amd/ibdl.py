@@ -110,6 +110,8 @@ def lib():
         "ibdl_server_poll": ([P, ctypes.c_uint64, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)], st),
         "ibdl_server_wait": ([P, ctypes.c_uint64, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)], st),
         "ibdl_server_get_stats": ([P, ctypes.POINTER(ServerStats)], st),
+        "ibdl_set_autotune": ([I], st),
+        "ibdl_autotune_report": ([ctypes.c_char_p, ctypes.c_size_t], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -158,6 +160,18 @@ def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=N
     d.normal = normal.data_ptr() if normal is not None else None
     d.weight = weight.data_ptr() if weight is not None else None
     return d
+
+
+def set_autotune(enable: bool = True):
+    """Clear the tile autotuner's choices and turn it on or off."""
+    _check(lib().ibdl_set_autotune(1 if enable else 0), "ibdl_set_autotune")
+
+
+def autotune_report() -> str:
+    n = lib().ibdl_autotune_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().ibdl_autotune_report(buf, n + 1)
+    return buf.value.decode()
 
 
 def footprint(dim, n, npts, bc=DIRICHLET, prec=FP64, nrhs=1, restart=50) -> int:
