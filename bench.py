@@ -240,7 +240,8 @@ def run_batch(args):
         "dtype": "f32 grid + f64 krylov", "data": "synthetic",
         "config": {"workload": "batch512", "description": "512 2-D ellipse instances, n in {128,192,256,384,512}, "
                    "2..8 rhs, Dirichlet/Neumann, alpha log-uniform [1,1000], tol 1e-8, mixed",
-                   "instances": batch.count, "total_rhs": R, "tol": tol, "precision": "mixed"},
+                   "instances": batch.count, "total_rhs": R, "tol": tol, "precision": "mixed",
+                   "graphs": args.graphs == "on"},
         "solves_per_s": round(args.steps * R / el, 2),
         "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
         "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
@@ -351,7 +352,8 @@ def run_serve(args):
         "config": {"workload": "serve", "requests": count, "templates": ntpl, "window": args.serve_window,
                    "description": "served stream: 80% 2-D (256^2..2048^2, circle/star, 1k..16k points, D/N), "
                                   "20% 3-D (64^3..256^3, sphere/ellipsoid, 5k..40k points), alpha logU[1,1000], "
-                                  "tol 1e-8, grid solution included", "precision": "mixed"},
+                                  "tol 1e-8, grid solution included", "precision": "mixed",
+                   "graphs": args.graphs == "on"},
         "saturation": {"solves_per_s": round(sat, 2), "applies_per_s": round(iters / sat_el, 1),
                        "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                        "latency_ms_p99": round(float(np.percentile(lat, 99)), 3)},
@@ -378,6 +380,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-templates", type=int, default=48)
     ap.add_argument("--serve-window", type=int, default=64)
+    ap.add_argument("--graphs", choices=["on", "off"], default="off",
+                    help="replay Arnoldi steps from recorded HIP graphs (on) or launch each kernel (off)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration runs)")
     args = ap.parse_args()
@@ -390,6 +394,7 @@ def main():
     from paper_2203_12126_amd import ibdl
 
     torch.cuda.set_device(0)
+    ibdl.set_graphs(args.graphs == "on")
     if args.workload == "batch512":
         run_batch(args)
         return
@@ -516,7 +521,7 @@ def main():
         "dtype": "f32 grid + f64 krylov", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": n, "dim": dim, "M": m,
                    "alpha": p0.alpha, "bc": "dirichlet", "nrhs": args.nrhs, "tol": tol,
-                   "precision": "mixed"},
+                   "precision": "mixed", "graphs": args.graphs == "on"},
         "solves_per_s": round(solves_s, 3),
         "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 4),
         "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 4),

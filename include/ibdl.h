@@ -313,6 +313,21 @@ ibdl_status ibdl_server_get_stats(ibdl_server server, ibdl_server_stats* out_hos
 ibdl_status ibdl_set_autotune(int32_t enable);
 int32_t ibdl_autotune_report(char* buf, size_t cap);
 
+/* Iteration graphs.  Once the operator pass of a solver's Krylov workspace has
+ * run once (which settles the tuned variants), a GMRES-Arnoldi step (Sec. 2.2:
+ * one operator application followed by the orthogonalisation of the new basis
+ * vector) is recorded as a HIP graph whose kernels read the step index from
+ * device memory; the workspace keeps it, and every later step, in this and later
+ * solves of the same plan, batch or cohort, is one replay on the solve's stream.
+ * Results are bit-identical to launching the kernels one by one.  On (1) or off
+ * (0, the default: the eager launches already keep the device queue full, and a
+ * replay adds device time); solves of plans with stage timing on never use
+ * graphs.  Takes effect for solves started after the call. */
+ibdl_status ibdl_set_graphs(int32_t enable);
+/* Process totals since load: out_host[0] = graphs recorded (one per Krylov run
+ * that replays), out_host[1] = replays.  out_host: HOST array of 2. */
+ibdl_status ibdl_graph_stats(int64_t* out_host);
+
 /* Message for the last failing call on this host thread ("" if none). */
 const char* ibdl_last_error(void);
 

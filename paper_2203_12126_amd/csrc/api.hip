@@ -228,6 +228,21 @@ void tune_store(const TuneKey& k, int variant, float ms) {
 }
 bool tune_enabled() { return g_tune_on.load() != 0; }
 
+bool& capturing() {
+    thread_local bool c = false;
+    return c;
+}
+
+namespace {
+std::atomic<int> g_graphs_on{0};
+std::atomic<int64_t> g_graphs_recorded{0}, g_graph_replays{0};
+}  // namespace
+bool graphs_enabled() { return g_graphs_on.load() != 0; }
+void note_graphs(int64_t recorded, int64_t replays) {
+    g_graphs_recorded += recorded;
+    g_graph_replays += replays;
+}
+
 void release_plan(ibdl_plan p, hipStream_t st) {
     AllocStream as(st);
     free_build_tmp(p);
@@ -667,6 +682,18 @@ ibdl_status ibdl_set_autotune(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
     g_tune_on.store(enable ? 1 : 0);
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_set_graphs(int32_t enable) {
+    g_graphs_on.store(enable ? 1 : 0);
+    return IBDL_OK;
+}
+
+ibdl_status ibdl_graph_stats(int64_t* out_host) {
+    if (!out_host) return set_error(IBDL_ERR_ARG, "ibdl_graph_stats: null output");
+    out_host[0] = g_graphs_recorded.load();
+    out_host[1] = g_graph_replays.load();
     return IBDL_OK;
 }
 

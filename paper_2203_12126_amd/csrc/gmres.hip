@@ -55,6 +55,8 @@ struct KArgs {
     const double* tolv; // [R] tolerance relative to ||b_r||
     int32_t* state;     // [R][4]
     const int32_t* skip;
+    const int32_t* jp;  // Arnoldi step index in device memory, or null: the launch argument
+    int32_t* jcur;      // the step index that replayed steps read; reset with each cycle
 };
 
 __device__ __forceinline__ int nblocks_of(int M) { return (M + GT - 1) / GT; }
@@ -120,6 +122,7 @@ __global__ void k_set_bnorm(KArgs a) {
     a.state[4 * r + ST_ITERS] = 0;
     a.state[4 * r + ST_STATUS] = isfinite(s) ? IBDL_OK : IBDL_ERR_NUMERIC;
     a.state[4 * r + ST_J] = 0;
+    if (r == 0 && a.jcur) *a.jcur = 0;
 }
 
 // start a cycle: v_0 = r / ||r||, g = (||r||, 0, ...); rhs already done are left alone
@@ -154,6 +157,7 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j) {
     __shared__ double hs[256];
     __shared__ double msh[(GT / 64) * 16];
     __shared__ double mout[16];
+    if (a.jp) j = *a.jp;
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     if (a.state[4 * r + ST_DONE] || (int)blockIdx.x >= nb) return;
@@ -210,6 +214,7 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     __shared__ double hs[256];
     __shared__ double hn_s[2];
     __shared__ double hc_s[256], cs_s[256], sn_s[256];
+    if (a.jp) j = *a.jp;
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     int32_t* st = a.state + 4 * r;
@@ -348,9 +353,14 @@ __global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* xpool) {
     xpool[a.xoff[r] + m] = acc;
 }
 
+// the device-side step index of replayed iterations
+__global__ void k_set_j(int32_t* jp, int v) { *jp = v; }
+__global__ void k_next_j(int32_t* jp) { *jp += 1; }
+
 __global__ void k_reset_j(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < a.R) a.state[4 * r + ST_J] = 0;
+    if (r == 0) *a.jcur = 0;
 }
 
 // pool vectors of the rhs not skipped: op 0: dst = 0, op 1: dst += src
@@ -365,6 +375,13 @@ __global__ __launch_bounds__(GT) void k_pool_op(KArgs a, int op, double* dst, co
 
 // ------------------------------------------------------------------ host
 void free_krylov(KWork& k) {
+    // no replay is in flight here: a solve task waits for its replays before it ends
+    if (k.gexec) (void)hipGraphExecDestroy(k.gexec);
+    k.gexec = nullptr;
+    k.graph_valid = k.op_ran = false;
+    k.op.reset();
+    k.op_key.clear();
+    arena_free(k.op_arena);
     for (void* p : k.mem) dev_free(p);
     k.mem.clear();
     pinned_put(k.host_pinned);
@@ -417,6 +434,7 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     k.d = A(xtot);
     k.state = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * 4 * sizeof(int32_t)));
     k.skip = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
+    k.jcur = reinterpret_cast<int32_t*>(dev_alloc(k.mem, sizeof(int32_t)));
     k.Mr = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
     k.voff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
     k.xoff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
@@ -461,6 +479,8 @@ static KArgs kargs(KrylovSet& ks, int m) {
     a.tolv = k.tolv;
     a.state = k.state;
     a.skip = k.skip;
+    a.jp = nullptr;
+    a.jcur = k.jcur;
     return a;
 }
 
@@ -490,7 +510,7 @@ static Staging staging(KWork& k, int R) {
 }
 
 GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, const JobMaker& make, bool fp64,
-                            hipStream_t st) {
+                            hipStream_t st, Arena* ar) {
     std::map<std::tuple<int, int, int>, std::vector<PassJob>> groups;
     for (size_t i : which) {
         const Inst& in = ks.inst[i];
@@ -500,7 +520,7 @@ GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, con
     GroupedPass gp;
     for (auto& kv : groups) {
         auto pp = prepare_pass(kv.second, fp64);
-        pp->upload(*ks.arena, st);
+        pp->upload(ar ? *ar : *ks.arena, st);
         gp.parts.push_back(std::move(pp));
     }
     return gp;
@@ -513,14 +533,21 @@ static std::vector<size_t> all_of(const KrylovSet& ks) {
 }
 
 // ------------------------------------------------------------------ solve task
-SolveTask::SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st)
+SolveTask::SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st, bool graphs)
     : ks_(ks), io_(std::move(io)), o_(o), st_(st) {
     m_ = o.restart;
     R_ = ks.R;
     IBDL_HIP_TRY(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+    // stage timing records events around each stage kernel: those iterations stay eager
+    use_graph_ = graphs && graphs_enabled();
+    for (const Inst& in : ks.inst)
+        if (in.p->tm->enabled) use_graph_ = false;
 }
 
 SolveTask::~SolveTask() {
+    // replays may still be in flight when the task ends early on an error; the set
+    // keeps its graph for later solves
+    if (graph_unmarked_) (void)hipStreamSynchronize(st_);
     if (ev_) (void)hipEventDestroy(ev_);
 }
 
@@ -547,6 +574,7 @@ void SolveTask::run_to_end() {
 void SolveTask::mark() {
     IBDL_HIP_TRY(hipGetLastError());
     IBDL_HIP_TRY(hipEventRecord(ev_, st_));
+    graph_unmarked_ = false;
 }
 
 // r = b - A x for every instance (operator in FP64 when fp64, else the plans' precision)
@@ -588,16 +616,92 @@ void SolveTask::snapshot(int buf) {
     IBDL_HIP_TRY(hipMemcpyAsync(hs.resid[buf], k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
 }
 
+// a private stream to record graphs on (recording launches nothing)
+static hipStream_t capture_stream() {
+    thread_local struct CS {
+        hipStream_t s = nullptr;
+        ~CS() {
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } cs;
+    if (!cs.s) IBDL_HIP_TRY(hipStreamCreateWithFlags(&cs.s, hipStreamNonBlocking));
+    return cs.s;
+}
+
+// Records one Arnoldi step (operator pass, both Gram-Schmidt passes, step index
+// increment) with the step index read from device memory, and instantiates it,
+// or updates the set's executable graph in place.  On failure: false, and the
+// solve goes on without graphs.
+bool SolveTask::capture_step() {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    a.jp = k.jcur;
+    const dim3 vg(k.nblk, R_);
+    const hipStream_t cs = capture_stream();
+    hipGraph_t graph = nullptr;
+    IBDL_HIP_TRY(hipGetLastError());
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    capturing() = true;
+    bool ok = true;
+    try {
+        k.op->run_dev(k.jcur, cs);
+        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, cs, a, 0);
+        hipLaunchKernelGGL(k_orth_final, vg, dim3(GT), 0, cs, a, 0);
+        hipLaunchKernelGGL(k_next_j, dim3(1), dim3(1), 0, cs, k.jcur);
+    } catch (const Error&) {
+        ok = false;
+    }
+    capturing() = false;
+    if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) ok = false;
+    if (hipGetLastError() != hipSuccess) ok = false;
+    if (ok && k.gexec) {
+        // replays of the previous recording queued since the last wait point finish first
+        if (graph_unmarked_) IBDL_HIP_TRY(hipStreamSynchronize(st_));
+        hipGraphExecUpdateResult res;
+        hipGraphNode_t bad = nullptr;
+        if (hipGraphExecUpdate(k.gexec, graph, &bad, &res) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(k.gexec);
+            k.gexec = nullptr;
+        }
+    }
+    if (ok && !k.gexec && hipGraphInstantiate(&k.gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        k.gexec = nullptr;
+        ok = false;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ok) note_graphs(1, 0);
+    return ok;
+}
+
 void SolveTask::enqueue_iters(int j0, int c) {
     KWork& k = ks_.w;
+    if (c <= 0) return;
+    if (use_graph_ && k.op_ran && !k.graph_valid) {
+        k.graph_valid = capture_step();
+        if (!k.graph_valid) use_graph_ = false;
+    }
+    if (use_graph_ && k.graph_valid) {
+        if (dev_j_ != j0) hipLaunchKernelGGL(k_set_j, dim3(1), dim3(1), 0, st_, k.jcur, j0);
+        for (int t = 0; t < c; ++t) IBDL_HIP_TRY(hipGraphLaunch(k.gexec, st_));
+        dev_j_ = j0 + c;
+        graph_unmarked_ = true;
+        note_graphs(0, c);
+        return;
+    }
     KArgs a = kargs(ks_, m_);
     const dim3 vg(k.nblk, R_);
     for (int t = 0; t < c; ++t) {
         const int j = j0 + t;
-        op_.run(j, st_);
+        k.op->run(j, st_);
         hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, st_, a, j);
         hipLaunchKernelGGL(k_orth_final, vg, dim3(GT), 0, st_, a, j);
     }
+    k.op_ran = true;
 }
 
 // c Arnoldi steps: the state is looked at before the last one, which keeps the
@@ -615,6 +719,53 @@ void SolveTask::enqueue_chunk(int c) {
     kj_ += c - c1;
     ktotal_ += c - c1;
     queued_after_ = c - c1;
+}
+
+// The operator step of an Arnoldi iteration, prepared once per restart length and
+// set of plan workspaces: the step index selects the basis vectors on the device.
+void SolveTask::prepare_op() {
+    KWork& k = ks_.w;
+    KArgs a = kargs(ks_, m_);
+    for (const Inst& in : ks_.inst) ensure_workspace(in.p, in.nrhs);
+    std::vector<const void*> key{reinterpret_cast<const void*>((intptr_t)m_)};
+    for (const Inst& in : ks_.inst) {
+        key.push_back(in.p->ws.spec);
+        key.push_back(in.p->ws.part);
+    }
+    if (k.op && key == k.op_key) return;
+    auto make = [&](size_t i) {
+        const Inst& in = ks_.inst[i];
+        const int M = in.p->M;
+        const size_t vb = k.hvoff[in.r0];
+        const size_t vs = (size_t)(k.cap_m + 1) * M;
+        PipeIn pi;
+        pi.q_dip = k.V + vb;
+        pi.c_dip = 1.0;
+        pi.q_stride = vs;
+        pi.q_jstride = M;
+        pi.skip = k.state + 4 * in.r0;
+        PipeOut po;
+        po.out = k.V + vb + M;
+        po.out_stride = vs;
+        po.out_jstride = M;
+        po.cA = -1.0;
+        po.in = k.V + vb;
+        po.in_stride = vs;
+        po.in_jstride = M;
+        po.cB = in.p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
+        po.dots_V = k.V + vb;
+        po.dots_vstride = vs;
+        po.dots_nv = 1;
+        po.dots = a.part + (size_t)in.r0 * a.pstride;
+        po.dots_rhs = a.pstride;
+        po.dots_stride = m_ + 2;
+        return PassJob{in.p, in.nrhs, pi, po};
+    };
+    // the previous tables were uploaded for an earlier solve, whose work is complete
+    arena_reset(k.op_arena);
+    k.op = std::make_shared<GroupedPass>(prepare_grouped(ks_, all_of(ks_), make, false, st_, &k.op_arena));
+    k.op_key = key;
+    k.op_ran = k.graph_valid = false;
 }
 
 // Restarted GMRES on A x = b (pool vectors) with each plan's operator in its own
@@ -648,37 +799,8 @@ void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
     hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, r0);
     hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st_, a, r0);
 
-    // the operator step of an Arnoldi iteration, prepared once: the iteration
-    // index selects the basis vectors on the device
-    auto make = [&](size_t i) {
-        const Inst& in = ks_.inst[i];
-        const int M = in.p->M;
-        const size_t vb = k.hvoff[in.r0];
-        const size_t vs = (size_t)(k.cap_m + 1) * M;
-        PipeIn pi;
-        pi.q_dip = k.V + vb;
-        pi.c_dip = 1.0;
-        pi.q_stride = vs;
-        pi.q_jstride = M;
-        pi.skip = k.state + 4 * in.r0;
-        PipeOut po;
-        po.out = k.V + vb + M;
-        po.out_stride = vs;
-        po.out_jstride = M;
-        po.cA = -1.0;
-        po.in = k.V + vb;
-        po.in_stride = vs;
-        po.in_jstride = M;
-        po.cB = in.p->bc == IBDL_DIRICHLET ? 0.5 : -0.5;
-        po.dots_V = k.V + vb;
-        po.dots_vstride = vs;
-        po.dots_nv = 1;
-        po.dots = a.part + (size_t)in.r0 * a.pstride;
-        po.dots_rhs = a.pstride;
-        po.dots_stride = m_ + 2;
-        return PassJob{in.p, in.nrhs, pi, po};
-    };
-    op_ = prepare_grouped(ks_, all_of(ks_), make, false, st_);
+    dev_j_ = 0;
+    prepare_op();
     // rhs already converged at the start skip every step on the device
     enqueue_chunk(std::min({3, m_, kmaxit_}));
     phase_ = ITER;
@@ -693,6 +815,7 @@ void SolveTask::after_krylov() {
     hipLaunchKernelGGL(k_backsolve, dim3(R_), dim3(BS_T), 0, st_, a);
     hipLaunchKernelGGL(k_update_x, dim3(k.nblk, R_), dim3(GT), 0, st_, a, kx_);
     hipLaunchKernelGGL(k_reset_j, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
+    dev_j_ = 0;
     snap_buf_ ^= 1;
     snapshot(snap_buf_);
     if (refining_) hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
@@ -886,6 +1009,7 @@ void SolveTask::advance() {
             hipLaunchKernelGGL(k_backsolve, dim3(R_), dim3(BS_T), 0, st_, a);
             hipLaunchKernelGGL(k_update_x, vg, dim3(GT), 0, st_, a, kx_);
             hipLaunchKernelGGL(k_reset_j, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
+            dev_j_ = 0;
             residual(kb_, kx_, k.r, false);
             hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, k.r);
             hipLaunchKernelGGL(k_init_cycle, vg, dim3(GT), 0, st_, a, k.r);

@@ -203,8 +203,9 @@ struct RowInvArgs {
 template <class A>
 struct Jobs {
     const A* list;
-    const int* start;   // n + 1 entries
+    const int* start;     // n + 1 entries
     int n;
+    const int32_t* itp;   // iteration index in device memory, or null: the launch argument
 };
 __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     int lo = 0, hi = n;
@@ -215,11 +216,12 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     return lo;
 }
 #define IBDL_JOB_ENTRY(BODY, A, a0, js, it)                          \
+    const int it_ = js.itp ? *js.itp : it;                            \
     if constexpr (MULTI) {                                            \
         const int j_ = job_of(js.start, js.n, (int)blockIdx.x);       \
-        BODY(js.list[j_], (int)blockIdx.x - js.start[j_], it);        \
+        BODY(js.list[j_], (int)blockIdx.x - js.start[j_], it_);       \
     } else {                                                          \
-        BODY(a0, (int)blockIdx.x, it);                                \
+        BODY(a0, (int)blockIdx.x, it_);                               \
     }
 
 // ------------------------------------------------------------ spread phase
@@ -893,7 +895,7 @@ struct StageTable {
     int njobs() const { return (int)args.size(); }
     int blocks() const { return start.back(); }
     bool multi() const { return njobs() > 1; }
-    Jobs<A> jobs() const { return Jobs<A>{dargs, dstart, njobs()}; }
+    Jobs<A> jobs(const int32_t* itp) const { return Jobs<A>{dargs, dstart, njobs(), itp}; }
     void upload(Arena& ar, hipStream_t st) {
         if (!multi()) return;
         dargs = reinterpret_cast<const A*>(arena_put(ar, args.data(), args.size() * sizeof(A), st));
@@ -998,19 +1000,19 @@ struct PreparedT : PreparedPass {
     void fwd(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = rf[v];
         go(t, [&](bool m) {
-            if (m) launch_row_fwd_t<R, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
-            else launch_row_fwd_t<R, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+            if (m) launch_row_fwd_t<R, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+            else launch_row_fwd_t<R, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
         });
     }
     void inv(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = ri[v];
         go(t, [&](bool m) {
             if (dense_out) {
-                if (m) launch_row_inv_t<R, 1, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
-                else launch_row_inv_t<R, 1, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+                if (m) launch_row_inv_t<R, 1, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 1, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             } else {
-                if (m) launch_row_inv_t<R, 0, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
-                else launch_row_inv_t<R, 0, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(), it);
+                if (m) launch_row_inv_t<R, 0, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 0, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             }
         });
     }
@@ -1022,7 +1024,7 @@ struct PreparedT : PreparedPass {
     int pick(int stage, int it, hipStream_t st, F&& launch) {
         int v = tune_lookup(key(stage));
         if (v >= 0) return v;
-        if (!tune_enabled()) return heuristic();
+        if (!tune_enabled() || capturing()) return heuristic();
         float best = 1e30f;
         int bv = heuristic();
         hipEvent_t e0, e1;
@@ -1060,24 +1062,24 @@ struct PreparedT : PreparedPass {
         if (dim == 2) {
             const StageEv e = stage_events(tplan, stage++, "fft_y+symbol");
             go(col[0], [&](bool m) {
-                if (m) launch_col_t<R, 1, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
-                else launch_col_t<R, 1, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+                if (m) launch_col_t<R, 1, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(itp_), it);
+                else launch_col_t<R, 1, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(itp_), it);
             });
         } else {
             StageEv e = stage_events(tplan, stage++, "fft_y");
             go(col[0], [&](bool m) {
-                if (m) launch_col_t<R, 0, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
-                else launch_col_t<R, 0, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(), it);
+                if (m) launch_col_t<R, 0, false, true>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(itp_), it);
+                else launch_col_t<R, 0, false, false>(n, col[0].blocks(), st, e, col[0].args[0], col[0].jobs(itp_), it);
             });
             e = stage_events(tplan, stage++, "fft_z+symbol");
             go(col[1], [&](bool m) {
-                if (m) launch_col_t<R, 1, true, true>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(), it);
-                else launch_col_t<R, 1, true, false>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(), it);
+                if (m) launch_col_t<R, 1, true, true>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(itp_), it);
+                else launch_col_t<R, 1, true, false>(n, col[1].blocks(), st, e, col[1].args[0], col[1].jobs(itp_), it);
             });
             e = stage_events(tplan, stage++, "ifft_y");
             go(col[2], [&](bool m) {
-                if (m) launch_col_t<R, 2, false, true>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(), it);
-                else launch_col_t<R, 2, false, false>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(), it);
+                if (m) launch_col_t<R, 2, false, true>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(itp_), it);
+                else launch_col_t<R, 2, false, false>(n, col[2].blocks(), st, e, col[2].args[0], col[2].jobs(itp_), it);
             });
         }
         {
@@ -1091,10 +1093,10 @@ struct PreparedT : PreparedPass {
             go(fi, [&](bool m) {
                 if (m)
                     hipExtLaunchKernelGGL((k_finish<R, true>), dim3(fi.blocks()), dim3(FIN_T), 0, st, e.a, e.b, 0,
-                                          fi.args[0], fi.jobs(), it);
+                                          fi.args[0], fi.jobs(itp_), it);
                 else
                     hipExtLaunchKernelGGL((k_finish<R, false>), dim3(fi.blocks()), dim3(FIN_T), 0, st, e.a, e.b,
-                                          0, fi.args[0], fi.jobs(), it);
+                                          0, fi.args[0], fi.jobs(itp_), it);
             });
         }
         IBDL_HIP_TRY(hipGetLastError());

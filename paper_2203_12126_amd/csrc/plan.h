@@ -55,6 +55,8 @@ struct Inst {
     int r0 = 0;
 };
 
+struct GroupedPass;
+
 // Device state of restarted GMRES for R right-hand sides of possibly different
 // lengths: rhs r has M_r unknowns, basis block voff[r] in V (cap_m+1 vectors),
 // vectors xoff[r] in the pools b, x, r, rr, d.
@@ -75,6 +77,7 @@ struct KWork {
     double* nrm = nullptr;      // [R] norms handed to the host
     int32_t* state = nullptr;   // [R][4]: done flag, iterations, status, j
     int32_t* skip = nullptr;    // [R]
+    int32_t* jcur = nullptr;    // Arnoldi step index read by replayed iteration graphs
     int32_t* Mr = nullptr;      // [R]
     size_t* voff = nullptr;     // [R]
     size_t* xoff = nullptr;     // [R]
@@ -86,6 +89,15 @@ struct KWork {
     void* host_pinned = nullptr;
     std::vector<size_t> hvoff, hxoff;
     std::vector<void*> mem;
+    // the operator step of an Arnoldi iteration, prepared once per restart length
+    // and set of plan workspaces (op_key), with its argument tables in an arena of
+    // its own; and that step with both Gram-Schmidt passes recorded as a graph
+    std::shared_ptr<GroupedPass> op;
+    std::vector<const void*> op_key;
+    Arena op_arena;
+    bool op_ran = false;       // has run eagerly: the tuned variants are settled
+    bool graph_valid = false;  // gexec records the current op
+    hipGraphExec_t gexec = nullptr;
 };
 void free_krylov(KWork& k);
 
@@ -254,6 +266,27 @@ struct PreparedPass {
     virtual ~PreparedPass() {}
     virtual void upload(Arena& arena, hipStream_t st) = 0;  // only needed for several jobs
     virtual void run(int it, hipStream_t st) = 0;            // it: iteration index
+    // the same with the iteration index read on the device from *itp
+    void run_dev(const int32_t* itp, hipStream_t st) {
+        itp_ = itp;
+        run(0, st);
+        itp_ = nullptr;
+    }
+
+protected:
+    const int32_t* itp_ = nullptr;
+};
+
+// A grid pass over chosen instances of a set, one prepared pass per
+// (dimension, grid size, precision) group.
+struct GroupedPass {
+    std::vector<std::unique_ptr<PreparedPass>> parts;
+    void run(int it, hipStream_t st) {
+        for (auto& p : parts) p->run(it, st);
+    }
+    void run_dev(const int32_t* itp, hipStream_t st) {
+        for (auto& p : parts) p->run_dev(itp, st);
+    }
 };
 std::unique_ptr<PreparedPass> prepare_f64(const std::vector<PassJob>& jobs);
 std::unique_ptr<PreparedPass> prepare_f32(const std::vector<PassJob>& jobs);
@@ -293,6 +326,11 @@ inline int tune_bucket(int v) {  // 1, 2-3, 4-7, ... -> 0, 1, 2, ...
 int tune_lookup(const TuneKey& k);                      // variant or -1
 void tune_store(const TuneKey& k, int variant, float ms);
 bool tune_enabled();
+// set while this thread records a graph: untuned stages take the heuristic
+// variant instead of timing the others
+bool& capturing();
+bool graphs_enabled();
+void note_graphs(int64_t recorded, int64_t replays);
 
 // timing helpers used by the pipeline: events to pass to the stage's launch
 // (both null when timing is off); stage 0 opens a new event set

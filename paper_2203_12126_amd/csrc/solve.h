@@ -25,18 +25,15 @@ struct SolveIO {
 // A grid pass over chosen instances of a set, one prepared pass per
 // (dimension, grid size, precision) group.
 using JobMaker = std::function<PassJob(size_t)>;
-struct GroupedPass {
-    std::vector<std::unique_ptr<PreparedPass>> parts;
-    void run(int it, hipStream_t st) {
-        for (auto& p : parts) p->run(it, st);
-    }
-};
+// tables go to the set's arena, or to *ar when given
 GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, const JobMaker& make, bool fp64,
-                            hipStream_t st);
+                            hipStream_t st, Arena* ar = nullptr);
 
 class SolveTask {
 public:
-    SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st);
+    // graphs: the Arnoldi steps may be replayed from a recorded graph (also subject
+    // to the process-wide switch and to stage timing being off)
+    SolveTask(KrylovSet& ks, SolveIO io, const ibdl_solve_opts& o, hipStream_t st, bool graphs = true);
     ~SolveTask();
     bool done() const { return phase_ == DONE; }
     bool ready();          // the last wait point has been reached (non-blocking)
@@ -52,6 +49,8 @@ private:
     void mark();                                  // record the wait point
     void kstart(const double* b, double* x, bool x_zero, int maxit);
     void enqueue_iters(int j0, int c);
+    void prepare_op();                            // the set's Arnoldi operator step, current
+    bool capture_step();                          // record one Arnoldi step as a graph
     void enqueue_chunk(int c);
     void snapshot(int buf);
     void after_krylov();
@@ -77,7 +76,11 @@ private:
     int queued_after_ = 0;  // steps enqueued after it
     int prev_iter_ = -1;    // cycle steps before the previous snapshot (-1: none this cycle)
     std::vector<double> prev_;
-    GroupedPass op_;
+    // Arnoldi steps replayed from the set's recorded graph once the operator step
+    // has run eagerly (which settles the tuned variants); the step index then lives
+    // on the device: dev_j_ is its value after the queued work (-1: not known)
+    bool use_graph_ = false, graph_unmarked_ = false;
+    int dev_j_ = -1;
     // solve state
     bool any_mixed_ = false, refining_ = false, fill_true_ = false;
     int round_ = 0;

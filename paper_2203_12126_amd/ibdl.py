@@ -111,6 +111,8 @@ def lib():
         "ibdl_server_wait": ([P, ctypes.c_uint64, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestTimes)], st),
         "ibdl_server_get_stats": ([P, ctypes.POINTER(ServerStats)], st),
         "ibdl_set_autotune": ([I], st),
+        "ibdl_set_graphs": ([I], st),
+        "ibdl_graph_stats": ([ctypes.c_void_p], st),
         "ibdl_autotune_report": ([ctypes.c_char_p, ctypes.c_size_t], I),
     }
     for name, (args, res) in sig.items():
@@ -165,6 +167,19 @@ def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=N
 def set_autotune(enable: bool = True):
     """Clear the tile autotuner's choices and turn it on or off."""
     _check(lib().ibdl_set_autotune(1 if enable else 0), "ibdl_set_autotune")
+
+
+def set_graphs(enable: bool = True):
+    """Replay each GMRES-Arnoldi step from a recorded HIP graph, or launch its
+    kernels one by one (the default); results are bit-identical."""
+    _check(lib().ibdl_set_graphs(1 if enable else 0), "ibdl_set_graphs")
+
+
+def graph_stats() -> dict:
+    """Process totals: graphs recorded and step replays."""
+    out = (ctypes.c_int64 * 2)()
+    _check(lib().ibdl_graph_stats(out), "ibdl_graph_stats")
+    return {"recorded": out[0], "replays": out[1]}
 
 
 def autotune_report() -> str:

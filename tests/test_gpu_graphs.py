@@ -1,0 +1,123 @@
+"""Arnoldi steps replayed from a recorded HIP graph (the step index read from
+device memory) give solves bit-identical to launching every kernel one by one:
+the same kernels, variants and reduction orders.  Each case replays the graph
+many times per solve, over several restart cycles and, for mixed precision,
+over the refinement runs that update the recorded graph in place; the graph
+solve is repeated with unrelated device work between the repetitions, and
+every repetition is compared."""
+import numpy as np
+import pytest
+
+from paper_2203_12126_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2203_12126_amd import ibdl  # noqa: E402
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def other_work(seed):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn(1 << 20, device="cuda", generator=g)
+    y = (x * x).cumsum(0)
+    torch.cuda.synchronize()
+    return float(y[-1])
+
+
+def compare_graph_eager(solve, between=None):
+    """The solve with graphs off, then three times with graphs on (the recorded
+    step is kept by the solver's workspace and replayed by later solves);
+    between(rep) runs after each repetition."""
+    ibdl.set_graphs(False)
+    s0 = ibdl.graph_stats()
+    ref, iref = solve()
+    assert ibdl.graph_stats() == s0, "graphs used while switched off"
+    ibdl.set_graphs(True)
+    try:
+        _graph_reps(solve, ref, iref, between)
+    finally:
+        ibdl.set_graphs(False)
+
+
+def _graph_reps(solve, ref, iref, between):
+    first = ibdl.graph_stats()
+    for rep in range(3):
+        s0 = ibdl.graph_stats()
+        out, info = solve()
+        s1 = ibdl.graph_stats()
+        assert s1["replays"] > s0["replays"], f"repetition {rep}"
+        assert [x["iters"] for x in info] == [x["iters"] for x in iref], f"repetition {rep}"
+        assert [x["status"] for x in info] == [x["status"] for x in iref], f"repetition {rep}"
+        if isinstance(out, list):
+            for i, (a, b) in enumerate(zip(out, ref)):
+                assert torch.equal(a, b), f"repetition {rep}, instance {i}"
+        else:
+            assert torch.equal(out, ref), f"repetition {rep}"
+        other_work(rep)
+        if between:
+            between(rep)
+    assert ibdl.graph_stats()["recorded"] > first["recorded"]
+
+
+@pytest.mark.parametrize("case", ["star_mixed", "star_fp64_neumann", "sphere_mixed"])
+def test_plan_solve_graph_equals_eager(case):
+    if case == "star_mixed":
+        p, prec, restart = W.config_star1024(m=1500, n=256, alpha=3.0, seed=9), ibdl.MIXED, 12
+    elif case == "star_fp64_neumann":
+        p, prec, restart = W.config_star1024(m=1200, n=192, alpha=1.0, bc=W.NEUMANN, seed=5), ibdl.FP64, 20
+    else:
+        p, prec, restart = W.table2_problem(32, 2000), ibdl.MIXED, 50
+    pl = ibdl.Plan.from_problem(p, prec=prec)
+    rng = np.random.default_rng(11)
+    data = T(np.stack([p.data, p.data + 0.1 * rng.standard_normal(p.data.shape)]))
+    g = T(np.stack([p.g_tilde, p.g_tilde]))
+    wide = T(rng.standard_normal((6, p.geom.m)))
+
+    def between(rep):
+        # more right-hand sides than the solve: the plan's workspace grows and
+        # moves, so the next solve must prepare and record its step anew
+        if rep == 0:
+            s0 = ibdl.graph_stats()["recorded"]
+            pl.apply(wide)
+            torch.cuda.synchronize()
+            assert ibdl.graph_stats()["recorded"] == s0
+
+    compare_graph_eager(lambda: pl.solve(data, g, tol=1e-10, restart=restart, maxit=400), between)
+    pl.close()
+
+
+def test_batch_solve_graph_equals_eager():
+    items = []
+    for sp in W.config_batch(count=5, seed=31, sizes=(64, 96, 128)):
+        sp["nrhs"] = 1 + sp["nrhs"] % 3
+        _, _, probs = W.batch_instance(sp)
+        items.append(probs)
+    batch = ibdl.Batch.from_problems([(probs[0], len(probs)) for probs in items], prec=ibdl.MIXED)
+    data = [T(np.stack([q.data for q in probs])) for probs in items]
+    g = [T(np.stack([q.g_tilde for q in probs])) for probs in items]
+    compare_graph_eager(lambda: batch.solve(data, g, tol=1e-10, restart=15))
+    batch.close()
+
+
+def test_timing_keeps_steps_eager():
+    p = W.config_star1024(m=1500, n=128, alpha=1.0, seed=2)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    data = T(p.data[None])
+    g = T(p.g_tilde[None])
+    pl.set_timing(True)
+    ibdl.set_graphs(True)
+    try:
+        s0 = ibdl.graph_stats()
+        pl.solve(data, g, tol=1e-10)
+        assert ibdl.graph_stats()["replays"] == s0["replays"]
+    finally:
+        ibdl.set_graphs(False)
+    pl.set_timing(False)
+    pl.close()
