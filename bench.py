@@ -158,14 +158,13 @@ def run_batch(args):
 
     t0 = time.perf_counter()
     specs = W.config_batch()
-    items, data, g, vb = [], [], [], []
+    items, data, g = [], [], []
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     for sp in specs:
         _, _, probs = W.batch_instance(sp)
         items.append((probs[0], len(probs)))
         data.append(t(np.stack([p.data for p in probs])))
         g.append(t(np.stack([p.g_tilde for p in probs])))
-        vb.append(data[-1] if sp["bc"] == W.NEUMANN else None)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     batch = ibdl.Batch.from_problems(items, prec=ibdl.MIXED)
@@ -175,15 +174,13 @@ def run_batch(args):
     tol = 1e-8
 
     for _ in range(args.warmup):
-        sol, info = batch.solve(data, g, tol=tol)
-        batch.eval_grid(sol, vb=vb, g=g)
+        sol, u, info = batch.solve_grid(data, g, tol=tol)
     torch.cuda.synchronize()
     lat, iters = [], 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        sol, info = batch.solve(data, g, tol=tol)
-        u = batch.eval_grid(sol, vb=vb, g=g)
+        sol, u, info = batch.solve_grid(data, g, tol=tol)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
         iters += sum(i["iters"] for i in info)
@@ -413,15 +410,13 @@ def main():
         the per-stage events on (their times feed the roofline)."""
         plan = ibdl.Plan.from_problem(p0, prec=prec)
         for _ in range(warmup):
-            sol, info = plan.solve(data, g, tol=tol)
-            plan.eval_grid(sol, g=g)
+            sol, u, info = plan.solve_grid(data, g, tol=tol)
         torch.cuda.synchronize()
         lat, iters = [], 0
         t0 = time.perf_counter()
         for _ in range(steps):
             s0 = time.perf_counter()
-            sol, info = plan.solve(data, g, tol=tol)
-            u = plan.eval_grid(sol, g=g)
+            sol, u, info = plan.solve_grid(data, g, tol=tol)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - s0)
             iters += sum(i["iters"] for i in info)

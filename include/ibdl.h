@@ -141,6 +141,17 @@ ibdl_status ibdl_solve(ibdl_plan plan, int32_t nrhs, const double* data, const d
                        const ibdl_solve_opts* opts, double* sol, ibdl_solve_info* info,
                        void* stream);
 
+/* Steps 1 and 2 in one call: ibdl_solve, then u = the grid solution of the
+ * solution as ibdl_eval_grid gives it, with V_b = data for Neumann plans.  For
+ * MIXED plans u comes out of the FP64 residual pass of the final iterate (one
+ * pass gives u = L^-1 (g~ - S~ x [- S V_b]) on the grid and the residual
+ * U_b - x/2 - S* u (Dirichlet) or x/2 - S* u (Neumann) at the points), so no
+ * separate grid pass runs; u equals ibdl_eval_grid of the returned sol.
+ * u: device [nrhs][n^dim]; the rest as for ibdl_solve. */
+ibdl_status ibdl_solve_grid(ibdl_plan plan, int32_t nrhs, const double* data, const double* g,
+                            const ibdl_solve_opts* opts, double* sol, double* u, ibdl_solve_info* info,
+                            void* stream);
+
 /* Step 2 of the method: the grid solution (async).
  *   Dirichlet  u = L^-1 (g~ - S~ Q)               (Sec. 4.1, Eq. (ibdl 1 again))
  *   Neumann    u = L^-1 (g~ - S~ U_b - S V_b)     (Sec. 4.3, Eq. (ib neumann 1))
@@ -224,6 +235,12 @@ ibdl_status ibdl_batch_apply(ibdl_batch batch, const double* const* q, double* c
 ibdl_status ibdl_batch_solve(ibdl_batch batch, const double* const* data, const double* const* g,
                              const ibdl_solve_opts* opts, double* const* sol, ibdl_solve_info* info,
                              void* stream);
+
+/* ibdl_batch_solve plus the grid solutions, as ibdl_solve_grid per instance.
+ * u: per instance a device [nrhs_i][n_i^dim_i] array. */
+ibdl_status ibdl_batch_solve_grid(ibdl_batch batch, const double* const* data, const double* const* g,
+                                  const ibdl_solve_opts* opts, double* const* sol, double* const* u,
+                                  ibdl_solve_info* info, void* stream);
 
 /* ibdl_eval_grid for every instance (FP64; async after the wait).  vb: per
  * instance, required for Neumann instances (may be NULL when none is Neumann);

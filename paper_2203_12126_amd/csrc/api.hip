@@ -394,8 +394,9 @@ ibdl_status ibdl_rhs(ibdl_plan p, int32_t nrhs, const double* data, const double
     IBDL_GUARD_END
 }
 
-ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const double* g,
-                       const ibdl_solve_opts* opts, double* sol, ibdl_solve_info* info, void* stream) {
+static ibdl_status plan_solve(ibdl_plan p, int32_t nrhs, const double* data, const double* g,
+                              const ibdl_solve_opts* opts, double* sol, double* u, ibdl_solve_info* info,
+                              void* stream) {
     if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
     if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
     if (!data || !sol) return fail(IBDL_ERR_ARG, "data and sol must be device pointers");
@@ -410,12 +411,24 @@ ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const doub
     int overall = IBDL_OK;
     p->ks.inst.assign(1, Inst{p, nrhs, 0});
     p->ks.R = nrhs;
-    solve_set(p->ks, {data}, {g}, {o.x0}, o, {sol}, info, S(stream), &overall);
+    solve_set(p->ks, {data}, {g}, {o.x0}, o, {sol}, info, S(stream), &overall, {u});
     if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
     if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
     g_last_error.clear();
     return IBDL_OK;
     IBDL_GUARD_END
+}
+
+ibdl_status ibdl_solve(ibdl_plan p, int32_t nrhs, const double* data, const double* g,
+                       const ibdl_solve_opts* opts, double* sol, ibdl_solve_info* info, void* stream) {
+    return plan_solve(p, nrhs, data, g, opts, sol, nullptr, info, stream);
+}
+
+ibdl_status ibdl_solve_grid(ibdl_plan p, int32_t nrhs, const double* data, const double* g,
+                            const ibdl_solve_opts* opts, double* sol, double* u, ibdl_solve_info* info,
+                            void* stream) {
+    if (!u) return fail(IBDL_ERR_ARG, "u must be a device pointer");
+    return plan_solve(p, nrhs, data, g, opts, sol, u, info, stream);
 }
 
 ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const double* vb,
@@ -592,9 +605,9 @@ ibdl_status ibdl_batch_apply(ibdl_batch b, const double* const* q, double* const
     IBDL_GUARD_END
 }
 
-ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const double* const* g,
-                             const ibdl_solve_opts* opts, double* const* sol, ibdl_solve_info* info,
-                             void* stream) {
+static ibdl_status batch_solve(ibdl_batch b, const double* const* data, const double* const* g,
+                               const ibdl_solve_opts* opts, double* const* sol, double* const* u,
+                               ibdl_solve_info* info, void* stream) {
     if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
     const int n = (int)b->plans.size();
     if (!ptr_array_ok((const void* const*)data, n) || !ptr_array_ok((const void* const*)sol, n))
@@ -614,6 +627,10 @@ ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const doub
     io.g.assign(n, nullptr);
     if (g) io.g.assign(g, g + n);
     io.sol.assign(sol, sol + n);
+    if (u) {
+        io.u.assign(u, u + n);
+        io.vb = io.data;  // Neumann grid solutions take V_b = the boundary data
+    }
     SolveTask t(b->ks, std::move(io), o, S(stream));
     t.run_to_end();
     int overall = IBDL_OK;
@@ -623,6 +640,21 @@ ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const doub
     g_last_error.clear();
     return IBDL_OK;
     IBDL_GUARD_END
+}
+
+ibdl_status ibdl_batch_solve(ibdl_batch b, const double* const* data, const double* const* g,
+                             const ibdl_solve_opts* opts, double* const* sol, ibdl_solve_info* info,
+                             void* stream) {
+    return batch_solve(b, data, g, opts, sol, nullptr, info, stream);
+}
+
+ibdl_status ibdl_batch_solve_grid(ibdl_batch b, const double* const* data, const double* const* g,
+                                  const ibdl_solve_opts* opts, double* const* sol, double* const* u,
+                                  ibdl_solve_info* info, void* stream) {
+    if (!b) return fail(IBDL_ERR_ARG, "batch is NULL");
+    if (!ptr_array_ok((const void* const*)u, (int)b->plans.size()))
+        return fail(IBDL_ERR_ARG, "u must hold a device pointer per instance");
+    return batch_solve(b, data, g, opts, sol, u, info, stream);
 }
 
 ibdl_status ibdl_batch_eval_grid(ibdl_batch b, const double* const* sol, const double* const* vb,

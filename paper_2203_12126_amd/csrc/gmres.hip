@@ -511,11 +511,13 @@ static Staging staging(KWork& k, int R) {
 
 GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, const JobMaker& make, bool fp64,
                             hipStream_t st, Arena* ar) {
-    std::map<std::tuple<int, int, int>, std::vector<PassJob>> groups;
+    std::map<std::tuple<int, int, int, int>, std::vector<PassJob>> groups;
     for (size_t i : which) {
         const Inst& in = ks.inst[i];
         const int pr = (fp64 || in.p->prec == IBDL_PREC_FP64) ? 0 : 1;
-        groups[std::make_tuple(in.p->dim, in.p->n, pr)].push_back(make(i));
+        PassJob jb = make(i);
+        const int om = jb.out.u ? (jb.out.out ? 2 : 1) : 0;
+        groups[std::make_tuple(in.p->dim, in.p->n, pr, om)].push_back(jb);
     }
     GroupedPass gp;
     for (auto& kv : groups) {
@@ -577,13 +579,50 @@ void SolveTask::mark() {
     graph_unmarked_ = false;
 }
 
-// r = b - A x for every instance (operator in FP64 when fp64, else the plans' precision)
-void SolveTask::residual(const double* b, const double* x, double* r, bool fp64) {
+// the grid solution of instance i can come out of its residual pass: asked for,
+// and (Neumann) taken with V_b = the boundary data
+bool SolveTask::grid_fusable(size_t i) const {
+    if (i >= io_.u.size() || !io_.u[i]) return false;
+    if (ks_.inst[i].p->bc == IBDL_DIRICHLET) return true;
+    return i < io_.vb.size() && io_.vb[i] == io_.data[i];
+}
+
+// r = b - A x for every instance (operator in FP64 when fp64, else the plans' precision).
+// with_grid: instances whose grid solution is asked for take it from the same pass
+// (FP64): with u = L^-1 (g~ - S~ x [- S V_b]), Dirichlet r = U_b - x/2 - S* u,
+// Neumann r = x/2 - S* u (the same r, since b = U_b - S* L^-1 g~, resp.
+// S* L^-1 (S V_b - g~)), and u is the grid solution for the density x.
+void SolveTask::residual(const double* b, const double* x, double* r, bool fp64, bool with_grid) {
     KWork& k = ks_.w;
     auto make = [&](size_t i) {
         // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
         const Inst& in = ks_.inst[i];
         const size_t off = k.hxoff[in.r0];
+        if (with_grid && grid_fusable(i)) {
+            PipeIn pi;
+            pi.q_dip = x + off;
+            pi.c_dip = -1.0;
+            if (in.p->bc == IBDL_NEUMANN) {
+                pi.q_mono = io_.data[i];
+                pi.c_mono = -1.0;
+            }
+            pi.grid = io_.g[i];
+            pi.c_grid = 1.0;
+            PipeOut po;
+            po.u = io_.u[i];
+            po.out = r + off;
+            po.cA = -1.0;
+            po.in = x + off;
+            if (in.p->bc == IBDL_DIRICHLET) {
+                po.cB = -0.5;
+                po.in2 = io_.data[i];
+                po.cC = 1.0;
+            } else {
+                po.cB = 0.5;
+            }
+            grid_done_[i] = 1;
+            return PassJob{in.p, in.nrhs, pi, po};
+        }
         PipeIn pi;
         pi.q_dip = x + off;
         pi.c_dip = 1.0;
@@ -820,7 +859,8 @@ void SolveTask::after_krylov() {
     snapshot(snap_buf_);
     if (refining_) hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
     if (any_mixed_) {
-        residual(k.b, k.x, k.rr, true);
+        // the grid solutions come with the residual of what may be the final iterate
+        residual(k.b, k.x, k.rr, true, true);
         norms_async(k.rr, hs.nrm);
     } else {
         if (o_.true_residual) {
@@ -871,7 +911,8 @@ void SolveTask::output() {
         const Inst& in = ks_.inst[i];
         IBDL_HIP_TRY(hipMemcpyAsync(io_.sol[i], k.x + k.hxoff[in.r0], (size_t)in.nrhs * in.p->M * sizeof(double),
                                     hipMemcpyDeviceToDevice, st_));
-        if (i < io_.u.size() && io_.u[i]) grid.push_back(i);
+        // grid solutions already written by the residual pass of the final iterate
+        if (i < io_.u.size() && io_.u[i] && !grid_done_[i]) grid.push_back(i);
     }
     if (!grid.empty()) {
         // the grid solution (FP64): u = L^-1 (g~ - S~ Q) or L^-1 (g~ - S~ U_b - S V_b)
@@ -902,6 +943,7 @@ void SolveTask::advance() {
         arena_reset(*ks_.arena);
         ensure_krylov(ks_, m_);
         const size_t NI = ks_.inst.size();
+        grid_done_.assign(NI, 0);
         iters_.assign(R_, 0);
         status_.assign(R_, IBDL_OK);
         est_.assign(R_, 0.0);
@@ -1128,7 +1170,7 @@ void SolveTask::results(ibdl_solve_info* info, int* overall) const {
 
 void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std::vector<const double*>& g,
                const std::vector<const double*>& x0, const ibdl_solve_opts& o, const std::vector<double*>& sol,
-               ibdl_solve_info* info, hipStream_t st, int* overall) {
+               ibdl_solve_info* info, hipStream_t st, int* overall, const std::vector<double*>& u) {
     // nothing queued earlier reads argument tables any more once the stream is idle
     IBDL_HIP_TRY(hipStreamSynchronize(st));
     SolveIO io;
@@ -1136,6 +1178,9 @@ void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std:
     io.g = g;
     io.x0 = x0;
     io.sol = sol;
+    io.u = u;
+    // Neumann grid solutions take V_b = the boundary data
+    io.vb = data;
     SolveTask t(ks, std::move(io), o, st);
     t.run_to_end();
     t.results(info, overall);

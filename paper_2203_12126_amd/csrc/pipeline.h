@@ -545,8 +545,8 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<
 }
 
 // ------------------------------------------------------------ row_inv
-// OUT 0: interpolation partial sums; OUT 1: grid output.  Blocks map to lines
-// and right-hand sides as in row_fwd.
+// OUT 0: interpolation partial sums; OUT 1: grid output; OUT 2: both.  Blocks
+// map to lines and right-hand sides as in row_fwd.
 template <typename R, int N, int OUT, int RB>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
     using CF = RowCfg<R, N, RB>;
@@ -581,7 +581,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     // cz in z-2..z+1, of every line of the block
     using TL = Tiles<R, N>;
     constexpr int C = TL::C;
-    __shared__ int rb[OUT == 0 ? G * 8 : 1], rc[OUT == 0 ? G * 8 : 1], roff[OUT == 0 ? G * 8 + 1 : 1];
+    __shared__ int rb[OUT != 1 ? G * 8 : 1], rc[OUT != 1 ? G * 8 : 1], roff[OUT != 1 ? G * 8 + 1 : 1];
     {
         // every load of the block's rows is issued before the first is stored
         constexpr int TOT = TL::NT * GB * C;
@@ -607,7 +607,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             if (id < TOT && k <= L) xs[l * (L + 1) + k] = v[u];
         }
     }
-    if constexpr (OUT == 0) {
+    if constexpr (OUT != 1) {
         const int nz = a.dim == 3 ? 4 : 1;
         for (int t = threadIdx.x; t < G * 4; t += T) {
             const int g = t / 4, dz = t % 4;
@@ -644,7 +644,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     int pf_s = -1, pf_r = 0, pf_rr = 0;
     int pf_cell[3] = {0, 0, 0};
     R pf_tp[12];
-    if constexpr (OUT == 0) {
+    if constexpr (OUT != 1) {
         if (threadIdx.x == 0) {
             int acc = 0;
             for (int r = 0; r < G * 8; ++r) {
@@ -681,7 +681,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     run_fft<R, L, GB, T, N, +1>(s, tw, split, LdsStore<R, GB>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
-    if constexpr (OUT == 1) {
+    if constexpr (OUT != 0) {
         for (int id = threadIdx.x; id < GB * N; id += T) {
             const int l = id / N, x = id % N;
             const int line = lines_s[l % G];
@@ -689,7 +689,8 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             if (line >= 0 && r >= 0)
                 a.u[(size_t)r * a.u_stride + (size_t)line * N + x] = (double)sr[2 * ((x >> 1) * GB + l) + (x & 1)];
         }
-    } else {
+    }
+    if constexpr (OUT != 1) {
         const int gpp = a.dim == 3 ? 16 : 4;
         // work item f: point f / RB for the block's right-hand side f % RB (adjacent
         // lanes share the point's cell and taps)
@@ -979,7 +980,7 @@ constexpr int kRowRB[3] = {1, 2, 4};
 template <typename R>
 struct PreparedT : PreparedPass {
     int n = 0, dim = 2;
-    bool dense_out = false;
+    int out_mode = 0;  // 0: point output, 1: grid output, 2: both
     int min_nrhs = 1, total_rhs = 1, njobs = 1;
     ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
     StageTable<RowFwdArgs<R>> rf[3];  // one table per row-block variant
@@ -994,7 +995,7 @@ struct PreparedT : PreparedPass {
         fi.upload(ar, st);
     }
     TuneKey key(int stage) const {
-        return TuneKey{(int)sizeof(R), dim, n, stage, dense_out ? 1 : 0, tune_bucket(min_nrhs),
+        return TuneKey{(int)sizeof(R), dim, n, stage, out_mode, tune_bucket(min_nrhs),
                        tune_bucket(total_rhs), njobs > 1 ? 1 : 0};
     }
     void fwd(int v, int it, hipStream_t st, StageEv e) {
@@ -1007,7 +1008,10 @@ struct PreparedT : PreparedPass {
     void inv(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = ri[v];
         go(t, [&](bool m) {
-            if (dense_out) {
+            if (out_mode == 2) {
+                if (m) launch_row_inv_t<R, 2, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 2, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+            } else if (out_mode == 1) {
                 if (m) launch_row_inv_t<R, 1, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
                 else launch_row_inv_t<R, 1, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             } else {
@@ -1084,10 +1088,10 @@ struct PreparedT : PreparedPass {
         }
         {
             const int v = pick(1, it, st, [&](int c, StageEv e) { inv(c, it, st, e); });
-            const StageEv e = stage_events(tplan, stage++, dense_out ? "ifft_x" : "ifft_x+interp");
+            const StageEv e = stage_events(tplan, stage++, out_mode == 1 ? "ifft_x" : "ifft_x+interp");
             if (v >= 0) inv(v, it, st, e);
         }
-        if (!dense_out) {
+        if (out_mode != 1) {
             StageEv e;
             e = stage_events(tplan, stage++, "finish");
             go(fi, [&](bool m) {
@@ -1111,7 +1115,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
     const int n = p0->n;
     P->n = n;
     P->dim = p0->dim;
-    P->dense_out = jobs[0].out.u != nullptr;
+    P->out_mode = jobs[0].out.u ? (jobs[0].out.out ? 2 : 1) : 0;
     P->tplan = p0;
     int minr = 1 << 30, tot = 0;
     for (const PassJob& jb : jobs) {
@@ -1249,7 +1253,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         }
 
         // ---- finish
-        if (!dense_out) {
+        if (out.out) {
             FinishArgs fa{};
             fa.skip = in.skip;
             fa.perm = p->perm;

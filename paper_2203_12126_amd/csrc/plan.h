@@ -305,7 +305,7 @@ void release_plan(ibdl_plan p, hipStream_t st);
 // solution buffers, [nrhs_i][M_i] / [nrhs_i][n^d].  info: host [R].
 void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std::vector<const double*>& g,
                const std::vector<const double*>& x0, const ibdl_solve_opts& o, const std::vector<double*>& sol,
-               ibdl_solve_info* info, hipStream_t st, int* overall);
+               ibdl_solve_info* info, hipStream_t st, int* overall, const std::vector<double*>& u = {});
 
 // Tile autotuner: per pass configuration, the row-block variant measured fastest.
 struct TuneKey {

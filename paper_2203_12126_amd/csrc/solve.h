@@ -57,7 +57,8 @@ private:
     void collect();
     void finish_mixed();
     void output();
-    void residual(const double* b, const double* x, double* r, bool fp64);
+    void residual(const double* b, const double* x, double* r, bool fp64, bool with_grid = false);
+    bool grid_fusable(size_t i) const;
     void norms_async(const double* pool, double* host);
 
     KrylovSet& ks_;
@@ -86,6 +87,7 @@ private:
     int round_ = 0;
     std::vector<double> bn_, tol_, est_, truer_;
     std::vector<int> skip_, iters_, status_, fp64_;
+    std::vector<char> grid_done_;  // per instance: u written by the last residual pass
 };
 
 }  // namespace ibdl

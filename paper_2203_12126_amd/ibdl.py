@@ -87,6 +87,7 @@ def lib():
         "ibdl_apply": ([P, I, P, P, P], st),
         "ibdl_rhs": ([P, I, P, P, P, P], st),
         "ibdl_solve": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P], st),
+        "ibdl_solve_grid": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(SolveInfo), P], st),
         "ibdl_eval_grid": ([P, I, P, P, P, P, P], st),
         "ibdl_plan_binning": ([P, P, P], st),
         "ibdl_plan_set_timing": ([P, I], st),
@@ -99,6 +100,7 @@ def lib():
         "ibdl_batch_apply": ([P, P, P, P], st),
         "ibdl_batch_get_stats": ([P, I, ctypes.POINTER(PlanStats)], st),
         "ibdl_batch_solve": ([P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P], st),
+        "ibdl_batch_solve_grid": ([P, P, P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(SolveInfo), P], st),
         "ibdl_batch_eval_grid": ([P, P, P, P, P, P], st),
         "ibdl_batch_set_timing": ([P, I], st),
         "ibdl_batch_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
@@ -266,6 +268,25 @@ class Plan:
                           rel_resid_true=i.rel_resid_true, status=i.status,
                           fp64_applies=i.fp64_applies) for i in info]
 
+    def solve_grid(self, data, g=None, tol=1e-8, restart=50, maxit=500, x0=None, true_residual=False,
+                   out=None, u=None, stream=None, raise_on_noconv=True):
+        """solve() and the grid solution (V_b = data for Neumann) in one call."""
+        nrhs = self._nrhs(data, self.m)
+        out = self._empty(*data.shape) if out is None else out
+        u = self._empty(nrhs, *([self.n] * self.dim)) if u is None else u
+        o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
+        if x0 is not None:
+            o.x0 = _dptr(x0, "x0", data.numel()).value
+        info = (SolveInfo * nrhs)()
+        st = lib().ibdl_solve_grid(self._h, nrhs, _dptr(data, "data"), _dptr(g, "g", nrhs * self.grid_size),
+                                   ctypes.byref(o), _dptr(out, "sol", data.numel()),
+                                   _dptr(u, "u", nrhs * self.grid_size), info, _stream(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            _check(st, "ibdl_solve_grid")
+        return out, u, [dict(iters=i.iters, rel_resid_est=i.rel_resid_est,
+                             rel_resid_true=i.rel_resid_true, status=i.status,
+                             fp64_applies=i.fp64_applies) for i in info]
+
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
         nrhs = self._nrhs(sol, self.m)
         out = self._empty(nrhs, *([self.n] * self.dim)) if out is None else out
@@ -405,6 +426,21 @@ class Batch:
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_batch_solve")
         return out, _info_dicts(info)
+
+    def solve_grid(self, data, g=None, tol=1e-8, restart=50, maxit=500, true_residual=False, out=None,
+                   u=None, stream=None, raise_on_noconv=True):
+        """solve() and every instance's grid solution (V_b = data for Neumann)."""
+        out = self._empty_like_sizes() if out is None else out
+        u = self._empty_like_sizes(grid=True) if u is None else u
+        o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
+        info = (SolveInfo * self.total_rhs)()
+        garr = None if g is None else _ptr_array(g, "g", self._sizes(grid=True), allow_none=True)
+        st = lib().ibdl_batch_solve_grid(self._h, _ptr_array(data, "data", self._sizes()), garr, ctypes.byref(o),
+                                         _ptr_array(out, "sol", self._sizes()),
+                                         _ptr_array(u, "u", self._sizes(grid=True)), info, _stream(stream))
+        if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
+            _check(st, "ibdl_batch_solve_grid")
+        return out, u, _info_dicts(info)
 
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
         out = self._empty_like_sizes(grid=True) if out is None else out

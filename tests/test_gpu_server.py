@@ -31,8 +31,8 @@ def alone(prob, prec):
     pl = ibdl.Plan.from_problem(prob, prec=prec)
     data = T(prob.data).reshape(1, -1)
     g = T(prob.g_tilde).reshape(1, -1)
-    sol, info = pl.solve(data, g, tol=1e-8)
-    u = pl.eval_grid(sol, vb=data if prob.bc == W.NEUMANN else None, g=g)
+    # a served request is a solve with its grid solution (V_b = data for Neumann)
+    sol, u, info = pl.solve_grid(data, g, tol=1e-8)
     pl.close()
     return sol, u, info
 

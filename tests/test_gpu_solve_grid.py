@@ -1,0 +1,116 @@
+"""Solve and grid solution in one call (ibdl_solve_grid / ibdl_batch_solve_grid).
+
+For MIXED plans the grid solution comes out of the FP64 residual pass of the
+final iterate: u = L^-1 (g~ - S~ x [- S V_b]) on the grid and the residual from
+the same spectrum at the points.  Bars: u is bit-identical to ibdl_eval_grid of
+the returned solution (the same FP64 spread, transforms and grid store); the
+solution and u are within 1e-6 of the oracle; the solution agrees with
+ibdl_solve's to 1e-10 (the refinement residual is formed from the boundary data
+instead of the stored right-hand side, equal up to rounding); FP64 plans are
+unchanged (bit-identical to ibdl_solve + ibdl_eval_grid); a batch equals its
+instances solved alone.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import ibdl_oracle as O
+from paper_2203_12126_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2203_12126_amd import ibdl  # noqa: E402
+
+SOLVE_MIXED_TOL = 1e-6
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def relerr(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("bc,alpha", [(W.DIRICHLET, 1.0), (W.NEUMANN, 1.0), (W.NEUMANN, 100.0)])
+def test_star1024_solve_grid_mixed(bc, alpha):
+    p = W.config_star1024(m=4096, alpha=alpha, bc=bc)
+    st = O.setup_from_problem(p)
+    tight, _ = O.solve(st, p.data, p.g_tilde, bc=bc, tol=1e-13)
+    uref = O.eval_grid(st, tight.x, vb=p.data if bc == W.NEUMANN else None, g_tilde=p.g_tilde, bc=bc)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    data = T(np.stack([p.data, p.data]))
+    g = T(np.stack([p.g_tilde, p.g_tilde]))
+    sol, u, info = pl.solve_grid(data, g, tol=1e-8)
+    assert all(i["rel_resid_true"] <= 1e-8 for i in info)
+    ue = pl.eval_grid(sol, vb=data if bc == W.NEUMANN else None, g=g)
+    assert torch.equal(u, ue)
+    for r in range(2):
+        assert relerr(sol[r].cpu().numpy(), tight.x) < SOLVE_MIXED_TOL
+        assert relerr(u[r].cpu().numpy(), uref) < SOLVE_MIXED_TOL
+    s1, i1 = pl.solve(data, g, tol=1e-8)
+    assert relerr(sol.cpu().numpy(), s1.cpu().numpy()) < 1e-10
+    pl.close()
+
+
+def test_solve_grid_3d_mixed():
+    p = W.table2_problem(32, 2000)
+    st = O.setup_from_problem(p)
+    tight, _ = O.solve(st, p.data, p.g_tilde, bc=p.bc, tol=1e-13)
+    uref = O.eval_grid(st, tight.x, g_tilde=p.g_tilde, bc=p.bc)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    data, g = T(p.data[None]), T(p.g_tilde[None])
+    sol, u, info = pl.solve_grid(data, g, tol=1e-9)
+    assert torch.equal(u, pl.eval_grid(sol, g=g))
+    assert relerr(sol[0].cpu().numpy(), tight.x) < SOLVE_MIXED_TOL
+    assert relerr(u[0].cpu().numpy(), uref) < SOLVE_MIXED_TOL
+    pl.close()
+
+
+@pytest.mark.parametrize("bc", [W.DIRICHLET, W.NEUMANN])
+def test_solve_grid_fp64_unchanged(bc):
+    p = W.config_star1024(m=1200, n=192, alpha=2.0, bc=bc, seed=8)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.FP64)
+    data, g = T(p.data[None]), T(p.g_tilde[None])
+    sol, u, info = pl.solve_grid(data, g, tol=1e-10)
+    s1, i1 = pl.solve(data, g, tol=1e-10)
+    assert torch.equal(sol, s1)
+    assert torch.equal(u, pl.eval_grid(s1, vb=data if bc == W.NEUMANN else None, g=g))
+    pl.close()
+
+
+def test_batch_solve_grid_equals_alone():
+    items = []
+    for sp in W.config_batch(count=5, seed=41, sizes=(64, 96, 128)):
+        sp["nrhs"] = 1 + sp["nrhs"] % 3
+        _, _, probs = W.batch_instance(sp)
+        items.append(probs)
+    batch = ibdl.Batch.from_problems([(probs[0], len(probs)) for probs in items], prec=ibdl.MIXED)
+    data = [T(np.stack([q.data for q in probs])) for probs in items]
+    g = [T(np.stack([q.g_tilde for q in probs])) for probs in items]
+    sol, u, info = batch.solve_grid(data, g, tol=1e-9)
+    for i, probs in enumerate(items):
+        pl = ibdl.Plan.from_problem(probs[0], prec=ibdl.MIXED)
+        s1, u1, _ = pl.solve_grid(data[i], g[i], tol=1e-9)
+        assert torch.equal(sol[i], s1), f"instance {i}"
+        assert torch.equal(u[i], u1), f"instance {i}"
+        pl.close()
+    batch.close()
+
+
+def test_solve_grid_argument_errors():
+    p = W.config_star1024(m=1200, n=128, seed=3)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    data, g = T(p.data[None]), T(p.g_tilde[None])
+    sol = torch.empty_like(data)
+    info = (ibdl.SolveInfo * 1)()
+    st = ibdl.lib().ibdl_solve_grid(pl._h, 1, data.data_ptr(), g.data_ptr(), None, sol.data_ptr(), None,
+                                    info, None)
+    assert st == ibdl.ERR_ARG and "u" in ibdl.last_error()
+    pl.close()
