@@ -310,21 +310,32 @@ __device__ __forceinline__ void reg_dft(cplx<R>* v) {
 }
 
 // ------------------------------------------------------------------ stages
-// LDS functors
-template <typename R, int C>
+// LDS row of element i with one padding row after every 2^PS rows (PS = 0: none).
+// The first stage of a transform writes rows RAD apart; with RAD = 2^PS the
+// padding moves consecutive butterflies' rows to different LDS banks.
+template <int PS>
+__device__ __forceinline__ constexpr int lds_row(int i) {
+    if constexpr (PS == 0) return i;
+    else return i + (i >> PS);
+}
+template <int L, int PS>
+struct PaddedRows { static constexpr int value = PS == 0 ? L : L + ((L - 1) >> PS) + 1; };
+
+// LDS functors (C elements per row)
+template <typename R, int C, int PS = 0>
 struct LdsLoad {
     const cplx<R>* s;
-    __device__ __forceinline__ cplx<R> operator()(int i, int c) const { return s[i * C + c]; }
+    __device__ __forceinline__ cplx<R> operator()(int i, int c) const { return s[lds_row<PS>(i) * C + c]; }
 };
-template <typename R, int C>
+template <typename R, int C, int PS = 0>
 struct LdsStore {
     cplx<R>* s;
-    __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[i * C + c] = v; }
+    __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[lds_row<PS>(i) * C + c] = v; }
 };
 
 // One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
-template <typename R, int L, int C, int TH, int NT, int SIGN, int NS, int RAD, int... REST, class TW, class LD,
-          class ST>
+template <typename R, int L, int C, int TH, int NT, int SIGN, int PS, int NS, int RAD, int... REST, class TW,
+          class LD, class ST>
 __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST st) {
     constexpr int NB = L / RAD;
     constexpr int TOT = NB * C;
@@ -363,15 +374,26 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST s
         emit(st);
     } else {
         __syncthreads();  // every input of this stage has been read
-        emit(LdsStore<R, C>{s});
+        emit(LdsStore<R, C, PS>{s});
         __syncthreads();
-        run_stages<R, L, C, TH, NT, SIGN, NS * RAD, REST...>(s, tw, LdsLoad<R, C>{s}, st);
+        run_stages<R, L, C, TH, NT, SIGN, PS, NS * RAD, REST...>(s, tw, LdsLoad<R, C, PS>{s}, st);
     }
 }
 
-template <typename R, int L, int C, int TH, int NT, int SIGN, class TW, class LD, class ST, int... Rs>
+// PS: padding of the intermediate LDS rows (lds_row); the caller's functors use
+// the same layout where they touch those rows.
+template <typename R, int L, int C, int TH, int NT, int SIGN, int PS = 0, class TW, class LD, class ST, int... Rs>
 __device__ __forceinline__ void run_fft(cplx<R>* s, const TW& tw, LD ld, ST st, Radices<Rs...>) {
-    run_stages<R, L, C, TH, NT, SIGN, 1, Rs...>(s, tw, ld, st);
+    run_stages<R, L, C, TH, NT, SIGN, PS, 1, Rs...>(s, tw, ld, st);
+}
+
+// log2 of the first radix of a plan when it is a power of two >= 4, else 0
+template <int L, int RMAX>
+constexpr int first_radix_shift() {
+    const int r = make_plan(L, RMAX).r[0];
+    int sh = 0;
+    while ((1 << sh) < r) ++sh;
+    return ((1 << sh) == r && r >= 4 && make_plan(L, RMAX).n > 1) ? sh : 0;
 }
 
 // Threads per block so that the largest radix stage has one butterfly per thread.

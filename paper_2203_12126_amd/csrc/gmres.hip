@@ -588,17 +588,20 @@ bool SolveTask::grid_fusable(size_t i) const {
 }
 
 // r = b - A x for every instance (operator in FP64 when fp64, else the plans' precision).
-// with_grid: instances whose grid solution is asked for take it from the same pass
-// (FP64): with u = L^-1 (g~ - S~ x [- S V_b]), Dirichlet r = U_b - x/2 - S* u,
-// Neumann r = x/2 - S* u (the same r, since b = U_b - S* L^-1 g~, resp.
-// S* L^-1 (S V_b - g~)), and u is the grid solution for the density x.
+// The FP64 residual of the system itself (b = the pool k.b) of an instance whose
+// grid solution is asked for is formed from the boundary data: with
+// u = L^-1 (g~ - S~ x [- S V_b]), Dirichlet r = U_b - x/2 - S* u, Neumann
+// r = x/2 - S* u (the same r, since b = U_b - S* L^-1 g~, resp.
+// S* L^-1 (S V_b - g~)); with_grid: u, the grid solution for the density x,
+// is written by the same pass.
 void SolveTask::residual(const double* b, const double* x, double* r, bool fp64, bool with_grid) {
     KWork& k = ks_.w;
+    const bool system = fp64 && b == k.b;
     auto make = [&](size_t i) {
         // A x = -S* L^-1 S~ x + s x/2, so b - A x = S* L^-1 S~ x - s x/2 + b
         const Inst& in = ks_.inst[i];
         const size_t off = k.hxoff[in.r0];
-        if (with_grid && grid_fusable(i)) {
+        if (system && grid_fusable(i)) {
             PipeIn pi;
             pi.q_dip = x + off;
             pi.c_dip = -1.0;
@@ -609,7 +612,7 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64,
             pi.grid = io_.g[i];
             pi.c_grid = 1.0;
             PipeOut po;
-            po.u = io_.u[i];
+            po.u = with_grid ? io_.u[i] : nullptr;
             po.out = r + off;
             po.cA = -1.0;
             po.in = x + off;
@@ -620,7 +623,7 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64,
             } else {
                 po.cB = 0.5;
             }
-            grid_done_[i] = 1;
+            if (with_grid) grid_done_[i] = 1;
             return PassJob{in.p, in.nrhs, pi, po};
         }
         PipeIn pi;
@@ -964,16 +967,21 @@ void SolveTask::advance() {
         auto bytes_of = [&](const Inst& in) { return (size_t)in.nrhs * in.p->M * sizeof(double); };
         // right-hand sides in FP64 (Dirichlet: U_b - S* L^-1 g~; Neumann: S* L^-1 (S V_b - g~));
         // Dirichlet instances without forcing need no pass: b = U_b
-        std::vector<size_t> need_pass;
+        // Mixed instances whose grid solution is asked for form every FP64 residual
+        // from the boundary data (see residual), so b only seeds their first
+        // FP32-operator solve: it is formed in FP32 like that operator.
+        std::vector<size_t> need64, need32;
         for (size_t i = 0; i < NI; ++i) {
             const Inst& in = ks_.inst[i];
             if (in.p->bc == IBDL_DIRICHLET && !io_.g[i])
                 IBDL_HIP_TRY(hipMemcpyAsync(k.b + k.hxoff[in.r0], io_.data[i], bytes_of(in), hipMemcpyDeviceToDevice,
                                             st_));
+            else if (in.p->prec == IBDL_PREC_MIXED && grid_fusable(i))
+                need32.push_back(i);
             else
-                need_pass.push_back(i);
+                need64.push_back(i);
         }
-        if (!need_pass.empty()) {
+        if (!need64.empty() || !need32.empty()) {
             auto make = [&](size_t i) {
                 const Inst& in = ks_.inst[i];
                 PipeIn pi;
@@ -996,7 +1004,8 @@ void SolveTask::advance() {
                 }
                 return PassJob{in.p, in.nrhs, pi, po};
             };
-            prepare_grouped(ks_, need_pass, make, true, st_).run(0, st_);
+            if (!need64.empty()) prepare_grouped(ks_, need64, make, true, st_).run(0, st_);
+            if (!need32.empty()) prepare_grouped(ks_, need32, make, false, st_).run(0, st_);
         }
         bool any_x0 = false;
         for (size_t i = 0; i < io_.x0.size(); ++i) any_x0 |= io_.x0[i] != nullptr;

@@ -60,6 +60,14 @@ struct RMax { static constexpr int value = sizeof(R) == 4 ? IBDL_RMAX_F32 : IBDL
 template <typename R>
 struct ColBytes { static constexpr int value = sizeof(R) == 4 ? IBDL_COLB_F32 : IBDL_COLB_F64; };
 
+// smallest p >= need with p = d (mod m): lines p elements apart start d elements
+// (d * element bytes / 4 banks) apart in the LDS banks
+constexpr int staggered_pitch(int need, int m, int d) {
+    int p = need;
+    while (p % m != d % m) ++p;
+    return p;
+}
+
 // Row passes: a block transforms G lines of each of RB right-hand sides (GB lines
 // in all); the right-hand sides of a block share the spread and interpolation tables.
 template <typename R, int N, int RB = 1>
@@ -68,6 +76,16 @@ struct RowCfg {
     static constexpr int G = imax(1, imin(64, IBDL_ROW_ELEMS / L) / RB);      // lines per rhs
     static constexpr int GB = G * RB;                                         // lines per block
     static constexpr int T = imax(256, fft_threads<L, GB, RMax<R>::value>());
+    // LDS rows of the block's lines narrower than the 64 four-byte banks: pad the
+    // transform's rows (lds_row) and stagger the row-inverse input lines (pitch XP)
+    // so that one half-wave's accesses spread over distinct banks
+    static constexpr bool NARROW = GB * 2 * (int)sizeof(R) < 256;
+    static constexpr int PS = NARROW ? first_radix_shift<L, RMax<R>::value>() : 0;
+    static constexpr int ROWS = PaddedRows<L, PS>::value;
+    // lanes served per LDS cycle: 256 bytes of elements; consecutive lines start
+    // (that many lanes / GB) elements apart in the banks
+    static constexpr int XP =
+        NARROW && GB > 1 ? staggered_pitch(L + 1, 128 / (int)sizeof(R), 128 / (int)sizeof(R) / GB) : L + 1;
 };
 // right-hand sides per row block the library is built for
 #define IBDL_ROW_RBS(X) X(1) X(2) X(4)
@@ -230,7 +248,7 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
 // the entries of a node are loaded once for all of them.  Each node is written
 // by exactly one thread, its entries summed in their stored order.  la[g] is the
 // first active node of line g and rs the prefix sums of the lines' node counts.
-template <typename R, int N, int G, int RB, int T>
+template <typename R, int N, int G, int RB, int T, int PS>
 __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it, const int* la, const int* rs,
                                              const int* rhs_s) {
     constexpr int GB = G * RB;
@@ -271,7 +289,7 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
             for (int u = 0; u < 8; ++u)
                 if (u < cnt) acc.add(ww[u], (R)qq[u]);
         }
-        sr[2 * ((x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
+        sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
     __syncthreads();
 }
@@ -283,8 +301,8 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
 template <typename R, int N, int RB>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int it) {
     using CF = RowCfg<R, N, RB>;
-    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
-    __shared__ cplx<R> s[L * GB];
+    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS;
+    __shared__ cplx<R> s[CF::ROWS * GB];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G], rhs_s[RB];
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
@@ -325,7 +343,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     }
     if (!live) return;
     if (threadIdx.x < RB) rhs_s[threadIdx.x] = rv[threadIdx.x];
-    for (int i = threadIdx.x; i < L * GB; i += T) s[i] = cplx<R>{R(0), R(0)};
+    for (int i = threadIdx.x; i < CF::ROWS * GB; i += T) s[i] = cplx<R>{R(0), R(0)};
     __syncthreads();
     if (threadIdx.x < 2) {
         int* r = rs[threadIdx.x];
@@ -348,14 +366,15 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
             const int l = id / N, x = id % N;
-            if (id < N * GB) sr[2 * ((x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
+            if (id < N * GB) sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
         }
     }
     __syncthreads();
-    if (a.dip.q) spread_phase<R, N, G, RB, T>(sr, a.dip, it, la[0], rs[0], rhs_s);
-    if (a.mono.q) spread_phase<R, N, G, RB, T>(sr, a.mono, it, la[1], rs[1], rhs_s);
+    if (a.dip.q) spread_phase<R, N, G, RB, T, PS>(sr, a.dip, it, la[0], rs[0], rhs_s);
+    if (a.mono.q) spread_phase<R, N, G, RB, T, PS>(sr, a.mono, it, la[1], rs[1], rhs_s);
 
-    run_fft<R, L, GB, T, N, -1>(s, tw, LdsLoad<R, GB>{s}, LdsStore<R, GB>{s}, FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, GB, T, N, -1, PS>(s, tw, LdsLoad<R, GB, PS>{s}, LdsStore<R, GB, PS>{s},
+                                    FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
@@ -369,8 +388,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         const int line = lines_s[l % G];
         const int r = rhs_s[l / G];
         if (k > L || line < 0 || r < 0) continue;
-        const cplx<R> zk = s[(k % L) * GB + l];
-        const cplx<R> zm = s[((L - k) % L) * GB + l];
+        const cplx<R> zk = s[lds_row<PS>(k % L) * GB + l];
+        const cplx<R> zm = s[lds_row<PS>((L - k) % L) * GB + l];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
         a.spec[(size_t)r * a.spec_stride + TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
@@ -550,10 +569,11 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<
 template <typename R, int N, int OUT, int RB>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
     using CF = RowCfg<R, N, RB>;
-    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
-    // the block's spectrum rows X[0..L] (line-major, xs) are only read by the
-    // first stage of the inverse transform, whose outputs (s) therefore share the storage
-    __shared__ cplx<R> s[(L + 1) * GB];
+    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS, XP = CF::XP;
+    // the block's spectrum rows X[0..L] (line-major with pitch XP, xs) are only read
+    // by the first stage of the inverse transform, whose outputs (s) therefore share
+    // the storage
+    __shared__ cplx<R> s[imax(XP, CF::ROWS) * GB];
     cplx<R>* xs = s;
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
     __shared__ cplx<R> twl[TWL::SIZE];
@@ -604,7 +624,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             const int t = id / (GB * C), rem = id % (GB * C);
             const int l = rem / C, c = rem % C;
             const int k = t * C + c;
-            if (id < TOT && k <= L) xs[l * (L + 1) + k] = v[u];
+            if (id < TOT && k <= L) xs[l * XP + k] = v[u];
         }
     }
     if constexpr (OUT != 1) {
@@ -672,13 +692,13 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     }
     // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
     auto split = [&](int k, int l) -> cplx<R> {
-        const cplx<R> xk = xs[l * (L + 1) + k];
-        const cplx<R> xm = xs[l * (L + 1) + L - k];
+        const cplx<R> xk = xs[l * XP + k];
+        const cplx<R> xm = xs[l * XP + L - k];
         const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
         const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
         return cadd(e, cmul_si<1>(cmul(cconj(tw.get(k)), d)));
     };
-    run_fft<R, L, GB, T, N, +1>(s, tw, split, LdsStore<R, GB>{s}, FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, GB, T, N, +1, PS>(s, tw, split, LdsStore<R, GB, PS>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     if constexpr (OUT != 0) {
@@ -687,7 +707,8 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             const int line = lines_s[l % G];
             const int r = rhs_s[l / G];
             if (line >= 0 && r >= 0)
-                a.u[(size_t)r * a.u_stride + (size_t)line * N + x] = (double)sr[2 * ((x >> 1) * GB + l) + (x & 1)];
+                a.u[(size_t)r * a.u_stride + (size_t)line * N + x] =
+                    (double)sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)];
         }
     }
     if constexpr (OUT != 1) {
@@ -707,7 +728,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int x = (cx - 1 + t + N) % N;
-                acc += tp[t] * sr[2 * ((x >> 1) * GB + l) + (x & 1)];
+                acc += tp[t] * sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)];
             }
             acc *= tp[4 + oy];
             int o = oy;
@@ -1061,7 +1082,11 @@ struct PreparedT : PreparedPass {
         {
             const int v = pick(0, it, st, [&](int c, StageEv e) { fwd(c, it, st, e); });
             const StageEv e = stage_events(tplan, stage++, "spread+fft_x");
+            // a stage tuned just now has run already; with timing on it runs once
+            // more (it overwrites its outputs from unchanged inputs) so that the
+            // stage's events are recorded
             if (v >= 0) fwd(v, it, st, e);
+            else if (e.a) fwd(-1 - v, it, st, e);
         }
         if (dim == 2) {
             const StageEv e = stage_events(tplan, stage++, "fft_y+symbol");
@@ -1090,6 +1115,7 @@ struct PreparedT : PreparedPass {
             const int v = pick(1, it, st, [&](int c, StageEv e) { inv(c, it, st, e); });
             const StageEv e = stage_events(tplan, stage++, out_mode == 1 ? "ifft_x" : "ifft_x+interp");
             if (v >= 0) inv(v, it, st, e);
+            else if (e.a) inv(-1 - v, it, st, e);
         }
         if (out_mode != 1) {
             StageEv e;

@@ -51,3 +51,19 @@ def test_autotuner_records_choices():
     rep = ibdl.autotune_report()
     assert "n=192" in rep and "row_fwd" in rep and "row_inv" in rep
     pl.close()
+
+
+def test_timing_on_a_pass_that_tunes():
+    """A pass that tunes its row stages while stage timing is on still records
+    every stage's events (the tuned stage runs once more under them)."""
+    ibdl.set_autotune(True)  # clears the choices: the next pass tunes
+    p = W.config_star1024(m=1500, n=128, alpha=1.0, seed=6)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    q = torch.as_tensor(np.random.default_rng(2).standard_normal((2, p.geom.m)), device="cuda")
+    pl.set_timing(True)
+    out = pl.apply(q)
+    names = [nm for nm, ms, calls in pl.stage_times()]
+    assert {"spread+fft_x", "fft_y+symbol", "ifft_x+interp", "finish"} <= set(names)
+    assert torch.equal(out, pl.apply(q))
+    pl.set_timing(False)
+    pl.close()
