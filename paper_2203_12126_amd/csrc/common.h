@@ -30,6 +30,46 @@ __device__ __forceinline__ cplx<R> cmul_si(cplx<R> a) {
     return S > 0 ? cplx<R>{-a.y, a.x} : cplx<R>{a.y, -a.x};
 }
 
+// Raw buffer access within one range [base, base + bytes) given by a buffer
+// descriptor: a 32-bit byte offset per lane; an offset at or beyond `bytes`
+// reads as zero and drops the store (the buffer unit's range check), so masked
+// elements need no branch.  bytes < 2^31.
+constexpr int kBufOut = 0x7ffffff0;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    // word 3: 32-bit data format, as untyped buffer loads and stores require on gfx9
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename R>
+struct BufIO;
+template <>
+struct BufIO<float> {
+    typedef unsigned int V __attribute__((ext_vector_type(2)));
+    __device__ __forceinline__ static cplx<float> load(__amdgpu_buffer_rsrc_t r, int off) {
+        const V v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return {__uint_as_float(v.x), __uint_as_float(v.y)};
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, int off, cplx<float> c) {
+        const V v = {__float_as_uint(c.x), __float_as_uint(c.y)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    }
+};
+template <>
+struct BufIO<double> {
+    typedef unsigned int V __attribute__((ext_vector_type(4)));
+    __device__ __forceinline__ static cplx<double> load(__amdgpu_buffer_rsrc_t r, int off) {
+        const V v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const unsigned long long a = ((unsigned long long)v.y << 32) | v.x;
+        const unsigned long long b = ((unsigned long long)v.w << 32) | v.z;
+        return {__longlong_as_double((long long)a), __longlong_as_double((long long)b)};
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, int off, cplx<double> c) {
+        const unsigned long long a = (unsigned long long)__double_as_longlong(c.x);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(c.y);
+        const V v = {(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    }
+};
+
 // Discrete delta kernels (Sec. 5.2).  Peskin's four-point function:
 //   phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8        0 <= |r| <= 1
 //          = (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8       1 <= |r| <= 2

@@ -405,25 +405,32 @@ __global__ __launch_bounds__((RowCfg<R, N, RB>::T)) void k_row_fwd(RowFwdArgs<R>
 // A block transforms K*C lines of length N: element i of line l at
 // base + i * es + l, with the C columns of tile t (kx = t*C + l % C) and, for
 // K > 1, K consecutive y-rows (ky = o*K + l / C) of the z-transform.
-template <typename R, int LC>
+// Element i of line l through the block's buffer descriptor (esb: bytes between
+// consecutive elements of a line, below 2^24): lines whose column l % C is past
+// the spectrum's width (l % C >= vcols) and rows outside the row mask map to an
+// offset outside the range (read as zero, store dropped), with no branch.
+template <typename R, int C>
+__device__ __forceinline__ int col_offset(int i, int l, int esb, int vcols, const uint8_t* m) {
+    const bool ok = ((l % C) < vcols) & (m[i] != 0);
+    const int off = (int)__umul24((unsigned)i, (unsigned)esb) + l * (int)sizeof(cplx<R>);
+    return ok ? off : kBufOut;
+}
+template <typename R, int C>
 struct ColLoad {
-    const cplx<R>* base;
-    size_t es;
-    const uint8_t* valid;  // LDS: line holds a real column
-    const uint8_t* m;      // LDS row mask
+    __amdgpu_buffer_rsrc_t rs;
+    int esb, vcols;
+    const uint8_t* m;  // LDS row mask
     __device__ __forceinline__ cplx<R> operator()(int i, int l) const {
-        if (valid[l] && m[i]) return base[(size_t)i * es + l];
-        return cplx<R>{R(0), R(0)};
+        return BufIO<R>::load(rs, col_offset<R, C>(i, l, esb, vcols, m));
     }
 };
-template <typename R, int LC>
+template <typename R, int C>
 struct ColStore {
-    cplx<R>* base;
-    size_t es;
-    const uint8_t* valid;
+    __amdgpu_buffer_rsrc_t rs;
+    int esb, vcols;
     const uint8_t* m;
     __device__ __forceinline__ void operator()(int i, int l, cplx<R> v) const {
-        if (valid[l] && m[i]) base[(size_t)i * es + l] = v;
+        BufIO<R>::store(rs, col_offset<R, C>(i, l, esb, vcols, m), v);
     }
 };
 // 1/x: hardware reciprocal (about 1 ulp) in FP32, exact division in FP64
@@ -459,7 +466,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     constexpr int C = CK::C, LC = CK::LC, T = CK::T, RM = RMax<R>::value;
     constexpr int NT = (N / 2 + 1 + C - 1) / C;
     __shared__ cplx<R> s[N * LC];
-    __shared__ uint8_t lmask[N], smask[N], valid[LC];
+    __shared__ uint8_t lmask[N], smask[N];
     __shared__ R srow[MODE == 1 ? N : 1];
     __shared__ R scol[MODE == 1 ? LC : 1];
     // the full twiddle table in LDS where it keeps two blocks per compute unit
@@ -508,7 +515,13 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
         }
     }
     if (skipv) return;
-    cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
+    // the block's elements i * es + l (i < N, l < LC) from its base: at most
+    // (511 * 65 * 512 * 4 + 16) * 16 bytes (3-D, n <= 512, FP64), below 2^31
+    const cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
+    const int es = (int)a.es;
+    const int esb = es * (int)sizeof(cplx<R>);
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, (uint32_t)(((N - 1) * es + LC) * (int)sizeof(cplx<R>)));
+    const int vcols = a.width - t * C;
 #pragma unroll
     for (int u = 0; u < PN; ++u) {
         const int i = threadIdx.x + u * T;
@@ -522,7 +535,6 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     for (int u = 0; u < PL; ++u) {
         const int l = threadIdx.x + u * T;
         if (l < LC) {
-            valid[l] = t * C + l % C < a.width;
             if constexpr (MODE == 1) scol[l] = scv[u];
         }
     }
@@ -530,8 +542,8 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     if constexpr (NYQ) {
         if (t == NT - 1) {
             // the last tile holds only the column kx = n/2: transform it alone
-            const ColLoad<R, 1> ld1{base, a.es, valid, lmask};
-            const ColStore<R, 1> st1{base, a.es, valid, smask};
+            const ColLoad<R, C> ld1{rs, esb, vcols, lmask};
+            const ColStore<R, C> st1{rs, esb, vcols, smask};
             if constexpr (MODE == 0) {
                 run_fft<R, N, 1, T, N, -1>(s, tw, ld1, st1, FwdRadices<N, RM>{});
             } else if constexpr (MODE == 2) {
@@ -545,8 +557,8 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
             return;
         }
     }
-    const ColLoad<R, LC> ld{base, a.es, valid, lmask};
-    const ColStore<R, LC> st{base, a.es, valid, smask};
+    const ColLoad<R, C> ld{rs, esb, vcols, lmask};
+    const ColStore<R, C> st{rs, esb, vcols, smask};
     if constexpr (MODE == 0) {
         run_fft<R, N, LC, T, N, -1>(s, tw, ld, st, FwdRadices<N, RM>{});
     } else if constexpr (MODE == 2) {
