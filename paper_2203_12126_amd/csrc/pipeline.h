@@ -270,24 +270,25 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
         const double* q = c.q + (size_t)r * c.q_stride + (size_t)it * c.q_jstride;
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
-        // entries in groups of 8: every load of a group is issued before any is used
+        // entries in groups of 8: every load of a group is issued before any is used;
+        // past the node's last entry the group re-reads that entry with weight 0
+        // (adding 0 * q leaves both parts of the sum exactly as they were), so the
+        // group has no branch
         for (int e = c.act_ptr[a]; e < e1; e += 8) {
-            const int cnt = e1 - e;
             uint32_t kk[8];
             R ww[8];
             double qq[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (u < cnt) {
-                    kk[u] = c.k[e + u];
-                    ww[u] = c.w[e + u];
-                }
+            for (int u = 0; u < 8; ++u) {
+                const int eu = e + u < e1 ? e + u : e1 - 1;
+                kk[u] = c.k[eu];
+                const R wv = c.w[eu];
+                ww[u] = e + u < e1 ? wv : R(0);
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (u < cnt) qq[u] = q[kk[u]];
+            for (int u = 0; u < 8; ++u) qq[u] = q[kk[u]];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (u < cnt) acc.add(ww[u], (R)qq[u]);
+            for (int u = 0; u < 8; ++u) acc.add(ww[u], (R)qq[u]);
         }
         sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
