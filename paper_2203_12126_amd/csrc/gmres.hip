@@ -61,6 +61,21 @@ struct KArgs {
 
 __device__ __forceinline__ int nblocks_of(int M) { return (M + GT - 1) / GT; }
 
+// s = sum over b < nb of p[b * stride] in b order, the loads issued eight at a time
+__device__ __forceinline__ double sum_strided(const double* __restrict__ p, int nb, size_t stride) {
+    double s = 0.0;
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = p[(size_t)(b + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; b < nb; ++b) s += p[(size_t)b * stride];
+    return s;
+}
+
 // Block sums of nv per-thread values at once: each wave reduces its values with
 // cross-lane shuffles, one LDS write per wave and value, one barrier, then
 // thread i adds the wave totals of value i (fixed order).  out[i] valid in
@@ -106,8 +121,7 @@ __global__ void k_norms(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.R) return;
     const int nb = nblocks_of(a.Mr[r]);
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
+    const double s = sum_strided(a.part + (size_t)r * a.pstride, nb, 1);
     a.nrm[r] = sqrt(s);
 }
 
@@ -115,8 +129,7 @@ __global__ void k_set_bnorm(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.R) return;
     const int nb = nblocks_of(a.Mr[r]);
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
+    const double s = sum_strided(a.part + (size_t)r * a.pstride, nb, 1);
     a.bnorm[r] = sqrt(s);
     a.state[4 * r + ST_DONE] = a.skip[r];
     a.state[4 * r + ST_ITERS] = 0;
@@ -131,8 +144,7 @@ __global__ __launch_bounds__(GT) void k_init_cycle(KArgs a, const double* __rest
     const int nb = nblocks_of(M);
     int32_t* st = a.state + 4 * r;
     if (st[ST_DONE] || (int)blockIdx.x >= nb) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += a.part[(size_t)r * a.pstride + b];
+    const double s = sum_strided(a.part + (size_t)r * a.pstride, nb, 1);
     const double beta = sqrt(s);
     const double bn = a.bnorm[r];
     const bool done = !(bn > 0.0) || beta <= a.tolv[r] * bn || !(beta > 0.0);
@@ -164,8 +176,7 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j) {
     const double* pin = a.part + (size_t)r * a.pstride;
     double* pout = a.part2 + (size_t)r * a.pstride;
     for (int vi = threadIdx.x; vi <= j; vi += GT) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        const double s = sum_strided(pin + vi, nb, (size_t)(a.m + 2));
         hs[vi] = s;
     }
     __syncthreads();
@@ -221,8 +232,7 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     if (st[ST_DONE] || (int)blockIdx.x >= nb) return;
     const double* pin = a.part2 + (size_t)r * a.pstride;
     for (int vi = threadIdx.x; vi <= j + 1; vi += GT) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += pin[(size_t)b * (a.m + 2) + vi];
+        const double s = sum_strided(pin + vi, nb, (size_t)(a.m + 2));
         hs[vi] = s;
     }
     __syncthreads();
