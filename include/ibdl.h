@@ -319,14 +319,16 @@ ibdl_status ibdl_server_wait(ibdl_server server, uint64_t ticket, ibdl_solve_inf
 ibdl_status ibdl_server_get_stats(ibdl_server server, ibdl_server_stats* out_host);
 
 /* Tile autotuner.  The row passes (spread + x-transform, x-inverse + interpolation)
- * are built for 1, 2 and 4 right-hand sides per workgroup; the first pass of a new
- * configuration (precision, dimension, n, grid or point output, right-hand-side
- * counts) runs every variant twice on the device, times the second run, and keeps
- * the fastest for the rest of the process.  Every variant gives bit-identical
- * results.  ibdl_set_autotune clears the choices and turns the tuner on (1) or off
- * (0: a fixed rule picks the variant).  ibdl_autotune_report writes the choices as
- * text lines into the HOST buffer (cap bytes, NUL-terminated) and returns the
- * length of the full report. */
+ * are built in four workgroup shapes: 1, 2 and 4 right-hand sides per workgroup
+ * with several lines each, and one line of one right-hand side; the first pass of
+ * a new configuration (precision, dimension, n, output kind, right-hand-side
+ * counts) runs every shape twice on the device, times the second run, and keeps
+ * the fastest for the rest of the process.  Every shape gives bit-identical
+ * results.  ibdl_set_autotune clears the choices and sets the mode: 1 tuner on,
+ * 0 off (a fixed rule picks the shape), 2..5 always row shape 0..3 (for tests);
+ * other values: IBDL_ERR_ARG.  ibdl_autotune_report writes the choices as text
+ * lines into the HOST buffer (cap bytes, NUL-terminated) and returns the length
+ * of the full report. */
 ibdl_status ibdl_set_autotune(int32_t enable);
 int32_t ibdl_autotune_report(char* buf, size_t cap);
 

@@ -226,7 +226,11 @@ void tune_store(const TuneKey& k, int variant, float ms) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[k] = {variant, ms};
 }
-bool tune_enabled() { return g_tune_on.load() != 0; }
+bool tune_enabled() { return g_tune_on.load() == 1; }
+int tune_forced() {
+    const int m = g_tune_on.load();
+    return m >= 2 ? m - 2 : -1;
+}
 
 bool& capturing() {
     thread_local bool c = false;
@@ -711,9 +715,10 @@ ibdl_status ibdl_batch_stage_times(ibdl_batch b, double* ms_host, const char** n
 
 // ------------------------------------------------------------------ tuning
 ibdl_status ibdl_set_autotune(int32_t enable) {
+    if (enable < 0 || enable > 5) return set_error(IBDL_ERR_ARG, "ibdl_set_autotune: mode must be 0..5");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.clear();
-    g_tune_on.store(enable ? 1 : 0);
+    g_tune_on.store(enable);
     return IBDL_OK;
 }
 
@@ -735,12 +740,17 @@ int32_t ibdl_autotune_report(char* buf, size_t cap) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         for (const auto& kv : g_tune) {
             const TuneKey& k = kv.first;
-            char line[200];
+            // row-block variants: right-hand sides per block, lines per right-hand side
+            static const char* const kVariant[] = {"rhs_per_block=1", "rhs_per_block=2", "rhs_per_block=4",
+                                                   "rhs_per_block=1 lines_per_block=1"};
+            static const char* const kOut[] = {"points", "grid", "grid+points"};
+            const int v = kv.second.first;
+            char line[240];
             std::snprintf(line, sizeof(line),
-                          "%s dim=%d n=%d stage=%s out=%s min_rhs_bucket=%d total_rhs_bucket=%d jobs=%s -> rhs_per_block=%d (%.4f ms)\n",
+                          "%s dim=%d n=%d stage=%s out=%s min_rhs_bucket=%d total_rhs_bucket=%d jobs=%s -> %s (%.4f ms)\n",
                           k.rbytes == 8 ? "fp64" : "fp32", k.dim, k.n, k.stage == 0 ? "row_fwd" : "row_inv",
-                          k.dense ? "grid" : "points", k.minr, k.totr, k.multi ? "many" : "one",
-                          1 << kv.second.first, kv.second.second);
+                          kOut[k.dense >= 0 && k.dense <= 2 ? k.dense : 0], k.minr, k.totr, k.multi ? "many" : "one",
+                          v >= 0 && v <= 3 ? kVariant[v] : "?", kv.second.second);
             out += line;
         }
     }

@@ -70,12 +70,23 @@ constexpr int staggered_pitch(int need, int m, int d) {
 
 // Row passes: a block transforms G lines of each of RB right-hand sides (GB lines
 // in all); the right-hand sides of a block share the spread and interpolation tables.
-template <typename R, int N, int RB = 1>
+// Variants V (chosen per configuration by the autotuner): RB = 1, 2, 4 with as
+// many lines as IBDL_ROW_ELEMS elements allow, and one line of one right-hand
+// side per block (most blocks, for launches with few right-hand sides).
+constexpr int kRowVars = 4;
+constexpr int kRowVarRB[kRowVars] = {1, 2, 4, 1};
+constexpr int kRowVarG[kRowVars] = {0, 0, 0, 1};
+// the one-line shape is built for FP32 only (in FP64 it spills registers)
+template <typename R>
+constexpr int row_vars() { return sizeof(R) == 4 ? kRowVars : 3; }
+template <typename R, int N, int V = 0>
 struct RowCfg {
+    static constexpr int RB = kRowVarRB[V];                                   // rhs per block
     static constexpr int L = N / 2;                                           // complex length
-    static constexpr int G = imax(1, imin(64, IBDL_ROW_ELEMS / L) / RB);      // lines per rhs
+    static constexpr int G = kRowVarG[V] > 0 ? kRowVarG[V]                    // lines per rhs
+                                             : imax(1, imin(64, IBDL_ROW_ELEMS / L) / RB);
     static constexpr int GB = G * RB;                                         // lines per block
-    static constexpr int T = imax(256, fft_threads<L, GB, RMax<R>::value>());
+    static constexpr int T = imax(kRowVarG[V] > 0 ? 64 : 256, fft_threads<L, GB, RMax<R>::value>());
     // LDS rows of the block's lines narrower than the 64 four-byte banks: pad the
     // transform's rows (lds_row) and stagger the row-inverse input lines (pitch XP)
     // so that one half-wave's accesses spread over distinct banks
@@ -87,8 +98,6 @@ struct RowCfg {
     static constexpr int XP =
         NARROW && GB > 1 ? staggered_pitch(L + 1, 128 / (int)sizeof(R), 128 / (int)sizeof(R) / GB) : L + 1;
 };
-// right-hand sides per row block the library is built for
-#define IBDL_ROW_RBS(X) X(1) X(2) X(4)
 template <typename R, int N>
 struct ColCfg {
     // at most 128 KiB of LDS for the block's lines
@@ -299,10 +308,10 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
 // Block lb covers lines [b G, b G + G) of the line list for the right-hand sides
 // rg RB .. rg RB + RB - 1 (b = lb % nblk, rg = lb / nblk); LDS line rr G + g holds
 // line g of the rr-th of them.
-template <typename R, int N, int RB>
+template <typename R, int N, int V>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int it) {
-    using CF = RowCfg<R, N, RB>;
-    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS;
+    using CF = RowCfg<R, N, V>;
+    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS;
     __shared__ cplx<R> s[CF::ROWS * GB];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G], rhs_s[RB];
@@ -396,10 +405,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         a.spec[(size_t)r * a.spec_stride + TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
     }
 }
-template <typename R, int N, int RB, bool MULTI>
-__global__ __launch_bounds__((RowCfg<R, N, RB>::T)) void k_row_fwd(RowFwdArgs<R> a0, Jobs<RowFwdArgs<R>> js,
+template <typename R, int N, int V, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N, V>::T)) void k_row_fwd(RowFwdArgs<R> a0, Jobs<RowFwdArgs<R>> js,
                                                                    int it) {
-    IBDL_JOB_ENTRY((row_fwd_body<R, N, RB>), RowFwdArgs<R>, a0, js, it)
+    IBDL_JOB_ENTRY((row_fwd_body<R, N, V>), RowFwdArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ col
@@ -453,6 +462,7 @@ struct SymStore {
     }
 };
 
+// A column block covers K y-rows (3-D z transform: K > 1) of its tile's C columns.
 template <typename R, int N, int K>
 struct ColK {
     static constexpr int C = ColCfg<R, N>::C;
@@ -579,10 +589,10 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<
 // ------------------------------------------------------------ row_inv
 // OUT 0: interpolation partial sums; OUT 1: grid output; OUT 2: both.  Blocks
 // map to lines and right-hand sides as in row_fwd.
-template <typename R, int N, int OUT, int RB>
+template <typename R, int N, int OUT, int V>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
-    using CF = RowCfg<R, N, RB>;
-    constexpr int L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS, XP = CF::XP;
+    using CF = RowCfg<R, N, V>;
+    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS, XP = CF::XP;
     // the block's spectrum rows X[0..L] (line-major with pitch XP, xs) are only read
     // by the first stage of the inverse transform, whose outputs (s) therefore share
     // the storage
@@ -772,10 +782,10 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
         }
     }
 }
-template <typename R, int N, int OUT, int RB, bool MULTI>
-__global__ __launch_bounds__((RowCfg<R, N, RB>::T)) void k_row_inv(RowInvArgs<R> a0, Jobs<RowInvArgs<R>> js,
+template <typename R, int N, int OUT, int V, bool MULTI>
+__global__ __launch_bounds__((RowCfg<R, N, V>::T)) void k_row_inv(RowInvArgs<R> a0, Jobs<RowInvArgs<R>> js,
                                                                    int it) {
-    IBDL_JOB_ENTRY((row_inv_body<R, N, OUT, RB>), RowInvArgs<R>, a0, js, it)
+    IBDL_JOB_ENTRY((row_inv_body<R, N, OUT, V>), RowInvArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ finish
@@ -875,10 +885,11 @@ __global__ __launch_bounds__(FIN_T) void k_finish(FinishArgs a0, Jobs<FinishArgs
     X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 template <typename R>
-inline int row_lines_per_block(int n, int rb) {
+inline int row_lines_per_block(int n, int v) {
     switch (n) {
 #define IBDL_C(NN) \
-    case NN: return rb == 4 ? RowCfg<R, NN, 4>::G : rb == 2 ? RowCfg<R, NN, 2>::G : RowCfg<R, NN, 1>::G;
+    case NN: return v == 3 ? RowCfg<R, NN, 3>::G : v == 2 ? RowCfg<R, NN, 2>::G : v == 1 ? RowCfg<R, NN, 1>::G \
+                                                                                      : RowCfg<R, NN, 0>::G;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
@@ -938,55 +949,61 @@ struct StageTable {
     }
 };
 
-template <typename R, int RB, bool MULTI>
-void launch_row_fwd_rb(int n, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
-                       Jobs<RowFwdArgs<R>> js, int it) {
+template <typename R, int V, bool MULTI>
+void launch_row_fwd_v(int n, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
+                      Jobs<RowFwdArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                          \
-    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN, RB, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, RB>::T), 0, \
+#define IBDL_C(NN)                                                                                        \
+    case NN: hipExtLaunchKernelGGL((k_row_fwd<R, NN, V, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, V>::T), 0, \
                                    st, e.a, e.b, 0, a, js, it); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
 template <typename R, bool MULTI>
-void launch_row_fwd_t(int n, int rb, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
+void launch_row_fwd_t(int n, int v, int blocks, hipStream_t st, StageEv e, const RowFwdArgs<R>& a,
                       Jobs<RowFwdArgs<R>> js, int it) {
-    if (rb == 4) launch_row_fwd_rb<R, 4, MULTI>(n, blocks, st, e, a, js, it);
-    else if (rb == 2) launch_row_fwd_rb<R, 2, MULTI>(n, blocks, st, e, a, js, it);
-    else launch_row_fwd_rb<R, 1, MULTI>(n, blocks, st, e, a, js, it);
+    if constexpr (row_vars<R>() > 3) {
+        if (v == 3) return launch_row_fwd_v<R, 3, MULTI>(n, blocks, st, e, a, js, it);
+    }
+    if (v == 2) launch_row_fwd_v<R, 2, MULTI>(n, blocks, st, e, a, js, it);
+    else if (v == 1) launch_row_fwd_v<R, 1, MULTI>(n, blocks, st, e, a, js, it);
+    else launch_row_fwd_v<R, 0, MULTI>(n, blocks, st, e, a, js, it);
 }
 template <typename R, int MODE, bool ZPASS, bool MULTI>
 void launch_col_t(int n, int blocks, hipStream_t st, StageEv e, const ColArgs<R>& a, Jobs<ColArgs<R>> js,
                   int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                    \
-    case NN: {                                                                                        \
-        constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                            \
-        hipExtLaunchKernelGGL((k_col<R, NN, MODE, K, MULTI>), dim3(blocks), dim3(ColK<R, NN, K>::T), 0, st, \
-                              e.a, e.b, 0, a, js, it);                                                \
+#define IBDL_C(NN)                                                                                        \
+    case NN: {                                                                                            \
+        constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                                \
+        hipExtLaunchKernelGGL((k_col<R, NN, MODE, K, MULTI>), dim3(blocks), dim3(ColK<R, NN, K>::T), 0,       \
+                              st, e.a, e.b, 0, a, js, it);                                                \
     } break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
-template <typename R, int OUT, int RB, bool MULTI>
-void launch_row_inv_rb(int n, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
-                       Jobs<RowInvArgs<R>> js, int it) {
+template <typename R, int OUT, int V, bool MULTI>
+void launch_row_inv_v(int n, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
+                      Jobs<RowInvArgs<R>> js, int it) {
     switch (n) {
-#define IBDL_C(NN)                                                                                           \
-    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT, RB, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, RB>::T), \
+#define IBDL_C(NN)                                                                                         \
+    case NN: hipExtLaunchKernelGGL((k_row_inv<R, NN, OUT, V, MULTI>), dim3(blocks), dim3(RowCfg<R, NN, V>::T), \
                                    0, st, e.a, e.b, 0, a, js, it); break;
         IBDL_SIZES(IBDL_C)
 #undef IBDL_C
     }
 }
 template <typename R, int OUT, bool MULTI>
-void launch_row_inv_t(int n, int rb, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
+void launch_row_inv_t(int n, int v, int blocks, hipStream_t st, StageEv e, const RowInvArgs<R>& a,
                       Jobs<RowInvArgs<R>> js, int it) {
-    if (rb == 4) launch_row_inv_rb<R, OUT, 4, MULTI>(n, blocks, st, e, a, js, it);
-    else if (rb == 2) launch_row_inv_rb<R, OUT, 2, MULTI>(n, blocks, st, e, a, js, it);
-    else launch_row_inv_rb<R, OUT, 1, MULTI>(n, blocks, st, e, a, js, it);
+    if constexpr (row_vars<R>() > 3) {
+        if (v == 3) return launch_row_inv_v<R, OUT, 3, MULTI>(n, blocks, st, e, a, js, it);
+    }
+    if (v == 2) launch_row_inv_v<R, OUT, 2, MULTI>(n, blocks, st, e, a, js, it);
+    else if (v == 1) launch_row_inv_v<R, OUT, 1, MULTI>(n, blocks, st, e, a, js, it);
+    else launch_row_inv_v<R, OUT, 0, MULTI>(n, blocks, st, e, a, js, it);
 }
 
 template <typename R>
@@ -1008,8 +1025,6 @@ struct PlanPrec<float> {
 
 // One pass of L^-1 for one or more jobs of the same dimension, grid size and
 // precision: per stage a table of per-job arguments.
-// right-hand sides per row block of the variants built: index 0, 1, 2 -> 1, 2, 4
-constexpr int kRowRB[3] = {1, 2, 4};
 
 template <typename R>
 struct PreparedT : PreparedPass {
@@ -1017,9 +1032,9 @@ struct PreparedT : PreparedPass {
     int out_mode = 0;  // 0: point output, 1: grid output, 2: both
     int min_nrhs = 1, total_rhs = 1, njobs = 1;
     ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
-    StageTable<RowFwdArgs<R>> rf[3];  // one table per row-block variant
+    StageTable<RowFwdArgs<R>> rf[kRowVars];  // one table per row-block variant
     StageTable<ColArgs<R>> col[3];
-    StageTable<RowInvArgs<R>> ri[3];
+    StageTable<RowInvArgs<R>> ri[kRowVars];
     StageTable<FinishArgs> fi;
 
     void upload(Arena& ar, hipStream_t st) override {
@@ -1035,22 +1050,22 @@ struct PreparedT : PreparedPass {
     void fwd(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = rf[v];
         go(t, [&](bool m) {
-            if (m) launch_row_fwd_t<R, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
-            else launch_row_fwd_t<R, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+            if (m) launch_row_fwd_t<R, true>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+            else launch_row_fwd_t<R, false>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
         });
     }
     void inv(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = ri[v];
         go(t, [&](bool m) {
             if (out_mode == 2) {
-                if (m) launch_row_inv_t<R, 2, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
-                else launch_row_inv_t<R, 2, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                if (m) launch_row_inv_t<R, 2, true>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 2, false>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             } else if (out_mode == 1) {
-                if (m) launch_row_inv_t<R, 1, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
-                else launch_row_inv_t<R, 1, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                if (m) launch_row_inv_t<R, 1, true>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 1, false>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             } else {
-                if (m) launch_row_inv_t<R, 0, true>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
-                else launch_row_inv_t<R, 0, false>(n, kRowRB[v], t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                if (m) launch_row_inv_t<R, 0, true>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
+                else launch_row_inv_t<R, 0, false>(n, v, t.blocks(), st, e, t.args[0], t.jobs(itp_), it);
             }
         });
     }
@@ -1060,6 +1075,8 @@ struct PreparedT : PreparedPass {
     // on its second run, and the fastest is kept.
     template <class F>
     int pick(int stage, int it, hipStream_t st, F&& launch) {
+        const int f = tune_forced();
+        if (f >= 0) return f < row_vars<R>() ? f : 0;
         int v = tune_lookup(key(stage));
         if (v >= 0) return v;
         if (!tune_enabled() || capturing()) return heuristic();
@@ -1068,7 +1085,7 @@ struct PreparedT : PreparedPass {
         hipEvent_t e0, e1;
         IBDL_HIP_TRY(hipEventCreate(&e0));
         IBDL_HIP_TRY(hipEventCreate(&e1));
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < row_vars<R>(); ++c) {
             launch(c, StageEv{});
             launch(c, StageEv{e0, e1});
             IBDL_HIP_TRY(hipEventSynchronize(e1));
@@ -1207,10 +1224,10 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ra.P = p->P;
         ra.tw = PP::tw(p);
         ra.nrhs = nrhs;
-        for (int v = 0; v < 3; ++v) {
-            const int G = row_lines_per_block<R>(n, kRowRB[v]);
+        for (int v = 0; v < kRowVars; ++v) {
+            const int G = row_lines_per_block<R>(n, v);
             ra.nblk = (ra.nproc + G - 1) / G;
-            P->rf[v].add(ra, ra.nblk * ((nrhs + kRowRB[v] - 1) / kRowRB[v]));
+            P->rf[v].add(ra, ra.nblk * ((nrhs + kRowVarRB[v] - 1) / kRowVarRB[v]));
         }
 
         // ---- columns
@@ -1285,10 +1302,10 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ia.M = p->M;
         ia.dim = p->dim;
         ia.nrhs = nrhs;
-        for (int v = 0; v < 3; ++v) {
-            const int G = row_lines_per_block<R>(n, kRowRB[v]);
+        for (int v = 0; v < kRowVars; ++v) {
+            const int G = row_lines_per_block<R>(n, v);
             ia.nblk = (ia.nproc + G - 1) / G;
-            P->ri[v].add(ia, ia.nblk * ((nrhs + kRowRB[v] - 1) / kRowRB[v]));
+            P->ri[v].add(ia, ia.nblk * ((nrhs + kRowVarRB[v] - 1) / kRowVarRB[v]));
         }
 
         // ---- finish

@@ -326,6 +326,7 @@ inline int tune_bucket(int v) {  // 1, 2-3, 4-7, ... -> 0, 1, 2, ...
 int tune_lookup(const TuneKey& k);                      // variant or -1
 void tune_store(const TuneKey& k, int variant, float ms);
 bool tune_enabled();
+int tune_forced();                                       // row variant forced for tests, or -1
 // set while this thread records a graph: untuned stages take the heuristic
 // variant instead of timing the others
 bool& capturing();

@@ -368,9 +368,10 @@ __device__ __forceinline__ int dip_offsets(int j, int dim, int* r) {
 
 __global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
                        int M, int dim, int n, int dipole, int npp, uint64_t* out) {
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (size_t)M * npp) return;
-    const int s = (int)(id / npp), j = (int)(id % npp);
+    // M * npp < 2^31 (checked by the caller): 32-bit index arithmetic
+    const int id = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (id >= M * npp) return;
+    const int s = id / npp, j = id - s * npp;
     int r[3] = {0, 0, 0};
     if (dipole) {
         dip_offsets(j, dim, r);

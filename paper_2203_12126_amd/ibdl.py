@@ -166,9 +166,11 @@ def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=N
     return d
 
 
-def set_autotune(enable: bool = True):
-    """Clear the tile autotuner's choices and turn it on or off."""
-    _check(lib().ibdl_set_autotune(1 if enable else 0), "ibdl_set_autotune")
+def set_autotune(enable: bool = True, force=None):
+    """Clear the tile autotuner's choices and turn it on or off; force=v (0..3)
+    uses row-block shape v everywhere (for tests)."""
+    mode = 2 + int(force) if force is not None else (1 if enable else 0)
+    _check(lib().ibdl_set_autotune(mode), "ibdl_set_autotune")
 
 
 def set_graphs(enable: bool = True):

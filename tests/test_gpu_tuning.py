@@ -1,6 +1,7 @@
-"""The row-pass variants the tile autotuner chooses between (1, 2 or 4
-right-hand sides per workgroup) give bit-identical results, and the tuner
-records its choices."""
+"""The row-pass shapes the tile autotuner chooses between (1, 2 or 4
+right-hand sides per workgroup with several lines each, or one line of one
+right-hand side) give bit-identical results, and the tuner records its
+choices."""
 import numpy as np
 import pytest
 
@@ -67,3 +68,33 @@ def test_timing_on_a_pass_that_tunes():
     assert torch.equal(out, pl.apply(q))
     pl.set_timing(False)
     pl.close()
+
+
+@pytest.mark.parametrize("prec", [ibdl.MIXED, ibdl.FP64])
+def test_every_row_shape_bit_identical(prec):
+    """Each of the four row-block shapes, forced in turn, gives the same apply,
+    grid solution and solve, bit for bit."""
+    p = W.config_star1024(m=1500, n=192, alpha=2.0, seed=12)
+    rng = np.random.default_rng(8)
+    q = torch.as_tensor(rng.standard_normal((3, p.geom.m)), device="cuda")
+    g = torch.as_tensor(np.stack([p.g_tilde.ravel()] * 3), device="cuda")
+    outs = []
+    try:
+        for v in range(4):
+            ibdl.set_autotune(force=v)
+            pl = ibdl.Plan.from_problem(p, prec=prec)
+            a = pl.apply(q)
+            u = pl.eval_grid(q, g=g)
+            s, _ = pl.solve(q, g, tol=1e-9)
+            outs.append((a, u, s))
+            pl.close()
+    finally:
+        ibdl.set_autotune(True)
+    for v in range(1, 4):
+        for x, y in zip(outs[0], outs[v]):
+            assert torch.equal(x, y), f"shape {v}"
+
+
+def test_autotune_mode_errors():
+    assert ibdl.lib().ibdl_set_autotune(9) == ibdl.ERR_ARG
+    ibdl.set_autotune(True)
