@@ -7,7 +7,10 @@
 // arrive while others are on the device overlaps with theirs (continuous
 // batching).  Each request keeps its own plan and Krylov state on the device; a
 // right-hand side's arithmetic does not depend on its cohort, so a result is the
-// same alone and in the mix.
+// same alone and in the mix.  Plans are built by a few builder threads, each on
+// its own stream, so that the worker keeps advancing running cohorts while new
+// geometries are binned and sorted; a cohort starts once all its plans are built,
+// its stream ordered after each build by an event.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +19,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -47,13 +51,16 @@ struct Request {
     std::vector<ibdl_solve_info> info;
     ibdl_plan plan = nullptr;
     int cohort_size = 0;
+    // plan construction by a builder thread: 0 queued, 1 built, 2 failed
+    std::atomic<int> build_state{0};
+    hipEvent_t plan_ready = nullptr;  // recorded on the builder's stream after the build
 };
 
 struct Cohort {
     std::vector<std::shared_ptr<Request>> reqs;
     KrylovSet ks;
     Arena arena;
-    std::unique_ptr<SolveTask> task;
+    std::unique_ptr<SolveTask> task;  // set once every plan is built
     int slot = -1;
 };
 
@@ -79,6 +86,13 @@ struct ibdl_server_s {
     int64_t submitted = 0, completed = 0, cohorts = 0;
     bool stop = false;
     std::thread worker;
+    // plan builders
+    std::vector<std::thread> builders;
+    std::vector<hipStream_t> build_streams;
+    std::deque<std::shared_ptr<ibdl::Request>> build_q;
+    std::mutex bmu;
+    std::condition_variable bcv;
+    bool bstop = false;
 };
 
 namespace ibdl {
@@ -117,6 +131,8 @@ static void release_cohort(ibdl_server s, Cohort& c) {
     for (auto& r : c.reqs) {
         if (r->plan) release_plan(r->plan, st);
         r->plan = nullptr;
+        if (r->plan_ready) (void)hipEventDestroy(r->plan_ready);
+        r->plan_ready = nullptr;
     }
 }
 
@@ -159,53 +175,95 @@ static void fail_cohort(ibdl_server s, Cohort& c, int status, const std::string&
     for (auto& r : c.reqs) complete(s, r, true);
 }
 
-static std::unique_ptr<Cohort> start_cohort(ibdl_server s, std::vector<std::shared_ptr<Request>>& adm, int slot) {
-    auto c = std::make_unique<Cohort>();
-    c->slot = slot;
-    c->ks.arena = &c->arena;
-    const hipStream_t st = s->streams[slot];
-    int r0 = 0;
-    for (auto& r : adm) {
-        r->cohort_size = (int)adm.size();
+// builder thread: plans of queued requests, on the builder's own stream
+static void builder_loop(ibdl_server s, int b) {
+    (void)hipSetDevice(s->device);
+    const hipStream_t bst = s->build_streams[b];
+    for (;;) {
+        std::shared_ptr<Request> r;
+        {
+            std::unique_lock<std::mutex> lk(s->bmu);
+            s->bcv.wait(lk, [&] { return s->bstop || !s->build_q.empty(); });
+            if (s->build_q.empty()) return;
+            r = s->build_q.front();
+            s->build_q.pop_front();
+        }
         ibdl_plan p = nullptr;
         ibdl_status status = IBDL_OK;
-        if (hipStreamWaitEvent(st, r->inputs_ready, 0) != hipSuccess) {
+        std::string msg;
+        if (hipStreamWaitEvent(bst, r->inputs_ready, 0) != hipSuccess) {
             (void)hipGetLastError();
             status = IBDL_ERR_HIP;
         } else {
-            status = ibdl_plan_create(&r->desc, st, &p);
+            status = ibdl_plan_create(&r->desc, bst, &p);
         }
+        if (status != IBDL_OK) msg = ibdl_last_error();
         if (status == IBDL_OK) {
             try {
-                AllocStream as(st);
+                AllocStream as(bst);
                 ensure_workspace(p, r->nrhs);
+                IBDL_HIP_TRY(hipEventCreateWithFlags(&r->plan_ready, hipEventDisableTiming));
+                IBDL_HIP_TRY(hipEventRecord(r->plan_ready, bst));
             } catch (const Error& e) {
-                release_plan(p, st);
+                release_plan(p, bst);
                 p = nullptr;
                 status = (ibdl_status)e.status;
+                msg = e.msg;
             }
         }
         if (status != IBDL_OK) {
             r->status = status;
-            r->msg = ibdl_last_error();
-            if (r->msg.empty()) r->msg = "plan construction failed";
-            r->info.assign(r->nrhs, ibdl_solve_info{0, -1.0, -1.0, (int32_t)status, 0});
-            complete(s, r, true);
-            continue;
+            r->msg = msg.empty() ? "plan construction failed" : msg;
         }
         r->plan = p;
-        c->ks.inst.push_back(Inst{p, r->nrhs, r0});
+        r->build_state.store(status == IBDL_OK ? 1 : 2, std::memory_order_release);
+    }
+}
+
+// a cohort of admitted requests: their plans go to the builders
+static std::unique_ptr<Cohort> queue_cohort(ibdl_server s, std::vector<std::shared_ptr<Request>>& adm, int slot) {
+    auto c = std::make_unique<Cohort>();
+    c->slot = slot;
+    c->ks.arena = &c->arena;
+    for (auto& r : adm) r->cohort_size = (int)adm.size();
+    c->reqs = adm;
+    {
+        std::lock_guard<std::mutex> lk(s->bmu);
+        for (auto& r : adm) s->build_q.push_back(r);
+    }
+    s->bcv.notify_all();
+    return c;
+}
+
+// once every plan of the cohort is built: requests whose build failed complete
+// with its error; the others are ordered after their builds and their inputs on
+// the cohort's stream and start as one solve task.  false: still building.
+static bool start_cohort(ibdl_server s, Cohort& c) {
+    for (auto& r : c.reqs)
+        if (r->build_state.load(std::memory_order_acquire) == 0) return false;
+    const hipStream_t st = s->streams[c.slot];
+    std::vector<std::shared_ptr<Request>> ok;
+    for (auto& r : c.reqs) {
+        if (r->build_state.load(std::memory_order_acquire) == 2) {
+            r->info.assign(r->nrhs, ibdl_solve_info{0, -1.0, -1.0, (int32_t)r->status, 0});
+            complete(s, r, true);
+        } else {
+            ok.push_back(r);
+        }
+    }
+    c.reqs = ok;
+    if (c.reqs.empty()) return true;
+    int r0 = 0;
+    for (auto& r : c.reqs) {
+        IBDL_HIP_TRY(hipStreamWaitEvent(st, r->plan_ready, 0));
+        IBDL_HIP_TRY(hipStreamWaitEvent(st, r->inputs_ready, 0));
+        r->plan->last_stream = st;  // the plan's work continues on the cohort's stream
+        c.ks.inst.push_back(Inst{r->plan, r->nrhs, r0});
         r0 += r->nrhs;
-        c->reqs.push_back(r);
     }
-    c->ks.R = r0;
-    if (c->reqs.empty()) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stream_busy[slot] = 0;
-        return nullptr;
-    }
+    c.ks.R = r0;
     SolveIO io;
-    for (auto& r : c->reqs) {
+    for (auto& r : c.reqs) {
         io.data.push_back(r->data);
         io.g.push_back(r->g);
         io.x0.push_back(nullptr);
@@ -213,9 +271,9 @@ static std::unique_ptr<Cohort> start_cohort(ibdl_server s, std::vector<std::shar
         io.u.push_back(r->u);
         io.vb.push_back(r->desc.bc == IBDL_NEUMANN ? r->data : nullptr);
     }
-    c->task = std::make_unique<SolveTask>(c->ks, std::move(io), c->reqs[0]->o, st);
-    c->task->advance();
-    return c;
+    c.task = std::make_unique<SolveTask>(c.ks, std::move(io), c.reqs[0]->o, st);
+    c.task->advance();
+    return true;
 }
 
 static void server_loop(ibdl_server s) {
@@ -254,28 +312,27 @@ static void server_loop(ibdl_server s) {
                 continue;
             }
         }
-        if (!adm.empty()) {
-            try {
-                auto c = start_cohort(s, adm, slot);
-                if (c) cohorts.push_back(std::move(c));
-            } catch (const Error& e) {
-                Cohort tmp;
-                tmp.slot = slot;
-                for (auto& r : adm)
-                    if (!r->done) tmp.reqs.push_back(r);
-                fail_cohort(s, tmp, e.status, e.msg);
-            }
-        }
+        if (!adm.empty()) cohorts.push_back(queue_cohort(s, adm, slot));
         bool progressed = !adm.empty();
         for (size_t i = 0; i < cohorts.size();) {
             Cohort& c = *cohorts[i];
             bool finished = false;
             try {
-                while (!c.task->done() && c.task->ready()) {
+                if (!c.task) {
+                    if (start_cohort(s, c)) {
+                        progressed = true;
+                        if (!c.task) {  // every build failed
+                            std::lock_guard<std::mutex> lk(s->mu);
+                            s->stream_busy[c.slot] = 0;
+                            finished = true;
+                        }
+                    }
+                }
+                while (c.task && !c.task->done() && c.task->ready()) {
                     c.task->advance();
                     progressed = true;
                 }
-                if (c.task->done()) {
+                if (c.task && c.task->done()) {
                     finish_cohort(s, c);
                     finished = true;
                 }
@@ -335,10 +392,30 @@ ibdl_status ibdl_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32
         s->streams.push_back(st);
         s->stream_busy.push_back(0);
     }
+    constexpr int kBuilders = 3;
+    for (int i = 0; i < kBuilders; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+            for (hipStream_t t : s->build_streams) (void)hipStreamDestroy(t);
+            delete s;
+            return sfail(IBDL_ERR_HIP, "stream creation failed");
+        }
+        s->build_streams.push_back(st);
+    }
     try {
+        for (int i = 0; i < kBuilders; ++i) s->builders.emplace_back(builder_loop, s, i);
         s->worker = std::thread(server_loop, s);
     } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->bmu);
+            s->bstop = true;
+        }
+        s->bcv.notify_all();
+        for (auto& t : s->builders)
+            if (t.joinable()) t.join();
         for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+        for (hipStream_t t : s->build_streams) (void)hipStreamDestroy(t);
         delete s;
         return sfail(IBDL_ERR_HIP, "worker thread could not start");
     }
@@ -353,7 +430,16 @@ ibdl_status ibdl_server_destroy(ibdl_server s) {
         s->stop = true;
     }
     s->cv_submit.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    if (s->worker.joinable()) s->worker.join();  // every cohort, built or not, has finished
+    {
+        std::lock_guard<std::mutex> lk(s->bmu);
+        s->bstop = true;
+    }
+    s->bcv.notify_all();
+    for (auto& t : s->builders)
+        if (t.joinable()) t.join();
+    for (hipStream_t t : s->build_streams) (void)hipStreamSynchronize(t);
+    for (hipStream_t t : s->build_streams) (void)hipStreamDestroy(t);
     for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
     delete s;
     return IBDL_OK;

@@ -47,7 +47,9 @@ def test_server_results_equal_alone():
     # a first wave, then more requests while the first is on the device
     for i in range(8):
         tickets.append(srv.submit_problem(probs[i], prec=precs[i]))
-    time.sleep(0.002)
+    t0 = time.perf_counter()
+    while srv.stats()["cohorts"] < 1 and time.perf_counter() - t0 < 10.0:
+        time.sleep(0.0005)  # the first wave is admitted (its plans are building or solving)
     for i in range(8, len(probs)):
         tickets.append(srv.submit_problem(probs[i], prec=precs[i]))
     res = [srv.wait(t) for t in tickets]
