@@ -170,53 +170,58 @@ __global__ void k_composite(const uint32_t* __restrict__ key, int M, size_t n2, 
 }
 
 // bitonic sort ------------------------------------------------------------
-constexpr int BIT_BLOCK = 2048;  // elements held in LDS by one 1024-thread block
+constexpr int BIT_T = 1024;              // threads of the LDS kernels
+constexpr int BIT_BLOCK = 8192;          // elements held in LDS by one block (64 KiB)
+constexpr int BIT_PER = BIT_BLOCK / 2 / BIT_T;  // compare-exchanges per thread and step
 
 __device__ __forceinline__ void bit_cmpx(uint64_t* a, size_t lo, size_t hi, bool asc) {
     const uint64_t x = a[lo], y = a[hi];
     if ((x > y) == asc) { a[lo] = y; a[hi] = x; }
 }
 
+// the block's elements into LDS and back, BIT_BLOCK / BIT_T per thread
+__device__ __forceinline__ void bit_load(uint64_t* s, const uint64_t* a, size_t base) {
+#pragma unroll
+    for (int u = 0; u < BIT_BLOCK / BIT_T; ++u) s[threadIdx.x + u * BIT_T] = a[base + threadIdx.x + u * BIT_T];
+}
+__device__ __forceinline__ void bit_store(const uint64_t* s, uint64_t* a, size_t base) {
+#pragma unroll
+    for (int u = 0; u < BIT_BLOCK / BIT_T; ++u) a[base + threadIdx.x + u * BIT_T] = s[threadIdx.x + u * BIT_T];
+}
+// one step (k, j) on the block's elements: pair t = lo | hi with lo's bit j clear
+__device__ __forceinline__ void bit_step(uint64_t* s, size_t base, size_t k, int j, bool fixed_dir, bool asc_all) {
+#pragma unroll
+    for (int u = 0; u < BIT_PER; ++u) {
+        const int t = threadIdx.x + u * BIT_T;
+        const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int hi = lo | j;
+        const bool asc = fixed_dir ? asc_all : (((base + lo) & k) == 0);
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x > y) == asc) { s[lo] = y; s[hi] = x; }
+    }
+    __syncthreads();
+}
+
 // all stages with k <= BIT_BLOCK inside each block
-__global__ __launch_bounds__(1024) void k_bitonic_local_sort(uint64_t* a) {
+__global__ __launch_bounds__(BIT_T) void k_bitonic_local_sort(uint64_t* a) {
     __shared__ uint64_t s[BIT_BLOCK];
     const size_t base = (size_t)blockIdx.x * BIT_BLOCK;
-    s[threadIdx.x] = a[base + threadIdx.x];
-    s[threadIdx.x + 1024] = a[base + threadIdx.x + 1024];
+    bit_load(s, a, base);
     __syncthreads();
-    for (int k = 2; k <= BIT_BLOCK; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int t = threadIdx.x;
-            const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-            const int hi = lo | j;
-            const bool asc = (((base + lo) & (size_t)k) == 0);
-            const uint64_t x = s[lo], y = s[hi];
-            if ((x > y) == asc) { s[lo] = y; s[hi] = x; }
-            __syncthreads();
-        }
-    }
-    a[base + threadIdx.x] = s[threadIdx.x];
-    a[base + threadIdx.x + 1024] = s[threadIdx.x + 1024];
+    for (int k = 2; k <= BIT_BLOCK; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) bit_step(s, base, (size_t)k, j, false, true);
+    bit_store(s, a, base);
 }
 
 // stages j < BIT_BLOCK of a merge with k > BIT_BLOCK
-__global__ __launch_bounds__(1024) void k_bitonic_local_merge(uint64_t* a, size_t k) {
+__global__ __launch_bounds__(BIT_T) void k_bitonic_local_merge(uint64_t* a, size_t k) {
     __shared__ uint64_t s[BIT_BLOCK];
     const size_t base = (size_t)blockIdx.x * BIT_BLOCK;
-    s[threadIdx.x] = a[base + threadIdx.x];
-    s[threadIdx.x + 1024] = a[base + threadIdx.x + 1024];
+    bit_load(s, a, base);
     __syncthreads();
     const bool asc = ((base & k) == 0);
-    for (int j = BIT_BLOCK >> 1; j > 0; j >>= 1) {
-        const int t = threadIdx.x;
-        const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-        const int hi = lo | j;
-        const uint64_t x = s[lo], y = s[hi];
-        if ((x > y) == asc) { s[lo] = y; s[hi] = x; }
-        __syncthreads();
-    }
-    a[base + threadIdx.x] = s[threadIdx.x];
-    a[base + threadIdx.x + 1024] = s[threadIdx.x + 1024];
+    for (int j = BIT_BLOCK >> 1; j > 0; j >>= 1) bit_step(s, base, k, j, true, asc);
+    bit_store(s, a, base);
 }
 
 __global__ void k_bitonic_global(uint64_t* a, size_t npairs, size_t k, size_t j) {
@@ -236,12 +241,12 @@ static size_t pow2_at_least(size_t n, size_t minv) {
 // sorts a[0..n2) ascending; n2 a power of two >= BIT_BLOCK
 static void bitonic_sort(uint64_t* a, size_t n2, hipStream_t st) {
     const int nb = (int)(n2 / BIT_BLOCK);
-    hipLaunchKernelGGL(k_bitonic_local_sort, dim3(nb), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_bitonic_local_sort, dim3(nb), dim3(BIT_T), 0, st, a);
     for (size_t k = 2 * BIT_BLOCK; k <= n2; k <<= 1) {
         for (size_t j = k >> 1; j >= (size_t)BIT_BLOCK; j >>= 1)
             hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(n2 / 2, 256)), dim3(256), 0, st, a,
                                n2 / 2, k, j);
-        hipLaunchKernelGGL(k_bitonic_local_merge, dim3(nb), dim3(1024), 0, st, a, k);
+        hipLaunchKernelGGL(k_bitonic_local_merge, dim3(nb), dim3(BIT_T), 0, st, a, k);
     }
     IBDL_HIP_TRY(hipGetLastError());
 }
