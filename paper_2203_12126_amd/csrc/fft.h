@@ -194,6 +194,8 @@ struct TwConst {
     static constexpr TwTab<RAD> tab = make_twtab<RAD>();
 };
 
+__device__ __forceinline__ int imin_c(int a, int b) { return a < b ? a : b; }
+
 // Stage twiddles W^idx (W = exp(-2 pi i / NT)) from two small LDS tables:
 // lo[i] = W^i for i < 64 and hi[j] = W^(64 j), W^idx = lo[idx % 64] hi[idx / 64].
 template <typename R>
@@ -212,11 +214,12 @@ struct Tw2Size {
 template <typename R, int NT, int T>
 __device__ __forceinline__ Tw2<R> load_tw2(cplx<R>* lds, const cplx<R>* __restrict__ tw) {
     using S = Tw2Size<NT>;
+    // every element loaded (clamped index), so the array stays in registers
     cplx<R> v[(S::ALL + T - 1) / T];
 #pragma unroll
     for (int u = 0; u < (S::ALL + T - 1) / T; ++u) {
-        const int i = threadIdx.x + u * T;
-        if (i < S::ALL) v[u] = tw[i < S::LO ? i : 64 * (i - S::LO)];
+        const int i = imin_c(threadIdx.x + u * T, S::ALL - 1);
+        v[u] = tw[i < S::LO ? i : 64 * (i - S::LO)];
     }
 #pragma unroll
     for (int u = 0; u < (S::ALL + T - 1) / T; ++u) {
@@ -235,12 +238,9 @@ struct TwFull {
 template <typename R, int NT, int T>
 __device__ __forceinline__ TwFull<R> load_twfull(cplx<R>* lds, const cplx<R>* __restrict__ tw) {
     constexpr int P = (NT + T - 1) / T;
-    cplx<R> v[P];
+    cplx<R> v[P];  // every element loaded (clamped index), so the array stays in registers
 #pragma unroll
-    for (int u = 0; u < P; ++u) {
-        const int i = threadIdx.x + u * T;
-        if (i < NT) v[u] = tw[i];
-    }
+    for (int u = 0; u < P; ++u) v[u] = tw[imin_c(threadIdx.x + u * T, NT - 1)];
 #pragma unroll
     for (int u = 0; u < P; ++u) {
         const int i = threadIdx.x + u * T;

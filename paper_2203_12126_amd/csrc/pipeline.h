@@ -32,6 +32,11 @@
 namespace ibdl {
 
 constexpr int imin(int a, int b) { return a < b ? a : b; }
+constexpr int pow2_floor(int a) {
+    int p = 1;
+    while (2 * p <= a) p *= 2;
+    return p;
+}
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 constexpr int rup64(int x) { return (x + 63) / 64 * 64; }
 
@@ -47,6 +52,9 @@ constexpr int rup64(int x) { return (x + 63) / 64 * 64; }
 #endif
 #ifndef IBDL_COLB_F64
 #define IBDL_COLB_F64 64
+#endif
+#ifndef IBDL_COL_LDS
+#define IBDL_COL_LDS 65536
 #endif
 #ifndef IBDL_ROW_ELEMS
 #define IBDL_ROW_ELEMS 2048
@@ -100,9 +108,9 @@ struct RowCfg {
 };
 template <typename R, int N>
 struct ColCfg {
-    // at most 128 KiB of LDS for the block's lines
-    static constexpr int C = imax(1, imin(ColBytes<R>::value / (2 * (int)sizeof(R)),
-                                          131072 / (N * 2 * (int)sizeof(R))));
+    // at most IBDL_COL_LDS bytes of LDS for the block's lines, a power of two columns
+    static constexpr int C = pow2_floor(imax(1, imin(ColBytes<R>::value / (2 * (int)sizeof(R)),
+                                                     IBDL_COL_LDS / (N * 2 * (int)sizeof(R)))));
     static constexpr int T = fft_threads<N, C, RMax<R>::value>();
 };
 
