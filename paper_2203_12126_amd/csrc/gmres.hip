@@ -383,7 +383,35 @@ __global__ __launch_bounds__(GT) void k_pool_op(KArgs a, int op, double* dst, co
     else dst[i] += src[i];
 }
 
+// copies of several device vectors in one launch (block row y: job y)
+struct CopyJob {
+    double* dst;
+    const double* src;
+    int64_t n;
+};
+__global__ __launch_bounds__(256) void k_copy_multi(const CopyJob* __restrict__ jobs) {
+    const CopyJob jb = jobs[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < jb.n; i += (int64_t)gridDim.x * 256)
+        jb.dst[i] = jb.src[i];
+}
+
 // ------------------------------------------------------------------ host
+// the copies as one launch (its table through the set's arena), or one by one
+// when there are only a few
+static void copy_multi(KrylovSet& ks, const std::vector<CopyJob>& jobs, hipStream_t st) {
+    if (jobs.size() <= 2) {
+        for (const CopyJob& j : jobs)
+            IBDL_HIP_TRY(hipMemcpyAsync(j.dst, j.src, (size_t)j.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        return;
+    }
+    int64_t maxn = 1;
+    for (const CopyJob& j : jobs) maxn = std::max(maxn, j.n);
+    const auto* d = reinterpret_cast<const CopyJob*>(arena_put(*ks.arena, jobs.data(), jobs.size() * sizeof(CopyJob), st));
+    const int bx = (int)std::min<int64_t>(64, (maxn + 255) / 256);
+    hipLaunchKernelGGL(k_copy_multi, dim3(bx, (unsigned)jobs.size()), dim3(256), 0, st, d);
+    IBDL_HIP_TRY(hipGetLastError());
+}
+
 void free_krylov(KWork& k) {
     // no replay is in flight here: a solve task waits for its replays before it ends
     if (k.gexec) (void)hipGraphExecDestroy(k.gexec);
@@ -920,13 +948,14 @@ void SolveTask::output() {
     KWork& k = ks_.w;
     const size_t NI = ks_.inst.size();
     std::vector<size_t> grid;
+    std::vector<CopyJob> copies;
     for (size_t i = 0; i < NI; ++i) {
         const Inst& in = ks_.inst[i];
-        IBDL_HIP_TRY(hipMemcpyAsync(io_.sol[i], k.x + k.hxoff[in.r0], (size_t)in.nrhs * in.p->M * sizeof(double),
-                                    hipMemcpyDeviceToDevice, st_));
+        copies.push_back(CopyJob{io_.sol[i], k.x + k.hxoff[in.r0], (int64_t)in.nrhs * in.p->M});
         // grid solutions already written by the residual pass of the final iterate
         if (i < io_.u.size() && io_.u[i] && !grid_done_[i]) grid.push_back(i);
     }
+    copy_multi(ks_, copies, st_);
     if (!grid.empty()) {
         // the grid solution (FP64): u = L^-1 (g~ - S~ Q) or L^-1 (g~ - S~ U_b - S V_b)
         auto make = [&](size_t i) {
@@ -981,16 +1010,17 @@ void SolveTask::advance() {
         // from the boundary data (see residual), so b only seeds their first
         // FP32-operator solve: it is formed in FP32 like that operator.
         std::vector<size_t> need64, need32;
+        std::vector<CopyJob> copies;
         for (size_t i = 0; i < NI; ++i) {
             const Inst& in = ks_.inst[i];
             if (in.p->bc == IBDL_DIRICHLET && !io_.g[i])
-                IBDL_HIP_TRY(hipMemcpyAsync(k.b + k.hxoff[in.r0], io_.data[i], bytes_of(in), hipMemcpyDeviceToDevice,
-                                            st_));
+                copies.push_back(CopyJob{k.b + k.hxoff[in.r0], io_.data[i], (int64_t)in.nrhs * in.p->M});
             else if (in.p->prec == IBDL_PREC_MIXED && grid_fusable(i))
                 need32.push_back(i);
             else
                 need64.push_back(i);
         }
+        copy_multi(ks_, copies, st_);
         if (!need64.empty() || !need32.empty()) {
             auto make = [&](size_t i) {
                 const Inst& in = ks_.inst[i];
