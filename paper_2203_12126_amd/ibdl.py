@@ -144,7 +144,7 @@ def _dptr(t, name, shape=None):
     import torch
     if t is None:
         return None
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError(f"{name} must be a float64 CUDA tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
@@ -401,7 +401,15 @@ class Batch:
         return cls(inst)
 
     def _sizes(self, grid=False):
-        return [mt["nrhs"] * (mt["n"] ** mt["dim"] if grid else mt["m"]) for mt in self.meta]
+        cache = self.__dict__.setdefault("_size_cache", {})
+        if grid not in cache:
+            cache[grid] = [mt["nrhs"] * (mt["n"] ** mt["dim"] if grid else mt["m"]) for mt in self.meta]
+        return cache[grid]
+
+    def empty(self, grid=False):
+        """Uninitialised output tensors, one per instance: solutions [nrhs, M] or,
+        with grid=True, grid solutions [nrhs, n, ...] (to pass as out= / u=)."""
+        return self._empty_like_sizes(grid)
 
     def _empty_like_sizes(self, grid=False):
         out = []
