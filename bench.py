@@ -199,7 +199,7 @@ def run_batch(args):
         sol, u, info = batch.solve_grid(data, g, tol=tol, out=sol_out, u=u_out)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - s0)
-        iters += sum(i["iters"] for i in info)
+        iters += int(info.field("iters").sum())
     el = time.perf_counter() - t0
     statuses = sorted({i["status"] for i in info})
 
@@ -438,7 +438,7 @@ def main():
             sol, u, info = plan.solve_grid(data, g, tol=tol, out=sol_out, u=u_out)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - s0)
-            iters += sum(i["iters"] for i in info)
+            iters += int(info.field("iters").sum())
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         stages = []

@@ -76,11 +76,27 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
     prepare_pass(jobs, fp64)->run(0, st);
 }
 
+void arena_flush(Arena& a, hipStream_t st) {
+    if (a.cur < (int)a.blocks.size() && a.pos > a.pend) {
+        Arena::Block& blk = a.blocks[a.cur];
+        IBDL_HIP_TRY(hipMemcpyAsync(blk.dev + a.pend, blk.host + a.pend, a.pos - a.pend, hipMemcpyHostToDevice, st));
+    }
+    a.pend = a.pos;
+}
+
 void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st) {
+    void* d = arena_stage(a, src, bytes, st);
+    arena_flush(a, st);
+    return d;
+}
+
+void* arena_stage(Arena& a, const void* src, size_t bytes, hipStream_t st) {
     const size_t need = (bytes + 255) / 256 * 256;
+    if (a.cur < (int)a.blocks.size() && a.pos + need > a.blocks[a.cur].cap) arena_flush(a, st);
     while (a.cur < (int)a.blocks.size() && a.pos + need > a.blocks[a.cur].cap) {
         ++a.cur;
         a.pos = 0;
+        a.pend = 0;
     }
     if (a.cur == (int)a.blocks.size()) {
         Arena::Block blk;
@@ -95,10 +111,10 @@ void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st) {
         }
         a.blocks.push_back(blk);
         a.pos = 0;
+        a.pend = 0;
     }
     Arena::Block& blk = a.blocks[a.cur];
     std::memcpy(blk.host + a.pos, src, bytes);
-    IBDL_HIP_TRY(hipMemcpyAsync(blk.dev + a.pos, blk.host + a.pos, bytes, hipMemcpyHostToDevice, st));
     void* d = blk.dev + a.pos;
     a.pos += need;
     return d;
@@ -107,6 +123,7 @@ void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st) {
 void arena_reset(Arena& a) {
     a.cur = 0;
     a.pos = 0;
+    a.pend = 0;
 }
 
 void arena_free(Arena& a) {
@@ -117,6 +134,7 @@ void arena_free(Arena& a) {
     a.blocks.clear();
     a.cur = 0;
     a.pos = 0;
+    a.pend = 0;
 }
 
 static void flush_set(Timing& t, int set) {

@@ -558,11 +558,13 @@ GroupedPass prepare_grouped(KrylovSet& ks, const std::vector<size_t>& which, con
         groups[std::make_tuple(in.p->dim, in.p->n, pr, om)].push_back(jb);
     }
     GroupedPass gp;
+    Arena& arena = ar ? *ar : *ks.arena;
     for (auto& kv : groups) {
         auto pp = prepare_pass(kv.second, fp64);
-        pp->upload(ar ? *ar : *ks.arena, st);
+        pp->upload(arena, st);
         gp.parts.push_back(std::move(pp));
     }
+    arena_flush(arena, st);
     return gp;
 }
 

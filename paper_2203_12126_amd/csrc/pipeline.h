@@ -952,8 +952,8 @@ struct StageTable {
     Jobs<A> jobs(const int32_t* itp) const { return Jobs<A>{dargs, dstart, njobs(), itp}; }
     void upload(Arena& ar, hipStream_t st) {
         if (!multi()) return;
-        dargs = reinterpret_cast<const A*>(arena_put(ar, args.data(), args.size() * sizeof(A), st));
-        dstart = reinterpret_cast<const int*>(arena_put(ar, start.data(), start.size() * sizeof(int), st));
+        dargs = reinterpret_cast<const A*>(arena_stage(ar, args.data(), args.size() * sizeof(A), st));
+        dstart = reinterpret_cast<const int*>(arena_stage(ar, start.data(), start.size() * sizeof(int), st));
     }
 };
 

@@ -43,8 +43,14 @@ struct Arena {
     std::vector<Block> blocks;
     int cur = 0;
     size_t pos = 0;
+    size_t pend = 0;  // blocks[cur] bytes [pend, pos) are staged on the host, not yet copied
 };
+// arena_put: stage and copy at once; arena_stage: host side only, the device
+// copies of everything staged since the last flush go out as one copy per block
+// in arena_flush, which must precede any launch that reads them
 void* arena_put(Arena& a, const void* src, size_t bytes, hipStream_t st);
+void* arena_stage(Arena& a, const void* src, size_t bytes, hipStream_t st);
+void arena_flush(Arena& a, hipStream_t st);
 void arena_reset(Arena& a);
 void arena_free(Arena& a);
 
@@ -264,7 +270,7 @@ struct PassJob {
 // precision; run() launches every stage once for all jobs.
 struct PreparedPass {
     virtual ~PreparedPass() {}
-    virtual void upload(Arena& arena, hipStream_t st) = 0;  // only needed for several jobs
+    virtual void upload(Arena& arena, hipStream_t st) = 0;  // several jobs only; stages, caller flushes
     virtual void run(int it, hipStream_t st) = 0;            // it: iteration index
     // the same with the iteration index read on the device from *itp
     void run_dev(const int32_t* itp, hipStream_t st) {

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections.abc import Sequence
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -266,9 +267,7 @@ class Plan:
                               ctypes.byref(o), _dptr(out, "sol", data.numel()), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_solve")
-        return out, [dict(iters=i.iters, rel_resid_est=i.rel_resid_est,
-                          rel_resid_true=i.rel_resid_true, status=i.status,
-                          fp64_applies=i.fp64_applies) for i in info]
+        return out, InfoList(info)
 
     def solve_grid(self, data, g=None, tol=1e-8, restart=50, maxit=500, x0=None, true_residual=False,
                    out=None, u=None, stream=None, raise_on_noconv=True):
@@ -285,9 +284,7 @@ class Plan:
                                    _dptr(u, "u", nrhs * self.grid_size), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_solve_grid")
-        return out, u, [dict(iters=i.iters, rel_resid_est=i.rel_resid_est,
-                             rel_resid_true=i.rel_resid_true, status=i.status,
-                             fp64_applies=i.fp64_applies) for i in info]
+        return out, u, InfoList(info)
 
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
         nrhs = self._nrhs(sol, self.m)
@@ -336,22 +333,56 @@ class Plan:
             pass
 
 
-def _info_dicts(info):
-    return [dict(iters=i.iters, rel_resid_est=i.rel_resid_est, rel_resid_true=i.rel_resid_true,
-                 status=i.status, fp64_applies=i.fp64_applies) for i in info]
+class InfoList(Sequence):
+    """Per-rhs solve reports over the C array the library filled: item r is a dict
+    (iters, rel_resid_est, rel_resid_true, status, fp64_applies), built when it is
+    read; field(name) returns one of them for every rhs as a numpy array."""
+
+    _keys = tuple(f for f, _ in SolveInfo._fields_)
+
+    def __init__(self, info):
+        import numpy as np
+        f = SolveInfo._fields_
+        dt = np.dtype(dict(names=[n for n, _ in f],
+                           formats=["<i4" if t is ctypes.c_int32 else "<f8" for _, t in f],
+                           offsets=[getattr(SolveInfo, n).offset for n, _ in f],
+                           itemsize=ctypes.sizeof(SolveInfo)))
+        self._a = np.frombuffer(info, dtype=dt)
+
+    def __len__(self):
+        return len(self._a)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self._a)))]
+        rec = self._a[i]
+        return {k: rec[k].item() for k in self._keys}
+
+    def field(self, name):
+        return self._a[name].copy()
+
+    def __repr__(self):
+        return repr(list(self))
 
 
 def _ptr_array(tensors, name, sizes, allow_none=False):
     """Host array of device pointers, one per instance (None entries -> NULL)."""
-    arr = (ctypes.c_void_p * len(tensors))()
+    import torch
+    f64, tensor = torch.float64, torch.Tensor
+    ptrs = [None] * len(tensors)
     for i, t in enumerate(tensors):
         if t is None:
             if not allow_none:
                 raise ValueError(f"{name}[{i}] is required")
-            arr[i] = None
-        else:
-            arr[i] = _dptr(t, f"{name}[{i}]", sizes[i] if sizes is not None else None).value
-    return arr
+            continue
+        if not isinstance(t, tensor) or t.dtype is not f64 or not t.is_cuda:
+            raise TypeError(f"{name}[{i}] must be a float64 CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}[{i}] must be contiguous")
+        if sizes is not None and t.numel() != sizes[i]:
+            raise ValueError(f"{name}[{i}] has {t.numel()} elements, expected {sizes[i]}")
+        ptrs[i] = t.data_ptr()
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
 
 
 class Batch:
@@ -435,7 +466,7 @@ class Batch:
                                     _ptr_array(out, "sol", self._sizes()), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_batch_solve")
-        return out, _info_dicts(info)
+        return out, InfoList(info)
 
     def solve_grid(self, data, g=None, tol=1e-8, restart=50, maxit=500, true_residual=False, out=None,
                    u=None, stream=None, raise_on_noconv=True):
@@ -450,7 +481,7 @@ class Batch:
                                          _ptr_array(u, "u", self._sizes(grid=True)), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_batch_solve_grid")
-        return out, u, _info_dicts(info)
+        return out, u, InfoList(info)
 
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
         out = self._empty_like_sizes(grid=True) if out is None else out
@@ -553,7 +584,7 @@ class Server:
         del self._req[ticket]
         if st != OK and raise_on_error and st != ERR_NOCONV:
             _check(st, "request")
-        return dict(status=st, sol=rq["sol"], u=rq["u"], info=_info_dicts(info),
+        return dict(status=st, sol=rq["sol"], u=rq["u"], info=InfoList(info),
                     times=dict(queue_ms=tm.queue_ms, run_ms=tm.run_ms, total_ms=tm.total_ms,
                                cohort_size=tm.cohort_size))
 
