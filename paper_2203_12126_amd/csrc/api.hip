@@ -359,6 +359,7 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += (nd + nm) * 24 + 2 * (nlines + 2) * 4;
     // line and plane masks, lists, line starts, FFT and symbol tables
     b += nlines * 18 + n * 64;
+    if (dim == 2 && d->prec == IBDL_PREC_MIXED) b += (size_t)tile_pitch_f32(d->n) * n * 4;
     // construction temporaries (sort keys, scan buffers), alive together at most
     b += M * 36 + pow2(M) * 8 + pow2(nd) * 8 + nd * 9 + pow2(nm) * 8 + nm * 9 + nlines * 12;
     // Krylov state: basis, five pools, two banks of block partial sums, Hessenberg and rotations

@@ -333,6 +333,21 @@ struct LdsStore {
     __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[lds_row<PS>(i) * C + c] = v; }
 };
 
+// Every stage hands output slot k = b * RAD + r of a thread (its b-th butterfly,
+// r-th output) to the store functor through store_out; a functor that needs the
+// slot (values prefetched per output) overloads it.
+template <class ST, typename R>
+__device__ __forceinline__ void store_out(ST& st, int i, int c, cplx<R> v, int) {
+    st(i, c, v);
+}
+
+// The last radix of a plan: its stage writes row j + r * (L / RAD) of column c for
+// the butterfly id = j * C + c (NS * RAD = L there).
+template <int L, int RMAX>
+constexpr int last_radix() {
+    return make_plan(L, RMAX).r[make_plan(L, RMAX).n - 1];
+}
+
 // One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
 template <typename R, int L, int C, int TH, int NT, int SIGN, int PS, int NS, int RAD, int... REST, class TW,
           class LD, class ST>
@@ -365,7 +380,7 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST s
                 const int c = id % C, j = id / C;
                 const int base = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) out(base + r * NS, c, v[b][r]);
+                for (int r = 0; r < RAD; ++r) store_out(out, base + r * NS, c, v[b][r], b * RAD + r);
             }
         }
     };

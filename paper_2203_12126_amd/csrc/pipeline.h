@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "fft.h"
@@ -196,7 +197,7 @@ struct ColArgs {
     const int32_t* outer_list;
     size_t tile_stride;   // between tiles
     size_t outer_stride;  // between outer indices (plane z, or a block of K rows)
-    size_t es;            // between consecutive elements of a line
+    size_t es;            // between consecutive elements of a line (C in K == 1 passes)
     int width;            // n/2 + 1 columns
     const uint8_t* lmask;
     int lm_outer, lm_stride;
@@ -206,6 +207,7 @@ struct ColArgs {
     const R* s2;
     R alpha;
     R norm;
+    const R* sym;         // 2-D FP32: norm / lambda per element in tile layout ([tile][row][C])
     int nouter;           // outer indices per right-hand side
     int nrhs;
 };
@@ -424,31 +426,35 @@ __global__ __launch_bounds__((RowCfg<R, N, V>::T)) void k_row_fwd(RowFwdArgs<R> 
 // base + i * es + l, with the C columns of tile t (kx = t*C + l % C) and, for
 // K > 1, K consecutive y-rows (ky = o*K + l / C) of the z-transform.
 // Element i of line l through the block's buffer descriptor (esb: bytes between
-// consecutive elements of a line, below 2^24): lines whose column l % C is past
-// the spectrum's width (l % C >= vcols) and rows outside the row mask map to an
-// offset outside the range (read as zero, store dropped), with no branch.
-template <typename R, int C>
+// consecutive elements of a line, below 2^24; ES > 0: the same as a compile-time
+// element count): lines whose column l % C is past the spectrum's width
+// (l % C >= vcols) and rows outside the row set map to an offset of 2^31 or more,
+// past every range (read as zero, store dropped), with no branch.  The row set
+// is held in LDS as one byte per row, 0 (in) or 0x80 (out), which lands on bit 31;
+// in-range offsets stay below 2^31.
+template <typename R, int C, int ES>
 __device__ __forceinline__ int col_offset(int i, int l, int esb, int vcols, const uint8_t* m) {
-    const bool ok = ((l % C) < vcols) & (m[i] != 0);
-    const int off = (int)__umul24((unsigned)i, (unsigned)esb) + l * (int)sizeof(cplx<R>);
-    return ok ? off : kBufOut;
+    const unsigned lo = (l % C) < vcols ? (unsigned)(l * (int)sizeof(cplx<R>)) : 0x80000000u;
+    const unsigned row = ES > 0 ? (unsigned)i * (unsigned)(ES * (int)sizeof(cplx<R>))
+                                : __umul24((unsigned)i, (unsigned)esb);
+    return (int)((row + lo) | ((unsigned)m[i] << 24));
 }
-template <typename R, int C>
+template <typename R, int C, int ES>
 struct ColLoad {
     __amdgpu_buffer_rsrc_t rs;
     int esb, vcols;
-    const uint8_t* m;  // LDS row mask
+    const uint8_t* m;  // LDS row set (0 in, 0x80 out)
     __device__ __forceinline__ cplx<R> operator()(int i, int l) const {
-        return BufIO<R>::load(rs, col_offset<R, C>(i, l, esb, vcols, m));
+        return BufIO<R>::load(rs, col_offset<R, C, ES>(i, l, esb, vcols, m));
     }
 };
-template <typename R, int C>
+template <typename R, int C, int ES>
 struct ColStore {
     __amdgpu_buffer_rsrc_t rs;
     int esb, vcols;
     const uint8_t* m;
     __device__ __forceinline__ void operator()(int i, int l, cplx<R> v) const {
-        BufIO<R>::store(rs, col_offset<R, C>(i, l, esb, vcols, m), v);
+        BufIO<R>::store(rs, col_offset<R, C, ES>(i, l, esb, vcols, m), v);
     }
 };
 // 1/x: hardware reciprocal (about 1 ulp) in FP32, exact division in FP64
@@ -469,6 +475,17 @@ struct SymStore {
         s[i * LC + l] = cscale(v, sig);
     }
 };
+
+// LDS store that multiplies output slot k by the inverse symbol prefetched for it
+template <typename R, int LC>
+struct SymTabStore {
+    cplx<R>* s;
+    const R* sig;  // the thread's prefetched values, one per output slot
+};
+template <typename R, int LC>
+__device__ __forceinline__ void store_out(SymTabStore<R, LC>& st, int i, int l, cplx<R> v, int k) {
+    st.s[i * LC + l] = cscale(v, st.sig[k]);
+}
 
 // A column block covers K y-rows (3-D z transform: K > 1) of its tile's C columns.
 template <typename R, int N, int K>
@@ -533,11 +550,34 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
                 scv[u] = kx < a.width ? a.s2[kx] + (K > 1 ? a.s2[o * K + l / C] : R(0)) + a.alpha : R(-1);
         }
     }
+    // 2-D FP32 (K == 1, MODE 1): the inverse symbol of every output of the last
+    // forward stage comes from the plan's table, loaded here with the other tables
+    // (not at n = 2048, whose kernel holds 121 VGPRs without the prefetched values
+    // and would lose its second block per compute unit past 128)
+    constexpr bool SYMT = MODE == 1 && K == 1 && sizeof(R) == 4 && N < 2048;
+    constexpr int RL = last_radix<N, RM>(), NBL = N / RL, TOTL = NBL * LC, PERL = (TOTL + T - 1) / T;
+    R sigv[SYMT ? PERL * RL : 1];
+    if constexpr (SYMT) {
+        // rows past N (threads beyond the last stage's butterflies) read 0 and are not used
+        const __amdgpu_buffer_rsrc_t rsym =
+            buf_rsrc(a.sym + (size_t)t * N * C, (uint32_t)(N * C * (int)sizeof(R)));
+#pragma unroll
+        for (int b = 0; b < PERL; ++b) {
+            const int id = threadIdx.x + b * T;
+            const int c = id % LC, j = id / LC;
+#pragma unroll
+            for (int r = 0; r < RL; ++r)
+                sigv[b * RL + r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    rsym, ((j + r * NBL) * C + c) * (int)sizeof(R), 0, 0));
+        }
+    }
     if (skipv) return;
     // the block's elements i * es + l (i < N, l < LC) from its base: at most
     // (511 * 65 * 512 * 4 + 16) * 16 bytes (3-D, n <= 512, FP64), below 2^31
     const cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
-    const int es = (int)a.es;
+    // K == 1 passes (2-D, and the 3-D y passes) step C elements along a line
+    constexpr int ES = K == 1 ? C : 0;
+    const int es = K == 1 ? C : (int)a.es;
     const int esb = es * (int)sizeof(cplx<R>);
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, (uint32_t)(((N - 1) * es + LC) * (int)sizeof(cplx<R>)));
     const int vcols = a.width - t * C;
@@ -545,8 +585,8 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     for (int u = 0; u < PN; ++u) {
         const int i = threadIdx.x + u * T;
         if (i < N) {
-            lmask[i] = lmv[u];
-            smask[i] = smv[u];
+            lmask[i] = lmv[u] ? 0 : 0x80;
+            smask[i] = smv[u] ? 0 : 0x80;
             if constexpr (MODE == 1) srow[i] = s2v[u];
         }
     }
@@ -561,8 +601,8 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     if constexpr (NYQ) {
         if (t == NT - 1) {
             // the last tile holds only the column kx = n/2: transform it alone
-            const ColLoad<R, C> ld1{rs, esb, vcols, lmask};
-            const ColStore<R, C> st1{rs, esb, vcols, smask};
+            const ColLoad<R, C, ES> ld1{rs, esb, vcols, lmask};
+            const ColStore<R, C, ES> st1{rs, esb, vcols, smask};
             if constexpr (MODE == 0) {
                 run_fft<R, N, 1, T, N, -1>(s, tw, ld1, st1, FwdRadices<N, RM>{});
             } else if constexpr (MODE == 2) {
@@ -576,12 +616,17 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
             return;
         }
     }
-    const ColLoad<R, C> ld{rs, esb, vcols, lmask};
-    const ColStore<R, C> st{rs, esb, vcols, smask};
+    const ColLoad<R, C, ES> ld{rs, esb, vcols, lmask};
+    const ColStore<R, C, ES> st{rs, esb, vcols, smask};
     if constexpr (MODE == 0) {
         run_fft<R, N, LC, T, N, -1>(s, tw, ld, st, FwdRadices<N, RM>{});
     } else if constexpr (MODE == 2) {
         run_fft<R, N, LC, T, N, +1>(s, tw, ld, st, FwdRadices<N, RM>{});
+    } else if constexpr (SYMT) {
+        static_assert(std::is_same<R, float>::value, "symbol table is FP32");
+        run_fft<R, N, LC, T, N, -1>(s, tw, ld, SymTabStore<R, LC>{s, sigv}, FwdRadices<N, RM>{});
+        __syncthreads();
+        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
     } else {
         const SymStore<R, LC> sym{s, srow, scol, a.norm};
         run_fft<R, N, LC, T, N, -1>(s, tw, ld, sym, FwdRadices<N, RM>{});
@@ -985,6 +1030,7 @@ void launch_col_t(int n, int blocks, hipStream_t st, StageEv e, const ColArgs<R>
 #define IBDL_C(NN)                                                                                        \
     case NN: {                                                                                            \
         constexpr int K = ZPASS ? ZRows<R, NN>::value : 1;                                                \
+        static_assert(!ZPASS || K > 1, "K == 1 marks the 2-D column pass");                                \
         hipExtLaunchKernelGGL((k_col<R, NN, MODE, K, MULTI>), dim3(blocks), dim3(ColK<R, NN, K>::T), 0,       \
                               st, e.a, e.b, 0, a, js, it);                                                \
     } break;
@@ -1248,6 +1294,10 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ca.s2 = PP::s2(p);
         ca.alpha = (R)p->alpha;
         ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
+        if constexpr (sizeof(R) == 4) {
+            if (p->dim == 2 && !p->sym32) throw Error{IBDL_ERR_HIP, "2-D plan without its FP32 symbol table"};
+            ca.sym = p->dim == 2 ? p->sym32 : nullptr;
+        }
         ca.tile_stride = (size_t)n * C;
         ca.nrhs = nrhs;
         if (p->dim == 2) {

@@ -177,6 +177,9 @@ struct ibdl_plan_s {
     float* tw32 = nullptr;
     double* s2_64 = nullptr;  // [n] (4/h^2) sin^2(pi m/n)
     float* s2_32 = nullptr;
+    // 2-D mixed plans: the FP32 column pass's factor norm / lambda(kx, ky) for every
+    // element of the half spectrum, in its column-tile layout [tile][ky][C]
+    float* sym32 = nullptr;
 
     ibdl::Workspace ws;
     ibdl::KrylovSet ks;     // Krylov state of solves through this plan alone
@@ -302,6 +305,7 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
                   bool fp64 = false);
 int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
+int col_width_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
 void free_build_tmp(ibdl_plan p);
 // frees every device allocation of a plan in stream order on st (no wait) and the plan

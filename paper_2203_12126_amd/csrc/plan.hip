@@ -527,6 +527,25 @@ __global__ void k_tables(int n, double h, double* tw64, float* tw32, double* s26
     s232[m] = (float)v;
 }
 
+// 2-D inverse symbol in FP32, from FP64 terms: norm / lambda(kx, ky) with
+// lambda = -(s2[kx] + s2[ky]) - alpha, 0 where lambda = 0 (the mean of a Poisson
+// solve) and in the padding columns kx >= W of the last tile; layout [tile][ky][C]
+__global__ void k_symtab(int n, int C, int W, size_t total, const double* __restrict__ s2, double alpha,
+                         double norm, float* out) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const size_t tile = (size_t)n * C;
+    const int t = (int)(e / tile);
+    const int rem = (int)(e - (size_t)t * tile);
+    const int ky = rem / C, kx = t * C + rem % C;
+    float v = 0.0f;
+    if (kx < W) {
+        const double lam = s2[ky] + (s2[kx] + alpha);
+        if (lam != 0.0) v = (float)(-norm / lam);
+    }
+    out[e] = v;
+}
+
 // ------------------------------------------------------------------ host
 static int compact(ibdl_plan p, const int32_t* flag, int n, int32_t** list, hipStream_t st) {
     int32_t* idx = tmp_n<int32_t>(p, (size_t)n + 1);
@@ -650,6 +669,12 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     p->s2_32 = alloc_n<float>(p, n);
     hipLaunchKernelGGL(k_tables, dim3(nblocks(n, 256)), dim3(256), 0, st, n, p->h, p->tw64, p->tw32,
                        p->s2_64, p->s2_32);
+    if (dim == 2 && p->prec == IBDL_PREC_MIXED) {
+        const size_t total = (size_t)tile_pitch_f32(n) * n;
+        p->sym32 = alloc_n<float>(p, total);
+        hipLaunchKernelGGL(k_symtab, dim3(nblocks(total, 256)), dim3(256), 0, st, n, col_width_f32(n), p->W,
+                           total, p->s2_64, p->alpha, 2.0 / ((double)p->nlines * (double)n), p->sym32);
+    }
     IBDL_HIP_TRY(hipGetLastError());
     IBDL_HIP_TRY(hipStreamSynchronize(st));
     free_build_tmp(p);
