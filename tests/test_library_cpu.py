@@ -64,3 +64,29 @@ def test_footprint_grows_with_size():
     d = ibdl.footprint(3, 256, 40000, prec=ibdl.MIXED)
     assert 0 < a < b < c and d > c
     assert ibdl.footprint(2, 1000, 10) == 0
+
+
+def test_info_list_reads_the_c_array():
+    """Solve reports: one dict per right-hand side, read from the C array the
+    library fills; slices give lists of dicts, field() whole columns."""
+    info = (ibdl.SolveInfo * 5)()
+    for r in range(5):
+        info[r].iters = 10 + r
+        info[r].rel_resid_est = 0.25 * r
+        info[r].rel_resid_true = 0.5 * r
+        info[r].status = ibdl.ERR_NOCONV if r == 3 else ibdl.OK
+        info[r].fp64_applies = 2 * r
+    lst = ibdl.InfoList(info)
+    assert len(lst) == 5
+    assert lst[2] == dict(iters=12, rel_resid_est=0.5, rel_resid_true=1.0, status=ibdl.OK, fp64_applies=4)
+    assert lst[-1]["iters"] == 14 and lst[3]["status"] == ibdl.ERR_NOCONV
+    assert [x["iters"] for x in lst] == [10, 11, 12, 13, 14]
+    assert [x["fp64_applies"] for x in lst[1:4]] == [2, 4, 6]
+    assert type(lst[0]["iters"]) is int and type(lst[0]["rel_resid_true"]) is float
+    assert lst.field("iters").tolist() == [10, 11, 12, 13, 14]
+    assert lst.field("rel_resid_est").tolist() == [0.0, 0.25, 0.5, 0.75, 1.0]
+    with pytest.raises(IndexError):
+        lst[5]
+    # a view of the array: later writes by the library show through
+    info[0].iters = 99
+    assert lst[0]["iters"] == 99
