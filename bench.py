@@ -264,6 +264,7 @@ def run_batch(args):
         "stages_ms_per_apply": {k: round(v, 5) for k, v in per_apply.items()},
         "rel_err_vs_oracle_sampled": errs,
         "setup_s": {"inputs": round(t_gen, 2), "plans": round(t_plan, 2)},
+        "autotune": ibdl.autotune_report().splitlines(),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -558,6 +559,7 @@ def main():
         "stages_ms_in_solves": {nm: round(ms, 5) for nm, ms, _ in mixed["stages"]},
         "stages_ms_apply": {nm: round(ms, 5) for nm, ms in dom_ms.items()},
         "full_grid_bytes_per_apply": full_grid_bytes_per_apply(dim, n, m, 1),
+        "autotune": ibdl.autotune_report().splitlines(),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -321,9 +321,10 @@ ibdl_status ibdl_server_get_stats(ibdl_server server, ibdl_server_stats* out_hos
 /* Tile autotuner.  The row passes (spread + x-transform, x-inverse + interpolation)
  * are built in four workgroup shapes: 1, 2 and 4 right-hand sides per workgroup
  * with several lines each, and one line of one right-hand side; the first pass of
- * a new configuration (precision, dimension, n, output kind, right-hand-side
- * counts) runs every shape twice on the device, times the second run, and keeps
- * the fastest for the rest of the process.  Every shape gives bit-identical
+ * a new configuration (precision, dimension, n, forcing-grid input or not, output
+ * kind, right-hand-side counts) runs every shape once untimed and then three
+ * timed rounds over all shapes on the device, and keeps the shape with the
+ * fastest run for the rest of the process.  Every shape gives bit-identical
  * results.  ibdl_set_autotune clears the choices and sets the mode: 1 tuner on,
  * 0 off (a fixed rule picks the shape), 2..5 always row shape 0..3 (for tests);
  * other values: IBDL_ERR_ARG.  ibdl_autotune_report writes the choices as text

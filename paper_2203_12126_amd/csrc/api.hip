@@ -764,12 +764,14 @@ int32_t ibdl_autotune_report(char* buf, size_t cap) {
                                                    "rhs_per_block=1 lines_per_block=1"};
             static const char* const kOut[] = {"points", "grid", "grid+points"};
             const int v = kv.second.first;
-            char line[240];
+            char line[256];
             std::snprintf(line, sizeof(line),
-                          "%s dim=%d n=%d stage=%s out=%s min_rhs_bucket=%d total_rhs_bucket=%d jobs=%s -> %s (%.4f ms)\n",
+                          "%s dim=%d n=%d stage=%s in=%s out=%s min_rhs_bucket=%d total_rhs_bucket=%d jobs=%s -> %s "
+                          "(%.4f ms)\n",
                           k.rbytes == 8 ? "fp64" : "fp32", k.dim, k.n, k.stage == 0 ? "row_fwd" : "row_inv",
-                          kOut[k.dense >= 0 && k.dense <= 2 ? k.dense : 0], k.minr, k.totr, k.multi ? "many" : "one",
-                          v >= 0 && v <= 3 ? kVariant[v] : "?", kv.second.second);
+                          k.grid_in ? "grid" : "points", kOut[k.dense >= 0 && k.dense <= 2 ? k.dense : 0], k.minr,
+                          k.totr, k.multi ? "many" : "one", v >= 0 && v <= 3 ? kVariant[v] : "?",
+                          kv.second.second);
             out += line;
         }
     }

@@ -1085,6 +1085,7 @@ struct PreparedT : PreparedPass {
     int n = 0, dim = 2;
     int out_mode = 0;  // 0: point output, 1: grid output, 2: both
     int min_nrhs = 1, total_rhs = 1, njobs = 1;
+    int grid_in = 0;  // some job reads a forcing grid: its forward rows cover every line
     ibdl_plan tplan = nullptr;  // plan whose stage timing records this pass
     StageTable<RowFwdArgs<R>> rf[kRowVars];  // one table per row-block variant
     StageTable<ColArgs<R>> col[3];
@@ -1099,7 +1100,7 @@ struct PreparedT : PreparedPass {
     }
     TuneKey key(int stage) const {
         return TuneKey{(int)sizeof(R), dim, n, stage, out_mode, tune_bucket(min_nrhs),
-                       tune_bucket(total_rhs), njobs > 1 ? 1 : 0};
+                       tune_bucket(total_rhs), njobs > 1 ? 1 : 0, stage == 0 ? grid_in : 0};
     }
     void fwd(int v, int it, hipStream_t st, StageEv e) {
         const auto& t = rf[v];
@@ -1134,24 +1135,35 @@ struct PreparedT : PreparedPass {
         int v = tune_lookup(key(stage));
         if (v >= 0) return v;
         if (!tune_enabled() || capturing()) return heuristic();
-        float best = 1e30f;
-        int bv = heuristic();
+        // every shape once untimed, then kTuneRounds timed rounds over all shapes in
+        // turn; a shape's time is its fastest run (a single sample per shape picked
+        // a 20% slower 3-D spread shape in some processes)
+        constexpr int kTuneRounds = 3;
+        float ms_min[kRowVars];
+        for (int c = 0; c < row_vars<R>(); ++c) {
+            ms_min[c] = 1e30f;
+            launch(c, StageEv{});
+        }
         hipEvent_t e0, e1;
         IBDL_HIP_TRY(hipEventCreate(&e0));
         IBDL_HIP_TRY(hipEventCreate(&e1));
-        for (int c = 0; c < row_vars<R>(); ++c) {
-            launch(c, StageEv{});
-            launch(c, StageEv{e0, e1});
-            IBDL_HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            IBDL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bv = c;
+        for (int round = 0; round < kTuneRounds; ++round)
+            for (int c = 0; c < row_vars<R>(); ++c) {
+                launch(c, StageEv{e0, e1});
+                IBDL_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                IBDL_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                ms_min[c] = std::min(ms_min[c], ms);
             }
-        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        float best = 1e30f;
+        int bv = heuristic();
+        for (int c = 0; c < row_vars<R>(); ++c)
+            if (ms_min[c] < best) {
+                best = ms_min[c];
+                bv = c;
+            }
         tune_store(key(stage), bv, best);
         return -1 - bv;  // already run
     }
@@ -1235,6 +1247,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
     P->min_nrhs = minr;
     P->total_rhs = tot;
     P->njobs = (int)jobs.size();
+    for (const PassJob& jb : jobs) P->grid_in |= jb.in.grid != nullptr;
     const int C = col_width<R>(n);
     const int NT = col_tiles<R>(n);
     const size_t plane = (size_t)NT * n * C;

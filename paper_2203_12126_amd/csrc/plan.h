@@ -318,12 +318,14 @@ void solve_set(KrylovSet& ks, const std::vector<const double*>& data, const std:
                ibdl_solve_info* info, hipStream_t st, int* overall, const std::vector<double*>& u = {});
 
 // Tile autotuner: per pass configuration, the row-block variant measured fastest.
+// dense: output mode (0 points, 1 grid, 2 both); grid_in: the forward row stage
+// reads a forcing grid (every line) rather than the spread lines alone
 struct TuneKey {
-    int rbytes, dim, n, stage, dense, minr, totr, multi;
+    int rbytes, dim, n, stage, dense, minr, totr, multi, grid_in;
     bool operator<(const TuneKey& o) const {
-        const int a[8] = {rbytes, dim, n, stage, dense, minr, totr, multi};
-        const int b[8] = {o.rbytes, o.dim, o.n, o.stage, o.dense, o.minr, o.totr, o.multi};
-        for (int i = 0; i < 8; ++i)
+        const int a[9] = {rbytes, dim, n, stage, dense, minr, totr, multi, grid_in};
+        const int b[9] = {o.rbytes, o.dim, o.n, o.stage, o.dense, o.minr, o.totr, o.multi, o.grid_in};
+        for (int i = 0; i < 9; ++i)
             if (a[i] != b[i]) return a[i] < b[i];
         return false;
     }
