@@ -74,7 +74,7 @@ typedef struct {
     int32_t bc;           /* ibdl_bc                                                        */
     int32_t delta;        /* ibdl_delta                                                     */
     int32_t prec;         /* ibdl_prec                                                      */
-    int32_t npts;         /* M >= 1 boundary points                                         */
+    int32_t npts;         /* M >= 1 boundary points; M < 2^28 / 32 (2-D), 2^28 / 160 (3-D)  */
     const double* X;      /* device [M][dim] point coordinates (any real values, wrapped periodically) */
     const double* normal; /* device [M][dim] unit normals pointing OUT of Omega (Sec. 4.1)    */
     const double* weight; /* device [M] quadrature weights: arclength Delta s_i (2-D, Sec. 5.2)

@@ -51,8 +51,10 @@ std::string check_desc(const ibdl_desc* d) {
     if (d->delta != IBDL_DELTA_PESKIN4 && d->delta != IBDL_DELTA_COSINE4) return "unknown delta kernel";
     if (d->prec != IBDL_PREC_FP64 && d->prec != IBDL_PREC_MIXED) return "unknown precision";
     if (d->npts < 1) return "npts must be >= 1";
+    // spread entries per point (dipole stencil); the spread kernels address the
+    // entries' FP64 weights with 32-bit byte offsets
     const long long per = d->dim == 2 ? 32 : 160;
-    if ((long long)d->npts * per >= (1LL << 31)) return "too many boundary points";
+    if ((long long)d->npts * per * 8 >= (1LL << 31)) return "too many boundary points";
     if (!d->X || !d->normal || !d->weight) return "X, normal and weight must be device pointers";
     return "";
 }

@@ -39,6 +39,23 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
     // word 3: 32-bit data format, as untyped buffer loads and stores require on gfx9
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
+// one real through a buffer descriptor (offset in bytes; past the range: 0)
+template <typename R>
+struct BufScalar;
+template <>
+struct BufScalar<float> {
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, int off) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+};
+template <>
+struct BufScalar<double> {
+    typedef unsigned int V __attribute__((ext_vector_type(2)));
+    __device__ __forceinline__ static double load(__amdgpu_buffer_rsrc_t r, int off) {
+        const V v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return __longlong_as_double((long long)(((unsigned long long)v.y << 32) | v.x));
+    }
+};
 template <typename R>
 struct BufIO;
 template <>

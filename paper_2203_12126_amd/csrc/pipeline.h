@@ -165,6 +165,7 @@ struct CsrView {
     const uint32_t* act_node;
     const uint32_t* k;
     const R* w;
+    uint32_t nnz;        // entries of k and w (nnz * sizeof(double) < 2^31)
     const double* q;     // q + rhs * q_stride + it * q_jstride: strengths of one right-hand side
     size_t q_stride;
     size_t q_jstride;    // offset per iteration index (Krylov basis vectors), else 0
@@ -289,20 +290,24 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
         const double* q = c.q + (size_t)r * c.q_stride + (size_t)it * c.q_jstride;
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
-        // entries in groups of 8: every load of a group is issued before any is used;
-        // past the node's last entry the group re-reads that entry with weight 0
-        // (adding 0 * q leaves both parts of the sum exactly as they were), so the
-        // group has no branch
+        // entries in groups of 8 through buffer descriptors over k and w (one offset per
+        // group, the entries at immediate offsets from it): every load of a group is
+        // issued before any is used; entries past the node's last belong to the next
+        // node or lie past the arrays (read as 0) and enter with weight 0 (adding
+        // 0 * q leaves both parts of the sum exactly as they were), so the group has
+        // no branch
+        const __amdgpu_buffer_rsrc_t rk = buf_rsrc(c.k, c.nnz * 4u);
+        const __amdgpu_buffer_rsrc_t rw = buf_rsrc(c.w, c.nnz * (uint32_t)sizeof(R));
         for (int e = c.act_ptr[a]; e < e1; e += 8) {
+            const int cnt = e1 - e;
             uint32_t kk[8];
             R ww[8];
             double qq[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int eu = e + u < e1 ? e + u : e1 - 1;
-                kk[u] = c.k[eu];
-                const R wv = c.w[eu];
-                ww[u] = e + u < e1 ? wv : R(0);
+                kk[u] = __builtin_amdgcn_raw_buffer_load_b32(rk, e * 4 + u * 4, 0, 0);
+                const R wv = BufScalar<R>::load(rw, e * (int)sizeof(R) + u * (int)sizeof(R));
+                ww[u] = u < cnt ? wv : R(0);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) qq[u] = q[kk[u]];
@@ -1277,6 +1282,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             v.act_node = c.act_node;
             v.k = c.k;
             v.w = PP::w(c);
+            v.nnz = (uint32_t)c.nnz;
             v.q = q;
             v.coef = coef;
             return v;

@@ -560,7 +560,7 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
     const int dim = p->dim, n = p->n, M = p->M;
     const int npp = dipole ? (dim == 2 ? 32 : 160) : (dim == 2 ? 16 : 64);
     const size_t nnz = (size_t)M * npp;
-    if (nnz >= (size_t)INT32_MAX) throw Error{IBDL_ERR_ARG, "too many spread entries"};
+    if (nnz * sizeof(double) >= (size_t)INT32_MAX) throw Error{IBDL_ERR_ARG, "too many spread entries"};
     const size_t n2 = pow2_at_least(nnz, BIT_BLOCK);
     uint64_t* keys = tmp_n<uint64_t>(p, n2);
     hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, (const uint32_t*)nullptr,
