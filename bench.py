@@ -400,7 +400,7 @@ def main():
                     help="also run one device copy of this size (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(each solve fits one MI355X); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
