@@ -902,8 +902,12 @@ void SolveTask::after_krylov() {
     snapshot(snap_buf_);
     if (refining_) hipLaunchKernelGGL(k_pool_op, dim3(k.nblk, R_), dim3(GT), 0, st_, a, 1, k.x, (const double*)k.d);
     if (any_mixed_) {
-        // the grid solutions come with the residual of what may be the final iterate
-        residual(k.b, k.x, k.rr, true, true);
+        // the grid solutions come with the residual of what may be the final iterate:
+        // not with the one after the first FP32-operator solve when tol lies below
+        // where that solve stops (its residual is then above tol; should it meet tol
+        // after all, output() computes the grid solutions in a pass of their own)
+        const bool maybe_final = refining_ || o_.tol >= kMixedFirstTol;
+        residual(k.b, k.x, k.rr, true, maybe_final);
         norms_async(k.rr, hs.nrm);
     } else {
         if (o_.true_residual) {

@@ -125,3 +125,24 @@ def test_solve_grid_argument_errors():
                                     info, None)
     assert st == ibdl.ERR_ARG and "u" in ibdl.last_error()
     pl.close()
+
+
+@pytest.mark.parametrize("bc", [W.DIRICHLET, W.NEUMANN])
+def test_solve_grid_mixed_tol_near_first_stage(bc):
+    """With tol just below where the first FP32-operator solve stops, the FP64
+    residual after it writes no grid solution; whether that residual turns out
+    final (the grid solution then comes from a pass of its own) or refinement
+    goes on, u equals ibdl_eval_grid of the returned solution."""
+    p = W.config_star1024(m=1500, n=256, alpha=1.0, bc=bc, seed=21)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    data = T(np.stack([p.data] * 3))
+    g = T(np.stack([p.g_tilde] * 3))
+    rounds = set()
+    for tol in (9.9e-7, 5e-7, 2e-7, 1e-9):
+        sol, u, info = pl.solve_grid(data, g, tol=tol)
+        assert all(i["status"] == ibdl.OK and i["rel_resid_true"] <= tol for i in info), (tol, list(info))
+        ue = pl.eval_grid(sol, vb=data if bc == W.NEUMANN else None, g=g)
+        assert torch.equal(u, ue), tol
+        rounds |= {i["fp64_applies"] for i in info}
+    print("FP64 residual passes seen:", sorted(rounds))
+    pl.close()
