@@ -1098,7 +1098,19 @@ void SolveTask::advance() {
         }
         prev_.assign(resid, resid + R_);
         prev_iter_ = snap_iter_;
-        int c = std::max(1, std::min(8, need - queued_after_));
+        const int want = need - queued_after_;
+        if (want <= 0 && queued_after_ > 0 && kj_ < m_) {
+            // the step queued behind the snapshot is expected to finish every rhs:
+            // look at its state before queuing more (a further step would find every
+            // rhs done and only cost its launches; a wrong guess costs one wait)
+            snap_buf_ ^= 1;
+            snapshot(snap_buf_);
+            mark();
+            snap_iter_ = kj_;
+            queued_after_ = 0;
+            return;
+        }
+        int c = std::max(1, std::min(8, want));
         if (kj_ >= m_) {
             // cycle end: restart the rhs still running from their current iterate
             KArgs a = kargs(ks_, m_);
