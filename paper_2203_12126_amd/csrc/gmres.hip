@@ -863,6 +863,12 @@ void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
     kmaxit_ = maxit;
     ktotal_ = kj_ = 0;
     prev_iter_ = -1;
+    if (x_zero) {
+        // from x = 0 every rhs starts at relative residual 1, so the first chunk
+        // decision of the run already has a rate of reduction to go by
+        prev_.assign(R_, 1.0);
+        prev_iter_ = 0;
+    }
     for (int r = 0; r < R_; ++r) {
         hs.tol[r] = tol_[r];
         hs.skip[r] = skip_[r];
