@@ -462,7 +462,9 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     k.partial = A((size_t)R * nblk * (m + 2) * 2);
     k.hcol = A((size_t)R * (m + 2));
     k.bnorm = A(R);
-    k.resid = A(R);
+    // residual estimates [R] followed by the state [R][4]: one snapshot copy
+    k.resid = A(R + 2 * (size_t)R);
+    k.state = reinterpret_cast<int32_t*>(k.resid + R);
     k.tolv = A(R);
     k.nrm = A(R);
     k.b = A(xtot);
@@ -470,7 +472,6 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     k.r = A(xtot);
     k.rr = A(xtot);
     k.d = A(xtot);
-    k.state = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * 4 * sizeof(int32_t)));
     k.skip = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
     k.jcur = reinterpret_cast<int32_t*>(dev_alloc(k.mem, sizeof(int32_t)));
     k.Mr = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
@@ -523,7 +524,8 @@ static KArgs kargs(KrylovSet& ks, int m) {
 }
 
 // host staging: tolerances, skip flags, norms of b, norms of other pools, and two
-// alternating snapshots of the per-rhs state and residual estimates
+// alternating snapshots of the per-rhs residual estimates and state (each laid out
+// as on the device: [R] doubles, then [R][4] int32)
 struct Staging {
     double* tol;
     double* bn;
@@ -538,12 +540,11 @@ static Staging staging(KWork& k, int R) {
     s.tol = d;
     s.bn = d + R;
     s.nrm = d + 2 * R;
-    s.resid[0] = d + 3 * R;
-    s.resid[1] = d + 4 * R;
-    int32_t* i = reinterpret_cast<int32_t*>(d + 5 * R);
-    s.state[0] = i;
-    s.state[1] = i + 4 * R;
-    s.skip = i + 8 * R;
+    for (int b = 0; b < 2; ++b) {
+        s.resid[b] = d + 3 * R + b * 3 * R;
+        s.state[b] = reinterpret_cast<int32_t*>(s.resid[b] + R);
+    }
+    s.skip = reinterpret_cast<int32_t*>(d + 9 * R);
     return s;
 }
 
@@ -693,9 +694,8 @@ void SolveTask::norms_async(const double* pool, double* host) {
 void SolveTask::snapshot(int buf) {
     KWork& k = ks_.w;
     Staging hs = staging(k, R_);
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.state[buf], k.state, (size_t)R_ * 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                st_));
-    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid[buf], k.resid, (size_t)R_ * sizeof(double), hipMemcpyDeviceToHost, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(hs.resid[buf], k.resid, (size_t)R_ * (sizeof(double) + 4 * sizeof(int32_t)),
+                                hipMemcpyDeviceToHost, st_));
 }
 
 // a private stream to record graphs on (recording launches nothing)

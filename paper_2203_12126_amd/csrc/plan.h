@@ -78,10 +78,10 @@ struct KWork {
     double* partial = nullptr;  // two banks of [R][nblk][m+2]
     double* hcol = nullptr;     // [R][m+2]
     double* bnorm = nullptr;    // [R]
-    double* resid = nullptr;    // [R]
+    double* resid = nullptr;    // [R], followed by state
     double* tolv = nullptr;     // [R]
     double* nrm = nullptr;      // [R] norms handed to the host
-    int32_t* state = nullptr;   // [R][4]: done flag, iterations, status, j
+    int32_t* state = nullptr;   // [R][4] right after resid: done flag, iterations, status, j
     int32_t* skip = nullptr;    // [R]
     int32_t* jcur = nullptr;    // Arnoldi step index read by replayed iteration graphs
     int32_t* Mr = nullptr;      // [R]
