@@ -110,8 +110,9 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
 ibdl_status ibdl_plan_destroy(ibdl_plan plan);
 
 /* Host-only estimate of the device bytes a plan plus solve workspace for `nrhs`
- * right-hand sides and Krylov size `restart` occupies (used for admission).
- * Returns 0 for an invalid desc. */
+ * right-hand sides and Krylov size `restart` occupies (used for admission): an
+ * upper bound, rounded up to whole 2 MiB device pages plus one.  Returns 0 for
+ * an invalid desc. */
 size_t ibdl_plan_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart);
 
 /* Aq[r] = A q[r] for r < nrhs (async).  q, Aq: device [nrhs][M], must not overlap.

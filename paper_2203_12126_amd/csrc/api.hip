@@ -353,6 +353,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     size_t b = 0;
     // workspace, FP64-sized: half spectra and gather partial sums
     b += R * nlines * P * 16 + R * M * gpp * 8;
+    // mixed: the Arnoldi step's strengths as FP32 in groups of four right-hand sides
+    if (d->prec == IBDL_PREC_MIXED) b += (R + 3) / 4 * 4 * M * 4;
     // sorted geometry: key, perm, skey, invperm, cell, normals, weights, taps (FP64 + FP32)
     b += M * (16 + 12 + 24 + 8 + 96 + 48);
     // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
@@ -367,9 +369,11 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     // Krylov state: basis, five pools, two banks of block partial sums, Hessenberg and rotations
     const size_t nblk = (M + 255) / 256;
     b += R * ((m + 1) * M * 8 + 5 * M * 8 + 2 * nblk * (m + 2) * 8 + (m * (m + 1) + 4 * m + 3 * (m + 2)) * 8 + 64);
-    // allocation granularity
+    // allocation granularity: small buffers, and the device's 2 MiB pages (one more
+    // page for buffers that straddle them)
     b += 96 * 4096;
-    return b;
+    const size_t page = (size_t)2 << 20;
+    return (b + page - 1) / page * page + page;
 }
 
 ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, void* stream) {

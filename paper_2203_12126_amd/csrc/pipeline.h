@@ -167,6 +167,8 @@ struct CsrView {
     const R* w;
     uint32_t nnz;        // entries of k and w (nnz * sizeof(double) < 2^31)
     const double* q;     // q + rhs * q_stride + it * q_jstride: strengths of one right-hand side
+    const float* qf;     // or null: the same strengths as FP32, [rhs / 4][M][rhs % 4] (FP32 passes)
+    int M;
     size_t q_stride;
     size_t q_jstride;    // offset per iteration index (Krylov basis vectors), else 0
     double coef;
@@ -262,6 +264,34 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
         BODY(a0, (int)blockIdx.x, it_);                               \
     }
 
+// ------------------------------------------------------------ strength packing
+// qf[g][k][rr] = (float) q[(4g + rr) * q_stride + it * q_jstride + k], 0 past nrhs:
+// the four right-hand sides of a group sit in one 16-byte segment, so the spread's
+// adjacent lanes of one node (its right-hand sides) read one cache line per entry
+struct PackArgs {
+    const double* q;
+    size_t q_stride, q_jstride;
+    int M, nrhs;
+    int nkb;  // blocks of 256 points per group
+    float* qf;
+};
+__device__ __forceinline__ void pack_body(const PackArgs& a, int lb, int it) {
+    const int g = lb / a.nkb;
+    const int k = (lb % a.nkb) * 256 + (int)threadIdx.x;
+    if (k >= a.M) return;
+    float v[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int r = 4 * g + rr;
+        v[rr] = r < a.nrhs ? (float)a.q[(size_t)r * a.q_stride + (size_t)it * a.q_jstride + k] : 0.0f;
+    }
+    reinterpret_cast<float4*>(a.qf)[(size_t)g * a.M + k] = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_pack(PackArgs a0, Jobs<PackArgs> js, int it) {
+    IBDL_JOB_ENTRY(pack_body, PackArgs, a0, js, it)
+}
+
 // ------------------------------------------------------------ spread phase
 // Adds coef * (sum_e w_e q[k_e]) into the LDS lines for every active node of
 // the block's lines, for each of the block's right-hand sides (rhs_s[rr] >= 0):
@@ -288,6 +318,12 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
         const int a = la[g] + (nf - rs[g]);
         const int x = (int)(c.act_node[a] % (uint32_t)N);
         const double* q = c.q + (size_t)r * c.q_stride + (size_t)it * c.q_jstride;
+        // packed FP32 strengths (the same values the FP32 sum rounds q to): the lanes
+        // of a node's right-hand sides read one 16-byte segment per entry
+        const float* qf = nullptr;
+        if constexpr (sizeof(R) == 4) {
+            if (c.qf) qf = c.qf + (size_t)(r >> 2) * c.M * 4 + (r & 3);
+        }
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
         // entries in groups of 8 through buffer descriptors over k and w (one offset per
@@ -302,17 +338,22 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
             const int cnt = e1 - e;
             uint32_t kk[8];
             R ww[8];
-            double qq[8];
+            R qq[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 kk[u] = __builtin_amdgcn_raw_buffer_load_b32(rk, e * 4 + u * 4, 0, 0);
                 const R wv = BufScalar<R>::load(rw, e * (int)sizeof(R) + u * (int)sizeof(R));
                 ww[u] = u < cnt ? wv : R(0);
             }
+            if (qf) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) qq[u] = q[kk[u]];
+                for (int u = 0; u < 8; ++u) qq[u] = (R)qf[(size_t)kk[u] * 4];
+            } else {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc.add(ww[u], (R)qq[u]);
+                for (int u = 0; u < 8; ++u) qq[u] = (R)q[kk[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc.add(ww[u], qq[u]);
         }
         sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
     }
@@ -1096,8 +1137,10 @@ struct PreparedT : PreparedPass {
     StageTable<ColArgs<R>> col[3];
     StageTable<RowInvArgs<R>> ri[kRowVars];
     StageTable<FinishArgs> fi;
+    StageTable<PackArgs> pk;  // FP32 strengths of the pass, packed before the forward rows
 
     void upload(Arena& ar, hipStream_t st) override {
+        pk.upload(ar, st);
         for (auto& t : rf) t.upload(ar, st);
         for (auto& c : col) c.upload(ar, st);
         for (auto& t : ri) t.upload(ar, st);
@@ -1180,6 +1223,10 @@ struct PreparedT : PreparedPass {
     }
     void run(int it, hipStream_t st) override {
         int stage = 0;
+        go(pk, [&](bool m) {
+            if (m) hipLaunchKernelGGL(k_pack<true>, dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
+            else hipLaunchKernelGGL(k_pack<false>, dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
+        });
         {
             const int v = pick(0, it, st, [&](int c, StageEv e) { fwd(c, it, st, e); });
             const StageEv e = stage_events(tplan, stage++, "spread+fft_x");
@@ -1285,9 +1332,30 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             v.nnz = (uint32_t)c.nnz;
             v.q = q;
             v.coef = coef;
+            v.M = p->M;
             return v;
         };
         ra.dip = view(p->dip, in.q_dip, in.c_dip);
+        // packing costs a launch per pass: it pays where a block serves several
+        // right-hand sides of a large spread (measured: sphere 256^3 at 32 rhs 6.5%
+        // faster, star 1024^2 at 32 rhs 1.4%; at 1 rhs and in the batch of small
+        // instances the extra launch made solves 2-4% slower)
+        constexpr int64_t kPackMinWork = (int64_t)1 << 21;  // spread entries x right-hand sides
+        if constexpr (sizeof(R) == 4) {
+            if (in.pack_f32 && in.q_dip && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
+                if (!p->ws.qf) throw Error{IBDL_ERR_HIP, "packed strengths requested without their workspace"};
+                PackArgs pa{};
+                pa.q = in.q_dip;
+                pa.q_stride = ra.dip.q_stride;
+                pa.q_jstride = in.q_jstride;
+                pa.M = p->M;
+                pa.nrhs = nrhs;
+                pa.nkb = (p->M + 255) / 256;
+                pa.qf = reinterpret_cast<float*>(p->ws.qf);
+                P->pk.add(pa, pa.nkb * ((nrhs + 3) / 4));
+                ra.dip.qf = pa.qf;
+            }
+        }
         ra.mono = view(p->mono, in.q_mono, in.c_mono);
         ra.grid = in.grid;
         ra.cg = in.c_grid;

@@ -693,15 +693,16 @@ void ensure_workspace(ibdl_plan p, int nrhs) {
     // grow: the old buffers are freed in stream order after the work already queued
     // on the plan's stream (a switch of stream waits for the old one first)
     if (p->ws.spec && p->last_stream != alloc_stream()) IBDL_HIP_TRY(hipStreamSynchronize(p->last_stream));
-    for (void* old : {p->ws.spec, p->ws.part}) {
+    for (void* old : {p->ws.spec, p->ws.part, p->ws.qf}) {
         if (!old) continue;
         p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), old), p->allocs.end());
         dev_free(old);
     }
-    p->ws.spec = p->ws.part = nullptr;
+    p->ws.spec = p->ws.part = p->ws.qf = nullptr;
     p->ws.cap_rhs = 0;
     p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
     p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);
+    if (p->prec == IBDL_PREC_MIXED) p->ws.qf = dev_alloc(p, (size_t)((nrhs + 3) / 4) * 4 * p->M * sizeof(float));
     p->ws.cap_rhs = nrhs;
 }
 
