@@ -356,20 +356,30 @@ __global__ void k_line_start(const uint32_t* __restrict__ skey, int M, int n, in
 // Stencil offsets r in -2..3 (dipole) or -1..2 (monopole) per axis; the dipole
 // keeps the nodes where at most one axis offset lies outside -1..2 (elsewhere
 // every term of div(S q n) vanishes).
-__device__ __forceinline__ int dip_offsets(int j, int dim, int* r) {
-    // enumerate 6^dim boxes and keep the structurally nonzero ones in order
-    int cnt = -1;
+// Offsets of the dipole stencil's nodes from a point's cell, in order: the boxes of
+// 6^dim around it whose weight is structurally nonzero (at most one axis outside
+// -1..2, where the centred difference reaches one node further): 32 in 2-D, 160 in 3-D
+struct DipStencil {
+    int8_t o[160][3];
+};
+constexpr DipStencil dip_stencil(int dim) {
+    DipStencil t{};
+    int cnt = 0;
     const int tot = dim == 2 ? 36 : 216;
     for (int b = 0; b < tot; ++b) {
-        int o[3] = {b % 6 - 2, (b / 6) % 6 - 2, dim == 3 ? b / 36 - 2 : 0};
-        int outside = 0;
-        for (int d = 0; d < dim; ++d) outside += (o[d] < -1 || o[d] > 2);
+        const int o0 = b % 6 - 2, o1 = (b / 6) % 6 - 2, o2 = dim == 3 ? b / 36 - 2 : 0;
+        const int outside = (o0 < -1 || o0 > 2) + (o1 < -1 || o1 > 2) + (o2 < -1 || o2 > 2);
         if (outside <= 1) {
-            if (++cnt == j) { r[0] = o[0]; r[1] = o[1]; r[2] = o[2]; return 1; }
+            t.o[cnt][0] = (int8_t)o0;
+            t.o[cnt][1] = (int8_t)o1;
+            t.o[cnt][2] = (int8_t)o2;
+            ++cnt;
         }
     }
-    return 0;
+    return t;
 }
+__constant__ DipStencil kDip2 = dip_stencil(2);
+__constant__ DipStencil kDip3 = dip_stencil(3);
 
 __global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
                        int M, int dim, int n, int dipole, int npp, uint64_t* out) {
@@ -379,7 +389,10 @@ __global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __res
     const int s = id / npp, j = id - s * npp;
     int r[3] = {0, 0, 0};
     if (dipole) {
-        dip_offsets(j, dim, r);
+        const int8_t* o = dim == 2 ? kDip2.o[j] : kDip3.o[j];
+        r[0] = o[0];
+        r[1] = o[1];
+        r[2] = o[2];
     } else {
         r[0] = j % 4 - 1;
         r[1] = (j / 4) % 4 - 1;
@@ -387,7 +400,10 @@ __global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __res
     }
     uint32_t node = 0, stride = 1;
     for (int d = 0; d < dim; ++d) {
-        const int c = (cell_s[3 * s + d] + r[d] + n) % n;
+        // cell in [0, n), offset in -2..3, n >= 8: one periodic wrap at most
+        int c = cell_s[3 * s + d] + r[d];
+        c += c < 0 ? n : 0;
+        c -= c >= n ? n : 0;
         node += (uint32_t)c * stride;
         stride *= (uint32_t)n;
     }
