@@ -232,6 +232,34 @@ __global__ void k_bitonic_global(uint64_t* a, size_t npairs, size_t k, size_t j)
     bit_cmpx(a, lo, hi, (lo & k) == 0);
 }
 
+// steps j and j/2 of stage k together (j/2 >= BIT_BLOCK): thread t owns the four
+// elements i0 | {0, h, j, j + h} (h = j/2, i0 with bits j and h clear), all in the
+// same direction (k > j), and does step j's two compare-exchanges and then step
+// j/2's two on them: half the passes over the array
+__global__ void k_bitonic_global2(uint64_t* a, size_t nquads, size_t k, size_t j) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nquads) return;
+    const size_t h = j >> 1;
+    const size_t i0 = ((t & ~(h - 1)) << 2) | (t & (h - 1));
+    const bool asc = (i0 & k) == 0;
+    uint64_t v0 = a[i0], v1 = a[i0 | h], v2 = a[i0 | j], v3 = a[i0 | j | h];
+    auto cx = [asc](uint64_t& x, uint64_t& y) {
+        if ((x > y) == asc) {
+            const uint64_t tmp = x;
+            x = y;
+            y = tmp;
+        }
+    };
+    cx(v0, v2);
+    cx(v1, v3);
+    cx(v0, v1);
+    cx(v2, v3);
+    a[i0] = v0;
+    a[i0 | h] = v1;
+    a[i0 | j] = v2;
+    a[i0 | j | h] = v3;
+}
+
 static size_t pow2_at_least(size_t n, size_t minv) {
     size_t p = minv;
     while (p < n) p <<= 1;
@@ -243,7 +271,11 @@ static void bitonic_sort(uint64_t* a, size_t n2, hipStream_t st) {
     const int nb = (int)(n2 / BIT_BLOCK);
     hipLaunchKernelGGL(k_bitonic_local_sort, dim3(nb), dim3(BIT_T), 0, st, a);
     for (size_t k = 2 * BIT_BLOCK; k <= n2; k <<= 1) {
-        for (size_t j = k >> 1; j >= (size_t)BIT_BLOCK; j >>= 1)
+        size_t j = k >> 1;
+        for (; j >= 2 * (size_t)BIT_BLOCK; j >>= 2)
+            hipLaunchKernelGGL(k_bitonic_global2, dim3(nblocks(n2 / 4, 256)), dim3(256), 0, st, a,
+                               n2 / 4, k, j);
+        if (j >= (size_t)BIT_BLOCK)
             hipLaunchKernelGGL(k_bitonic_global, dim3(nblocks(n2 / 2, 256)), dim3(256), 0, st, a,
                                n2 / 2, k, j);
         hipLaunchKernelGGL(k_bitonic_local_merge, dim3(nb), dim3(BIT_T), 0, st, a, k);
