@@ -93,6 +93,18 @@ def test_plan_solve_graph_equals_eager(case):
     pl.close()
 
 
+def test_packed_strengths_graph_equals_eager():
+    """Sixteen right-hand sides on the star 1024^2 plan: the recorded Arnoldi step
+    includes the packing of its strengths as FP32 (step index read on the device)."""
+    p = W.config_star1024(m=4096, alpha=2.0, seed=13)
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    rng = np.random.default_rng(17)
+    data = T(np.stack([p.data + 0.05 * r * rng.standard_normal(p.data.shape) for r in range(16)]))
+    g = T(np.stack([p.g_tilde] * 16))
+    compare_graph_eager(lambda: pl.solve(data, g, tol=1e-10, restart=12, maxit=400))
+    pl.close()
+
+
 def test_batch_solve_graph_equals_eager():
     items = []
     for sp in W.config_batch(count=5, seed=31, sizes=(64, 96, 128)):
