@@ -202,14 +202,49 @@ __device__ __forceinline__ void bit_step(uint64_t* s, size_t base, size_t k, int
     __syncthreads();
 }
 
+// Steps with j < BIT_GROUP pair elements of one aligned group of BIT_GROUP: each
+// thread holds the group 8t..8t+7 in registers for them (one LDS round trip and one
+// barrier for up to three steps), stages k from kmin to kmax with steps j < 8 of each
+constexpr int BIT_GROUP = BIT_BLOCK / BIT_T;  // 8
+static_assert(BIT_GROUP == 8, "register steps assume groups of eight");
+__device__ __forceinline__ void bit_group_steps(uint64_t* s, size_t base, int kmin, int kmax, bool fixed_dir,
+                                                bool asc_all) {
+    const int g0 = (int)threadIdx.x * BIT_GROUP;
+    uint64_t v[BIT_GROUP];
+#pragma unroll
+    for (int i = 0; i < BIT_GROUP; ++i) v[i] = s[g0 + i];
+    for (int k = kmin; k <= kmax; k <<= 1) {
+#pragma unroll
+        for (int j = 4; j > 0; j >>= 1) {
+            if (j >= k) continue;  // stage k has steps j = k/2 .. 1
+#pragma unroll
+            for (int i = 0; i < BIT_GROUP; ++i) {
+                if (i & j) continue;
+                const bool asc = fixed_dir ? asc_all : (((base + g0 + i) & (size_t)k) == 0);
+                if ((v[i] > v[i | j]) == asc) {
+                    const uint64_t t = v[i];
+                    v[i] = v[i | j];
+                    v[i | j] = t;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BIT_GROUP; ++i) s[g0 + i] = v[i];
+    __syncthreads();
+}
+
 // all stages with k <= BIT_BLOCK inside each block
 __global__ __launch_bounds__(BIT_T) void k_bitonic_local_sort(uint64_t* a) {
     __shared__ uint64_t s[BIT_BLOCK];
     const size_t base = (size_t)blockIdx.x * BIT_BLOCK;
     bit_load(s, a, base);
     __syncthreads();
-    for (int k = 2; k <= BIT_BLOCK; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) bit_step(s, base, (size_t)k, j, false, true);
+    bit_group_steps(s, base, 2, BIT_GROUP, false, true);  // stages k = 2, 4, 8 entirely
+    for (int k = 2 * BIT_GROUP; k <= BIT_BLOCK; k <<= 1) {
+        for (int j = k >> 1; j >= BIT_GROUP; j >>= 1) bit_step(s, base, (size_t)k, j, false, true);
+        bit_group_steps(s, base, k, k, false, true);
+    }
     bit_store(s, a, base);
 }
 
@@ -220,7 +255,9 @@ __global__ __launch_bounds__(BIT_T) void k_bitonic_local_merge(uint64_t* a, size
     bit_load(s, a, base);
     __syncthreads();
     const bool asc = ((base & k) == 0);
-    for (int j = BIT_BLOCK >> 1; j > 0; j >>= 1) bit_step(s, base, k, j, true, asc);
+    for (int j = BIT_BLOCK >> 1; j >= BIT_GROUP; j >>= 1) bit_step(s, base, k, j, true, asc);
+    // the group steps only need j < 8 (any stage value >= 8 gives all three)
+    bit_group_steps(s, base, 2 * BIT_GROUP, 2 * BIT_GROUP, true, asc);
     bit_store(s, a, base);
 }
 
