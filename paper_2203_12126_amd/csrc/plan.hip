@@ -375,6 +375,15 @@ static int32_t read_i32(const int32_t* d, hipStream_t st) {
     return v;
 }
 
+__global__ void k_sum2(const int32_t* a, const int32_t* b, int32_t* out) { *out = *a + *b; }
+
+// a count from an exclusive scan: its last entry plus the last flag, read with one wait
+static int32_t read_count(ibdl_plan p, const int32_t* scan_last, const int32_t* flag_last, hipStream_t st) {
+    int32_t* d = tmp_n<int32_t>(p, 1);
+    hipLaunchKernelGGL(k_sum2, dim3(1), dim3(1), 0, st, scan_last, flag_last, d);
+    return read_i32(d, st);
+}
+
 // ------------------------------------------------------------------ sorted geometry
 __global__ void k_unpack(const uint64_t* __restrict__ srt, int M, uint32_t* perm, uint32_t* skey,
                          uint32_t* invperm) {
@@ -635,7 +644,7 @@ __global__ void k_symtab(int n, int C, int W, size_t total, const double* __rest
 static int compact(ibdl_plan p, const int32_t* flag, int n, int32_t** list, hipStream_t st) {
     int32_t* idx = tmp_n<int32_t>(p, (size_t)n + 1);
     scan_excl(p, flag, idx, (size_t)n, st);
-    const int cnt = read_i32(idx + n - 1, st) + read_i32(flag + n - 1, st);
+    const int cnt = read_count(p, idx + n - 1, flag + n - 1, st);
     *list = alloc_n<int32_t>(p, (size_t)std::max(cnt, 1));
     hipLaunchKernelGGL(k_compact_list, dim3(nblocks(n, 256)), dim3(256), 0, st, flag, idx, n, *list);
     return cnt;
@@ -663,7 +672,7 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
                        p->cell, p->taps64, p->nrm, p->wgt, dim, n, p->h, dipole ? 1 : 0, c.k, c.w64,
                        c.w32, head);
     scan_excl(p, head, idx, nnz, st);
-    c.nact = read_i32(idx + nnz - 1, st) + read_i32(head + nnz - 1, st);
+    c.nact = read_count(p, idx + nnz - 1, head + nnz - 1, st);
     c.act_node = alloc_n<uint32_t>(p, (size_t)c.nact);
     c.act_ptr = alloc_n<int32_t>(p, (size_t)c.nact + 1);
     hipLaunchKernelGGL(k_compact_heads, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, head, idx,
