@@ -826,7 +826,7 @@ void SolveTask::prepare_op() {
         pi.q_stride = vs;
         pi.q_jstride = M;
         pi.skip = k.state + 4 * in.r0;
-        pi.pack_f32 = true;
+        pi.pack_q = true;
         PipeOut po;
         po.out = k.V + vb + M;
         po.out_stride = vs;

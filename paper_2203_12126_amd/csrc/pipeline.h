@@ -167,7 +167,7 @@ struct CsrView {
     const R* w;
     uint32_t nnz;        // entries of k and w (nnz * sizeof(double) < 2^31)
     const double* q;     // q + rhs * q_stride + it * q_jstride: strengths of one right-hand side
-    const float* qf;     // or null: the same strengths as FP32, [rhs / 4][M][rhs % 4] (FP32 passes)
+    const R* qf;         // or null: the same strengths in R, [rhs / 4][M][rhs % 4]
     int M;
     size_t q_stride;
     size_t q_jstride;    // offset per iteration index (Krylov basis vectors), else 0
@@ -265,31 +265,33 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     }
 
 // ------------------------------------------------------------ strength packing
-// qf[g][k][rr] = (float) q[(4g + rr) * q_stride + it * q_jstride + k], 0 past nrhs:
-// the four right-hand sides of a group sit in one 16-byte segment, so the spread's
-// adjacent lanes of one node (its right-hand sides) read one cache line per entry
+// qf[g][k][rr] = (R) q[(4g + rr) * q_stride + it * q_jstride + k], 0 past nrhs:
+// the four right-hand sides of a group sit in one 16- (FP32) or 32-byte (FP64)
+// segment, so the spread's adjacent lanes of one node (its right-hand sides) read
+// one cache line per entry
+template <typename R>
 struct PackArgs {
     const double* q;
     size_t q_stride, q_jstride;
     int M, nrhs;
     int nkb;  // blocks of 256 points per group
-    float* qf;
+    R* qf;
 };
-__device__ __forceinline__ void pack_body(const PackArgs& a, int lb, int it) {
+template <typename R>
+__device__ __forceinline__ void pack_body(const PackArgs<R>& a, int lb, int it) {
     const int g = lb / a.nkb;
     const int k = (lb % a.nkb) * 256 + (int)threadIdx.x;
     if (k >= a.M) return;
-    float v[4];
+    R* out = a.qf + ((size_t)g * a.M + k) * 4;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int r = 4 * g + rr;
-        v[rr] = r < a.nrhs ? (float)a.q[(size_t)r * a.q_stride + (size_t)it * a.q_jstride + k] : 0.0f;
+        out[rr] = r < a.nrhs ? (R)a.q[(size_t)r * a.q_stride + (size_t)it * a.q_jstride + k] : R(0);
     }
-    reinterpret_cast<float4*>(a.qf)[(size_t)g * a.M + k] = make_float4(v[0], v[1], v[2], v[3]);
 }
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_pack(PackArgs a0, Jobs<PackArgs> js, int it) {
-    IBDL_JOB_ENTRY(pack_body, PackArgs, a0, js, it)
+template <typename R, bool MULTI>
+__global__ __launch_bounds__(256) void k_pack(PackArgs<R> a0, Jobs<PackArgs<R>> js, int it) {
+    IBDL_JOB_ENTRY(pack_body<R>, PackArgs<R>, a0, js, it)
 }
 
 // ------------------------------------------------------------ spread phase
@@ -318,12 +320,9 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
         const int a = la[g] + (nf - rs[g]);
         const int x = (int)(c.act_node[a] % (uint32_t)N);
         const double* q = c.q + (size_t)r * c.q_stride + (size_t)it * c.q_jstride;
-        // packed FP32 strengths (the same values the FP32 sum rounds q to): the lanes
-        // of a node's right-hand sides read one 16-byte segment per entry
-        const float* qf = nullptr;
-        if constexpr (sizeof(R) == 4) {
-            if (c.qf) qf = c.qf + (size_t)(r >> 2) * c.M * 4 + (r & 3);
-        }
+        // packed strengths (the same values the sum rounds q to): the lanes of a
+        // node's right-hand sides read one segment per entry
+        const R* qf = c.qf ? c.qf + (size_t)(r >> 2) * c.M * 4 + (r & 3) : nullptr;
         Acc<R> acc;
         const int e1 = c.act_ptr[a + 1];
         // entries in groups of 8 through buffer descriptors over k and w (one offset per
@@ -1137,7 +1136,7 @@ struct PreparedT : PreparedPass {
     StageTable<ColArgs<R>> col[3];
     StageTable<RowInvArgs<R>> ri[kRowVars];
     StageTable<FinishArgs> fi;
-    StageTable<PackArgs> pk;  // FP32 strengths of the pass, packed before the forward rows
+    StageTable<PackArgs<R>> pk;  // strengths of the pass, packed before the forward rows
 
     void upload(Arena& ar, hipStream_t st) override {
         pk.upload(ar, st);
@@ -1224,8 +1223,8 @@ struct PreparedT : PreparedPass {
     void run(int it, hipStream_t st) override {
         int stage = 0;
         go(pk, [&](bool m) {
-            if (m) hipLaunchKernelGGL(k_pack<true>, dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
-            else hipLaunchKernelGGL(k_pack<false>, dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
+            if (m) hipLaunchKernelGGL((k_pack<R, true>), dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
+            else hipLaunchKernelGGL((k_pack<R, false>), dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
         });
         {
             const int v = pick(0, it, st, [&](int c, StageEv e) { fwd(c, it, st, e); });
@@ -1341,20 +1340,21 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         // faster, star 1024^2 at 32 rhs 1.4%; at 1 rhs and in the batch of small
         // instances the extra launch made solves 2-4% slower)
         constexpr int64_t kPackMinWork = (int64_t)1 << 21;  // spread entries x right-hand sides
-        if constexpr (sizeof(R) == 4) {
-            if (in.pack_f32 && in.q_dip && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
-                if (!p->ws.qf) throw Error{IBDL_ERR_HIP, "packed strengths requested without their workspace"};
-                PackArgs pa{};
-                pa.q = in.q_dip;
-                pa.q_stride = ra.dip.q_stride;
-                pa.q_jstride = in.q_jstride;
-                pa.M = p->M;
-                pa.nrhs = nrhs;
-                pa.nkb = (p->M + 255) / 256;
-                pa.qf = reinterpret_cast<float*>(p->ws.qf);
-                P->pk.add(pa, pa.nkb * ((nrhs + 3) / 4));
-                ra.dip.qf = pa.qf;
-            }
+        // FP32 only: FP64 packing was measured to gain nothing (star 1024^2 and sphere
+        // 256^3 FP64 solves at 32 rhs unchanged), and mixed plans alone hold ws.qf
+        const bool fp32_mixed = sizeof(R) == 4 && p->prec == IBDL_PREC_MIXED;
+        if (in.pack_q && in.q_dip && fp32_mixed && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
+            if (!p->ws.qf) throw Error{IBDL_ERR_HIP, "packed strengths requested without their workspace"};
+            PackArgs<R> pa{};
+            pa.q = in.q_dip;
+            pa.q_stride = ra.dip.q_stride;
+            pa.q_jstride = in.q_jstride;
+            pa.M = p->M;
+            pa.nrhs = nrhs;
+            pa.nkb = (p->M + 255) / 256;
+            pa.qf = reinterpret_cast<R*>(p->ws.qf);
+            P->pk.add(pa, pa.nkb * ((nrhs + 3) / 4));
+            ra.dip.qf = pa.qf;
         }
         ra.mono = view(p->mono, in.q_mono, in.c_mono);
         ra.grid = in.grid;

@@ -29,7 +29,7 @@ struct Workspace {
     int cap_rhs = 0;
     void* spec = nullptr;       // [cap][nlines*P] complex
     void* part = nullptr;       // [cap][M][4^(dim-1)] gather partial sums
-    void* qf = nullptr;         // [ceil(cap/4)][M][4] FP32 strengths of the Arnoldi step's pass
+    void* qf = nullptr;         // mixed plans: [ceil(cap/4)][M][4] FP32 strengths of the Arnoldi step
 };
 
 // Staging of per-job argument tables: pinned host blocks with device twins.
@@ -217,9 +217,9 @@ struct PipeIn {
     size_t q_stride = 0;             // distance between right-hand sides of q_dip/q_mono (0: M)
     size_t q_jstride = 0;            // added per iteration index (Krylov basis)
     const int32_t* skip = nullptr;   // per-rhs flags (stride 4): set -> the rhs is not processed
-    // FP32 passes: q_dip is first copied as FP32 into the plan's workspace in groups
-    // of four right-hand sides (ws.qf), which the spread reads instead
-    bool pack_f32 = false;
+    // q_dip is first copied in the pass's precision into the plan's workspace in
+    // groups of four right-hand sides (ws.qf), which the spread reads instead
+    bool pack_q = false;
 };
 struct PipeOut {
     // gather: out[k] = cA * (S* u)_k + cB * in[k] + cC * in2[k]   (strides 0: M)

@@ -148,17 +148,19 @@ def test_solve_grid_mixed_tol_near_first_stage(bc):
     pl.close()
 
 
-def test_packed_strengths_change_nothing():
+@pytest.mark.parametrize("prec", [ibdl.MIXED, ibdl.FP64])
+def test_packed_strengths_change_nothing(prec):
     """A mixed solve of 16 right-hand sides on the star 1024^2 plan takes the
     Arnoldi step's spread through strengths packed as FP32 in groups of four; the
-    same right-hand sides solved two at a time read them directly.  Solutions,
-    grid solutions and iteration counts are bit-identical."""
+    same right-hand sides solved two at a time read them directly (FP64 solves
+    read them directly either way).  Solutions, grid solutions and iteration
+    counts are bit-identical."""
     p = W.config_star1024(m=4096, alpha=1.0, seed=31)
     rng = np.random.default_rng(5)
     R = 16
     data = np.stack([p.data * (1.0 + 0.1 * r) + 0.01 * rng.standard_normal(p.geom.m) for r in range(R)])
     g = np.stack([p.g_tilde * (1.0 - 0.05 * r) for r in range(R)])
-    pl = ibdl.Plan.from_problem(p, prec=ibdl.MIXED)
+    pl = ibdl.Plan.from_problem(p, prec=prec)
     sol, u, info = pl.solve_grid(T(data), T(g), tol=1e-8)
     for r0 in range(0, R, 2):
         s2, u2, i2 = pl.solve_grid(T(data[r0:r0 + 2]), T(g[r0:r0 + 2]), tol=1e-8)
