@@ -1,38 +1,45 @@
 """Benchmark of the IBDL hot path on one MI355X.
 
-A step is one complete IBDL solve of a batch of right-hand sides (32 by
-default: enough column tiles to give every compute unit eight blocks) on the 2-D
-star workload (periodic unit square, 1024^2 grid, star r = 0.3 + 0.05 cos 5t
-with 4096 boundary points, alpha = 1, Dirichlet, random-Fourier manufactured
-data): the right-hand side, unpreconditioned GMRES on the device to tol 1e-8,
-and the grid solution.  The geometry's plan (binning, sort, spread matrices) is
-built once before timing.  Inputs are resident on the GPU.
+Default workload (sphere256): the 3-D Dirichlet problem on a periodic unit cube
+with a 256^3 grid, a sphere R = 0.3 with 40000 Fibonacci-lattice points, alpha =
+10 and 32 distinct manufactured right-hand sides (harmonic u = exp(k.x)
+cos(l.x + phase), forcing g = -alpha u inside the sphere).  A step is one
+complete IBDL solve of all of them: the right-hand side, unpreconditioned GMRES
+on the device to tol 1e-8, and the grid solution.  The geometry's plan
+(binning, sort, spread matrices) is built once before timing.  Inputs are
+resident on the GPU.
 
-value = operator applications per second over the timed steps (every GMRES
+value = operator applications per second of the FP64 path (every GMRES
 iteration of every right-hand side counts one application; the time includes
-the right-hand side, the Krylov arithmetic and the grid solution).  The line
-also reports solves/s, per-step latency percentiles, the FP64 path, the error
-of both against the FP64 oracle, the roofline of the dominant kernel (timed with
-HIP events on the library's stream) and the oracle's own throughput on the
-host.
+the right-hand side, the Krylov arithmetic and the grid solution).  Beside it
+the line reports the mixed path (FP32 grid, FP64 Krylov with FP64 refinement):
+applies/s, solves/s and latency percentiles; the error of both against FP64
+oracle solves of the same right-hand sides; the HBM roofline of the dominant
+kernel and of the whole operator (timed with HIP events on the library's
+stream); and the oracle's own throughput on the host, on one thread and on all
+cores.
 
-With --workload serve the line reports the served stream instead: 2000
-requests (80% 2-D, 20% 3-D, sizes 256^2..2048^2 and 64^3..256^3, alpha
-log-uniform in [1, 1000], mixed precision, grid solution included) cycling
-through a set of materialised request templates; first the saturation
-throughput with a bounded number of requests outstanding, then seeded Poisson
-arrivals at 0.5x and 0.8x of it, with p50/p99 of submission-to-result latency.
+--workload star1024: the 2-D star workload (1024^2 grid, star r = 0.3 + 0.05
+cos 5t with 4096 points, alpha = 1, random-Fourier manufactured data) in the
+same form.
 
-With --workload batch512 a step is one batched solve of the 512-instance
-ellipse batch (grid sizes 128..512, 2..8 right-hand sides each, Dirichlet and
-Neumann, alpha log-uniform in [1, 1000], mixed precision) followed by the grid
-solutions of every instance; the roofline is that of one batched operator
-application over all instances.
+--workload serve: the served stream: 2000 requests (80% 2-D, 20% 3-D, sizes
+256^2..2048^2 and 64^3..256^3, alpha log-uniform in [1, 1000], mixed
+precision, grid solution included) cycling through a set of materialised
+request templates; first the saturation throughput with a bounded number of
+requests outstanding, then seeded Poisson arrivals at 0.5x and 0.8x of it, with
+p50/p99 of submission-to-result latency.
+
+--workload batch512: a step is one batched solve of the 512-instance ellipse
+batch (grid sizes 128..512, 2..8 right-hand sides each, Dirichlet and Neumann,
+alpha log-uniform in [1, 1000], mixed precision) followed by the grid solutions
+of every instance.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs R]
-                       [--workload star1024|sphere256|batch512|serve]
+                       [--workload sphere256|star1024|batch512|serve]
 """
 import argparse
+import glob
 import json
 import math
 import os
@@ -46,11 +53,48 @@ sys.path.insert(0, ROOT)
 
 METRIC = "IBDL operator applies/s + batched solves/s at 1e-6 rel err; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+ROOF_APPLIES = 20
+KERNEL_SOURCES = ["paper_2203_12126_amd/csrc/pipeline.h", "paper_2203_12126_amd/csrc/fft.h",
+                  "paper_2203_12126_amd/csrc/common.h"]
+CPU_WORKERS_MAX = 16  # the host share of one GPU
 
 
-def stage_bytes(st, dim, n, m, prec, nrhs):
-    """Algorithmic bytes per call of each grid stage for this geometry: every
-    necessary read and write counted once (see the design notes)."""
+def half_spectrum_bytes(dim, n, prec):
+    """H = n^(d-1) (n/2+1) complex values of the pass's precision."""
+    b = 8 if prec == 0 else 4
+    return n ** (dim - 1) * (n // 2 + 1) * 2 * b
+
+
+def operator_bytes(dim, n, m, prec):
+    """Algorithmic bytes of one operator application (one right-hand side):
+    B = (4d-4) H + M (16 + 2 d b): every axis pass reads and writes the half
+    spectrum once, with the spread fused into the first pass and the
+    interpolation into the last, plus the point data."""
+    b = 8 if prec == 0 else 4
+    return (4 * dim - 4) * half_spectrum_bytes(dim, n, prec) + m * (16 + 2 * dim * b)
+
+
+def stage_share_bytes(dim, n, m, prec):
+    """B split over the stages of a pass (one right-hand side): the first and last
+    row passes write / read H, each column pass reads and writes H; the point
+    terms go to the stages that move them.  The shares sum to B."""
+    b = 8 if prec == 0 else 4
+    H = half_spectrum_bytes(dim, n, prec)
+    out = {"spread+fft_x": H + 8 * m}
+    if dim == 2:
+        out["fft_y+symbol"] = 2 * H
+    else:
+        out["fft_y"] = 2 * H
+        out["fft_z+symbol"] = 2 * H
+        out["ifft_y"] = 2 * H
+    out["ifft_x+interp"] = H + 2 * dim * b * m
+    out["finish"] = 8 * m
+    return out
+
+
+def stage_touched_bytes(st, dim, n, m, prec, nrhs):
+    """Bytes each stage must move for this geometry, per call: only the lines
+    that carry forcing or are read (the passes skip the rest)."""
     bc = 16 if prec == 0 else 8      # complex
     br = 8 if prec == 0 else 4       # real
     W = n // 2 + 1
@@ -58,8 +102,7 @@ def stage_bytes(st, dim, n, m, prec, nrhs):
     gpp = 4 if dim == 2 else 16
     csr = st["dip_nnz"] * (4 + br) + st["dip_active_nodes"] * 8 + (st["nlines"] + 1) * 4 + S * 4
     pts = m * (12 + 12 * br + 4)
-    out = {}
-    out["spread+fft_x"] = nrhs * (S * W * bc + m * 8) + csr
+    out = {"spread+fft_x": nrhs * (S * W * bc + m * 8) + csr}
     if dim == 2:
         out["fft_y+symbol"] = nrhs * (S + G) * W * bc
     else:
@@ -72,69 +115,43 @@ def stage_bytes(st, dim, n, m, prec, nrhs):
     return out
 
 
-def stage_flops(dim, n, nrhs):
-    """Algorithmic floating-point operations per call of the 2-D column stage
-    (every column k_x = 0..n/2 of every right-hand side: forward and inverse
-    length-n complex FFT at the conventional 5 n log2 n each, and the real
-    symbol scaling, 2 per element).  The row stages' FFTs run only over the
-    lines that carry forcing or are read, and are not counted here."""
-    if dim != 2:
-        return {}
-    W = n // 2 + 1
-    return {"fft_y+symbol": nrhs * W * (10 * n * math.log2(n) + 2 * n)}
-
-
-# FP32 vector peak of MI355X (256 CUs x 2.4 GHz x 128 lanes x 2 per FMA)
-ALU_PEAK_TFLOPS = 157.3
-ROOF_APPLIES = 50
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "star1024_nrhs32_traffic.md")
-KERNEL_SOURCES = ["paper_2203_12126_amd/csrc/pipeline.h", "paper_2203_12126_amd/csrc/fft.h",
-                  "paper_2203_12126_amd/csrc/common.h"]
-
-
-def stage_kernel(stage, dim, n):
-    """Kernel (FP32 instantiation) behind a stage name of a mixed 2-D apply."""
-    if dim != 2:
-        return stage
-    return {"spread+fft_x": f"k_row_fwd<float, {n}, false>",
-            "fft_y+symbol": f"k_col<float, {n}, 1, 1, false>",
-            "ifft_x+interp": f"k_row_inv<float, {n}, 0, false>",
-            "finish": "k_finish<float, false>"}.get(stage, stage)
+def stage_kernel(stage, dim, n, prec):
+    """Kernel template behind a stage name (the row variants are tuned per shape)."""
+    R = "double" if prec == 0 else "float"
+    names = {"spread+fft_x": f"k_row_fwd<{R}, {n}>", "ifft_x+interp": f"k_row_inv<{R}, {n}, 0>",
+             "finish": f"k_finish<{R}>"}
+    if dim == 2:
+        names["fft_y+symbol"] = f"k_col<{R}, {n}, 1, 1>"
+    else:
+        names["fft_y"] = f"k_col<{R}, {n}, 0, 1>"
+        names["fft_z+symbol"] = f"k_col<{R}, {n}, 1, K>"
+        names["ifft_y"] = f"k_col<{R}, {n}, 2, 1>"
+    return names.get(stage, stage)
 
 
 def kernel_sources_sha1():
     import hashlib
     h = hashlib.sha1()
-    root = os.path.dirname(os.path.abspath(__file__))
     for f in KERNEL_SOURCES:
-        with open(os.path.join(root, f), "rb") as fh:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def read_traffic(workload, nrhs, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary
-    is for another configuration or the kernel sources changed since."""
-    try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
-    except OSError:
-        return None
-    for ln in lines:
-        if not ln.startswith("traffic:"):
-            continue
-        kv = dict(x.strip().split("=", 1) for x in ln[len("traffic:"):].split(";") if "=" in x)
-        if (kv.get("workload") == workload and int(kv.get("nrhs", -1)) == nrhs and kv.get("kernel") == kernel
-                and kv.get("sources_sha1") == kernel_sources_sha1()):
-            return int(kv["bytes_per_launch"])
+    """HBM bytes per launch of a kernel from the committed counter summaries
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no summary covers
+    this configuration or the kernel sources changed since the counters ran."""
+    sha = kernel_sources_sha1()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        for ln in open(path).read().splitlines():
+            if not ln.startswith("traffic:"):
+                continue
+            kv = dict(x.strip().split("=", 1) for x in ln[len("traffic:"):].split(";") if "=" in x)
+            if (kv.get("workload") == workload and int(kv.get("nrhs", -1)) == nrhs and kv.get("kernel") == kernel
+                    and kv.get("sources_sha1") == sha):
+                return int(kv["bytes_per_launch"])
     return None
-
-
-def full_grid_bytes_per_apply(dim, n, m, prec):
-    """(4d-4) H + M (16 + 2 d b): the full-grid byte count of one apply."""
-    b = 8 if prec == 0 else 4
-    H = n ** (dim - 1) * (n // 2 + 1) * 2 * b
-    return (4 * dim - 4) * H + m * (16 + 2 * dim * b)
 
 
 def make_workload(name, nrhs):
@@ -142,26 +159,73 @@ def make_workload(name, nrhs):
     if name == "star1024":
         probs = [W.config_star1024(m=4096, alpha=1.0, bc=W.DIRICHLET, seed=2203 + r) for r in range(nrhs)]
         desc = ("2-D Dirichlet screened Poisson, periodic unit square, 1024^2 grid, star "
-                "r=0.3+0.05cos(5t) with 4096 points, alpha=1, random-Fourier manufactured data")
-        tol = 1e-8
+                "r=0.3+0.05cos(5t) with 4096 points, alpha=1, random-Fourier manufactured data "
+                "(one seed per right-hand side)")
     elif name == "sphere256":
-        probs = [W.config_sphere256()]
-        for r in range(1, nrhs):
-            probs.append(W.config_sphere256())
-        desc = ("3-D Dirichlet, periodic unit cube, 256^3 grid, sphere R=0.3 with 40000 Fibonacci "
-                "points, alpha=10, u=exp(x+y)cos(sqrt2 z-0.3)")
-        tol = 1e-8
+        probs = [W.config_sphere256(seed=r) for r in range(nrhs)]
+        desc = ("3-D Dirichlet screened Poisson, periodic unit cube, 256^3 grid, sphere R=0.3 with 40000 "
+                "Fibonacci points, alpha=10, harmonic manufactured u=exp(k.x)cos(l.x+phase) "
+                "(one seed per right-hand side)")
     else:
         raise SystemExit(f"unknown workload {name}")
-    return probs, desc, tol
+    return probs, desc, 1e-8
 
 
-def batch_stage_bytes(stats, metas):
+def workload_problem(name, r):
+    """Right-hand side r of a named workload (rebuilt in oracle worker processes)."""
+    from paper_2203_12126_amd import workloads as W
+    if name == "star1024":
+        return W.config_star1024(m=4096, alpha=1.0, bc=W.DIRICHLET, seed=2203 + r)
+    return W.config_sphere256(seed=r)
+
+
+def _oracle_solve_worker(name, r, tol):
+    """One FP64 oracle solve (right-hand side, GMRES, grid solution) on one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ibdl_oracle as O
+    p = workload_problem(name, r)
+    st = O.setup_from_problem(p)
+    with threadpool_limits(limits=1):
+        c0 = time.perf_counter()
+        res, _ = O.solve(st, p.data, p.g_tilde, tol=tol)
+        u = O.eval_grid(st, res.x, g_tilde=p.g_tilde)
+        el = time.perf_counter() - c0
+    # applies: GMRES iterations, plus the right-hand side and the grid solution passes
+    return r, res.iters, el, res.x, u
+
+
+def _oracle_apply_worker(name, seconds):
+    """Oracle operator applications on one thread for at least `seconds` (at least 2)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ibdl_oracle as O
+    from paper_2203_12126_amd import workloads as W
+    p = workload_problem(name, 0)
+    st = O.setup_from_problem(p)
+    q = W.random_density(p.geom.m, seed=1, nrhs=1)[0]
+    k = 0
+    with threadpool_limits(limits=1):
+        c0 = time.perf_counter()
+        while k < 2 or time.perf_counter() - c0 < seconds:
+            O.apply_A(st, q)
+            k += 1
+        el = time.perf_counter() - c0
+    return k, el
+
+
+def host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(CPU_WORKERS_MAX, n))
+
+
+def batch_stage_bytes(metas):
     """Algorithmic bytes of one batched mixed apply, per stage, summed over instances."""
     tot = {}
-    for st, mt in zip(stats, metas):
-        for k, v in stage_bytes(st, mt["dim"], mt["n"], mt["m"], 1, mt["nrhs"]).items():
-            tot[k] = tot.get(k, 0) + v
+    for mt in metas:
+        for k, v in stage_share_bytes(mt["dim"], mt["n"], mt["m"], 1).items():
+            tot[k] = tot.get(k, 0) + v * mt["nrhs"]
     return tot
 
 
@@ -214,16 +278,19 @@ def run_batch(args):
         batch.apply(q, out=out)
     stages = batch.stage_times()
     batch.set_timing(False)
-    stats = [batch.stats(i) for i in range(batch.count)]
-    sb = batch_stage_bytes(stats, batch.meta)
+    sb = batch_stage_bytes(batch.meta)
     per_apply = {nm: ms * calls / napp for nm, ms, calls in stages}
     dom = max(per_apply, key=per_apply.get)
     achieved = sb.get(dom, 0) / (per_apply[dom] * 1e-3) / 1e9
     apply_ms = sum(per_apply.values())
+    op_bytes = sum(operator_bytes(mt["dim"], mt["n"], mt["m"], 1) * mt["nrhs"] for mt in batch.meta)
+    op_gbs = op_bytes / (apply_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(sb.get(dom, 0)), "ms_per_launch": round(per_apply[dom], 5),
-            "note": "stage summed over the (grid size) groups of one batched apply"}
+            "note": "stage summed over the (grid size) groups of one batched apply",
+            "operator": {"achieved": round(op_gbs, 1), "frac": round(op_gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_apply": int(op_bytes), "ms_per_apply": round(apply_ms, 5)}}
 
     # accuracy of a few instances against the FP64 oracle (outside the timed region)
     from oracle import ibdl_oracle as O
@@ -388,9 +455,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nrhs", type=int, default=32)
-    ap.add_argument("--workload", default="star1024")
+    ap.add_argument("--workload", default="sphere256")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="length of the oracle CPU sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="length of the one-thread oracle sample (operator applications)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-templates", type=int, default=48)
     ap.add_argument("--serve-window", type=int, default=64)
@@ -421,14 +489,15 @@ def main():
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     data = t(np.stack([p.data for p in probs]))
     g = t(np.stack([p.g_tilde for p in probs]))
+    del probs[1:]
+    nrhs = data.shape[0]
 
-    def run(prec, steps, warmup, timing):
-        """Timed steps with stage timing off; then, if asked, a few more steps with
-        the per-stage events on (their times feed the roofline)."""
+    def run(prec, steps, warmup):
+        """Timed solve steps (ibdl_solve_grid of every right-hand side)."""
         plan = ibdl.Plan.from_problem(p0, prec=prec)
         # outputs allocated once, outside the timed steps
         sol_out = torch.empty_like(data)
-        u_out = torch.empty((data.shape[0],) + (n,) * dim, dtype=torch.float64, device="cuda")
+        u_out = torch.empty((nrhs,) + (n,) * dim, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
             sol, u, info = plan.solve_grid(data, g, tol=tol, out=sol_out, u=u_out)
         torch.cuda.synchronize()
@@ -440,23 +509,59 @@ def main():
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - s0)
             iters += int(info.field("iters").sum())
-        torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        stages = []
-        if timing:
-            plan.set_timing(True)
-            for _ in range(max(3, steps // 4)):
-                plan.solve(data, g, tol=tol)
-            stages = plan.stage_times()
-            plan.set_timing(False)
-        stats = plan.stats()
-        out = dict(elapsed=el, lat=lat, iters=iters, sol=sol.cpu().numpy(), u=u.cpu().numpy(),
-                   info=info, stages=stages, stats=stats)
+        out = dict(elapsed=el, lat=lat, iters=iters, steps=steps, sol=sol.cpu().numpy(), u=u,
+                   statuses=sorted({int(x) for x in info.field("status")}),
+                   fp64_applies=int(info.field("fp64_applies").sum()), stats=plan.stats())
         plan.close()
         return out
 
-    mixed = run(ibdl.MIXED, args.steps, args.warmup, True)
-    fp64 = run(ibdl.FP64, max(3, args.steps // 2), 1, False)
+    def roofline(prec):
+        """A dedicated loop of operator applications with every right-hand side
+        active and the stage events on (recorded in each stage kernel's own
+        dispatch on the library's stream)."""
+        rplan = ibdl.Plan.from_problem(p0, prec=prec)
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        q = torch.randn(nrhs, m, dtype=torch.float64, device="cuda", generator=gen)
+        out = rplan.apply(q)
+        for _ in range(3):
+            rplan.apply(q, out=out)
+        torch.cuda.synchronize()
+        rplan.set_timing(True)
+        for _ in range(ROOF_APPLIES):
+            rplan.apply(q, out=out)
+        stages = rplan.stage_times()
+        rplan.set_timing(False)
+        rstats = rplan.stats()
+        rplan.close()
+        ms = {nm: v for nm, v, _ in stages}
+        share = stage_share_bytes(dim, n, m, prec)
+        touched = stage_touched_bytes(rstats, dim, n, m, prec, nrhs)
+        dom = max(ms, key=ms.get)
+        bpl = share[dom] * nrhs
+        achieved = bpl / (ms[dom] * 1e-3) / 1e9
+        apply_ms = sum(ms.values())
+        opb = operator_bytes(dim, n, m, prec) * nrhs
+        op_gbs = opb / (apply_ms * 1e-3) / 1e9
+        kname = stage_kernel(dom, dim, n, prec)
+        return {
+            "bound": "hbm", "kernel": kname, "stage": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(args.workload, nrhs, kname),
+            "bytes_per_launch": int(bpl), "ms_per_launch": round(ms[dom], 5), "launches": ROOF_APPLIES,
+            "touched_bytes_per_launch": int(touched[dom]),
+            "operator": {"achieved": round(op_gbs, 1), "frac": round(op_gbs / HBM_PEAK_GBS, 4),
+                         "bytes_per_apply": int(opb), "ms_per_apply": round(apply_ms, 5),
+                         "applies_per_s": round(nrhs / (apply_ms * 1e-3), 1)},
+            "stages_ms": {k: round(v, 5) for k, v in ms.items()},
+            "stages_frac": {k: round(share[k] * nrhs / (ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for k in ms
+                            if k in share},
+        }
+
+    fp64 = run(ibdl.FP64, args.steps, args.warmup)
+    mixed = run(ibdl.MIXED, args.steps, args.warmup)
+    roof64 = roofline(0)
+    roof32 = roofline(1)
 
     if args.calib_copy_mib:
         nb = args.calib_copy_mib * (1 << 20) // 4
@@ -465,102 +570,68 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # accuracy against the FP64 oracle (outside the timed region), and the
-    # oracle's own throughput on a bounded sample of the same right-hand sides
-    from oracle import ibdl_oracle as O
-    from threadpoolctl import threadpool_limits
-    st = O.setup_from_problem(p0)
-    tight, _ = O.solve(st, p0.data, p0.g_tilde, tol=1e-13)
-    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    err_mixed = rel(mixed["sol"][0], tight.x)
-    err_fp64 = rel(fp64["sol"][0], tight.x)
-    err_u_mixed = rel(mixed["u"][0], O.eval_grid(st, tight.x, g_tilde=p0.g_tilde))
-    cpu_iters, cpu_solves, t_cpu = 0, 0, 0.0
+    # the oracle on the host: operator applications on one thread, and FP64 solves of
+    # distinct right-hand sides in one process per core; the GPU solutions of the
+    # same right-hand sides are compared with those solves
+    cpu, errs = None, None
     if not args.no_cpu:
-        with threadpool_limits(limits=1):
-            for pr in probs:
-                c0 = time.perf_counter()
-                res, _ = O.solve(st, pr.data, pr.g_tilde, tol=tol)
-                O.eval_grid(st, res.x, g_tilde=pr.g_tilde)
-                t_cpu += time.perf_counter() - c0
-                cpu_iters += res.iters
-                cpu_solves += 1
-                if t_cpu >= args.cpu_seconds:
-                    break
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        cores = min(host_cores(), nrhs)
+        with cf.ProcessPoolExecutor(max_workers=1, mp_context=ctx) as ex:
+            k1, el1 = ex.submit(_oracle_apply_worker, args.workload, args.cpu_seconds).result()
+        c0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+            futs = [ex.submit(_oracle_solve_worker, args.workload, r, tol) for r in range(cores)]
+            res = [f.result() for f in futs]
+        wall = time.perf_counter() - c0
+        tot_iters = sum(x[1] for x in res)
+        rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+        errs = {"rhs": [x[0] for x in res],
+                "Q_fp64": [rel(fp64["sol"][x[0]], x[3]) for x in res],
+                "Q_mixed": [rel(mixed["sol"][x[0]], x[3]) for x in res],
+                "u_fp64": [rel(fp64["u"][x[0]].cpu().numpy(), x[4]) for x in res],
+                "u_mixed": [rel(mixed["u"][x[0]].cpu().numpy(), x[4]) for x in res],
+                "oracle_tol": tol}
+        errs["max"] = {k: max(v) for k, v in errs.items() if k.startswith(("Q_", "u_"))}
+        cpu = {"value": round(tot_iters / wall, 3), "unit": "applies/s", "cores": cores, "kind": "oracle",
+               "sample": f"FP64 oracle solves (right-hand side, GMRES to tol {tol:g}, grid solution) of the first "
+                         f"{cores} right-hand sides of the workload, one single-threaded process per core: "
+                         f"{tot_iters} GMRES applies in {wall:.1f} s wall",
+               "solves_per_s": round(cores / wall, 4), "host_cpus": os.cpu_count(),
+               "one_thread": {"value": round(k1 / el1, 3), "unit": "applies/s", "cores": 1,
+                              "sample": f"{k1} oracle operator applications in {el1:.1f} s on one thread "
+                                        "(numpy FFT; BLAS pools limited to 1)"}}
 
     K = args.steps
-    el = mixed["elapsed"]
-    applies_s = mixed["iters"] / el
-    solves_s = K * args.nrhs / el
-    lat_ms = np.array(mixed["lat"]) * 1e3
-
-    # roofline of the dominant kernel: a dedicated loop of mixed operator
-    # applications with every right-hand side active and the stage events on
-    rplan = ibdl.Plan.from_problem(p0, prec=ibdl.MIXED)
-    gen = torch.Generator(device="cuda").manual_seed(7)
-    q = torch.randn(args.nrhs, m, dtype=torch.float64, device="cuda", generator=gen)
-    out = rplan.apply(q)
-    for _ in range(5):
-        rplan.apply(q, out=out)
-    torch.cuda.synchronize()
-    rplan.set_timing(True)
-    for _ in range(ROOF_APPLIES):
-        rplan.apply(q, out=out)
-    stages = rplan.stage_times()
-    rplan.set_timing(False)
-    rstats = rplan.stats()
-    rplan.close()
-    sb = stage_bytes(rstats, dim, n, m, 1, args.nrhs)
-    dom_ms = {nm: ms for nm, ms, _ in stages}
-    dom = max(dom_ms, key=dom_ms.get)
-    achieved = sb.get(dom, 0) / (dom_ms[dom] * 1e-3) / 1e9
-    kname = stage_kernel(dom, dim, n)
-    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": int(sb.get(dom, 0))}
-    flops = stage_flops(dim, n, args.nrhs).get(dom)
-    if flops:
-        # the column stage issues FFT arithmetic at a rate set by the vector ALUs
-        # (instruction-issue bound in the counters), not by HBM bandwidth
-        tf = flops / (dom_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": kname, "stage": dom, "achieved": round(tf, 2),
-                "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / ALU_PEAK_TFLOPS, 4),
-                "traffic": read_traffic(args.workload, args.nrhs, kname), "flops_per_launch": int(flops),
-                "ms_per_launch": round(dom_ms[dom], 5), "launches": ROOF_APPLIES, "hbm": hbm}
-    else:
-        roof = {"bound": "hbm", "kernel": kname, "stage": dom, "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": hbm["frac"], "traffic": read_traffic(args.workload, args.nrhs, kname),
-                "bytes_per_launch": hbm["bytes_per_launch"], "ms_per_launch": round(dom_ms[dom], 5),
-                "launches": ROOF_APPLIES}
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = {"value": round(cpu_iters / t_cpu, 3), "unit": "applies/s", "cores": 1, "kind": "oracle",
-               "sample": f"FP64 oracle solves (rhs, GMRES to tol {tol:g}, grid solution) of the first "
-                         f"{cpu_solves} right-hand sides of the workload: {cpu_iters} applies in {t_cpu:.1f} s, "
-                         f"one thread (numpy FFT; BLAS pools limited to 1)",
-               "solves_per_s": round(cpu_solves / t_cpu, 4), "host_cpus": os.cpu_count()}
-
+    el = fp64["elapsed"]
+    lat64 = np.array(fp64["lat"]) * 1e3
+    lat32 = np.array(mixed["lat"]) * 1e3
     line = {
-        "metric": METRIC, "value": round(applies_s, 2), "unit": "applies/s", "n_gpus": 1,
+        "metric": METRIC, "value": round(fp64["iters"] / el, 2), "unit": "applies/s", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": round(el / K * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 grid + f64 krylov", "data": "synthetic",
+        "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": n, "dim": dim, "M": m,
-                   "alpha": p0.alpha, "bc": "dirichlet", "nrhs": args.nrhs, "tol": tol,
-                   "precision": "mixed", "graphs": args.graphs == "on"},
-        "solves_per_s": round(solves_s, 3),
-        "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 4),
-        "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 4),
-        "iters_per_solve": round(mixed["iters"] / (K * args.nrhs), 2),
-        "rel_err_vs_oracle": {"Q_mixed": err_mixed, "Q_fp64": err_fp64, "u_mixed": err_u_mixed},
-        "fp64_path": {"applies_per_s": round(fp64["iters"] / fp64["elapsed"], 2),
-                      "solves_per_s": round(len(fp64["lat"]) * args.nrhs / fp64["elapsed"], 3),
-                      "latency_ms_p50": round(float(np.percentile(np.array(fp64["lat"]) * 1e3, 50)), 4)},
-        "stages_ms_in_solves": {nm: round(ms, 5) for nm, ms, _ in mixed["stages"]},
-        "stages_ms_apply": {nm: round(ms, 5) for nm, ms in dom_ms.items()},
-        "full_grid_bytes_per_apply": full_grid_bytes_per_apply(dim, n, m, 1),
+                   "alpha": p0.alpha, "bc": "dirichlet", "nrhs": nrhs, "tol": tol, "precision": "fp64",
+                   "graphs": args.graphs == "on"},
+        "solves_per_s": round(K * nrhs / el, 3),
+        "latency_ms_p50": round(float(np.percentile(lat64, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(lat64, 99)), 4),
+        "iters_per_solve": round(fp64["iters"] / (K * nrhs), 2),
+        "statuses": fp64["statuses"],
+        "mixed_path": {"dtype": "f32 grid + f64 krylov", "applies_per_s": round(mixed["iters"] / mixed["elapsed"], 2),
+                       "solves_per_s": round(K * nrhs / mixed["elapsed"], 3),
+                       "ms_per_step": round(mixed["elapsed"] / K * 1e3, 4),
+                       "latency_ms_p50": round(float(np.percentile(lat32, 50)), 4),
+                       "latency_ms_p99": round(float(np.percentile(lat32, 99)), 4),
+                       "iters_per_solve": round(mixed["iters"] / (K * nrhs), 2),
+                       "fp64_residual_passes_per_solve": round(mixed["fp64_applies"] / nrhs, 2),
+                       "statuses": mixed["statuses"], "roofline": roof32},
+        "rel_err_vs_oracle": errs,
         "autotune": ibdl.autotune_report().splitlines(),
-        "roofline": roof,
+        "roofline": roof64,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -6,12 +6,12 @@
  * on a periodic box by representing u with a regularised double layer (dipole
  * spread) of strength Q on the boundary points.  Its hot path is the matrix-free
  * boundary operator applied at every GMRES iteration:
- *     Dirichlet:  A q = -S* L^-1 S~ q + q/2      (Sec. 5.3, Eq. (ibdl schur again))
- *     Neumann:    A q = -S* L^-1 S~ q - q/2      (Sec. 4.3, Eq. (Neumann saddle point))
- * with S~ q = div(S (q n)) the dipole spread (Sec. 5.2, Eq. (Stilde)), S the spread
- * (Eq. (spread operator again2)), S* the interpolation (Eq. (interpolation again)),
- * delta_h the Peskin four-point kernel (Eqs. (delta eqn 1)-(delta eqn 2)) and
- * L = Lap_h - alpha the periodic 5-point (2-D) / 7-point (3-D) operator (Sec. 5.1).
+ *     Dirichlet:  A q = -S* L^-1 S~ q + q/2      (Sec. 5.3: the equation for Q once L is inverted)
+ *     Neumann:    A q = -S* L^-1 S~ q - q/2      (Sec. 4.4: the equation for the unknown U_b)
+ * with S~ q = div(S (q n)) the dipole spread (Sec. 5.2), S the discrete spread and
+ * S* the discrete interpolation (Sec. 5.2), delta_h the product of Peskin's
+ * four-point kernel phi over the axes (Sec. 5.2) and L = Lap_h - alpha the periodic
+ * 5-point (2-D) / 7-point (3-D) operator (Sec. 5.1).
  *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers (for example a torch tensor's
@@ -56,7 +56,7 @@ typedef enum {
 typedef enum { IBDL_DIRICHLET = 0, IBDL_NEUMANN = 1 } ibdl_bc;
 
 /* Discrete delta kernel phi (delta_h(x) = prod_d phi(x_d/h)/h):
- * PESKIN4 is the paper's kernel (Sec. 5.2, Eq. (delta eqn 2));
+ * PESKIN4 is the paper's kernel (Sec. 5.2);
  * COSINE4 is phi(r) = (1 + cos(pi r/2))/4 for |r| < 2. */
 typedef enum { IBDL_DELTA_PESKIN4 = 0, IBDL_DELTA_COSINE4 = 1 } ibdl_delta;
 
@@ -120,14 +120,14 @@ size_t ibdl_plan_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart)
 ibdl_status ibdl_apply(ibdl_plan plan, int32_t nrhs, const double* q, double* Aq, void* stream);
 
 /* Right-hand side of the boundary equation (async):
- *   Dirichlet  b = U_b - S* L^-1 g~               (Eq. (ibdl schur again))
- *   Neumann    b = S* L^-1 (S V_b - g~)           (Eq. (Neumann saddle point))
+ *   Dirichlet  b = U_b - S* L^-1 g~               (Sec. 5.3, right side of the equation for Q)
+ *   Neumann    b = S* L^-1 (S V_b - g~)           (Sec. 4.4, right side of the equation for U_b)
  * data: device [nrhs][M] U_b or V_b;  g: device [nrhs][n^dim] g~ or NULL (zero);
  * b: device [nrhs][M]. */
 ibdl_status ibdl_rhs(ibdl_plan plan, int32_t nrhs, const double* data, const double* g,
                      double* b, void* stream);
 
-/* Step 1 of the method (Sec. 4.1, Sec. 5.3): form the right-hand side and run
+/* Step 1 of the method (Sec. 4.2, Sec. 5.3): form the right-hand side and run
  * unpreconditioned restarted GMRES on the device (FP64 Arnoldi with classical
  * Gram-Schmidt applied twice, Givens rotations) for each right-hand side.
  * The right-hand side is formed in FP64 for every plan.  MIXED plans iterate
@@ -154,8 +154,8 @@ ibdl_status ibdl_solve_grid(ibdl_plan plan, int32_t nrhs, const double* data, co
                             void* stream);
 
 /* Step 2 of the method: the grid solution (async).
- *   Dirichlet  u = L^-1 (g~ - S~ Q)               (Sec. 4.1, Eq. (ibdl 1 again))
- *   Neumann    u = L^-1 (g~ - S~ U_b - S V_b)     (Sec. 4.3, Eq. (ib neumann 1))
+ *   Dirichlet  u = L^-1 (g~ - S~ Q)               (Sec. 4.2, step 2)
+ *   Neumann    u = L^-1 (g~ - S~ U_b - S V_b)     (Sec. 4.4, the grid equation of the Neumann system)
  * sol: device [nrhs][M] (Q or U_b); vb: device [nrhs][M] V_b (Neumann only, else NULL);
  * g: device [nrhs][n^dim] or NULL; u: device [nrhs][n^dim]. */
 ibdl_status ibdl_eval_grid(ibdl_plan plan, int32_t nrhs, const double* sol, const double* vb,
@@ -223,10 +223,10 @@ ibdl_status ibdl_batch_size(ibdl_batch batch, int32_t* count, int32_t* total_rhs
 /* ibdl_plan_get_stats of instance i (0 <= i < count). */
 ibdl_status ibdl_batch_get_stats(ibdl_batch batch, int32_t i, ibdl_plan_stats* out_host);
 
-/* Aq_i = A_i q_i for every instance (Sec. 5.3 / Sec. 4.3 operators; async after the wait). */
+/* Aq_i = A_i q_i for every instance (Sec. 5.3 / Sec. 4.4 operators; async after the wait). */
 ibdl_status ibdl_batch_apply(ibdl_batch batch, const double* const* q, double* const* Aq, void* stream);
 
-/* ibdl_solve for every instance (Sec. 4.1, Sec. 5.3): right-hand sides, GMRES
+/* ibdl_solve for every instance (Sec. 4.2, Sec. 5.3): right-hand sides, GMRES
  * with the instances' own stopping tests, FP64 refinement of MIXED instances.
  * data, sol: per instance; g: NULL (no forcing anywhere) or per instance with
  * NULL entries allowed.  opts as for ibdl_solve except that opts->x0 must be NULL.
@@ -295,7 +295,7 @@ ibdl_status ibdl_server_destroy(ibdl_server server);
 ibdl_status ibdl_server_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart, size_t* bytes);
 
 /* Queue a solve (non-blocking): the right-hand side, GMRES (Sec. 5.3) with FP64
- * refinement for MIXED, and, when u is not NULL, the grid solution (Sec. 4.1).
+ * refinement for MIXED, and, when u is not NULL, the grid solution (Sec. 4.2, step 2).
  * desc, data [nrhs][M], g [nrhs][n^dim] or NULL, sol [nrhs][M], u [nrhs][n^dim]
  * or NULL: as for ibdl_plan_create / ibdl_solve / ibdl_eval_grid (Neumann
  * requests use data as V_b for the grid solution).  The geometry, data and g are
@@ -335,7 +335,7 @@ ibdl_status ibdl_set_autotune(int32_t enable);
 int32_t ibdl_autotune_report(char* buf, size_t cap);
 
 /* Iteration graphs.  Once the operator pass of a solver's Krylov workspace has
- * run once (which settles the tuned variants), a GMRES-Arnoldi step (Sec. 2.2:
+ * run once (which settles the tuned variants), a GMRES-Arnoldi step (Sec. 5.3:
  * one operator application followed by the orthogonalisation of the new basis
  * vector) is recorded as a HIP graph whose kernels read the step index from
  * device memory; the workspace keeps it, and every later step, in this and later

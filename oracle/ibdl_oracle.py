@@ -10,14 +10,14 @@ Everything is written to be checked by eye against the paper (Leathers & Guy,
 "Immersed Boundary Double Layer method: an introduction of methodology on the
 Helmholtz equation"):
 
-* the Peskin four-point kernel phi and delta_h             (Sec. 5.2, Eqs. (delta eqn 1)-(delta eqn 2))
-* the spread S and interpolation S*                        (Sec. 5.2, Eqs. (spread operator again2), (interpolation again))
-* the dipole spread  S~Q = div(S Q n), centred divergence  (Sec. 5.2, Eq. (Stilde); Sec. 4.1, Eq. (ibdl))
+* the Peskin four-point kernel phi and delta_h             (Sec. 5.2, delta_h as a product of phi)
+* the spread S and interpolation S*                        (Sec. 5.2, their discrete sums)
+* the dipole spread  S~Q = div(S Q n), centred divergence  (Sec. 5.2; Sec. 4.1, the IBDL system)
 * L = Lap_h - alpha with the 5-/7-point Laplacian on a periodic box,
   inverted by diagonalisation with the DFT                 (Sec. 5.1; Sec. 5.3)
-* the Dirichlet operator  -S* L^-1 S~ + 1/2 I  and RHS     (Sec. 5.3, Eq. (ibdl schur again))
-* the Neumann operator    -S* L^-1 S~ - 1/2 I  and RHS     (Sec. 4.3, Eq. (Neumann saddle point))
-* the grid solution  L u = g~ - S~Q  (- S V_b for Neumann) (Sec. 4.1 step 2; Sec. 4.3, Eq. (ib neumann 1))
+* the Dirichlet operator  -S* L^-1 S~ + 1/2 I  and RHS     (Sec. 5.3, the equation for Q)
+* the Neumann operator    -S* L^-1 S~ - 1/2 I  and RHS     (Sec. 4.4, the equation for U_b)
+* the grid solution  L u = g~ - S~Q  (- S V_b for Neumann) (Sec. 4.2 step 2; Sec. 4.4, the Neumann grid equation)
 * unpreconditioned GMRES on the boundary density           (Sec. 5.3)
 * the mean-zero inverse for alpha = 0                      (Sec. 5.4.2; App. C)
 * the indicator-function construction                      (App. D)
@@ -50,7 +50,7 @@ COSINE4 = "cosine"
 # the discrete delta (Sec. 5.2)
 # ----------------------------------------------------------------------------
 def phi_peskin4(r):
-    """Peskin's four-point kernel phi(r) (Eq. (delta eqn 2))."""
+    """Peskin's four-point kernel phi(r) (Sec. 5.2)."""
     a = np.abs(np.asarray(r, dtype=np.float64))
     out = np.zeros_like(a)
     m1 = a <= 1.0
@@ -148,7 +148,7 @@ def stencil(st: Setup):
 # spread and interpolation (Sec. 5.2)
 # ----------------------------------------------------------------------------
 def spread(st: Setup, F):
-    """(S F)(x) = sum_k F_k delta_h(x - X_k) Delta s_k  (Eq. (spread operator again2))."""
+    """(S F)(x) = sum_k F_k delta_h(x - X_k) Delta s_k  (Sec. 5.2, the discrete spread)."""
     idx, wts = stencil(st)
     vals = (np.asarray(F, dtype=np.float64) * st.weight)[:, None] * wts / st.h ** st.dim
     out = np.bincount(idx.ravel(), weights=vals.ravel(), minlength=st.n ** st.dim)
@@ -156,7 +156,7 @@ def spread(st: Setup, F):
 
 
 def interp(st: Setup, u):
-    """(S* u)_k = sum_x u(x) delta_h(x - X_k) h^d  (Eq. (interpolation again))."""
+    """(S* u)_k = sum_x u(x) delta_h(x - X_k) h^d  (Sec. 5.2, the discrete interpolation)."""
     idx, wts = stencil(st)
     return np.sum(np.asarray(u, dtype=np.float64).ravel()[idx] * wts, axis=1)
 
@@ -177,7 +177,7 @@ def gradient(st: Setup, u):
 
 
 def spread_dipole(st: Setup, Q):
-    """S~ Q = div(S (Q n))  (Eq. (Stilde)): spread the vector Q n, then the centred divergence."""
+    """S~ Q = div(S (Q n))  (Sec. 5.2): spread the vector Q n, then the centred divergence."""
     Q = np.asarray(Q, dtype=np.float64)
     v = [spread(st, Q * st.normal[:, d]) for d in range(st.dim)]
     return divergence(st, v)
@@ -225,8 +225,8 @@ def solve_L(st: Setup, f):
 # the IBDL boundary operator and its right-hand sides
 # ----------------------------------------------------------------------------
 def apply_A(st: Setup, q, bc=DIRICHLET):
-    """Dirichlet: -S* L^-1 S~ q + q/2 (Eq. (ibdl schur again));
-    Neumann:   -S* L^-1 S~ q - q/2 (Eq. (Neumann saddle point))."""
+    """Dirichlet: -S* L^-1 S~ q + q/2 (Sec. 5.3, the equation for Q);
+    Neumann:   -S* L^-1 S~ q - q/2 (Sec. 4.4, the equation for U_b)."""
     q = np.asarray(q, dtype=np.float64)
     w = -interp(st, solve_L(st, spread_dipole(st, q)))
     return w + 0.5 * q if bc == DIRICHLET else w - 0.5 * q
@@ -242,8 +242,8 @@ def rhs(st: Setup, data, g_tilde=None, bc=DIRICHLET):
 
 
 def eval_grid(st: Setup, sol, vb=None, g_tilde=None, bc=DIRICHLET):
-    """Grid solution: L u = g~ - S~ Q (Dirichlet, step 2 of Sec. 4.1), or
-    L u = g~ - S~ U_b - S V_b (Neumann, Eq. (ib neumann 1))."""
+    """Grid solution: L u = g~ - S~ Q (Dirichlet, step 2 of Sec. 4.2), or
+    L u = g~ - S~ U_b - S V_b (Neumann, the grid equation of Sec. 4.4)."""
     g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
     f = g - spread_dipole(st, sol)
     if bc == NEUMANN:

@@ -55,6 +55,7 @@ struct KArgs {
     const double* tolv; // [R] tolerance relative to ||b_r||
     int32_t* state;     // [R][4]
     const int32_t* skip;
+    const int32_t* maxv;  // [R] Arnoldi steps each rhs may take in the current Krylov run
     const int32_t* jp;  // Arnoldi step index in device memory, or null: the launch argument
     int32_t* jcur;      // the step index that replayed steps read; reset with each cycle
 };
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     if (!isfinite(res) || !isfinite(hn_s[1])) {
         st[ST_STATUS] = IBDL_ERR_NUMERIC;
         st[ST_DONE] = 1;
-    } else if (res <= a.tolv[r] || !(hn > 0.0)) {
+    } else if (res <= a.tolv[r] || !(hn > 0.0) || st[ST_ITERS] >= a.maxv[r]) {
         st[ST_DONE] = 1;
     }
 }
@@ -472,7 +473,8 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     k.r = A(xtot);
     k.rr = A(xtot);
     k.d = A(xtot);
-    k.skip = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
+    // skip flags [R] followed by the per-rhs step budgets [R]: one copy per Krylov run
+    k.skip = reinterpret_cast<int32_t*>(dev_alloc(k.mem, 2 * (size_t)R * sizeof(int32_t)));
     k.jcur = reinterpret_cast<int32_t*>(dev_alloc(k.mem, sizeof(int32_t)));
     k.Mr = reinterpret_cast<int32_t*>(dev_alloc(k.mem, (size_t)R * sizeof(int32_t)));
     k.voff = reinterpret_cast<size_t*>(dev_alloc(k.mem, (size_t)R * sizeof(size_t)));
@@ -485,7 +487,7 @@ static void ensure_krylov(KrylovSet& ks, int m) {
     IBDL_HIP_TRY(hipMemcpyAsync(k.xoff, xoff.data(), R * sizeof(size_t), hipMemcpyHostToDevice, ast));
     IBDL_HIP_TRY(hipStreamSynchronize(ast));
     // host staging: tolerances, skip flags, state, residuals, norms
-    k.host_pinned = pinned_get((size_t)R * (5 * 8 + 9 * 4) + 64);  // the Staging layout
+    k.host_pinned = pinned_get((size_t)R * (5 * 8 + 10 * 4) + 64);  // the Staging layout
     k.cap_m = m;
     k.R = R;
     k.nblk = nblk;
@@ -518,6 +520,7 @@ static KArgs kargs(KrylovSet& ks, int m) {
     a.tolv = k.tolv;
     a.state = k.state;
     a.skip = k.skip;
+    a.maxv = k.skip + ks.R;
     a.jp = nullptr;
     a.jcur = k.jcur;
     return a;
@@ -532,7 +535,7 @@ struct Staging {
     double* nrm;
     double* resid[2];
     int32_t* state[2];
-    int32_t* skip;
+    int32_t* skip;   // [R] skip flags, then [R] step budgets (as on the device)
 };
 static Staging staging(KWork& k, int R) {
     double* d = reinterpret_cast<double*>(k.host_pinned);
@@ -853,15 +856,18 @@ void SolveTask::prepare_op() {
 
 // Restarted GMRES on A x = b (pool vectors) with each plan's operator in its own
 // precision, for every rhs not marked in skip_, to the tolerances tol_ (relative
-// to ||b_r||); x_zero: start from x = 0, else from the iterate in x.
-void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
+// to ||b_r||) within at most budget_[r] Arnoldi steps each; x_zero: start from
+// x = 0, else from the iterate in x.
+void SolveTask::kstart(const double* b, double* x, bool x_zero) {
     KWork& k = ks_.w;
     KArgs a = kargs(ks_, m_);
     const dim3 vg(k.nblk, R_);
     Staging hs = staging(k, R_);
     kb_ = b;
     kx_ = x;
-    kmaxit_ = maxit;
+    kmaxit_ = 0;
+    for (int r = 0; r < R_; ++r)
+        if (!skip_[r]) kmaxit_ = std::max(kmaxit_, budget_[r]);
     ktotal_ = kj_ = 0;
     prev_iter_ = -1;
     if (x_zero) {
@@ -873,9 +879,10 @@ void SolveTask::kstart(const double* b, double* x, bool x_zero, int maxit) {
     for (int r = 0; r < R_; ++r) {
         hs.tol[r] = tol_[r];
         hs.skip[r] = skip_[r];
+        hs.skip[R_ + r] = budget_[r];
     }
     IBDL_HIP_TRY(hipMemcpyAsync(k.tolv, hs.tol, R_ * sizeof(double), hipMemcpyHostToDevice, st_));
-    IBDL_HIP_TRY(hipMemcpyAsync(k.skip, hs.skip, R_ * sizeof(int32_t), hipMemcpyHostToDevice, st_));
+    IBDL_HIP_TRY(hipMemcpyAsync(k.skip, hs.skip, 2 * R_ * sizeof(int32_t), hipMemcpyHostToDevice, st_));
     hipLaunchKernelGGL(k_sumsq, vg, dim3(GT), 0, st_, a, b);
     hipLaunchKernelGGL(k_set_bnorm, dim3((R_ + 63) / 64), dim3(64), 0, st_, a);
     const double* r0 = b;
@@ -1073,7 +1080,8 @@ void SolveTask::advance() {
             }
         }
         norms_async(k.b, staging(k, R_).bn);
-        kstart(k.b, k.x, !any_x0, o_.maxit);
+        budget_.assign(R_, o_.maxit);
+        kstart(k.b, k.x, !any_x0);
         return;
     }
     case ITER: {
@@ -1189,17 +1197,24 @@ void SolveTask::advance() {
             finish_mixed();
             return;
         }
-        int used = 0;
-        for (int r = 0; r < R_; ++r)
-            if (!skip_[r]) used = std::max(used, iters_[r]);
-        const int left = o_.maxit - used;
-        if (round_ >= 4 || left <= 0) {
-            for (int r = 0; r < R_; ++r)
-                if (!skip_[r] && status_[r] != IBDL_ERR_NUMERIC) status_[r] = IBDL_ERR_NOCONV;
+        // every rhs keeps its own budget: maxit less the steps it has taken itself, so
+        // a right-hand side ends as it would in a solve of its own, whatever the others
+        bool any = false;
+        for (int r = 0; r < R_; ++r) {
+            if (skip_[r]) continue;
+            budget_[r] = o_.maxit - iters_[r];
+            if (round_ >= 4 || budget_[r] <= 0) {
+                if (status_[r] != IBDL_ERR_NUMERIC) status_[r] = IBDL_ERR_NOCONV;
+                skip_[r] = 1;
+            } else {
+                any = true;
+            }
+        }
+        if (!any) {
             finish_mixed();
             return;
         }
-        kstart(k.rr, k.d, true, left);
+        kstart(k.rr, k.d, true);
         return;
     }
     case OUT: {

@@ -5,8 +5,8 @@
 //    sort of the 64-bit composite keys (key << 32 | index) -- unique, so the
 //    order of equal cell keys is the caller order;
 //  * per point the 1-D delta taps phi(p - t) for p = c-1..c+2 (Sec. 5.2);
-//  * the sparse dipole spread S~ q = div(S (q n)) (Sec. 5.2, Eq. (Stilde)) and,
-//    for Neumann plans, the monopole spread S (Eq. (spread operator again2)),
+//  * the sparse dipole spread S~ q = div(S (q n)) (Sec. 5.2) and, for Neumann
+//    plans, the monopole spread S (the discrete spread of Sec. 5.2),
 //    as rows over the active grid nodes: every (node, point) pair the stencil
 //    reaches is emitted, sorted by (node, point), and weighed;
 //  * the x-lines that receive forcing and the x-lines interpolated from;

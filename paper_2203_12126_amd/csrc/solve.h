@@ -47,7 +47,7 @@ public:
 private:
     enum Phase { BEGIN, ITER, KEND, OUT, DONE };
     void mark();                                  // record the wait point
-    void kstart(const double* b, double* x, bool x_zero, int maxit);
+    void kstart(const double* b, double* x, bool x_zero);
     void enqueue_iters(int j0, int c);
     void prepare_op();                            // the set's Arnoldi operator step, current
     bool capture_step();                          // record one Arnoldi step as a graph
@@ -87,6 +87,7 @@ private:
     int round_ = 0;
     std::vector<double> bn_, tol_, est_, truer_;
     std::vector<int> skip_, iters_, status_, fp64_;
+    std::vector<int> budget_;  // Arnoldi steps each rhs may still take (maxit less its own)
     std::vector<char> grid_done_;  // per instance: u written by the last residual pass
 };
 

@@ -9,7 +9,7 @@ Conventions (Sec. 5.1 of the paper): the computational domain is a periodic box
 of side ``length`` with ``n`` nodes per axis, node ``i`` at ``lo + i*h`` with
 ``h = length/n``.  Grid arrays are C-ordered ``[iz][iy][ix]`` (x fastest);
 point coordinates are ``X[:, 0] = x``, ``X[:, 1] = y``, ``X[:, 2] = z``.
-The PDE is ``Lap(u) - alpha*u = g`` (Eq. (1) with ``alpha = k^2``).
+The PDE is ``Lap(u) - alpha*u = g`` (the model problem of Sec. 2 with ``alpha = k^2``).
 """
 from __future__ import annotations
 
@@ -262,6 +262,47 @@ def sol_exp_cos3d() -> Solution:
     return Solution(u, grad, lambda p: np.zeros(p.shape[0]))
 
 
+def harmonic3d_params(seed: int):
+    """(k, l, phase) of u = exp(k.x) cos(l.x + phase) with |k| = |l|, k . l = 0, so
+    that u is harmonic.  seed 0 is exp(x+y) cos(sqrt(2) z - 0.3); other seeds
+    draw an orthonormal pair of directions, a common length in U(0.8, 1.6) and a
+    phase in U(0, 2 pi)."""
+    if seed == 0:
+        return np.array([1.0, 1.0, 0.0]), np.array([0.0, 0.0, math.sqrt(2.0)]), -0.3
+    rng = np.random.default_rng(seed)
+    e1 = rng.standard_normal(3)
+    e1 /= np.linalg.norm(e1)
+    e2 = rng.standard_normal(3)
+    e2 -= np.dot(e2, e1) * e1
+    e2 /= np.linalg.norm(e2)
+    s = rng.uniform(0.8, 1.6)
+    return s * e1, s * e2, float(rng.uniform(0.0, 2 * math.pi))
+
+
+def sol_harmonic3d(seed: int) -> Solution:
+    """u = exp(k.x) cos(l.x + phase) with the parameters of harmonic3d_params (harmonic)."""
+    k, l, ph = harmonic3d_params(seed)
+
+    def u(p):
+        return np.exp(p @ k) * np.cos(p @ l + ph)
+
+    def grad(p):
+        e = np.exp(p @ k)
+        c = np.cos(p @ l + ph)
+        s = np.sin(p @ l + ph)
+        return e[:, None] * (c[:, None] * k[None, :] - s[:, None] * l[None, :])
+
+    return Solution(u, grad, lambda p: np.zeros(p.shape[0]))
+
+
+def harmonic3d_grid(seed: int, grid: "Grid") -> np.ndarray:
+    """sol_harmonic3d(seed) at the grid nodes by separable evaluation:
+    u = Re(e^{i phase} prod_d exp((k_d + i l_d) x_d))."""
+    k, l, ph = harmonic3d_params(seed)
+    f = [np.exp((k[d] + 1j * l[d]) * grid.axis_coords(d)) for d in range(3)]
+    return np.real(np.exp(1j * ph) * f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :])
+
+
 def sol_bessel_sin2(center=(0.0, 0.0), radius=0.25, k=1.0) -> Solution:
     """u = I_2(k r) sin(2 theta) / I_2(k R): solves Lap u - k^2 u = 0 (Sec. 6.1)."""
     from scipy.special import iv, ivp
@@ -428,12 +469,26 @@ def _star_geometry(m: int) -> Geometry:
     return _STAR_CACHE[m]
 
 
-def config_sphere256(n: int = 256, m: int = 40000, alpha: float = 10.0) -> Problem:
-    """3-D Dirichlet: sphere R=0.3 at the box centre, Fibonacci lattice,
-    u = exp(x+y) cos(sqrt(2) z - 0.3), alpha = 10."""
+def config_sphere256(n: int = 256, m: int = 40000, alpha: float = 10.0, seed: int = 0) -> Problem:
+    """3-D Dirichlet: sphere R=0.3 at the box centre, Fibonacci lattice, alpha = 10,
+    manufactured harmonic u = exp(k.x) cos(l.x + phase) (seed 0: exp(x+y)
+    cos(sqrt(2) z - 0.3)); forcing g = -alpha u inside the sphere (separable
+    evaluation, the same values as make_problem up to rounding)."""
     grid = Grid(3, n, (0.0, 0.0, 0.0), 1.0)
-    geom = fibonacci_sphere((0.5, 0.5, 0.5), 0.3, m)
-    return make_problem(grid, geom, alpha, DIRICHLET, sol_exp_cos3d(), name=f"sphere{n}_m{m}")
+    if m not in _SPHERE_CACHE:
+        _SPHERE_CACHE.clear()
+        _SPHERE_CACHE[m] = fibonacci_sphere((0.5, 0.5, 0.5), 0.3, m)
+    geom = _SPHERE_CACHE[m]
+    x = grid.axis_coords(0) - 0.5
+    inside = (x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2) < 0.3 ** 2
+    u = harmonic3d_grid(seed, grid)
+    g = np.where(inside, -alpha * u, 0.0)
+    data = sol_harmonic3d(seed).u(geom.X)
+    return Problem(grid, geom, alpha, DIRICHLET, np.ascontiguousarray(data), np.ascontiguousarray(g),
+                   sol_harmonic3d(seed), f"sphere{n}_m{m}_s{seed}")
+
+
+_SPHERE_CACHE: dict = {}
 
 
 def config_batch(count: int = 512, seed: int = 12126, sizes=(128, 192, 256, 384, 512),

@@ -1,10 +1,12 @@
-"""Serving loop: results alone vs in the mix, admission by memory footprint,
-isolation of failing requests, the footprint as an upper bound."""
+"""Serving loop: results alone vs in the mix and against the FP64 oracle,
+admission by memory footprint, isolation of failing requests, the footprint as
+an upper bound, per-request iteration budgets."""
 import time
 
 import numpy as np
 import pytest
 
+from oracle import ibdl_oracle as O
 from paper_2203_12126_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -18,6 +20,28 @@ from paper_2203_12126_amd import ibdl  # noqa: E402
 
 def T(a):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def relerr(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def oracle_solution(prob, tol=1e-13):
+    """The oracle's boundary solution and grid solution of a served request (tight tol)."""
+    st = O.setup_from_problem(prob)
+    tight, _ = O.solve(st, prob.data, prob.g_tilde, bc=prob.bc, tol=tol)
+    u = O.eval_grid(st, tight.x, vb=prob.data if prob.bc == W.NEUMANN else None, g_tilde=prob.g_tilde,
+                    bc=prob.bc)
+    return tight.x, u
+
+
+def check_against_oracle(res, prob, what):
+    x, u = oracle_solution(prob)
+    es = relerr(res["sol"][0].cpu().numpy(), x)
+    eu = relerr(res["u"][0].cpu().numpy(), u)
+    print(f"  {what}: Q err {es:.2e} u err {eu:.2e} iters {res['info'][0]['iters']}", flush=True)
+    assert es < 1e-6 and eu < 1e-6, (what, es, eu)
 
 
 def small_stream(count=40, seed=355):
@@ -62,6 +86,68 @@ def test_server_results_equal_alone():
         assert torch.equal(r["u"], u), f"request {i}"
         assert r["info"][0]["iters"] == info[0]["iters"]
         assert r["times"]["total_ms"] >= r["times"]["run_ms"] >= 0.0
+        check_against_oracle(r, probs[i], f"request {i} ({specs[i]['dim']}-D n={specs[i]['n']})")
+
+
+@pytest.mark.timeout(600)
+def test_served_requests_at_stream_sizes_match_oracle():
+    """Requests of the served stream's largest kinds, admitted while others run:
+    2-D 1536^2 and 2048^2 (star Neumann, circle Dirichlet) and 3-D 96^3 and 192^3
+    (sphere, ellipsoid), each against the oracle's tight solve."""
+    specs = [
+        dict(dim=2, n=1536, shape="star", radius=0.3, bc=W.NEUMANN, alpha=700.0, m=5580, c=0.6, seed=21),
+        dict(dim=3, n=192, shape="ellipsoid", axes=(0.33, 0.27, 0.22), bc=W.DIRICHLET, alpha=4.0, m=12000,
+             c=1.3, seed=22),
+        dict(dim=2, n=2048, shape="circle", radius=0.21, bc=W.DIRICHLET, alpha=2.0, m=3400, c=0.8, seed=23),
+        dict(dim=3, n=96, shape="sphere", axes=(0.3, 0.3, 0.3), bc=W.DIRICHLET, alpha=900.0, m=5000, c=1.0,
+             seed=24),
+        dict(dim=2, n=768, shape="star", radius=0.3, bc=W.DIRICHLET, alpha=30.0, m=1500, c=1.1, seed=25),
+    ]
+    probs = [W.serve_instance(s) for s in specs]
+    srv = ibdl.Server(max_slots=64, streams=4)
+    tickets = [srv.submit_problem(probs[0]), srv.submit_problem(probs[1])]
+    t0 = time.perf_counter()
+    while srv.stats()["cohorts"] < 1 and time.perf_counter() - t0 < 10.0:
+        time.sleep(0.0005)
+    tickets += [srv.submit_problem(p) for p in probs[2:]]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for i, r in enumerate(res):
+        assert r["status"] == ibdl.OK
+        check_against_oracle(r, probs[i], f"{specs[i]['dim']}-D n={specs[i]['n']} {specs[i]['shape']}")
+
+
+def test_iteration_budget_is_per_request():
+    """maxit bounds each request by its own iterations, whatever its cohort: a fast
+    and a slow request admitted together end as each does alone."""
+    fast = W.serve_instance(dict(dim=2, n=128, shape="circle", radius=0.3, bc=W.DIRICHLET, alpha=900.0, m=600,
+                                 c=1.0, seed=3))
+    slow = W.serve_instance(dict(dim=2, n=128, shape="star", radius=0.3, bc=W.NEUMANN, alpha=1.0, m=600,
+                                 c=1.0, seed=4))
+    alone_f = alone(fast, ibdl.MIXED)
+    alone_s = alone(slow, ibdl.MIXED)
+    it_f, it_s = alone_f[2][0]["iters"], alone_s[2][0]["iters"]
+    assert it_s > it_f
+    # a budget the fast request meets alone: the slow one must not shrink it
+    maxit = it_f + 1
+    ref_f = _alone_budget(fast, maxit)
+    ref_s = _alone_budget(slow, maxit)
+    srv = ibdl.Server(max_slots=64, streams=1)
+    ts = [srv.submit_problem(p, maxit=maxit) for p in (slow, fast)]
+    res = [srv.wait(t, raise_on_error=False) for t in ts]
+    srv.close()
+    for r, ref in zip(res, (ref_s, ref_f)):
+        assert r["info"][0]["status"] == ref[2][0]["status"]
+        assert r["info"][0]["iters"] == ref[2][0]["iters"] <= maxit
+        assert torch.equal(r["sol"], ref[0])
+
+
+def _alone_budget(prob, maxit):
+    pl = ibdl.Plan.from_problem(prob, prec=ibdl.MIXED)
+    sol, u, info = pl.solve_grid(T(prob.data).reshape(1, -1), T(prob.g_tilde).reshape(1, -1), tol=1e-8,
+                                 maxit=maxit, raise_on_noconv=False)
+    pl.close()
+    return sol, u, info
 
 
 def test_server_admission_by_footprint():

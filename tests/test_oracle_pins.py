@@ -48,7 +48,7 @@ def test_phi_discrete_conditions(kind):
 
 
 def test_phi_peskin_values_and_support():
-    """Values of Eq. (delta eqn 2) at the knots, continuity at |r| = 1, support |r| < 2."""
+    """Values of Peskin's phi (Sec. 5.2) at the knots, continuity at |r| = 1, support |r| < 2."""
     assert O.phi_peskin4(0.0) == 0.5
     assert abs(O.phi_peskin4(1.0) - 0.25) < 1e-16
     assert abs(O.phi_peskin4(1.0 + 1e-12) - 0.25) < 1e-10
@@ -58,7 +58,7 @@ def test_phi_peskin_values_and_support():
 
 # ---------------------------------------------------------- spread / interp
 def _brute_delta(st, node_xyz, Xk):
-    """delta_h(x - X) summed over periodic images, straight from Eq. (delta eqn 1)."""
+    """delta_h(x - X) summed over periodic images, straight from delta_h = prod phi(x_d/h)/h (Sec. 5.2)."""
     tot = 0.0
     L = st.length
     for shift in np.ndindex(*([3] * st.dim)):
@@ -90,7 +90,7 @@ def test_spread_interp_bruteforce(dim, n, m, kind):
 
 @pytest.mark.parametrize("dim,n", [(2, 32), (3, 12)])
 def test_adjointness_and_moments(dim, n):
-    """<S F, u>_grid = <F, S* u>_Gamma (Eqs. (operators)-(adjoint)); S* 1 = 1; h^d sum S F = sum w F."""
+    """<S F, u>_grid = <F, S* u>_Gamma (Sec. 2.1, the adjointness of S and S*); S* 1 = 1; h^d sum S F = sum w F."""
     st = _setup(dim, n, 40, seed=3 * dim)
     rng = np.random.default_rng(7)
     F = rng.standard_normal(st.m)
@@ -174,7 +174,7 @@ def test_gmres_matches_dense_solve():
 @pytest.mark.parametrize("mode", [0, 3, 5])
 def test_circle_eigenvalues(mode):
     """On a circle the continuum Dirichlet operator maps e^{i m theta} to
-    mu_m = -kR I_m(kR) K_m'(kR) (double-layer jump, Sec. 2.2 and Eq. (ibdl connect5)
+    mu_m = -kR I_m(kR) K_m'(kR) (double-layer jump, Sec. 2.2 and the continuous limit of Sec. 4.1
     with Q = -gamma); the Neumann operator to mu_m - 1.  alpha = 1000 keeps the
     periodic images negligible; the discrete value converges at first order."""
     from scipy.special import iv, kvp
