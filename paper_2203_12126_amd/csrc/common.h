@@ -12,13 +12,20 @@ struct __align__(2 * sizeof(R)) cplx {
     R x, y;
 };
 
+// The library is built without floating-point contraction (-ffp-contract=off), so
+// every multiply-add that should be fused says so (fmac): the rounding of each
+// result then does not depend on how the compiler schedules a kernel's code, and
+// every workgroup shape of a pass gives bit-identical results.
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename R>
 __device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R>
 __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename R>
 __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fmac(a.x, b.x, -(a.y * b.y)), fmac(a.x, b.y, a.y * b.x)};
 }
 template <typename R>
 __device__ __forceinline__ cplx<R> cconj(cplx<R> a) { return {a.x, -a.y}; }

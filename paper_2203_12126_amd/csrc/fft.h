@@ -108,7 +108,7 @@ __device__ __forceinline__ void butterfly(cplx<R>* v) {
         const R s1 = R(0.86602540378443864676);  // sqrt(3)/2
         cplx<R> t = cadd(v[1], v[2]);
         cplx<R> d = csub(v[1], v[2]);
-        cplx<R> m = {v[0].x + c1 * t.x, v[0].y + c1 * t.y};
+        cplx<R> m = {fmac(c1, t.x, v[0].x), fmac(c1, t.y, v[0].y)};
         cplx<R> id = cmul_si<SIGN>(cscale(d, s1));
         v[0] = cadd(v[0], t);
         v[1] = cadd(m, id);

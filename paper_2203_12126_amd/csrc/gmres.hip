@@ -196,9 +196,9 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc -= hs[vi + u] * t[u];
+            for (int u = 0; u < 8; ++u) acc = fmac(-hs[vi + u], t[u], acc);
         }
-        for (; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
+        for (; vi <= j; ++vi) acc = fmac(-hs[vi], V[(size_t)vi * M + m], acc);
         wl = acc;
         w[m] = acc;
     }
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     __syncthreads();
     if (threadIdx.x == 0) {
         double q = 0.0;
-        for (int vi = 0; vi <= j; ++vi) q += hs[vi] * hs[vi];
+        for (int vi = 0; vi <= j; ++vi) q = fmac(hs[vi], hs[vi], q);
         const double d = hs[j + 1] - q;
         hn_s[0] = d > 0.0 ? sqrt(d) : 0.0;
         hn_s[1] = hs[j + 1];
@@ -258,9 +258,9 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc -= hs[vi + u] * t[u];
+            for (int u = 0; u < 8; ++u) acc = fmac(-hs[vi + u], t[u], acc);
         }
-        for (; vi <= j; ++vi) acc -= hs[vi] * V[(size_t)vi * M + m];
+        for (; vi <= j; ++vi) acc = fmac(-hs[vi], V[(size_t)vi * M + m], acc);
         w[m] = acc * inv;
     }
     if (blockIdx.x != 0) return;
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     double* g = a.g + (size_t)r * (a.m + 1);
     hc_s[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-        const double t = cs_s[i] * hc_s[i] + sn_s[i] * hc_s[i + 1];
-        hc_s[i + 1] = -sn_s[i] * hc_s[i] + cs_s[i] * hc_s[i + 1];
+        const double t = fmac(cs_s[i], hc_s[i], sn_s[i] * hc_s[i + 1]);
+        hc_s[i + 1] = fmac(-sn_s[i], hc_s[i], cs_s[i] * hc_s[i + 1]);
         hc_s[i] = t;
     }
     const double den = hypot(hc_s[j], hc_s[j + 1]);
@@ -358,9 +358,9 @@ __global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* xpool) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) t[u] = V[(size_t)(vi + u) * M + m];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += ys[vi + u] * t[u];
+        for (int u = 0; u < 8; ++u) acc = fmac(ys[vi + u], t[u], acc);
     }
-    for (; vi < jr; ++vi) acc += ys[vi] * V[(size_t)vi * M + m];
+    for (; vi < jr; ++vi) acc = fmac(ys[vi], V[(size_t)vi * M + m], acc);
     xpool[a.xoff[r] + m] = acc;
 }
 

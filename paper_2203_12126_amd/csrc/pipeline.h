@@ -354,7 +354,8 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc.add(ww[u], qq[u]);
         }
-        sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)] += (R)c.coef * acc.value();
+        R& node = sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)];
+        node = fmac((R)c.coef, acc.value(), node);
     }
     __syncthreads();
 }
@@ -849,7 +850,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int x = (cx - 1 + t + N) % N;
-                acc += tp[t] * sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)];
+                acc = fmac(tp[t], sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)], acc);
             }
             acc *= tp[4 + oy];
             int o = oy;
