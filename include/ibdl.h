@@ -119,6 +119,20 @@ size_t ibdl_plan_footprint(const ibdl_desc* desc, int32_t nrhs, int32_t restart)
  * A is the Dirichlet or Neumann operator chosen by the plan's bc. */
 ibdl_status ibdl_apply(ibdl_plan plan, int32_t nrhs, const double* q, double* Aq, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): ibdl_apply with the
+ * pass's half spectra and gather partial sums in a fixed device scratch area of
+ * 256 MiB that the library holds on each device from its first call there until
+ * the process ends.  Calls no hipMalloc, hipFree or other allocating routine; row
+ * shapes not tuned yet take the fixed rule instead of being timed.  The scratch
+ * must hold nrhs * (spectrum + partials) of the plan's precision: FP64 plans
+ * nrhs * (nlines * pitch * 16 + M * 4^(dim-1) * 8) bytes, MIXED plans half of it
+ * (ibdl_plan_get_stats gives nlines and pitch); larger calls return IBDL_ERR_ARG
+ * before any work.  Every call on a device shares that device's scratch, so calls
+ * whose work overlaps on one device (different streams, or host threads) race:
+ * order them on one stream.  Results equal ibdl_apply's. */
+ibdl_status ibdl_apply_noalloc(ibdl_plan plan, int32_t nrhs, const double* q, double* Aq, void* stream);
+
 /* Right-hand side of the boundary equation (async):
  *   Dirichlet  b = U_b - S* L^-1 g~               (Sec. 5.3, right side of the equation for Q)
  *   Neumann    b = S* L^-1 (S V_b - g~)           (Sec. 4.4, right side of the equation for U_b)

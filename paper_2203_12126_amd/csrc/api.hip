@@ -230,6 +230,46 @@ void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, doub
     run_pipeline(p, nrhs, in, o, st);
 }
 
+// ------------------------------------------------------------------ allocation-free apply
+// The device scratch of ibdl_apply_noalloc: the half spectra and gather partial
+// sums of its pass.  Each device that loads the library holds its own copy until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// the current device's scratch address, looked up once per device
+static char* scratch_base() {
+    int dev = 0;
+    IBDL_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error{IBDL_ERR_HIP, "device index beyond the scratch table"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        IBDL_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error{IBDL_ERR_HIP, "hipGetSymbolAddress gave no scratch address"};
+        g_scratch_dev[dev] = ptr;
+    }
+    return reinterpret_cast<char*>(g_scratch_dev[dev]);
+}
+
+// bytes of scratch the pass of ibdl_apply_noalloc needs: spectra and partials in
+// the precision of the plan's operator pass, each part 256-byte aligned
+static size_t noalloc_bytes(ibdl_plan p, int nrhs, size_t* spec_bytes) {
+    const bool f64 = p->prec == IBDL_PREC_FP64;
+    const size_t cs = f64 ? 16 : 8, rs = f64 ? 8 : 4;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t sb = up((size_t)nrhs * p->spec_elems * cs);
+    if (spec_bytes) *spec_bytes = sb;
+    return sb + up((size_t)nrhs * p->M * p->gpp * rs);
+}
+
 // ------------------------------------------------------------------ tile autotuner
 namespace {
 std::mutex g_tune_mu;
@@ -385,6 +425,43 @@ ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, v
     AllocStream as(S(stream));
     p->last_stream = S(stream);
     apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_apply_noalloc(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!q || !Aq) return fail(IBDL_ERR_ARG, "q and Aq must be device pointers");
+    if (q == Aq) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
+    size_t spec_b = 0;
+    const size_t need = noalloc_bytes(p, nrhs, &spec_b);
+    if (need > kScratchBytes)
+        return fail(IBDL_ERR_ARG, "ibdl_apply_noalloc: " + std::to_string(nrhs) + " right-hand sides of this plan need " +
+                                      std::to_string(need) + " bytes of scratch, more than its " +
+                                      std::to_string(kScratchBytes) + " (use fewer right-hand sides per call)");
+    IBDL_GUARD_BEGIN
+    char* base = scratch_base();
+    // the pass reads its workspace from the plan: point it at the scratch for this
+    // call (the kernels take the addresses at launch) and restore it afterwards;
+    // untuned row shapes take the fixed rule instead of timing every shape
+    const Workspace saved = p->ws;
+    const bool was_capturing = capturing();
+    p->ws.spec = base;
+    p->ws.part = base + spec_b;
+    p->ws.qf = nullptr;
+    p->ws.cap_rhs = nrhs;
+    capturing() = true;
+    try {
+        apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
+    } catch (...) {
+        p->ws = saved;
+        capturing() = was_capturing;
+        throw;
+    }
+    p->ws = saved;
+    capturing() = was_capturing;
+    p->last_stream = S(stream);
     return IBDL_OK;
     IBDL_GUARD_END
 }

@@ -86,6 +86,7 @@ def lib():
         "ibdl_plan_destroy": ([P], st),
         "ibdl_plan_footprint": ([ctypes.POINTER(Desc), I, I], ctypes.c_size_t),
         "ibdl_apply": ([P, I, P, P, P], st),
+        "ibdl_apply_noalloc": ([P, I, P, P, P], st),
         "ibdl_rhs": ([P, I, P, P, P, P], st),
         "ibdl_solve": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveInfo), P], st),
         "ibdl_solve_grid": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(SolveInfo), P], st),
@@ -245,6 +246,14 @@ class Plan:
         out = self._empty(*q.shape) if out is None else out
         _check(lib().ibdl_apply(self._h, nrhs, _dptr(q, "q"), _dptr(out, "Aq", q.numel()),
                                 _stream(stream)), "ibdl_apply")
+        return out
+
+    def apply_noalloc(self, q, out, stream=None):
+        """ibdl_apply_noalloc: the operator with the library's fixed device scratch
+        (no device allocation; out must be given)."""
+        nrhs = self._nrhs(q, self.m)
+        _check(lib().ibdl_apply_noalloc(self._h, nrhs, _dptr(q, "q"), _dptr(out, "Aq", q.numel()),
+                                        _stream(stream)), "ibdl_apply_noalloc")
         return out
 
     def rhs(self, data, g=None, out=None, stream=None):
