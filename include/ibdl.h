@@ -65,6 +65,14 @@ typedef enum { IBDL_DELTA_PESKIN4 = 0, IBDL_DELTA_COSINE4 = 1 } ibdl_delta;
  *        identity term, all GMRES arithmetic and every output stay FP64. */
 typedef enum { IBDL_PREC_FP64 = 0, IBDL_PREC_MIXED = 1 } ibdl_prec;
 
+/* Discretisation of the Laplacian in L = Lap_h - alpha (both diagonal in the DFT):
+ * FD is the 5-point (2-D) / 7-point (3-D) stencil, eigenvalues
+ * -(4/h^2) sin^2(pi m_d/n) per axis (Sec. 5.1); SPECTRAL is the Fourier-spectral
+ * Laplacian, -(2 pi k_d/L)^2 per axis with k_d the signed frequency of mode m_d
+ * (Sec. 6.2.1).  The divergence inside S~ stays the centred difference of Sec. 5.2
+ * in both. */
+typedef enum { IBDL_LAP_FD = 0, IBDL_LAP_SPECTRAL = 1 } ibdl_lap;
+
 typedef struct {
     int32_t dim;          /* 2 or 3                                                        */
     int32_t n;            /* nodes per axis, n = 2^a 3^b, 8 <= n <= 2048 (2-D), <= 512 (3-D) */
@@ -79,6 +87,7 @@ typedef struct {
     const double* normal; /* device [M][dim] unit normals pointing OUT of Omega (Sec. 4.1)    */
     const double* weight; /* device [M] quadrature weights: arclength Delta s_i (2-D, Sec. 5.2)
                              or area dA_i (3-D, Sec. 6.7), > 0                               */
+    int32_t lap;          /* ibdl_lap                                                       */
 } ibdl_desc;
 
 typedef struct {
@@ -174,6 +183,38 @@ ibdl_status ibdl_solve_grid(ibdl_plan plan, int32_t nrhs, const double* data, co
  * g: device [nrhs][n^dim] or NULL; u: device [nrhs][n^dim]. */
 ibdl_status ibdl_eval_grid(ibdl_plan plan, int32_t nrhs, const double* sol, const double* vb,
                            const double* g, double* u, void* stream);
+
+/* Step 3 of the method (Sec. 4.2, Sec. 5.5), first part: the PDE domain on the
+ * grid from the regularised indicator function of App. D (async).
+ *   chi = -Delta_0^-1 S~ 1 - (its value at the corner node lo)
+ * (the FP64 grid pipeline with unit strengths and the mean-zero inverse of the
+ * Laplacian, whatever the plan's alpha).  For normals pointing away from the
+ * region the boundary encloses (Omega that region) chi is about 1 in Omega and 0
+ * elsewhere and flags = chi > 1/2; for normals pointing into it (Omega the rest of
+ * the box) chi is about -1 inside and flags = chi > -1/2.  The orientation is the
+ * sign of sum_k w_k (X_k - X_0) . n_k.  chi: device [n^dim] FP64 out; flags:
+ * device [n^dim] uint8 out, 1 for nodes of Omega. */
+ibdl_status ibdl_indicator(ibdl_plan plan, double* chi, uint8_t* flags, void* stream);
+
+/* Step 3, second part: the re-interpolation of App. A (async).  u_out = u except at
+ * nodes with flags = 1 whose nearest boundary point lies within m1 meshwidths:
+ *   u(x_p) = u(x_A) |x_B - x_p| / |x_B - x_A| + u(x_B) |x_A - x_p| / |x_B - x_A|,
+ * with x_A the point nearest x_p on the chord of its two nearest boundary points
+ * (2-D; when the foot of the perpendicular leaves the chord, the two of its three
+ * nearest points farthest apart span the chord, clamped to it), u(x_A) the linear
+ * interpolation of ub along the chord; in 3-D x_A is the nearest boundary point and
+ * u(x_A) its ub; x_B = x_A + (x_p - x_A)/|x_p - x_A| m2 h and u(x_B) the bilinear
+ * (2-D) or trilinear (3-D) interpolation of u.  Values are read from u only.
+ * The paper's widths are m1 = 6, m2 = 8 with the finite-difference Laplacian
+ * (Sec. 6.1) and m1 = 2(log2 n - 4), m2 = m1 + 2 with the spectral one (Sec. 6.2.1).
+ * u, u_out: device [nrhs][n^dim], distinct; ub: device [nrhs][M] boundary values
+ * (U_b: the Dirichlet data, or the solved U_b of a Neumann plan), caller order;
+ * flags: device [n^dim] from ibdl_indicator (or the caller's).  2-D points more
+ * than two meshwidths apart may make the second and third nearest points fall
+ * outside the cells searched (m1 + 5 cells around the node).
+ * Errors: IBDL_ERR_ARG for 0 < m1 < m2 <= n/4 violated or missing buffers. */
+ibdl_status ibdl_fixup(ibdl_plan plan, int32_t nrhs, const double* u, const double* ub, const uint8_t* flags,
+                       double m1, double m2, double* u_out, void* stream);
 
 /* The plan's binning (for inspection and tests), copied to HOST arrays of M
  * entries: key[k] = cell key of caller point k; perm[s] = caller index of the

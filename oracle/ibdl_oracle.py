@@ -20,7 +20,11 @@ Helmholtz equation"):
 * the grid solution  L u = g~ - S~Q  (- S V_b for Neumann) (Sec. 4.2 step 2; Sec. 4.4, the Neumann grid equation)
 * unpreconditioned GMRES on the boundary density           (Sec. 5.3)
 * the mean-zero inverse for alpha = 0                      (Sec. 5.4.2; App. C)
-* the indicator-function construction                      (App. D)
+* the Fourier-spectral Laplacian as an alternative to the
+  finite-difference one                                    (Sec. 5.1; Sec. 6.2.1)
+* the indicator-function construction and the flags of the
+  PDE domain                                               (App. D)
+* the near-boundary re-interpolation of the grid solution  (Sec. 5.5; App. A)
 * the discrete L1/L2 norms rescaled by |Omega|             (Sec. 5.1)
 
 Library primitives used as single steps: numpy's FFT (the DFT that diagonalises
@@ -44,6 +48,8 @@ DIRICHLET = 0
 NEUMANN = 1
 PESKIN4 = "peskin4"
 COSINE4 = "cosine"
+LAP_FD = "fd"              # the 5-point (2-D) / 7-point (3-D) Laplacian (Sec. 5.1)
+LAP_SPECTRAL = "spectral"  # the Fourier-spectral Laplacian (Sec. 6.2.1)
 
 
 # ----------------------------------------------------------------------------
@@ -86,6 +92,7 @@ class Setup:
     normal: np.ndarray    # (M, dim), pointing out of Omega
     weight: np.ndarray    # (M,) Delta s_i or dA_i
     delta: str = PESKIN4
+    lap: str = LAP_FD     # discretisation of the Laplacian in L = Lap_h - alpha
 
     @property
     def h(self):
@@ -100,11 +107,11 @@ class Setup:
         return (self.n,) * self.dim
 
 
-def setup_from_problem(prob, delta=PESKIN4) -> Setup:
+def setup_from_problem(prob, delta=PESKIN4, lap=LAP_FD) -> Setup:
     g = prob.grid
     return Setup(g.dim, g.n, np.asarray(g.lo, dtype=np.float64), float(g.length), float(prob.alpha),
                  np.asarray(prob.geom.X, dtype=np.float64), np.asarray(prob.geom.normal, dtype=np.float64),
-                 np.asarray(prob.geom.weight, dtype=np.float64), delta)
+                 np.asarray(prob.geom.weight, dtype=np.float64), delta, lap)
 
 
 def _axis(st: Setup, d: int) -> int:
@@ -187,11 +194,18 @@ def spread_dipole(st: Setup, Q):
 # L = Lap_h - alpha on the periodic box (Sec. 5.1, Sec. 5.3, App. C)
 # ----------------------------------------------------------------------------
 def symbol(st: Setup):
-    """Eigenvalues of the periodic 5-point (2-D) / 7-point (3-D) Laplacian minus alpha."""
+    """Eigenvalues of the periodic Laplacian minus alpha on the DFT modes m:
+    5-point (2-D) / 7-point (3-D) stencil, -(4/h^2) sin^2(pi m_d/n) per axis
+    (Sec. 5.1); Fourier-spectral, -(2 pi k_d/L)^2 per axis with k_d the signed
+    frequency of m_d (Sec. 6.2.1)."""
     lam = np.zeros(st.shape)
     for d in range(st.dim):
         m = np.arange(st.n)
-        ev = -(4.0 / st.h ** 2) * np.sin(np.pi * m / st.n) ** 2
+        if st.lap == LAP_SPECTRAL:
+            k = np.where(m <= st.n // 2, m, m - st.n)
+            ev = -(2.0 * np.pi * k / st.length) ** 2
+        else:
+            ev = -(4.0 / st.h ** 2) * np.sin(np.pi * m / st.n) ** 2
         sh = [1] * st.dim
         sh[_axis(st, d)] = st.n
         lam = lam + ev.reshape(sh)
@@ -199,7 +213,8 @@ def symbol(st: Setup):
 
 
 def apply_L(st: Setup, u):
-    """L u with the explicit stencil (used to check the inverse)."""
+    """L u with the explicit stencil (used to check the inverse; finite differences only)."""
+    assert st.lap == LAP_FD
     out = -st.alpha * u
     for d in range(st.dim):
         ax = _axis(st, d)
@@ -356,10 +371,117 @@ def binning(st: Setup):
 # ----------------------------------------------------------------------------
 def indicator(st: Setup, corner_index=0):
     """chi_h = -Delta_0^-1 S~ 1 shifted so the chosen corner node is 0; and its 1/2 threshold."""
-    st0 = Setup(st.dim, st.n, st.lo, st.length, 0.0, st.X, st.normal, st.weight, st.delta)
+    st0 = Setup(st.dim, st.n, st.lo, st.length, 0.0, st.X, st.normal, st.weight, st.delta, st.lap)
     u = -solve_L(st0, spread_dipole(st0, np.ones(st.m)))
     chi_h = u - u.flat[corner_index]
     return chi_h, (chi_h > 0.5).astype(np.int8)
+
+
+def orientation(st: Setup):
+    """+1 when the normals point away from the region the boundary encloses (the PDE
+    domain is that region), -1 when they point into it (the PDE domain is the rest of
+    the box): the sign of sum_k w_k (X_k - X_0) . n_k, the discrete form of the
+    divergence theorem's  int_Gamma x . n ds = d |enclosed region|  for outward n."""
+    v = float(np.sum(st.weight * np.sum((st.X - st.X[0]) * st.normal, axis=1)))
+    return 1 if v > 0.0 else -1
+
+
+def omega_flags(st: Setup):
+    """App. D with the corner as the far-field reference: chi_h is ~1 inside the
+    enclosed region for outward normals, so the PDE domain is chi_h > 1/2; with
+    normals pointing into the enclosed region chi_h is ~-1 there and 0 in the
+    domain, which is then chi_h > -1/2.  Returns (chi_h, flags of the domain)."""
+    chi_h, _ = indicator(st)
+    thr = 0.5 if orientation(st) > 0 else -0.5
+    return chi_h, (chi_h > thr).astype(np.int8)
+
+
+def _min_image(st: Setup, v):
+    """Periodic minimum-image form of displacement vectors."""
+    L = st.length
+    return v - L * np.round(v / L)
+
+
+def near_boundary_fixup(st: Setup, u, ub, in_omega, m1=6.0, m2=8.0):
+    """App. A: every node of the PDE domain whose nearest boundary point lies within
+    m1 meshwidths gets u(x_p) = u(x_A) |x_B - x_p|/|x_B - x_A| + u(x_B) |x_A - x_p|/|x_B - x_A|.
+
+    2-D: x_A is the point of the segment between the two nearest boundary points x1,
+    x2 closest to x_p (orthogonal projection; when it falls outside the segment the
+    third nearest point is taken and the two of the three farthest apart span the
+    segment), with u(x_A) interpolated linearly from U_b(x1), U_b(x2).
+    3-D: x_A is the nearest boundary point and u(x_A) its U_b.
+    x_B = x_A + (x_p - x_A)/|x_p - x_A| m2 h, with u(x_B) the bi-/trilinear
+    interpolation of the grid solution.  Values are read from u before any
+    replacement.  Returns the new grid and the mask of replaced nodes."""
+    from scipy.spatial import cKDTree
+    u = np.asarray(u, dtype=np.float64)
+    ub = np.asarray(ub, dtype=np.float64)
+    h, L, d = st.h, st.length, st.dim
+    out = u.copy()
+    done = np.zeros(st.shape, dtype=bool)
+    tree = cKDTree(np.mod(st.X - st.lo, L), boxsize=L)
+    nodes = np.stack([c.ravel() for c in _grid_nodes(st)], axis=1)
+    dist, idx = tree.query(np.mod(nodes - st.lo, L), k=3 if d == 2 else 1)
+    d1 = dist[:, 0] if d == 2 else dist
+    cand = np.nonzero((np.asarray(in_omega).ravel() != 0) & (d1 <= m1 * h))[0]
+    for p in cand:
+        xp = nodes[p]
+        if d == 2:
+            i1, i2, i3 = idx[p]
+            x1 = xp + _min_image(st, st.X[i1] - xp)
+            x2 = xp + _min_image(st, st.X[i2] - xp)
+            e = x1 - x2
+            t = float(np.dot(xp - x2, e) / np.dot(e, e))
+            if t < 0.0 or t > 1.0:
+                x3 = xp + _min_image(st, st.X[i3] - xp)
+                pairs = [((i1, x1), (i2, x2)), ((i1, x1), (i3, x3)), ((i2, x2), (i3, x3))]
+                (i1, x1), (i2, x2) = max(pairs, key=lambda ab: float(np.sum((ab[0][1] - ab[1][1]) ** 2)))
+                e = x1 - x2
+                t = min(1.0, max(0.0, float(np.dot(xp - x2, e) / np.dot(e, e))))
+            xa = x2 + t * e
+            le = math.sqrt(float(np.dot(e, e)))
+            ua = (ub[i1] * math.sqrt(float(np.sum((xa - x2) ** 2))) +
+                  ub[i2] * math.sqrt(float(np.sum((xa - x1) ** 2)))) / le
+        else:
+            i1 = idx[p]
+            xa = xp + _min_image(st, st.X[i1] - xp)
+            ua = ub[i1]
+        dp = math.sqrt(float(np.sum((xp - xa) ** 2)))
+        if dp == 0.0:
+            val = ua
+        else:
+            xb = xa + (xp - xa) / dp * (m2 * h)
+            ubv = _multilinear(st, u, xb)
+            dab = math.sqrt(float(np.sum((xb - xa) ** 2)))
+            dbp = math.sqrt(float(np.sum((xb - xp) ** 2)))
+            val = ua * dbp / dab + ubv * dp / dab
+        out.flat[p] = val
+        done.flat[p] = True
+    return out, done
+
+
+def _grid_nodes(st: Setup):
+    ax = [st.lo[dd] + st.h * np.arange(st.n) for dd in range(st.dim)]
+    mesh = np.meshgrid(*ax[::-1], indexing="ij")
+    return tuple(mesh[::-1])
+
+
+def _multilinear(st: Setup, u, x):
+    """Bi-/trilinear interpolation of the grid field u at the point x (periodic)."""
+    t = (np.asarray(x) - st.lo) / st.h
+    fl = np.floor(t)
+    fr = t - fl
+    val = 0.0
+    for corner in range(2 ** st.dim):
+        w = 1.0
+        ix = []
+        for dd in range(st.dim):
+            bit = (corner >> dd) & 1
+            w *= fr[dd] if bit else 1.0 - fr[dd]
+            ix.append(int(fl[dd] + bit) % st.n)
+        val += w * u[tuple(ix[::-1])]
+    return val
 
 
 def norms(st: Setup, err, mask, area):

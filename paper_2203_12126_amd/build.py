@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibdl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "plan.hip", "gmres.hip", "server.hip", "pipeline_f64.hip", "pipeline_f32.hip"]
+SOURCES = ["api.hip", "plan.hip", "gmres.hip", "server.hip", "nearfix.hip", "pipeline_f64.hip",
+           "pipeline_f32.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -50,6 +50,7 @@ std::string check_desc(const ibdl_desc* d) {
     if (d->bc != IBDL_DIRICHLET && d->bc != IBDL_NEUMANN) return "bc must be IBDL_DIRICHLET or IBDL_NEUMANN";
     if (d->delta != IBDL_DELTA_PESKIN4 && d->delta != IBDL_DELTA_COSINE4) return "unknown delta kernel";
     if (d->prec != IBDL_PREC_FP64 && d->prec != IBDL_PREC_MIXED) return "unknown precision";
+    if (d->lap != IBDL_LAP_FD && d->lap != IBDL_LAP_SPECTRAL) return "lap must be IBDL_LAP_FD or IBDL_LAP_SPECTRAL";
     if (d->npts < 1) return "npts must be >= 1";
     // spread entries per point (dipole stencil); the spread kernels address the
     // entries' FP64 weights with 32-bit byte offsets
@@ -347,6 +348,7 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
         p->n = desc->n;
         p->bc = desc->bc;
         p->delta = desc->delta;
+        p->lap = desc->lap;
         p->prec = desc->prec;
         p->M = desc->npts;
         for (int i = 0; i < 3; ++i) p->lo[i] = i < desc->dim ? desc->lo[i] : 0.0;
@@ -395,8 +397,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += R * nlines * P * 16 + R * M * gpp * 8;
     // mixed: the Arnoldi step's strengths as FP32 in groups of four right-hand sides
     if (d->prec == IBDL_PREC_MIXED) b += (R + 3) / 4 * 4 * M * 4;
-    // sorted geometry: key, perm, skey, invperm, cell, normals, weights, taps (FP64 + FP32)
-    b += M * (16 + 12 + 24 + 8 + 96 + 48);
+    // sorted geometry: key, perm, skey, invperm, cell, coordinates, normals, weights, taps (FP64 + FP32)
+    b += M * (16 + 12 + 24 + 24 + 8 + 96 + 48);
     // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
     const size_t nd = M * (dim == 2 ? 32 : 160);
     const size_t nm = d->bc == IBDL_NEUMANN ? M * (dim == 2 ? 16 : 64) : 0;
@@ -558,6 +560,34 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     PipeOut out;
     out.u = u;
     run_pipeline(p, nrhs, in, out, S(stream), true);
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_indicator(ibdl_plan p, double* chi, uint8_t* flags, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (!chi || !flags) return fail(IBDL_ERR_ARG, "chi and flags must be device pointers");
+    IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
+    nearfix_indicator(p, chi, flags, S(stream));
+    return IBDL_OK;
+    IBDL_GUARD_END
+}
+
+ibdl_status ibdl_fixup(ibdl_plan p, int32_t nrhs, const double* u, const double* ub, const uint8_t* flags,
+                       double m1, double m2, double* u_out, void* stream) {
+    if (!p) return fail(IBDL_ERR_ARG, "plan is NULL");
+    if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
+    if (!u || !ub || !flags || !u_out) return fail(IBDL_ERR_ARG, "u, ub, flags and u_out must be device pointers");
+    if (u == u_out) return fail(IBDL_ERR_ARG, "u and u_out must not overlap");
+    if (!(m1 > 0.0) || !std::isfinite(m1) || !(m2 > m1) || !std::isfinite(m2))
+        return fail(IBDL_ERR_ARG, "widths must satisfy 0 < m1 < m2");
+    if (m2 > 0.25 * p->n) return fail(IBDL_ERR_ARG, "m2 must stay below a quarter of the grid");
+    IBDL_GUARD_BEGIN
+    AllocStream as(S(stream));
+    p->last_stream = S(stream);
+    nearfix_fixup(p, nrhs, u, ub, flags, m1, m2, u_out, S(stream));
     return IBDL_OK;
     IBDL_GUARD_END
 }

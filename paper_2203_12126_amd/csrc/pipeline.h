@@ -1380,7 +1380,9 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ca.width = p->W;
         ca.tw = PP::tw(p);
         ca.s2 = PP::s2(p);
-        ca.alpha = (R)p->alpha;
+        if (in.alpha_zero && sizeof(R) == 4 && p->dim == 2)
+            throw Error{IBDL_ERR_HIP, "a mean-zero pass needs the FP64 pipeline"};
+        ca.alpha = in.alpha_zero ? R(0) : (R)p->alpha;
         ca.norm = (R)(2.0 / ((double)p->nlines * (double)n));
         if constexpr (sizeof(R) == 4) {
             if (p->dim == 2 && !p->sym32) throw Error{IBDL_ERR_HIP, "2-D plan without its FP32 symbol table"};

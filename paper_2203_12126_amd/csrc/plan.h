@@ -141,6 +141,7 @@ struct KrylovSet {
 struct ibdl_plan_s {
     // description
     int dim = 2, n = 0, bc = 0, delta = 0, prec = 0, M = 0;
+    int lap = IBDL_LAP_FD;  // Laplacian discretisation (ibdl_lap)
     double lo[3] = {0, 0, 0}, length = 1, h = 1, alpha = 0;
     int P = 0;          // complex elements per line of the tiled half spectrum (>= n/2+1)
     int W = 0;          // half-spectrum width n/2+1
@@ -156,6 +157,7 @@ struct ibdl_plan_s {
     int32_t* cell = nullptr;        // [M][3] cell of sorted point s
     double* taps64 = nullptr;       // [M][3][4] phi(p - t) for p = c-1..c+2, sorted order
     float* taps32 = nullptr;
+    double* X = nullptr;            // [M][3] caller order (coordinates as given)
     double* nrm = nullptr;          // [M][3] caller order
     double* wgt = nullptr;          // [M] caller order
     int32_t* line_start = nullptr;  // [nlines+1] first sorted point of each x-line (cell key / n)
@@ -176,11 +178,18 @@ struct ibdl_plan_s {
     // tables
     double* tw64 = nullptr;   // [n] exp(-2 pi i m/n) as (re, im)
     float* tw32 = nullptr;
-    double* s2_64 = nullptr;  // [n] (4/h^2) sin^2(pi m/n)
+    double* s2_64 = nullptr;  // [n] minus the 1-D Laplacian eigenvalue of mode m: (4/h^2) sin^2(pi m/n)
+                              // (finite differences) or (2 pi k/L)^2, k the signed frequency (spectral)
     float* s2_32 = nullptr;
     // 2-D mixed plans: the FP32 column pass's factor norm / lambda(kx, ky) for every
     // element of the half spectrum, in its column-tile layout [tile][ky][C]
     float* sym32 = nullptr;
+
+    // near-boundary step, allocated at its first use: unit strengths, the candidate
+    // mask of the re-interpolation and two reference values of the indicator
+    double* ones = nullptr;
+    uint8_t* fix_mask = nullptr;
+    double* fix_refs = nullptr;
 
     ibdl::Workspace ws;
     ibdl::KrylovSet ks;     // Krylov state of solves through this plan alone
@@ -220,6 +229,8 @@ struct PipeIn {
     // q_dip is first copied in the pass's precision into the plan's workspace in
     // groups of four right-hand sides (ws.qf), which the spread reads instead
     bool pack_q = false;
+    // invert Lap_h with alpha = 0 (mean-zero) whatever the plan's alpha (FP64 passes)
+    bool alpha_zero = false;
 };
 struct PipeOut {
     // gather: out[k] = cA * (S* u)_k + cB * in[k] + cC * in2[k]   (strides 0: M)
@@ -311,6 +322,10 @@ int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
 int col_width_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
+// near-boundary step (nearfix.hip): App. D indicator and flags, App. A fix-up
+void nearfix_indicator(ibdl_plan p, double* chi, uint8_t* flags, hipStream_t st);
+void nearfix_fixup(ibdl_plan p, int nrhs, const double* u, const double* ub, const uint8_t* flags, double m1,
+                   double m2, double* uout, hipStream_t st);
 void free_build_tmp(ibdl_plan p);
 // frees every device allocation of a plan in stream order on st (no wait) and the plan
 void release_plan(ibdl_plan p, hipStream_t st);

@@ -10,7 +10,9 @@
 //    as rows over the active grid nodes: every (node, point) pair the stencil
 //    reaches is emitted, sorted by (node, point), and weighed;
 //  * the x-lines that receive forcing and the x-lines interpolated from;
-//  * twiddles exp(-2 pi i m/n) and the symbol terms (4/h^2) sin^2(pi m/n).
+//  * twiddles exp(-2 pi i m/n) and the symbol terms: (4/h^2) sin^2(pi m/n) for the
+//    finite-difference Laplacian (Sec. 5.1), (2 pi k/L)^2 with k the signed
+//    frequency for the Fourier-spectral one (Sec. 6.2.1).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -155,10 +157,11 @@ __global__ void k_check_geom(const double* __restrict__ nrm, const double* __res
     if (!(w[k] > 0.0) || !isfinite(w[k])) bad[2] = 1;
 }
 
-__global__ void k_copy_geom(const double* __restrict__ nrm, const double* __restrict__ w, int M,
-                            int dim, double* nrm3, double* w1) {
+__global__ void k_copy_geom(const double* __restrict__ X, const double* __restrict__ nrm,
+                            const double* __restrict__ w, int M, int dim, double* X3, double* nrm3, double* w1) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
+    for (int d = 0; d < 3; ++d) X3[3 * k + d] = d < dim ? X[(size_t)k * dim + d] : 0.0;
     for (int d = 0; d < 3; ++d) nrm3[3 * k + d] = d < dim ? nrm[(size_t)k * dim + d] : 0.0;
     w1[k] = w[k];
 }
@@ -606,7 +609,8 @@ __global__ void k_compact_list(const int32_t* __restrict__ flag, const int32_t* 
 }
 
 // ------------------------------------------------------------------ tables
-__global__ void k_tables(int n, double h, double* tw64, float* tw32, double* s264, float* s232) {
+__global__ void k_tables(int n, double h, double length, int spectral, double* tw64, float* tw32, double* s264,
+                         float* s232) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
     double sv, cv;
@@ -615,8 +619,14 @@ __global__ void k_tables(int n, double h, double* tw64, float* tw32, double* s26
     tw64[2 * m + 1] = -sv;
     tw32[2 * m] = (float)cv;
     tw32[2 * m + 1] = (float)(-sv);
-    const double sp = sinpi((double)m / (double)n);
-    const double v = 4.0 / (h * h) * sp * sp;
+    double v;
+    if (spectral) {
+        const double k = 2.0 * M_PI * (double)(m <= n / 2 ? m : m - n) / length;
+        v = k * k;
+    } else {
+        const double sp = sinpi((double)m / (double)n);
+        v = 4.0 / (h * h) * sp * sp;
+    }
     s264[m] = v;
     s232[m] = (float)v;
 }
@@ -702,10 +712,11 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     if (hb[1]) throw Error{IBDL_ERR_ARG, "normals must have unit length"};
     if (hb[2]) throw Error{IBDL_ERR_ARG, "weights must be positive and finite"};
 
+    p->X = alloc_n<double>(p, 3 * (size_t)M);
     p->nrm = alloc_n<double>(p, 3 * (size_t)M);
     p->wgt = alloc_n<double>(p, M);
-    hipLaunchKernelGGL(k_copy_geom, dim3(nblocks(M, 256)), dim3(256), 0, st, d->normal, d->weight, M,
-                       dim, p->nrm, p->wgt);
+    hipLaunchKernelGGL(k_copy_geom, dim3(nblocks(M, 256)), dim3(256), 0, st, d->X, d->normal, d->weight, M,
+                       dim, p->X, p->nrm, p->wgt);
 
     // stable order of (key, index)
     const size_t n2 = pow2_at_least((size_t)M, BIT_BLOCK);
@@ -761,8 +772,8 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     p->tw32 = alloc_n<float>(p, 2 * (size_t)n);
     p->s2_64 = alloc_n<double>(p, n);
     p->s2_32 = alloc_n<float>(p, n);
-    hipLaunchKernelGGL(k_tables, dim3(nblocks(n, 256)), dim3(256), 0, st, n, p->h, p->tw64, p->tw32,
-                       p->s2_64, p->s2_32);
+    hipLaunchKernelGGL(k_tables, dim3(nblocks(n, 256)), dim3(256), 0, st, n, p->h, p->length,
+                       p->lap == IBDL_LAP_SPECTRAL ? 1 : 0, p->tw64, p->tw32, p->s2_64, p->s2_32);
     if (dim == 2 && p->prec == IBDL_PREC_MIXED) {
         const size_t total = (size_t)tile_pitch_f32(n) * n;
         p->sym32 = alloc_n<float>(p, total);

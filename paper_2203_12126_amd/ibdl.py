@@ -18,6 +18,7 @@ OK, ERR_ARG, ERR_OOM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC, ERR_STATE = range(7)
 DIRICHLET, NEUMANN = 0, 1
 PESKIN4, COSINE4 = 0, 1
 FP64, MIXED = 0, 1
+LAP_FD, LAP_SPECTRAL = 0, 1
 
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NUMERIC",
            6: "ERR_STATE"}
@@ -33,7 +34,8 @@ class Desc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("lo", ctypes.c_double * 3),
                 ("length", ctypes.c_double), ("alpha", ctypes.c_double), ("bc", ctypes.c_int32),
                 ("delta", ctypes.c_int32), ("prec", ctypes.c_int32), ("npts", ctypes.c_int32),
-                ("X", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+                ("X", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("lap", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -92,6 +94,8 @@ def lib():
         "ibdl_solve_grid": ([P, I, P, P, ctypes.POINTER(SolveOpts), P, P, ctypes.POINTER(SolveInfo), P], st),
         "ibdl_eval_grid": ([P, I, P, P, P, P, P], st),
         "ibdl_plan_binning": ([P, P, P], st),
+        "ibdl_indicator": ([P, P, P, P], st),
+        "ibdl_fixup": ([P, I, P, P, P, ctypes.c_double, ctypes.c_double, P, P], st),
         "ibdl_plan_set_timing": ([P, I], st),
         "ibdl_plan_stage_times": ([P, P, P, P, I, ctypes.POINTER(I)], st),
         "ibdl_plan_get_stats": ([P, ctypes.POINTER(PlanStats)], st),
@@ -142,6 +146,16 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _bptr(t, name, shape):
+    """A contiguous uint8 CUDA tensor of `shape` elements as a device pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous uint8 CUDA tensor")
+    if t.numel() != shape:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _dptr(t, name, shape=None):
     import torch
     if t is None:
@@ -155,7 +169,7 @@ def _dptr(t, name, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=None, weight=None):
+def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=None, weight=None, lap=0):
     d = Desc()
     d.dim, d.n = dim, n
     for i in range(3):
@@ -165,6 +179,7 @@ def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=N
     d.X = X.data_ptr() if X is not None else None
     d.normal = normal.data_ptr() if normal is not None else None
     d.weight = weight.data_ptr() if weight is not None else None
+    d.lap = lap
     return d
 
 
@@ -206,7 +221,7 @@ class Plan:
     """One geometry on one periodic grid (``ibdl_plan``)."""
 
     def __init__(self, dim, n, lo, length, alpha, X, normal, weight, bc=DIRICHLET, delta=PESKIN4,
-                 prec=FP64, stream=None):
+                 prec=FP64, stream=None, lap=0):
         import torch
         self._keep = [t.contiguous() for t in (X, normal, weight)]
         X, normal, weight = self._keep
@@ -216,7 +231,7 @@ class Plan:
         _dptr(weight, "weight", m)
         self.dim, self.n, self.m, self.bc, self.prec = dim, n, m, bc, prec
         self.grid_size = n ** dim
-        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight)
+        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight, lap=lap)
         h = ctypes.c_void_p()
         _check(lib().ibdl_plan_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)),
                "ibdl_plan_create")
@@ -225,12 +240,12 @@ class Plan:
         self._torch = torch
 
     @classmethod
-    def from_problem(cls, prob, delta=PESKIN4, prec=FP64, device="cuda"):
+    def from_problem(cls, prob, delta=PESKIN4, prec=FP64, device="cuda", lap=0):
         import torch
         g = prob.grid
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
         return cls(g.dim, g.n, tuple(g.lo), g.length, prob.alpha, t(prob.geom.X), t(prob.geom.normal),
-                   t(prob.geom.weight), bc=prob.bc, delta=delta, prec=prec)
+                   t(prob.geom.weight), bc=prob.bc, delta=delta, prec=prec, lap=lap)
 
     # ------------------------------------------------------------------
     def _empty(self, *shape):
@@ -302,6 +317,25 @@ class Plan:
                                     _dptr(g, "g", nrhs * self.grid_size),
                                     _dptr(out, "u", nrhs * self.grid_size), _stream(stream)),
                "ibdl_eval_grid")
+        return out
+
+    def indicator(self, stream=None):
+        """ibdl_indicator: (chi, flags) on the grid (App. D)."""
+        import torch
+        chi = self._empty(*([self.n] * self.dim))
+        flags = torch.empty(*([self.n] * self.dim), dtype=torch.uint8, device="cuda")
+        _check(lib().ibdl_indicator(self._h, _dptr(chi, "chi", self.grid_size), _bptr(flags, "flags", self.grid_size),
+                                    _stream(stream)), "ibdl_indicator")
+        return chi, flags
+
+    def fixup(self, u, ub, flags, m1=6.0, m2=8.0, out=None, stream=None):
+        """ibdl_fixup: the near-boundary re-interpolation of App. A."""
+        nrhs = self._nrhs(u, self.grid_size)
+        out = self._empty(*u.shape) if out is None else out
+        _check(lib().ibdl_fixup(self._h, nrhs, _dptr(u, "u"), _dptr(ub, "ub", nrhs * self.m),
+                                _bptr(flags, "flags", self.grid_size),
+                                float(m1), float(m2), _dptr(out, "u_out", u.numel()), _stream(stream)),
+               "ibdl_fixup")
         return out
 
     def binning(self):
@@ -417,7 +451,7 @@ class Batch:
             _dptr(w, "weight", m)
             descs[i] = make_desc(dim, n, ins.get("lo", (0.0, 0.0, 0.0)), ins.get("length", 1.0),
                                  ins["alpha"], ins.get("bc", DIRICHLET), ins.get("delta", PESKIN4),
-                                 ins.get("prec", MIXED), m, X, nrm, w)
+                                 ins.get("prec", MIXED), m, X, nrm, w, lap=ins.get("lap", 0))
             nrhs[i] = int(ins["nrhs"])
             self.meta.append(dict(dim=dim, n=n, m=m, nrhs=int(ins["nrhs"]), bc=ins.get("bc", DIRICHLET)))
         h = ctypes.c_void_p()
@@ -554,7 +588,7 @@ class Server:
 
     def submit(self, dim, n, lo, length, alpha, X, normal, weight, data, g=None, bc=DIRICHLET,
                delta=PESKIN4, prec=MIXED, tol=1e-8, restart=50, maxit=500, grid=True, true_residual=False,
-               stream=None):
+               stream=None, lap=0):
         """Queue one solve; returns a ticket.  data: (nrhs, M); g: (nrhs, n^dim) or None."""
         import torch
         m = int(weight.numel())
@@ -564,7 +598,7 @@ class Server:
         _dptr(weight, "weight", m)
         sol = torch.empty(nrhs, m, dtype=torch.float64, device="cuda")
         u = torch.empty(nrhs, *([n] * dim), dtype=torch.float64, device="cuda") if grid else None
-        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight)
+        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight, lap=lap)
         o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
         t = ctypes.c_uint64()
         _check(lib().ibdl_server_submit(self._h, ctypes.byref(d), nrhs, _dptr(data, "data", nrhs * m),

@@ -378,3 +378,144 @@ def test_binning_keys_and_stable_order():
         ties = np.diff(ks.astype(np.int64)) == 0
         assert np.all(np.diff(perm.astype(np.int64))[ties] > 0)
         assert sorted(perm.tolist()) == list(range(m))
+
+
+# ------------------------------------------------------------------- Fourier-spectral Laplacian (Sec. 6.2.1)
+@pytest.mark.parametrize("dim,n,length,alpha", [(2, 32, 1.3, 2.5), (3, 12, 0.8, 0.0), (2, 24, 1.0, 0.0)])
+def test_spectral_inverse_exact_on_fourier_modes(dim, n, length, alpha):
+    """The spectral Laplacian is exact on band-limited fields: L^-1 of a Fourier mode
+    exp(2 pi i k.x/L) is the mode divided by -(2 pi |k|/L)^2 - alpha, including the
+    Nyquist frequency n/2 (the textbook property of the spectral method)."""
+    st = O.Setup(dim, n, np.zeros(dim), length, alpha, np.zeros((1, dim)), np.ones((1, dim)) / math.sqrt(dim),
+                 np.ones(1), O.PESKIN4, O.LAP_SPECTRAL)
+    g = W.Grid(dim, n, (0.0,) * dim, length)
+    xs = g.nodes()
+    rng = np.random.default_rng(n)
+    modes = [rng.integers(-n // 2 + 1, n // 2, size=dim) for _ in range(3)] + [np.array([n // 2] + [0] * (dim - 1))]
+    for k in modes:
+        if alpha == 0.0 and not np.any(k):
+            continue
+        ph = sum(2 * math.pi * k[d] * xs[d] / length for d in range(dim)) + 0.4
+        u = np.cos(ph)
+        lam = -(2 * math.pi / length) ** 2 * float(np.sum(k * k)) - alpha
+        assert np.max(np.abs(O.solve_L(st, u) - u / lam)) < 1e-12 * np.max(np.abs(u / lam))
+
+
+def test_fd_and_spectral_symbols_differ_by_sinc_squared():
+    """On one axis the 5-point eigenvalue is the spectral one times sinc^2(pi m/n):
+    (4/h^2) sin^2(pi m/n) = (2 pi m/L)^2 [sin(pi m/n)/(pi m/n)]^2 for 0 < m <= n/2."""
+    n, L = 48, 1.7
+    mk = lambda lap: O.Setup(2, n, np.zeros(2), L, 0.0, np.zeros((1, 2)), np.ones((1, 2)) / math.sqrt(2),
+                             np.ones(1), O.PESKIN4, lap)
+    fd, sp = O.symbol(mk(O.LAP_FD)), O.symbol(mk(O.LAP_SPECTRAL))
+    m = np.arange(1, n // 2 + 1)
+    x = np.pi * m / n
+    assert np.max(np.abs(fd[0, m] / sp[0, m] - (np.sin(x) / x) ** 2)) < 1e-14
+    assert np.array_equal(sp[0, 1:n // 2], sp[0, n - 1:n // 2:-1])
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_spectral_ibdl_iterations_flat(n):
+    """With the spectral Laplacian the IBDL system keeps its small, grid-independent
+    iteration counts (4-5 at tol 1e-8 on the problem of Table 1)."""
+    for c in (2.0, 0.75):
+        p = W.table1_problem(n, c)
+        st = O.setup_from_problem(p, lap=O.LAP_SPECTRAL)
+        res, _ = O.solve(st, p.data, p.g_tilde, tol=1e-8)
+        assert 4 <= res.iters <= 5, (n, c, res.iters)
+
+
+# ------------------------------------------------------------------- near-boundary fix-up (Sec. 5.5, App. A)
+def _linear_field(g, coef):
+    xs = g.nodes()
+    return coef[0] + sum(coef[d + 1] * xs[d] for d in range(g.dim))
+
+
+@pytest.mark.parametrize("dim,shape", [(2, "circle"), (2, "star"), (3, "sphere")])
+def test_fixup_reproduces_linear_fields(dim, shape):
+    """Every step of App. A (linear interpolation along the chord, bi-/trilinear
+    interpolation at x_B, linear interpolation between x_A and x_B through x_p) is
+    exact for a linear field, so the re-interpolated nodes keep its values."""
+    n = 64 if dim == 2 else 32
+    g = W.Grid(dim, n, (0.0,) * dim, 1.0)
+    if dim == 2:
+        geom = W.circle((0.5, 0.5), 0.27, 300) if shape == "circle" else W.star((0.5, 0.5), 0.3, 0.05, 5, 500)
+    else:
+        geom = W.fibonacci_sphere((0.5, 0.5, 0.5), 0.3, 3000)
+    st = O.Setup(dim, n, np.zeros(dim), 1.0, 1.0, geom.X, geom.normal, geom.weight)
+    coef = np.array([0.3, 1.7, -2.2, 0.9][:dim + 1])
+    u = _linear_field(g, coef)
+    ub = coef[0] + geom.X @ coef[1:]
+    inside = geom.inside(np.stack([c.ravel() for c in g.nodes()], axis=1)).reshape(u.shape)
+    fixed, done = O.near_boundary_fixup(st, u, ub, inside, m1=4.0, m2=6.0)
+    assert done.sum() > 50
+    assert np.max(np.abs(fixed - u)[done]) < 1e-12
+    assert np.array_equal(fixed[~done], u[~done])
+    # a wrong constant on the boundary data moves every replaced node by the
+    # weight of x_A, |x_B - x_p| / |x_B - x_A|, which lies in (0, 1]
+    fixed2, _ = O.near_boundary_fixup(st, u, ub + 1.0, inside, m1=4.0, m2=6.0)
+    shift = (fixed2 - fixed)[done]
+    assert np.all(shift > 0.0) and np.all(shift <= 1.0 + 1e-12)
+
+
+def test_fixup_projection_on_a_straight_boundary():
+    """Points on the line y = y0: x_A is the foot of the perpendicular from x_p and
+    u(x_A) the chord interpolation of U_b (the definition of App. A)."""
+    n = 64
+    h = 1.0 / n
+    xs = np.arange(0.0, 1.0, 0.7 * h) + 0.013
+    X = np.stack([xs, np.full_like(xs, 0.40321)], axis=1)
+    nrm = np.tile([0.0, -1.0], (len(xs), 1))   # the domain is y > y0
+    st = O.Setup(2, n, np.zeros(2), 1.0, 1.0, X, nrm, np.full(len(xs), 0.7 * h))
+    g = W.Grid(2, n, (0.0, 0.0), 1.0)
+    x, y = g.nodes()
+    ub = np.sin(3.0 * X[:, 0])
+    u = np.cos(x) * 0.0 + 5.0             # constant grid value 5 away from the boundary
+    om = (y > 0.40321).astype(np.int8)
+    fixed, done = O.near_boundary_fixup(st, u, ub, om, m1=3.0, m2=5.0)
+    iy, ix = np.nonzero(done & (x > 0.1) & (x < 0.9))   # away from the periodic seam of the line
+    assert len(iy) > 40
+    for a, b in zip(iy[:40], ix[:40]):
+        xp = np.array([x[a, b], y[a, b]])
+        j = np.searchsorted(xs, xp[0]) - 1
+        t = (xp[0] - xs[j]) / (xs[j + 1] - xs[j])
+        ua = (1 - t) * ub[j] + t * ub[j + 1]
+        dp = xp[1] - 0.40321
+        val = ua * (5 * h - dp) / (5 * h) + 5.0 * dp / (5 * h)
+        assert abs(fixed[a, b] - val) < 1e-12
+
+
+def test_fixup_recovers_convergence_up_to_the_boundary():
+    """Sec. 6.1 with m1 = 6, m2 = 8: without the re-interpolation the max-norm error
+    over the whole domain does not converge; with it, it falls at least first order."""
+    errs_b, errs_a = [], []
+    for n in (64, 128, 256):
+        p = W.table1_problem(n, 0.75)
+        st = O.setup_from_problem(p)
+        res, _ = O.solve(st, p.data, p.g_tilde, tol=1e-10)
+        u = O.eval_grid(st, res.x, g_tilde=p.g_tilde)
+        _, flags = O.omega_flags(st)
+        ex = p.exact_grid()
+        om = flags.astype(bool)
+        fixed, _ = O.near_boundary_fixup(st, u, p.data, flags, 6.0, 8.0)
+        errs_b.append(np.abs(u - ex)[om].max())
+        errs_a.append(np.abs(fixed - ex)[om].max())
+    assert min(errs_b) > 0.5
+    assert errs_a[1] / errs_a[0] < 0.55 and errs_a[2] / errs_a[1] < 0.55, errs_a
+
+
+def test_omega_flags_interior_and_exterior():
+    """App. D flags: with normals pointing out of the disc the domain is the disc;
+    with normals pointing into it the domain is the rest of the box."""
+    n = 128
+    grid = W.Grid(2, n, (0.0, 0.0), 1.0)
+    geom = W.circle((0.5, 0.5), 0.25, int(round(2 * math.pi * 0.25 / (0.75 / n))))
+    nodes = np.stack([c.ravel() for c in grid.nodes()], axis=1)
+    disc = geom.body_inside(nodes)
+    for sign, want in ((1.0, disc), (-1.0, ~disc)):
+        st = O.Setup(2, n, np.zeros(2), 1.0, 3.0, geom.X, sign * geom.normal, geom.weight)
+        assert O.orientation(st) == (1 if sign > 0 else -1)
+        _, flags = O.omega_flags(st)
+        d = O.distance_to_points(st, nodes, geom.X)
+        far = d > 3 * grid.h
+        assert np.array_equal(flags.ravel()[far].astype(bool), want[far])
