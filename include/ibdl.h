@@ -73,6 +73,20 @@ typedef enum { IBDL_PREC_FP64 = 0, IBDL_PREC_MIXED = 1 } ibdl_prec;
  * in both. */
 typedef enum { IBDL_LAP_FD = 0, IBDL_LAP_SPECTRAL = 1 } ibdl_lap;
 
+/* Formulation of the boundary equation.
+ * DOUBLE_LAYER: the IBDL system (Sec. 4.1, Sec. 4.4, Sec. 5.3), Dirichlet or Neumann.
+ * COMPLETED: the completed IBDL system for the Poisson equation (Sec. 5.4.1,
+ *   App. C): alpha = 0, Dirichlet, eta > 0.  Its unknown is z = [Q; ubar]
+ *   (M + 1 values per right-hand side) and its operator the bordered matrix
+ *     [-S* D0^-1 (S~ + eta S) + I/2,  1;  eta w^T,  0]
+ *   (D0^-1 the mean-zero inverse of the periodic Laplacian, w the point weights),
+ *   with right-hand side [U_b - S* D0^-1 g~;  h^d sum_x g~(x)] and grid solution
+ *   u = D0^-1 (g~ - (S~ + eta S) Q) + ubar.  For such plans q, Aq, b and sol of
+ *   ibdl_apply / ibdl_rhs / ibdl_solve / ibdl_solve_grid / ibdl_eval_grid hold
+ *   M + 1 values per right-hand side ([nrhs][M+1], ubar last); the boundary
+ *   data stay [nrhs][M].  Not accepted by batches and servers. */
+typedef enum { IBDL_FORM_DOUBLE_LAYER = 0, IBDL_FORM_COMPLETED = 1 } ibdl_form;
+
 typedef struct {
     int32_t dim;          /* 2 or 3                                                        */
     int32_t n;            /* nodes per axis, n = 2^a 3^b, 8 <= n <= 2048 (2-D), <= 512 (3-D) */
@@ -88,6 +102,8 @@ typedef struct {
     const double* weight; /* device [M] quadrature weights: arclength Delta s_i (2-D, Sec. 5.2)
                              or area dA_i (3-D, Sec. 6.7), > 0                               */
     int32_t lap;          /* ibdl_lap                                                       */
+    int32_t form;         /* ibdl_form                                                      */
+    double eta;           /* COMPLETED: weight eta > 0 of the single layer (the paper uses 10) */
 } ibdl_desc;
 
 typedef struct {

@@ -20,6 +20,7 @@ Helmholtz equation"):
 * the grid solution  L u = g~ - S~Q  (- S V_b for Neumann) (Sec. 4.2 step 2; Sec. 4.4, the Neumann grid equation)
 * unpreconditioned GMRES on the boundary density           (Sec. 5.3)
 * the mean-zero inverse for alpha = 0                      (Sec. 5.4.2; App. C)
+* the completed IBDL system for the Poisson equation       (Sec. 5.4.1; App. C)
 * the Fourier-spectral Laplacian as an alternative to the
   finite-difference one                                    (Sec. 5.1; Sec. 6.2.1)
 * the indicator-function construction and the flags of the
@@ -264,6 +265,43 @@ def eval_grid(st: Setup, sol, vb=None, g_tilde=None, bc=DIRICHLET):
     if bc == NEUMANN:
         f = f - spread(st, vb)
     return solve_L(st, f)
+
+
+# ----------------------------------------------------------------------------
+# the completed IBDL system for the Poisson equation (Sec. 5.4.1; App. C)
+# ----------------------------------------------------------------------------
+def apply_completed(st: Setup, z, eta):
+    """App. C on z = [Q; ubar] (alpha = 0, Delta_0^-1 the mean-zero inverse):
+    rows 1..M:  -S* Delta_0^-1 S~ Q - eta S* Delta_0^-1 S Q + ubar + Q/2,
+    row M+1:    eta sum_k Delta s_k Q_k  (the solvability condition; Delta s_k the
+    point weights, the paper's uniform Delta s)."""
+    assert st.alpha == 0.0
+    z = np.asarray(z, dtype=np.float64)
+    Q, ubar = z[:-1], z[-1]
+    top = -interp(st, solve_L(st, spread_dipole(st, Q))) - eta * interp(st, solve_L(st, spread(st, Q)))
+    top = top + ubar + 0.5 * Q
+    return np.append(top, eta * np.sum(st.weight * Q))
+
+
+def rhs_completed(st: Setup, data, g_tilde=None):
+    """App. C right-hand side: [U_b - S* Delta_0^-1 g~;  h^d sum_x g~(x)]."""
+    assert st.alpha == 0.0
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    return np.append(np.asarray(data, dtype=np.float64) - interp(st, solve_L(st, g)), st.h ** st.dim * np.sum(g))
+
+
+def eval_grid_completed(st: Setup, z, g_tilde=None, eta=0.0):
+    """App. C: u = -Delta_0^-1 (S~ + eta S) Q + Delta_0^-1 g~ + ubar."""
+    z = np.asarray(z, dtype=np.float64)
+    Q, ubar = z[:-1], z[-1]
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    return solve_L(st, g - spread_dipole(st, Q) - eta * spread(st, Q)) + ubar
+
+
+def solve_completed(st: Setup, data, g_tilde=None, eta=10.0, tol=1e-8, restart=50, maxit=500):
+    """GMRES on the completed system for [Q; ubar] (App. C)."""
+    b = rhs_completed(st, data, g_tilde)
+    return gmres(lambda v: apply_completed(st, v, eta), b, tol=tol, restart=restart, maxit=maxit), b
 
 
 # ----------------------------------------------------------------------------

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibdl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "plan.hip", "gmres.hip", "server.hip", "nearfix.hip", "pipeline_f64.hip",
+SOURCES = ["api.hip", "plan.hip", "gmres.hip", "server.hip", "nearfix.hip", "forms.hip", "pipeline_f64.hip",
            "pipeline_f32.hip"]
 
 FLAGS = [

@@ -51,6 +51,12 @@ std::string check_desc(const ibdl_desc* d) {
     if (d->delta != IBDL_DELTA_PESKIN4 && d->delta != IBDL_DELTA_COSINE4) return "unknown delta kernel";
     if (d->prec != IBDL_PREC_FP64 && d->prec != IBDL_PREC_MIXED) return "unknown precision";
     if (d->lap != IBDL_LAP_FD && d->lap != IBDL_LAP_SPECTRAL) return "lap must be IBDL_LAP_FD or IBDL_LAP_SPECTRAL";
+    if (d->form != IBDL_FORM_DOUBLE_LAYER && d->form != IBDL_FORM_COMPLETED) return "unknown formulation";
+    if (d->form == IBDL_FORM_COMPLETED) {
+        if (d->alpha != 0.0) return "the completed formulation is for the Poisson equation (alpha = 0)";
+        if (d->bc != IBDL_DIRICHLET) return "the completed formulation takes Dirichlet data";
+        if (!(d->eta > 0.0) || !std::isfinite(d->eta)) return "eta must be positive and finite";
+    }
     if (d->npts < 1) return "npts must be >= 1";
     // spread entries per point (dipole stencil); the spread kernels address the
     // entries' FP64 weights with 32-bit byte offsets
@@ -349,6 +355,8 @@ ibdl_status ibdl_plan_create(const ibdl_desc* desc, void* stream, ibdl_plan* out
         p->bc = desc->bc;
         p->delta = desc->delta;
         p->lap = desc->lap;
+        p->form = desc->form;
+        p->eta = desc->form == IBDL_FORM_COMPLETED ? desc->eta : 0.0;
         p->prec = desc->prec;
         p->M = desc->npts;
         for (int i = 0; i < 3; ++i) p->lo[i] = i < desc->dim ? desc->lo[i] : 0.0;
@@ -401,7 +409,7 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += M * (16 + 12 + 24 + 24 + 8 + 96 + 48);
     // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
     const size_t nd = M * (dim == 2 ? 32 : 160);
-    const size_t nm = d->bc == IBDL_NEUMANN ? M * (dim == 2 ? 16 : 64) : 0;
+    const size_t nm = (d->bc == IBDL_NEUMANN || d->form != IBDL_FORM_DOUBLE_LAYER) ? M * (dim == 2 ? 16 : 64) : 0;
     b += (nd + nm) * 24 + 2 * (nlines + 2) * 4;
     // line and plane masks, lists, line starts, FFT and symbol tables
     b += nlines * 18 + n * 64;
@@ -413,6 +421,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += R * ((m + 1) * M * 8 + 5 * M * 8 + 2 * nblk * (m + 2) * 8 + (m * (m + 1) + 4 * m + 3 * (m + 2)) * 8 + 64);
     // allocation granularity: small buffers, and the device's 2 MiB pages (one more
     // page for buffers that straddle them)
+    // completed formulation: Q2, the per-call Q1 and sums, grid-sum partials
+    if (d->form == IBDL_FORM_COMPLETED) b += (M + 1) * 8 + R * (M + 2) * 8 + R * 256 * 8 + 3 * 4096;
     b += 96 * 4096;
     const size_t page = (size_t)2 << 20;
     return (b + page - 1) / page * page + page;
@@ -426,6 +436,10 @@ ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, v
     IBDL_GUARD_BEGIN
     AllocStream as(S(stream));
     p->last_stream = S(stream);
+    if (p->form == IBDL_FORM_COMPLETED) {
+        completed_apply(p, nrhs, q, Aq, S(stream));
+        return IBDL_OK;
+    }
     apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
     return IBDL_OK;
     IBDL_GUARD_END
@@ -436,6 +450,8 @@ ibdl_status ibdl_apply_noalloc(ibdl_plan p, int32_t nrhs, const double* q, doubl
     if (nrhs < 1) return fail(IBDL_ERR_ARG, "nrhs must be >= 1");
     if (!q || !Aq) return fail(IBDL_ERR_ARG, "q and Aq must be device pointers");
     if (q == Aq) return fail(IBDL_ERR_ARG, "q and Aq must not overlap");
+    if (p->form != IBDL_FORM_DOUBLE_LAYER)
+        return fail(IBDL_ERR_ARG, "ibdl_apply_noalloc takes plans of the double-layer formulation");
     size_t spec_b = 0;
     const size_t need = noalloc_bytes(p, nrhs, &spec_b);
     if (need > kScratchBytes)
@@ -476,6 +492,10 @@ ibdl_status ibdl_rhs(ibdl_plan p, int32_t nrhs, const double* data, const double
     IBDL_GUARD_BEGIN
     AllocStream as(S(stream));
     p->last_stream = S(stream);
+    if (p->form == IBDL_FORM_COMPLETED) {
+        completed_rhs(p, nrhs, data, g, b, S(stream));
+        return IBDL_OK;
+    }
     PipeIn in;
     PipeOut out;
     out.out = b;
@@ -513,10 +533,18 @@ static ibdl_status plan_solve(ibdl_plan p, int32_t nrhs, const double* data, con
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(IBDL_ERR_ARG, "tol must be positive");
     if (o.restart < 1 || o.restart > 200) return fail(IBDL_ERR_ARG, "restart must be in 1..200");
     if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
+    if (p->form == IBDL_FORM_COMPLETED && o.x0) return fail(IBDL_ERR_ARG, "opts->x0 must be NULL for completed plans");
     IBDL_GUARD_BEGIN
     AllocStream as(S(stream));
     p->last_stream = S(stream);
     int overall = IBDL_OK;
+    if (p->form == IBDL_FORM_COMPLETED) {
+        overall = completed_solve(p, nrhs, data, g, o, sol, u, info, S(stream));
+        if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
+        if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
+        g_last_error.clear();
+        return IBDL_OK;
+    }
     p->ks.inst.assign(1, Inst{p, nrhs, 0});
     p->ks.R = nrhs;
     solve_set(p->ks, {data}, {g}, {o.x0}, o, {sol}, info, S(stream), &overall, {u});
@@ -548,6 +576,10 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     IBDL_GUARD_BEGIN
     AllocStream as(S(stream));
     p->last_stream = S(stream);
+    if (p->form == IBDL_FORM_COMPLETED) {
+        completed_eval_grid(p, nrhs, sol, g, u, S(stream));
+        return IBDL_OK;
+    }
     PipeIn in;
     in.q_dip = sol;
     in.c_dip = -1.0;
@@ -650,6 +682,8 @@ ibdl_status ibdl_batch_create(const ibdl_desc* descs, int32_t count, const int32
     for (int i = 0; i < count; ++i) {
         const std::string why = check_desc(&descs[i]);
         if (!why.empty()) return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": " + why);
+        if (descs[i].form != IBDL_FORM_DOUBLE_LAYER)
+            return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": batches take the double-layer formulation");
         if (nrhs[i] < 1) return fail(IBDL_ERR_ARG, "instance " + std::to_string(i) + ": nrhs must be >= 1");
         R += nrhs[i];
     }

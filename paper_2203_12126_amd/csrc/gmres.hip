@@ -627,6 +627,7 @@ void SolveTask::mark() {
 // and (Neumann) taken with V_b = the boundary data
 bool SolveTask::grid_fusable(size_t i) const {
     if (i >= io_.u.size() || !io_.u[i]) return false;
+    if (ks_.inst[i].p->form != IBDL_FORM_DOUBLE_LAYER) return false;
     if (ks_.inst[i].p->bc == IBDL_DIRICHLET) return true;
     return i < io_.vb.size() && io_.vb[i] == io_.data[i];
 }
@@ -673,6 +674,11 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64,
         PipeIn pi;
         pi.q_dip = x + off;
         pi.c_dip = 1.0;
+        if (in.p->form == IBDL_FORM_COMPLETED) {
+            // the completion's single layer: A x = -S* D0^-1 (S~ + eta S) x + x/2
+            pi.q_mono = x + off;
+            pi.c_mono = in.p->eta;
+        }
         PipeOut po;
         po.out = r + off;
         po.cA = 1.0;
@@ -830,6 +836,10 @@ void SolveTask::prepare_op() {
         pi.q_jstride = M;
         pi.skip = k.state + 4 * in.r0;
         pi.pack_q = true;
+        if (in.p->form == IBDL_FORM_COMPLETED) {
+            pi.q_mono = k.V + vb;
+            pi.c_mono = in.p->eta;
+        }
         PipeOut po;
         po.out = k.V + vb + M;
         po.out_stride = vs;

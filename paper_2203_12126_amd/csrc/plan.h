@@ -142,6 +142,8 @@ struct ibdl_plan_s {
     // description
     int dim = 2, n = 0, bc = 0, delta = 0, prec = 0, M = 0;
     int lap = IBDL_LAP_FD;  // Laplacian discretisation (ibdl_lap)
+    int form = IBDL_FORM_DOUBLE_LAYER;  // ibdl_form
+    double eta = 0.0;       // completed formulation: weight of the single layer
     double lo[3] = {0, 0, 0}, length = 1, h = 1, alpha = 0;
     int P = 0;          // complex elements per line of the tiled half spectrum (>= n/2+1)
     int W = 0;          // half-spectrum width n/2+1
@@ -190,6 +192,8 @@ struct ibdl_plan_s {
     double* ones = nullptr;
     uint8_t* fix_mask = nullptr;
     double* fix_refs = nullptr;
+    // completed formulation: Q2 with K Q2 = 1 and, last, eta w.Q2 (solved at the first solve)
+    double* cq2 = nullptr;
 
     ibdl::Workspace ws;
     ibdl::KrylovSet ks;     // Krylov state of solves through this plan alone
@@ -324,6 +328,12 @@ int col_width_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
 // near-boundary step (nearfix.hip): App. D indicator and flags, App. A fix-up
 void nearfix_indicator(ibdl_plan p, double* chi, uint8_t* flags, hipStream_t st);
+// completed formulation (forms.hip): vectors z = [Q; ubar] of M + 1 values per rhs
+void completed_apply(ibdl_plan p, int nrhs, const double* z, double* out, hipStream_t st);
+void completed_rhs(ibdl_plan p, int nrhs, const double* data, const double* g, double* b, hipStream_t st);
+void completed_eval_grid(ibdl_plan p, int nrhs, const double* z, const double* g, double* u, hipStream_t st);
+int completed_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
+                    double* sol, double* u, ibdl_solve_info* info, hipStream_t st);
 void nearfix_fixup(ibdl_plan p, int nrhs, const double* u, const double* ub, const uint8_t* flags, double m1,
                    double m2, double* uout, hipStream_t st);
 void free_build_tmp(ibdl_plan p);

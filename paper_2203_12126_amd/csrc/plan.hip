@@ -739,7 +739,8 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
                        p->skey, M, n, p->nlines, p->line_start);
 
     build_csr(p, p->dip, true, st);
-    if (p->bc == IBDL_NEUMANN) build_csr(p, p->mono, false, st);
+    // the single layer: Neumann data (S V_b) and the completion (eta S Q)
+    if (p->bc == IBDL_NEUMANN || p->form != IBDL_FORM_DOUBLE_LAYER) build_csr(p, p->mono, false, st);
 
     // line and plane sets
     int32_t* flag = tmp_n<int32_t>(p, (size_t)std::max(p->nlines, n));

@@ -464,6 +464,7 @@ ibdl_status ibdl_server_submit(ibdl_server s, const ibdl_desc* desc, int32_t nrh
     if (o.restart < 1 || o.restart > 200) return sfail(IBDL_ERR_ARG, "restart must be in 1..200");
     if (o.maxit < 1) return sfail(IBDL_ERR_ARG, "maxit must be >= 1");
     if (o.x0) return sfail(IBDL_ERR_ARG, "opts->x0 must be NULL for served solves");
+    if (desc->form != IBDL_FORM_DOUBLE_LAYER) return sfail(IBDL_ERR_ARG, "servers take the double-layer formulation");
     const size_t fp = request_footprint(desc, nrhs, o.restart);
     if (!fp) return sfail(IBDL_ERR_ARG, "invalid desc");
     if (fp > s->budget) return sfail(IBDL_ERR_OOM, "request footprint exceeds the server's memory budget");

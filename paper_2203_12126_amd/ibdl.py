@@ -19,6 +19,7 @@ DIRICHLET, NEUMANN = 0, 1
 PESKIN4, COSINE4 = 0, 1
 FP64, MIXED = 0, 1
 LAP_FD, LAP_SPECTRAL = 0, 1
+FORM_DOUBLE_LAYER, FORM_COMPLETED = 0, 1
 
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NUMERIC",
            6: "ERR_STATE"}
@@ -35,7 +36,7 @@ class Desc(ctypes.Structure):
                 ("length", ctypes.c_double), ("alpha", ctypes.c_double), ("bc", ctypes.c_int32),
                 ("delta", ctypes.c_int32), ("prec", ctypes.c_int32), ("npts", ctypes.c_int32),
                 ("X", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("weight", ctypes.c_void_p),
-                ("lap", ctypes.c_int32)]
+                ("lap", ctypes.c_int32), ("form", ctypes.c_int32), ("eta", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -169,7 +170,8 @@ def _dptr(t, name, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=None, weight=None, lap=0):
+def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=None, weight=None, lap=0, form=0,
+              eta=0.0):
     d = Desc()
     d.dim, d.n = dim, n
     for i in range(3):
@@ -180,6 +182,8 @@ def make_desc(dim, n, lo, length, alpha, bc, delta, prec, npts, X=None, normal=N
     d.normal = normal.data_ptr() if normal is not None else None
     d.weight = weight.data_ptr() if weight is not None else None
     d.lap = lap
+    d.form = form
+    d.eta = float(eta)
     return d
 
 
@@ -221,7 +225,7 @@ class Plan:
     """One geometry on one periodic grid (``ibdl_plan``)."""
 
     def __init__(self, dim, n, lo, length, alpha, X, normal, weight, bc=DIRICHLET, delta=PESKIN4,
-                 prec=FP64, stream=None, lap=0):
+                 prec=FP64, stream=None, lap=0, form=0, eta=0.0):
         import torch
         self._keep = [t.contiguous() for t in (X, normal, weight)]
         X, normal, weight = self._keep
@@ -230,8 +234,11 @@ class Plan:
         _dptr(normal, "normal", m * dim)
         _dptr(weight, "weight", m)
         self.dim, self.n, self.m, self.bc, self.prec = dim, n, m, bc, prec
+        self.form = form
+        # unknowns per right-hand side: M, or M + 1 for the completed formulation ([Q; ubar])
+        self.nu = m + 1 if form == FORM_COMPLETED else m
         self.grid_size = n ** dim
-        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight, lap=lap)
+        d = make_desc(dim, n, lo, length, alpha, bc, delta, prec, m, X, normal, weight, lap=lap, form=form, eta=eta)
         h = ctypes.c_void_p()
         _check(lib().ibdl_plan_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)),
                "ibdl_plan_create")
@@ -240,12 +247,12 @@ class Plan:
         self._torch = torch
 
     @classmethod
-    def from_problem(cls, prob, delta=PESKIN4, prec=FP64, device="cuda", lap=0):
+    def from_problem(cls, prob, delta=PESKIN4, prec=FP64, device="cuda", lap=0, form=0, eta=0.0):
         import torch
         g = prob.grid
         t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
         return cls(g.dim, g.n, tuple(g.lo), g.length, prob.alpha, t(prob.geom.X), t(prob.geom.normal),
-                   t(prob.geom.weight), bc=prob.bc, delta=delta, prec=prec, lap=lap)
+                   t(prob.geom.weight), bc=prob.bc, delta=delta, prec=prec, lap=lap, form=form, eta=eta)
 
     # ------------------------------------------------------------------
     def _empty(self, *shape):
@@ -257,7 +264,7 @@ class Plan:
         return t.numel() // per
 
     def apply(self, q, out=None, stream=None):
-        nrhs = self._nrhs(q, self.m)
+        nrhs = self._nrhs(q, self.nu)
         out = self._empty(*q.shape) if out is None else out
         _check(lib().ibdl_apply(self._h, nrhs, _dptr(q, "q"), _dptr(out, "Aq", q.numel()),
                                 _stream(stream)), "ibdl_apply")
@@ -273,22 +280,22 @@ class Plan:
 
     def rhs(self, data, g=None, out=None, stream=None):
         nrhs = self._nrhs(data, self.m)
-        out = self._empty(*data.shape) if out is None else out
+        out = self._empty(nrhs, self.nu) if out is None else out
         _check(lib().ibdl_rhs(self._h, nrhs, _dptr(data, "data"),
-                              _dptr(g, "g", nrhs * self.grid_size), _dptr(out, "b", data.numel()),
+                              _dptr(g, "g", nrhs * self.grid_size), _dptr(out, "b", nrhs * self.nu),
                               _stream(stream)), "ibdl_rhs")
         return out
 
     def solve(self, data, g=None, tol=1e-8, restart=50, maxit=500, x0=None, true_residual=False,
               out=None, stream=None, raise_on_noconv=True):
         nrhs = self._nrhs(data, self.m)
-        out = self._empty(*data.shape) if out is None else out
+        out = self._empty(nrhs, self.nu) if out is None else out
         o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
         if x0 is not None:
             o.x0 = _dptr(x0, "x0", data.numel()).value
         info = (SolveInfo * nrhs)()
         st = lib().ibdl_solve(self._h, nrhs, _dptr(data, "data"), _dptr(g, "g", nrhs * self.grid_size),
-                              ctypes.byref(o), _dptr(out, "sol", data.numel()), info, _stream(stream))
+                              ctypes.byref(o), _dptr(out, "sol", nrhs * self.nu), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_solve")
         return out, InfoList(info)
@@ -297,23 +304,23 @@ class Plan:
                    out=None, u=None, stream=None, raise_on_noconv=True):
         """solve() and the grid solution (V_b = data for Neumann) in one call."""
         nrhs = self._nrhs(data, self.m)
-        out = self._empty(*data.shape) if out is None else out
+        out = self._empty(nrhs, self.nu) if out is None else out
         u = self._empty(nrhs, *([self.n] * self.dim)) if u is None else u
         o = SolveOpts(tol, restart, maxit, None, 1 if true_residual else 0)
         if x0 is not None:
             o.x0 = _dptr(x0, "x0", data.numel()).value
         info = (SolveInfo * nrhs)()
         st = lib().ibdl_solve_grid(self._h, nrhs, _dptr(data, "data"), _dptr(g, "g", nrhs * self.grid_size),
-                                   ctypes.byref(o), _dptr(out, "sol", data.numel()),
+                                   ctypes.byref(o), _dptr(out, "sol", nrhs * self.nu),
                                    _dptr(u, "u", nrhs * self.grid_size), info, _stream(stream))
         if st != OK and not (st == ERR_NOCONV and not raise_on_noconv):
             _check(st, "ibdl_solve_grid")
         return out, u, InfoList(info)
 
     def eval_grid(self, sol, vb=None, g=None, out=None, stream=None):
-        nrhs = self._nrhs(sol, self.m)
+        nrhs = self._nrhs(sol, self.nu)
         out = self._empty(nrhs, *([self.n] * self.dim)) if out is None else out
-        _check(lib().ibdl_eval_grid(self._h, nrhs, _dptr(sol, "sol"), _dptr(vb, "vb", sol.numel()),
+        _check(lib().ibdl_eval_grid(self._h, nrhs, _dptr(sol, "sol"), _dptr(vb, "vb", nrhs * self.m),
                                     _dptr(g, "g", nrhs * self.grid_size),
                                     _dptr(out, "u", nrhs * self.grid_size), _stream(stream)),
                "ibdl_eval_grid")

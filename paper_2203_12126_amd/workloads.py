@@ -131,24 +131,24 @@ def circle(center, radius, m, interior=True, equispaced_theta=True) -> Geometry:
                     2 * np.pi * radius, body_inside=body)
 
 
-def star(center, r0, amp, lobes, m, interior=True) -> Geometry:
-    """r(theta) = r0 + amp*cos(lobes*theta) about ``center``."""
+def star(center, r0, amp, lobes, m, interior=True, phase=0.0) -> Geometry:
+    """r(theta) = r0 + amp*cos(lobes*theta + phase) about ``center``."""
     c = np.asarray(center, dtype=np.float64)
 
     def pos(t):
-        r = r0 + amp * np.cos(lobes * t)
+        r = r0 + amp * np.cos(lobes * t + phase)
         return c[0] + r * np.cos(t), c[1] + r * np.sin(t)
 
     def vel(t):
-        r = r0 + amp * np.cos(lobes * t)
-        dr = -amp * lobes * np.sin(lobes * t)
+        r = r0 + amp * np.cos(lobes * t + phase)
+        dr = -amp * lobes * np.sin(lobes * t + phase)
         return dr * np.cos(t) - r * np.sin(t), dr * np.sin(t) + r * np.cos(t)
 
     def level(p):
         d = p - c
         rr = np.hypot(d[:, 0], d[:, 1])
         th = np.arctan2(d[:, 1], d[:, 0])
-        return rr - (r0 + amp * np.cos(lobes * th))
+        return rr - (r0 + amp * np.cos(lobes * th + phase))
 
     return _curve_geometry(pos, vel, m, level, interior)
 
@@ -652,6 +652,63 @@ def table2_problem(n: int, m: int) -> Problem:
     grid = Grid(3, n, (-0.5, -0.5, -0.5), 1.0)
     geom = fibonacci_sphere((0.0, 0.0, 0.0), 0.25, m)
     return make_problem(grid, geom, 1.0, DIRICHLET, sol_exp_cos3d(), name=f"table2_n{n}_m{m}")
+
+
+def _balance_forcing(p: "Problem") -> "Problem":
+    """g_e = -(sum of g over the domain's nodes) / (number of other nodes): the
+    discrete form of the solvability choice g_e = -int_Omega g / |C \\ Omega| for
+    the periodic Laplacian (App. C), so that the grid sum of g~ vanishes."""
+    inside = p.inside_mask()
+    ge = -float(np.sum(p.g_tilde[inside])) / float(np.count_nonzero(~inside))
+    p.g_tilde = np.ascontiguousarray(np.where(inside, p.g_tilde, ge))
+    return p
+
+
+def sol_exp_sin2pix() -> Solution:
+    """u = exp(sin(2 pi x)), Lap u = 4 pi^2 exp(sin 2 pi x) (cos^2 2 pi x - sin 2 pi x) (Sec. 6.3)."""
+    tp = 2 * math.pi
+
+    def u(p):
+        return np.exp(np.sin(tp * p[:, 0]))
+
+    def grad(p):
+        g = np.zeros_like(p)
+        g[:, 0] = tp * np.cos(tp * p[:, 0]) * u(p)
+        return g
+
+    def lap(p):
+        x = p[:, 0]
+        return tp * tp * np.exp(np.sin(tp * x)) * (np.cos(tp * x) ** 2 - np.sin(tp * x))
+
+    return Solution(u, grad, lap)
+
+
+def poisson_exterior_problem(n: int, length: float, c: float = 0.75, balanced: bool = True) -> Problem:
+    """Sec. 6.3: Lap u = g exterior to the circle R = 0.25 at the origin in the
+    periodic box [-L/2, L/2]^2, u = exp(sin 2 pi x), alpha = 0, Dirichlet data,
+    points with Delta s ~ c Delta x.  balanced: g inside the circle set so the
+    grid sum of g~ vanishes (App. C, the original formulation); else g_e = 0 (the
+    completed formulation needs no condition on g_e)."""
+    grid = Grid(2, n, (-length / 2, -length / 2), length)
+    m = int(round(2 * math.pi * 0.25 / (c * length / n)))
+    geom = circle((0.0, 0.0), 0.25, m, interior=False)
+    p = make_problem(grid, geom, 0.0, DIRICHLET, sol_exp_sin2pix(), name=f"poisson_ext_n{n}_L{length:g}")
+    return _balance_forcing(p) if balanced else p
+
+
+def starfish_problem(n: int, c: float = 0.75) -> Problem:
+    """Sec. 6.4: Lap u = g exterior to the starfish r = 1 + sin(10 pi theta)/4 in the
+    periodic box [-2, 2]^2, u = sin(pi x/2) - cos(pi y/2), alpha = 0, Dirichlet,
+    points with Delta s ~ c Delta x, forcing balanced for solvability (App. C)."""
+    grid = Grid(2, n, (-2.0, -2.0), 4.0)
+    per = star_perimeter(1.0, 0.25, 5)
+    m = int(round(per / (c * 4.0 / n)))
+    geom = star((0.0, 0.0), 1.0, 0.25, 5, m, interior=False, phase=-math.pi / 2)
+    hp = math.pi / 2
+    sol = Solution(lambda p: np.sin(hp * p[:, 0]) - np.cos(hp * p[:, 1]),
+                   lambda p: np.stack([hp * np.cos(hp * p[:, 0]), hp * np.sin(hp * p[:, 1])], axis=1),
+                   lambda p: hp * hp * (np.cos(hp * p[:, 1]) - np.sin(hp * p[:, 0])))
+    return _balance_forcing(make_problem(grid, geom, 0.0, DIRICHLET, sol, name=f"starfish_n{n}"))
 
 
 def random_density(m: int, seed: int, nrhs: int = 1) -> np.ndarray:
