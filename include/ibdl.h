@@ -85,7 +85,15 @@ typedef enum { IBDL_LAP_FD = 0, IBDL_LAP_SPECTRAL = 1 } ibdl_lap;
  *   ibdl_apply / ibdl_rhs / ibdl_solve / ibdl_solve_grid / ibdl_eval_grid hold
  *   M + 1 values per right-hand side ([nrhs][M+1], ubar last); the boundary
  *   data stay [nrhs][M].  Not accepted by batches and servers. */
-typedef enum { IBDL_FORM_DOUBLE_LAYER = 0, IBDL_FORM_COMPLETED = 1 } ibdl_form;
+/* SINGLE_LAYER: the IB constraint system the paper compares against (Sec. 2.1;
+ *   Tables 1 and 2): Dirichlet, FP64.  ibdl_apply gives -(S* L^-1 S) F, ibdl_rhs
+ *   U_b - S* L^-1 g~, ibdl_eval_grid u = L^-1 (g~ - S F), and ibdl_solve runs
+ *   MINRES on the device in the inner product <x, y>_W = sum_k w_k x_k y_k, in
+ *   which the operator is self-adjoint (plain MINRES for equal weights), from
+ *   F = 0 until the W-norm residual estimate falls to tol; info.iters counts
+ *   operator applications and rel_resid_est is that estimate.  opts->restart is
+ *   ignored.  Not accepted by batches and servers. */
+typedef enum { IBDL_FORM_DOUBLE_LAYER = 0, IBDL_FORM_COMPLETED = 1, IBDL_FORM_SINGLE_LAYER = 2 } ibdl_form;
 
 typedef struct {
     int32_t dim;          /* 2 or 3                                                        */

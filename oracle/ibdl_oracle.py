@@ -21,6 +21,8 @@ Helmholtz equation"):
 * unpreconditioned GMRES on the boundary density           (Sec. 5.3)
 * the mean-zero inverse for alpha = 0                      (Sec. 5.4.2; App. C)
 * the completed IBDL system for the Poisson equation       (Sec. 5.4.1; App. C)
+* the IB constraint (single-layer) system and MINRES, the
+  comparison method of the paper's tables                  (Sec. 2.1; Table 1, Table 2)
 * the Fourier-spectral Laplacian as an alternative to the
   finite-difference one                                    (Sec. 5.1; Sec. 6.2.1)
 * the indicator-function construction and the flags of the
@@ -302,6 +304,89 @@ def solve_completed(st: Setup, data, g_tilde=None, eta=10.0, tol=1e-8, restart=5
     """GMRES on the completed system for [Q; ubar] (App. C)."""
     b = rhs_completed(st, data, g_tilde)
     return gmres(lambda v: apply_completed(st, v, eta), b, tol=tol, restart=restart, maxit=maxit), b
+
+
+# ----------------------------------------------------------------------------
+# the IB constraint (single-layer) system compared with the IBDL method (Sec. 2.1)
+# ----------------------------------------------------------------------------
+def apply_ibsl(st: Setup, F):
+    """-(S* L^-1 S) F: the Schur complement of the IB constraint system (Sec. 2.1)."""
+    return -interp(st, solve_L(st, spread(st, np.asarray(F, dtype=np.float64))))
+
+
+def rhs_ibsl(st: Setup, data, g_tilde=None):
+    """U_b - S* L^-1 g~ (Sec. 2.1)."""
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    return np.asarray(data, dtype=np.float64) - interp(st, solve_L(st, g))
+
+
+def eval_grid_ibsl(st: Setup, F, g_tilde=None):
+    """u = L^-1 (g~ - S F) (Sec. 2.1, the first row of the constraint system)."""
+    g = np.zeros(st.shape) if g_tilde is None else np.asarray(g_tilde, dtype=np.float64)
+    return solve_L(st, g - spread(st, F))
+
+
+@dataclass
+class MinresResult:
+    x: np.ndarray
+    iters: int
+    rel_resid: float
+    converged: bool
+
+
+def minres(apply, b, weight, tol=1e-8, maxit=20000):
+    """MINRES (Paige and Saunders) for an operator self-adjoint in the inner product
+    <x, y>_W = sum_k w_k x_k y_k (the IBSL operator -S* L^-1 S is, since S spreads
+    with the weights w); with equal weights it is the plain MINRES the paper runs.
+    x0 = 0; stops when the W-norm residual estimate falls to tol ||b||_W; one
+    iteration per operator application."""
+    b = np.asarray(b, dtype=np.float64)
+    w = np.asarray(weight, dtype=np.float64)
+    dot = lambda a, c: float(np.sum(w * a * c))
+    x = np.zeros_like(b)
+    beta1 = math.sqrt(dot(b, b))
+    if beta1 == 0.0:
+        return MinresResult(x, 0, 0.0, True)
+    r1 = b.copy()
+    r2 = b.copy()
+    beta, oldb = beta1, 0.0
+    dbar = epsln = 0.0
+    phibar = beta1
+    cs, sn = -1.0, 0.0
+    wv = np.zeros_like(b)
+    w2 = np.zeros_like(b)
+    itn = 0
+    while itn < maxit:
+        itn += 1
+        v = r2 / beta
+        y = apply(v)
+        if itn >= 2:
+            y = y - (beta / oldb) * r1
+        alfa = dot(v, y)
+        y = y - (alfa / beta) * r2
+        r1, r2 = r2, y
+        oldb, beta = beta, math.sqrt(dot(r2, r2))
+        oldeps = epsln
+        delta = cs * dbar + sn * alfa
+        gbar = sn * dbar - cs * alfa
+        epsln = sn * beta
+        dbar = -cs * beta
+        gamma = math.hypot(gbar, beta)
+        cs, sn = gbar / gamma, beta / gamma
+        phi = cs * phibar
+        phibar = sn * phibar
+        w1, w2 = w2, wv
+        wv = (v - oldeps * w1 - delta * w2) / gamma
+        x = x + phi * wv
+        if phibar / beta1 <= tol or beta == 0.0:
+            return MinresResult(x, itn, phibar / beta1, True)
+    return MinresResult(x, itn, phibar / beta1, False)
+
+
+def solve_ibsl(st: Setup, data, g_tilde=None, tol=1e-8, maxit=20000):
+    """The IBSL comparison: MINRES on -(S* L^-1 S) F = U_b - S* L^-1 g~ (Sec. 2.1, Table 1)."""
+    b = rhs_ibsl(st, data, g_tilde)
+    return minres(lambda v: apply_ibsl(st, v), b, st.weight, tol=tol, maxit=maxit), b
 
 
 # ----------------------------------------------------------------------------

@@ -51,7 +51,12 @@ std::string check_desc(const ibdl_desc* d) {
     if (d->delta != IBDL_DELTA_PESKIN4 && d->delta != IBDL_DELTA_COSINE4) return "unknown delta kernel";
     if (d->prec != IBDL_PREC_FP64 && d->prec != IBDL_PREC_MIXED) return "unknown precision";
     if (d->lap != IBDL_LAP_FD && d->lap != IBDL_LAP_SPECTRAL) return "lap must be IBDL_LAP_FD or IBDL_LAP_SPECTRAL";
-    if (d->form != IBDL_FORM_DOUBLE_LAYER && d->form != IBDL_FORM_COMPLETED) return "unknown formulation";
+    if (d->form != IBDL_FORM_DOUBLE_LAYER && d->form != IBDL_FORM_COMPLETED && d->form != IBDL_FORM_SINGLE_LAYER)
+        return "unknown formulation";
+    if (d->form == IBDL_FORM_SINGLE_LAYER) {
+        if (d->bc != IBDL_DIRICHLET) return "the single-layer formulation takes Dirichlet data";
+        if (d->prec != IBDL_PREC_FP64) return "the single-layer formulation runs in FP64";
+    }
     if (d->form == IBDL_FORM_COMPLETED) {
         if (d->alpha != 0.0) return "the completed formulation is for the Poisson equation (alpha = 0)";
         if (d->bc != IBDL_DIRICHLET) return "the completed formulation takes Dirichlet data";
@@ -423,6 +428,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     // page for buffers that straddle them)
     // completed formulation: Q2, the per-call Q1 and sums, grid-sum partials
     if (d->form == IBDL_FORM_COMPLETED) b += (M + 1) * 8 + R * (M + 2) * 8 + R * 256 * 8 + 3 * 4096;
+    // single-layer formulation: the nine MINRES vectors, block partials and scalars
+    if (d->form == IBDL_FORM_SINGLE_LAYER) b += R * (9 * M * 8 + ((M + 255) / 256) * 8 + 14 * 8 + 16) + 13 * 4096;
     b += 96 * 4096;
     const size_t page = (size_t)2 << 20;
     return (b + page - 1) / page * page + page;
@@ -438,6 +445,10 @@ ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, v
     p->last_stream = S(stream);
     if (p->form == IBDL_FORM_COMPLETED) {
         completed_apply(p, nrhs, q, Aq, S(stream));
+        return IBDL_OK;
+    }
+    if (p->form == IBDL_FORM_SINGLE_LAYER) {
+        ibsl_apply(p, nrhs, q, Aq, S(stream));
         return IBDL_OK;
     }
     apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
@@ -533,13 +544,15 @@ static ibdl_status plan_solve(ibdl_plan p, int32_t nrhs, const double* data, con
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(IBDL_ERR_ARG, "tol must be positive");
     if (o.restart < 1 || o.restart > 200) return fail(IBDL_ERR_ARG, "restart must be in 1..200");
     if (o.maxit < 1) return fail(IBDL_ERR_ARG, "maxit must be >= 1");
-    if (p->form == IBDL_FORM_COMPLETED && o.x0) return fail(IBDL_ERR_ARG, "opts->x0 must be NULL for completed plans");
+    if (p->form != IBDL_FORM_DOUBLE_LAYER && o.x0)
+        return fail(IBDL_ERR_ARG, "opts->x0 must be NULL for completed and single-layer plans");
     IBDL_GUARD_BEGIN
     AllocStream as(S(stream));
     p->last_stream = S(stream);
     int overall = IBDL_OK;
-    if (p->form == IBDL_FORM_COMPLETED) {
-        overall = completed_solve(p, nrhs, data, g, o, sol, u, info, S(stream));
+    if (p->form != IBDL_FORM_DOUBLE_LAYER) {
+        overall = p->form == IBDL_FORM_COMPLETED ? completed_solve(p, nrhs, data, g, o, sol, u, info, S(stream))
+                                                 : ibsl_solve(p, nrhs, data, g, o, sol, u, info, S(stream));
         if (overall == IBDL_ERR_NOCONV) return fail(IBDL_ERR_NOCONV, "GMRES did not reach tol within maxit");
         if (overall == IBDL_ERR_NUMERIC) return fail(IBDL_ERR_NUMERIC, "non-finite residual");
         g_last_error.clear();
@@ -578,6 +591,10 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     p->last_stream = S(stream);
     if (p->form == IBDL_FORM_COMPLETED) {
         completed_eval_grid(p, nrhs, sol, g, u, S(stream));
+        return IBDL_OK;
+    }
+    if (p->form == IBDL_FORM_SINGLE_LAYER) {
+        ibsl_eval_grid(p, nrhs, sol, g, u, S(stream));
         return IBDL_OK;
     }
     PipeIn in;

@@ -231,3 +231,319 @@ int completed_solve(ibdl_plan p, int nrhs, const double* data, const double* g, 
 }
 
 }  // namespace ibdl
+
+// ---------------------------------------------------------------------------
+// The IB constraint (single-layer) system, the paper's comparison method
+// (Sec. 2.1; Table 1, Table 2): A F = -S* L^-1 S F, right-hand side
+// U_b - S* L^-1 g~, grid solution u = L^-1 (g~ - S F), solved by MINRES
+// (Paige-Saunders).  A is self-adjoint in <x, y>_W = sum_k w_k x_k y_k (S spreads
+// with the point weights), so the Lanczos process runs in that inner product;
+// with equal weights it is the plain MINRES of the paper.  All vectors and
+// scalars of the iteration stay on the device; the host only looks at the
+// per-rhs state between chunks of iterations.
+namespace ibdl {
+
+namespace {
+
+enum { MR_DONE = 0, MR_ITERS = 1, MR_STATUS = 2, MR_ACTIVE = 3 };
+// per-rhs scalars
+enum { S_BETA1, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_ALFA, S_PHI, S_GINV, S_DELTA, S_OLDEPS,
+       S_TOL, S_N };
+
+struct MrArgs {
+    int R, M, nblk, maxit;
+    const double* w;     // [M] point weights
+    double *b, *x, *r1, *r2, *v, *y, *wv, *w1, *w2;  // [R][M]
+    double* part;        // [R][nblk]
+    double* sc;          // [R][S_N]
+    int32_t* state;      // [R][4]
+};
+
+// block partial of sum_k w_k a_k c_k over this block's points (fixed order)
+__device__ __forceinline__ void mr_block_dot(const MrArgs& a, int r, double val) {
+    __shared__ double sh[RT];
+    sh[threadIdx.x] = val;
+    __syncthreads();
+    for (int off = RT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.part[(size_t)r * a.nblk + blockIdx.x] = sh[0];
+}
+
+__device__ __forceinline__ double mr_sum_parts(const MrArgs& a, int r) {
+    double s = 0.0;
+    for (int b = 0; b < a.nblk; ++b) s += a.part[(size_t)r * a.nblk + b];
+    return s;
+}
+
+// x = 0, r1 = r2 = b, wv = w2 = 0; partials of ||b||_W^2
+__global__ __launch_bounds__(RT) void k_mr_init(MrArgs a) {
+    const int r = blockIdx.y, k = blockIdx.x * RT + threadIdx.x;
+    double val = 0.0;
+    if (k < a.M) {
+        const size_t i = (size_t)r * a.M + k;
+        const double bv = a.b[i];
+        a.x[i] = 0.0;
+        a.r1[i] = bv;
+        a.r2[i] = bv;
+        a.wv[i] = 0.0;
+        a.w2[i] = 0.0;
+        val = a.w[k] * bv * bv;
+    }
+    mr_block_dot(a, r, val);
+}
+
+__global__ void k_mr_init_scalars(MrArgs a, double tol) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    double* s = a.sc + (size_t)r * S_N;
+    const double beta1 = sqrt(mr_sum_parts(a, r));
+    s[S_BETA1] = beta1;
+    s[S_BETA] = beta1;
+    s[S_OLDB] = 0.0;
+    s[S_DBAR] = 0.0;
+    s[S_EPS] = 0.0;
+    s[S_PHIBAR] = beta1;
+    s[S_CS] = -1.0;
+    s[S_SN] = 0.0;
+    s[S_TOL] = tol;
+    int32_t* st = a.state + 4 * r;
+    st[MR_DONE] = !(beta1 > 0.0);
+    st[MR_ITERS] = 0;
+    st[MR_STATUS] = isfinite(beta1) ? IBDL_OK : IBDL_ERR_NUMERIC;
+    st[MR_ACTIVE] = 0;
+    if (!isfinite(beta1)) st[MR_DONE] = 1;
+}
+
+// v = r2 / beta
+__global__ __launch_bounds__(RT) void k_mr_v(MrArgs a) {
+    const int r = blockIdx.y, k = blockIdx.x * RT + threadIdx.x;
+    if (a.state[4 * r + MR_DONE] || k >= a.M) return;
+    const size_t i = (size_t)r * a.M + k;
+    a.v[i] = a.r2[i] / a.sc[(size_t)r * S_N + S_BETA];
+}
+
+// y -= (beta / oldb) r1 (from the second iteration); partials of <v, y>_W
+__global__ __launch_bounds__(RT) void k_mr_p1(MrArgs a) {
+    const int r = blockIdx.y, k = blockIdx.x * RT + threadIdx.x;
+    if (a.state[4 * r + MR_DONE]) return;
+    const double* s = a.sc + (size_t)r * S_N;
+    const bool later = a.state[4 * r + MR_ITERS] >= 1;
+    double val = 0.0;
+    if (k < a.M) {
+        const size_t i = (size_t)r * a.M + k;
+        double yv = a.y[i];
+        if (later) yv = fmac(-(s[S_BETA] / s[S_OLDB]), a.r1[i], yv);
+        a.y[i] = yv;
+        val = a.w[k] * a.v[i] * yv;
+    }
+    mr_block_dot(a, r, val);
+}
+
+__global__ void k_mr_alfa(MrArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R || a.state[4 * r + MR_DONE]) return;
+    a.sc[(size_t)r * S_N + S_ALFA] = mr_sum_parts(a, r);
+}
+
+// y -= (alfa / beta) r2; r1 = r2; r2 = y; partials of ||r2||_W^2
+__global__ __launch_bounds__(RT) void k_mr_p2(MrArgs a) {
+    const int r = blockIdx.y, k = blockIdx.x * RT + threadIdx.x;
+    if (a.state[4 * r + MR_DONE]) return;
+    const double* s = a.sc + (size_t)r * S_N;
+    double val = 0.0;
+    if (k < a.M) {
+        const size_t i = (size_t)r * a.M + k;
+        const double yv = fmac(-(s[S_ALFA] / s[S_BETA]), a.r2[i], a.y[i]);
+        a.r1[i] = a.r2[i];
+        a.r2[i] = yv;
+        val = a.w[k] * yv * yv;
+    }
+    mr_block_dot(a, r, val);
+}
+
+// the Lanczos coefficient beta_{k+1}, the QR update of the tridiagonal matrix by a
+// Givens rotation, the residual estimate and the stopping decision
+__global__ void k_mr_scal(MrArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    int32_t* st = a.state + 4 * r;
+    if (st[MR_DONE]) return;
+    double* s = a.sc + (size_t)r * S_N;
+    const double beta = sqrt(mr_sum_parts(a, r));
+    const double alfa = s[S_ALFA], cs = s[S_CS], sn = s[S_SN], dbar = s[S_DBAR];
+    s[S_OLDB] = s[S_BETA];
+    s[S_BETA] = beta;
+    s[S_OLDEPS] = s[S_EPS];
+    s[S_DELTA] = cs * dbar + sn * alfa;
+    const double gbar = sn * dbar - cs * alfa;
+    s[S_EPS] = sn * beta;
+    s[S_DBAR] = -cs * beta;
+    const double gamma = hypot(gbar, beta);
+    const double c2 = gbar / gamma, s2 = beta / gamma;
+    s[S_CS] = c2;
+    s[S_SN] = s2;
+    s[S_PHI] = c2 * s[S_PHIBAR];
+    s[S_PHIBAR] = s2 * s[S_PHIBAR];
+    s[S_GINV] = 1.0 / gamma;
+    st[MR_ITERS] += 1;
+    st[MR_ACTIVE] = 1;
+    const double rel = s[S_PHIBAR] / s[S_BETA1];
+    if (!isfinite(rel) || !isfinite(gamma)) {
+        st[MR_STATUS] = IBDL_ERR_NUMERIC;
+        st[MR_DONE] = 1;
+        st[MR_ACTIVE] = 0;
+    } else if (rel <= s[S_TOL] || !(beta > 0.0)) {
+        st[MR_DONE] = 1;
+    } else if (st[MR_ITERS] >= a.maxit) {
+        st[MR_STATUS] = IBDL_ERR_NOCONV;
+        st[MR_DONE] = 1;
+    }
+}
+
+// w1 = w2; w2 = wv; wv = (v - oldeps w1 - delta w2) / gamma; x += phi wv
+__global__ __launch_bounds__(RT) void k_mr_update(MrArgs a) {
+    const int r = blockIdx.y, k = blockIdx.x * RT + threadIdx.x;
+    if (!a.state[4 * r + MR_ACTIVE]) return;
+    const double* s = a.sc + (size_t)r * S_N;
+    if (k < a.M) {
+        const size_t i = (size_t)r * a.M + k;
+        const double w1 = a.w2[i], w2 = a.wv[i];
+        const double wn = (a.v[i] - s[S_OLDEPS] * w1 - s[S_DELTA] * w2) * s[S_GINV];
+        a.w1[i] = w1;
+        a.w2[i] = w2;
+        a.wv[i] = wn;
+        a.x[i] = fmac(s[S_PHI], wn, a.x[i]);
+    }
+}
+
+__global__ void k_mr_clear_active(MrArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < a.R) a.state[4 * r + MR_ACTIVE] = 0;
+}
+
+}  // namespace
+
+void ibsl_apply(ibdl_plan p, int nrhs, const double* q, double* out, hipStream_t st) {
+    PipeIn in;
+    in.q_mono = q;
+    in.c_mono = 1.0;
+    PipeOut o;
+    o.out = out;
+    o.cA = -1.0;
+    run_pipeline(p, nrhs, in, o, st);
+}
+
+void ibsl_eval_grid(ibdl_plan p, int nrhs, const double* f, const double* g, double* u, hipStream_t st) {
+    PipeIn in;
+    in.q_mono = f;
+    in.c_mono = -1.0;
+    in.grid = g;
+    in.c_grid = 1.0;
+    PipeOut o;
+    o.u = u;
+    run_pipeline(p, nrhs, in, o, st, true);
+}
+
+int ibsl_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o, double* sol,
+               double* u, ibdl_solve_info* info, hipStream_t st) {
+    const int M = p->M, R = nrhs;
+    const int nblk = (M + RT - 1) / RT;
+    std::vector<void*> tmp;
+    auto A = [&](size_t n) { return reinterpret_cast<double*>(dev_alloc(tmp, n * sizeof(double))); };
+    MrArgs a{};
+    a.R = R;
+    a.M = M;
+    a.nblk = nblk;
+    a.maxit = o.maxit;
+    a.w = p->wgt;
+    const size_t V = (size_t)R * M;
+    a.b = A(V);
+    a.x = A(V);
+    a.r1 = A(V);
+    a.r2 = A(V);
+    a.v = A(V);
+    a.y = A(V);
+    a.wv = A(V);
+    a.w1 = A(V);
+    a.w2 = A(V);
+    a.part = A((size_t)R * nblk);
+    a.sc = A((size_t)R * S_N);
+    a.state = reinterpret_cast<int32_t*>(dev_alloc(tmp, (size_t)R * 4 * sizeof(int32_t)));
+    // right-hand side U_b - S* L^-1 g~ (FP64)
+    {
+        PipeIn in;
+        PipeOut po;
+        po.out = a.b;
+        if (g) {
+            in.grid = g;
+            in.c_grid = 1.0;
+            po.cA = -1.0;
+            po.in = data;
+            po.cB = 1.0;
+            run_pipeline(p, R, in, po, st, true);
+        } else {
+            IBDL_HIP_TRY(hipMemcpyAsync(a.b, data, V * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+    }
+    const dim3 vg(nblk, R), sg((R + 63) / 64);
+    hipLaunchKernelGGL(k_mr_init, vg, dim3(RT), 0, st, a);
+    hipLaunchKernelGGL(k_mr_init_scalars, sg, dim3(64), 0, st, a, o.tol);
+    // the operator pass y = A v, prepared once; converged rhs are skipped by their flag
+    PipeIn in;
+    in.q_mono = a.v;
+    in.c_mono = 1.0;
+    in.skip = a.state;
+    PipeOut po;
+    po.out = a.y;
+    po.cA = -1.0;
+    std::vector<PassJob> jobs{PassJob{p, R, in, po}};
+    std::unique_ptr<PreparedPass> op = prepare_pass(jobs, true);
+    std::vector<int32_t> hstate((size_t)R * 4);
+    std::vector<double> hsc((size_t)R * S_N);
+    int done_iters = 0;
+    for (;;) {
+        const int chunk = std::min(64, o.maxit - done_iters);
+        for (int c = 0; c < chunk; ++c) {
+            hipLaunchKernelGGL(k_mr_v, vg, dim3(RT), 0, st, a);
+            op->run(0, st);
+            hipLaunchKernelGGL(k_mr_p1, vg, dim3(RT), 0, st, a);
+            hipLaunchKernelGGL(k_mr_alfa, sg, dim3(64), 0, st, a);
+            hipLaunchKernelGGL(k_mr_p2, vg, dim3(RT), 0, st, a);
+            hipLaunchKernelGGL(k_mr_scal, sg, dim3(64), 0, st, a);
+            hipLaunchKernelGGL(k_mr_update, vg, dim3(RT), 0, st, a);
+            hipLaunchKernelGGL(k_mr_clear_active, sg, dim3(64), 0, st, a);
+        }
+        done_iters += chunk;
+        IBDL_HIP_TRY(hipGetLastError());
+        IBDL_HIP_TRY(hipMemcpyAsync(hstate.data(), a.state, hstate.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        IBDL_HIP_TRY(hipStreamSynchronize(st));
+        bool all = true;
+        for (int r = 0; r < R; ++r) all &= hstate[4 * r + MR_DONE] != 0;
+        if (all || done_iters >= o.maxit) break;
+    }
+    IBDL_HIP_TRY(hipMemcpyAsync(hsc.data(), a.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    IBDL_HIP_TRY(hipMemcpyAsync(sol, a.x, V * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (u) ibsl_eval_grid(p, R, sol, g, u, st);
+    IBDL_HIP_TRY(hipStreamSynchronize(st));
+    int overall = IBDL_OK;
+    for (int r = 0; r < R; ++r) {
+        int s = hstate[4 * r + MR_STATUS];
+        if (s == IBDL_OK && !hstate[4 * r + MR_DONE]) s = IBDL_ERR_NOCONV;
+        if (info) {
+            info[r].iters = hstate[4 * r + MR_ITERS];
+            const double b1 = hsc[(size_t)r * S_N + S_BETA1];
+            info[r].rel_resid_est = b1 > 0.0 ? hsc[(size_t)r * S_N + S_PHIBAR] / b1 : 0.0;
+            info[r].rel_resid_true = -1.0;
+            info[r].status = s;
+            info[r].fp64_applies = 0;
+        }
+        if (s == IBDL_ERR_NUMERIC) overall = IBDL_ERR_NUMERIC;
+        else if (s == IBDL_ERR_NOCONV && overall == IBDL_OK) overall = IBDL_ERR_NOCONV;
+    }
+    for (void* t : tmp) dev_free(t);
+    return overall;
+}
+
+}  // namespace ibdl

@@ -334,6 +334,11 @@ void completed_rhs(ibdl_plan p, int nrhs, const double* data, const double* g, d
 void completed_eval_grid(ibdl_plan p, int nrhs, const double* z, const double* g, double* u, hipStream_t st);
 int completed_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o,
                     double* sol, double* u, ibdl_solve_info* info, hipStream_t st);
+// single-layer (IB constraint) formulation with MINRES (forms.hip)
+void ibsl_apply(ibdl_plan p, int nrhs, const double* q, double* out, hipStream_t st);
+void ibsl_eval_grid(ibdl_plan p, int nrhs, const double* f, const double* g, double* u, hipStream_t st);
+int ibsl_solve(ibdl_plan p, int nrhs, const double* data, const double* g, const ibdl_solve_opts& o, double* sol,
+               double* u, ibdl_solve_info* info, hipStream_t st);
 void nearfix_fixup(ibdl_plan p, int nrhs, const double* u, const double* ub, const uint8_t* flags, double m1,
                    double m2, double* uout, hipStream_t st);
 void free_build_tmp(ibdl_plan p);

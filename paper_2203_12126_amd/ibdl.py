@@ -19,7 +19,7 @@ DIRICHLET, NEUMANN = 0, 1
 PESKIN4, COSINE4 = 0, 1
 FP64, MIXED = 0, 1
 LAP_FD, LAP_SPECTRAL = 0, 1
-FORM_DOUBLE_LAYER, FORM_COMPLETED = 0, 1
+FORM_DOUBLE_LAYER, FORM_COMPLETED, FORM_SINGLE_LAYER = 0, 1, 2
 
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NUMERIC",
            6: "ERR_STATE"}

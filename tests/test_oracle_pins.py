@@ -576,3 +576,49 @@ def test_completed_system_is_well_posed():
     sb = np.linalg.svd(B, compute_uv=False)
     s0 = np.linalg.svd(K0, compute_uv=False)
     assert sb[-1] > 0.45 and s0[-1] < 0.1
+
+
+# ------------------------------------------------------------------- IBSL comparison and MINRES (Sec. 2.1, Table 1)
+def test_ibsl_operator_self_adjoint_positive():
+    """-S* L^-1 S is self-adjoint and positive in <x, y>_W = sum w x y: S spreads with
+    the weights and S* interpolates with h^d, adjoint up to them (Sec. 2.1), and
+    -L^-1 is positive for alpha > 0."""
+    p = W.table1_problem(64, 1.3)
+    st = O.setup_from_problem(p)
+    rng = np.random.default_rng(2)
+    x, y = rng.standard_normal((2, st.m))
+    w = st.weight
+    ax, ay = O.apply_ibsl(st, x), O.apply_ibsl(st, y)
+    assert abs(np.sum(w * ax * y) - np.sum(w * x * ay)) < 1e-12 * abs(np.sum(w * ax * y))
+    assert np.sum(w * ax * x) > 0 and np.sum(w * ay * y) > 0
+
+
+def test_minres_against_dense_solve():
+    """MINRES reaches the dense solution of a small IBSL system; with unequal weights
+    it still converges (the W inner product)."""
+    p = W.table1_problem(32, 2.0)
+    st = O.setup_from_problem(p)
+    st.weight = st.weight * (1.0 + 0.3 * np.cos(np.arange(st.m)))  # unequal weights
+    A = np.stack([O.apply_ibsl(st, e) for e in np.eye(st.m)], axis=1)
+    b = O.rhs_ibsl(st, p.data)
+    ref = np.linalg.solve(A, b)
+    res = O.minres(lambda v: O.apply_ibsl(st, v), b, st.weight, tol=1e-13)
+    assert res.converged and np.linalg.norm(res.x - ref) < 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("log2n,cs", [(6, (2.0, 1.5, 1.0, 0.75)), (7, (2.0, 1.5))])
+def test_table1_ibsl_minres_counts(log2n, cs):
+    """Table 1, IBSL columns: the MINRES counts at tol 1e-8 within 8% of the paper's
+    (MATLAB's minres), growing as the points crowd (c smaller) and with n."""
+    with open(GOLDEN) as f:
+        gold = json.load(f)["table1_ibsl_minres_tol1e-8"]
+    row = gold["rows_log2_inv_dx"].index(log2n)
+    counts = []
+    for c in cs:
+        p = W.table1_problem(2 ** log2n, c)
+        st = O.setup_from_problem(p)
+        res, _ = O.solve_ibsl(st, p.data, p.g_tilde, tol=1e-8)
+        want = gold["counts"][row][gold["columns_ds_over_dx"].index(c)]
+        assert res.converged and abs(res.iters - want) <= max(2, 0.08 * want), (c, res.iters, want)
+        counts.append(res.iters)
+    assert all(a < b for a, b in zip(counts, counts[1:]))
