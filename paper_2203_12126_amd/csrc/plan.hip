@@ -1,14 +1,17 @@
 // Plan construction: everything that depends only on the geometry and grid.
 //
 //  * cell binning: c_d = floor((X_d - lo_d)/h) mod n in IEEE FP64, key = row-major
-//    cell index with x fastest; stable order of (key, caller index) by a bitonic
-//    sort of the 64-bit composite keys (key << 32 | index) -- unique, so the
-//    order of equal cell keys is the caller order;
+//    cell index with x fastest; stable order of (key, caller index) as the order
+//    of the 64-bit composites (key << 32 | index) -- unique, so the order of equal
+//    cell keys is the caller order -- by ranking (small point counts) or a
+//    bitonic sort;
 //  * per point the 1-D delta taps phi(p - t) for p = c-1..c+2 (Sec. 5.2);
 //  * the sparse dipole spread S~ q = div(S (q n)) (Sec. 5.2) and, for Neumann
 //    plans, the monopole spread S (the discrete spread of Sec. 5.2),
-//    as rows over the active grid nodes: every (node, point) pair the stencil
-//    reaches is emitted, sorted by (node, point), and weighed;
+//    as rows over the active grid nodes: entries per node are counted from the
+//    points' stencils, and each node then collects its entries from the cells
+//    around it in sorted-point order (cell key, then caller index) -- no sort of
+//    the entries; every (node, point) pair the stencil reaches is one entry;
 //  * the x-lines that receive forcing and the x-lines interpolated from;
 //  * twiddles exp(-2 pi i m/n) and the symbol terms: (4/h^2) sin^2(pi m/n) for the
 //    finite-difference Laplacian (Sec. 5.1), (2 pi k/L)^2 with k the signed
@@ -326,14 +329,16 @@ static void bitonic_sort(uint64_t* a, size_t n2, hipStream_t st) {
 // exclusive scan of int32 ----------------------------------------------------
 constexpr int SCAN_T = 256, SCAN_PER = 8, SCAN_TILE = SCAN_T * SCAN_PER;
 
+// scans in, or the flags in > 0 when positive is set
 __global__ __launch_bounds__(SCAN_T) void k_scan_tile(const int32_t* in, int32_t* out, size_t n,
-                                                      int32_t* sums) {
+                                                      int32_t* sums, int positive) {
     __shared__ int32_t s[SCAN_T];
     const size_t base = (size_t)blockIdx.x * SCAN_TILE + (size_t)threadIdx.x * SCAN_PER;
     int32_t v[SCAN_PER];
     int32_t tot = 0;
     for (int i = 0; i < SCAN_PER; ++i) {
         v[i] = (base + i < n) ? in[base + i] : 0;
+        if (positive) v[i] = v[i] > 0;
         tot += v[i];
     }
     s[threadIdx.x] = tot;
@@ -357,16 +362,18 @@ __global__ void k_scan_add(int32_t* out, size_t n, const int32_t* offs) {
     if (i < n) out[i] += offs[i / SCAN_TILE];
 }
 
-// out = exclusive scan of in (n entries); returns nothing, total = out[n-1] + in[n-1]
-static void scan_excl(ibdl_plan p, const int32_t* in, int32_t* out, size_t n, hipStream_t st) {
+// out = exclusive scan of in (n entries), or of the flags in > 0 with positive set;
+// the total is out[n-1] plus the last entry (or flag)
+static void scan_excl(ibdl_plan p, const int32_t* in, int32_t* out, size_t n, hipStream_t st, bool positive = false) {
     const size_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nt <= 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (int32_t*)nullptr);
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (int32_t*)nullptr,
+                           positive ? 1 : 0);
         return;
     }
     int32_t* sums = tmp_n<int32_t>(p, nt);
     int32_t* soff = tmp_n<int32_t>(p, nt);
-    hipLaunchKernelGGL(k_scan_tile, dim3((int)nt), dim3(SCAN_T), 0, st, in, out, n, sums);
+    hipLaunchKernelGGL(k_scan_tile, dim3((int)nt), dim3(SCAN_T), 0, st, in, out, n, sums, positive ? 1 : 0);
     scan_excl(p, sums, soff, nt, st);
     hipLaunchKernelGGL(k_scan_add, dim3(nblocks(n, 256)), dim3(256), 0, st, out, n, soff);
 }
@@ -388,6 +395,40 @@ static int32_t read_count(ibdl_plan p, const int32_t* scan_last, const int32_t* 
 }
 
 // ------------------------------------------------------------------ sorted geometry
+// Rank sort for small point counts: the sorted position of point k is the number of
+// composites (key << 32 | index) below its own -- all distinct, so the ranks are a
+// permutation and equal keys keep the caller order.  A block ranks RS_K points,
+// RS_SPLIT threads per point each counting over a quarter of every tile of RS_T.
+constexpr int RS_K = 64, RS_SPLIT = 4, RS_T = RS_K * RS_SPLIT;
+constexpr int RANK_SORT_MAX = 16384;  // above this the bitonic sort is faster
+
+__global__ __launch_bounds__(RS_T) void k_rank_sort(const uint32_t* __restrict__ key, int M, uint32_t* perm,
+                                                    uint32_t* skey, uint32_t* invperm) {
+    __shared__ uint64_t tile[RS_T];
+    __shared__ int part[RS_SPLIT][RS_K];
+    const int kk = threadIdx.x % RS_K, q = threadIdx.x / RS_K;
+    const int k = blockIdx.x * RS_K + kk;
+    const uint64_t mine = k < M ? (((uint64_t)key[k]) << 32) | (uint64_t)k : ~0ull;
+    int rank = 0;
+    for (int base = 0; base < M; base += RS_T) {
+        const int j = base + threadIdx.x;
+        tile[threadIdx.x] = j < M ? (((uint64_t)key[j]) << 32) | (uint64_t)j : ~0ull;
+        __syncthreads();
+#pragma unroll 16
+        for (int t = 0; t < RS_K; ++t) rank += tile[q * RS_K + t] < mine;
+        __syncthreads();
+    }
+    part[q][kk] = rank;
+    __syncthreads();
+    if (q == 0 && k < M) {
+        int r = 0;
+        for (int i = 0; i < RS_SPLIT; ++i) r += part[i][kk];
+        perm[r] = (uint32_t)k;
+        skey[r] = key[k];
+        invperm[k] = (uint32_t)r;
+    }
+}
+
 __global__ void k_unpack(const uint64_t* __restrict__ srt, int M, uint32_t* perm, uint32_t* skey,
                          uint32_t* invperm) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -462,12 +503,9 @@ constexpr DipStencil dip_stencil(int dim) {
 __constant__ DipStencil kDip2 = dip_stencil(2);
 __constant__ DipStencil kDip3 = dip_stencil(3);
 
-__global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
-                       int M, int dim, int n, int dipole, int npp, uint64_t* out) {
-    // M * npp < 2^31 (checked by the caller): 32-bit index arithmetic
-    const int id = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (id >= M * npp) return;
-    const int s = id / npp, j = id - s * npp;
+// node id of stencil entry j of the point at sorted position s
+__device__ __forceinline__ uint32_t stencil_node(const int32_t* __restrict__ cell_s, int s, int j, int dim, int n,
+                                                 int dipole) {
     int r[3] = {0, 0, 0};
     if (dipole) {
         const int8_t* o = dim == 2 ? kDip2.o[j] : kDip3.o[j];
@@ -488,7 +526,28 @@ __global__ void k_emit(const int32_t* __restrict__ cell_s, const uint32_t* __res
         node += (uint32_t)c * stride;
         stride *= (uint32_t)n;
     }
-    out[id] = ((uint64_t)node << 32) | (uint64_t)perm[s];
+    return node;
+}
+
+// entries per grid node: every (point, stencil node) pair counts once
+__global__ void k_node_count(const int32_t* __restrict__ cell_s, int M, int dim, int n, int dipole, int npp,
+                             int32_t* cnt) {
+    // M * npp < 2^31 (checked by the caller): 32-bit index arithmetic
+    const int id = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (id >= M * npp) return;
+    const int s = id / npp;
+    atomicAdd(&cnt[stencil_node(cell_s, s, id - s * npp, dim, n, dipole)], 1);
+}
+
+__global__ void k_flag_of(const int32_t* cnt, int32_t* flag) { *flag = *cnt > 0; }
+
+// active nodes in ascending id and their entry counts; idx = exclusive scan of the flags
+__global__ void k_compact_nodes(const int32_t* __restrict__ cnt, const int32_t* __restrict__ idx, size_t ncell,
+                                uint32_t* act_node, int32_t* act_cnt) {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell || cnt[c] == 0) return;
+    act_node[idx[c]] = (uint32_t)c;
+    act_cnt[idx[c]] = cnt[c];
 }
 
 // A_d(r) = phi(c - 1 + i - t) at r = i - 1 in -1..2, zero outside
@@ -496,30 +555,14 @@ __device__ __forceinline__ double tap_at(const double* t4, int r) {
     return (r >= -1 && r <= 2) ? t4[r + 1] : 0.0;
 }
 
-__global__ void k_weights(const uint64_t* __restrict__ srt, size_t nnz,
-                          const uint32_t* __restrict__ invperm, const int32_t* __restrict__ cell_s,
-                          const double* __restrict__ taps64, const double* __restrict__ nrm3,
-                          const double* __restrict__ w1, int dim, int n, double h, int dipole,
-                          uint32_t* K, double* W64, float* W32, int32_t* head) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nnz) return;
-    const uint64_t v = srt[e];
-    const uint32_t node = (uint32_t)(v >> 32);
-    const uint32_t k = (uint32_t)(v & 0xffffffffull);
-    const uint32_t s = invperm[k];
-    int r[3] = {0, 0, 0};
-    uint32_t rem = node;
-    for (int d = 0; d < dim; ++d) {
-        const int p = (int)(rem % (uint32_t)n);
-        rem /= (uint32_t)n;
-        r[d] = ((p - cell_s[3 * s + d] + 2 + 2 * n) % n) - 2;   // in -2..3
-    }
-    const double* t = taps64 + 12 * (size_t)s;
+// weight of point k (sorted position s, stencil offsets r) at a node: the dipole
+// (w_k / h^d) sum_d n_d (A_d(r_d+1) - A_d(r_d-1)) / (2h) prod_{e != d} A_e(r_e),
+// or the monopole (w_k / h^d) prod_d A_d(r_d)
+__device__ double entry_weight(const double* __restrict__ t, const double* __restrict__ nrm3, double wk, uint32_t k,
+                               const int* r, int dim, double h, int dipole) {
     double hd = 1.0;
     for (int d = 0; d < dim; ++d) hd *= h;
-    double wv;
     if (dipole) {
-        // (w_k / h^d) sum_d n_d (A_d(r_d+1) - A_d(r_d-1)) / (2h) prod_{e != d} A_e(r_e)
         double acc = 0.0;
         for (int d = 0; d < dim; ++d) {
             double term = (tap_at(t + 4 * d, r[d] + 1) - tap_at(t + 4 * d, r[d] - 1)) / (2.0 * h);
@@ -527,27 +570,128 @@ __global__ void k_weights(const uint64_t* __restrict__ srt, size_t nnz,
                 if (q != d) term *= tap_at(t + 4 * q, r[q]);
             acc += nrm3[3 * k + d] * term;
         }
-        wv = w1[k] / hd * acc;
-    } else {
-        double prod = 1.0;
-        for (int d = 0; d < dim; ++d) prod *= tap_at(t + 4 * d, r[d]);
-        wv = w1[k] / hd * prod;
+        return wk / hd * acc;
     }
+    double prod = 1.0;
+    for (int d = 0; d < dim; ++d) prod *= tap_at(t + 4 * d, r[d]);
+    return wk / hd * prod;
+}
+
+// The cells c = p - r, r in [rlo, rhi], of one axis in ascending (periodic) order:
+// start at the first unwrapped offset u0 + t whose wrapped value is the smallest
+struct AxisRun {
+    int u0, cnt, t0;
+};
+__device__ __forceinline__ AxisRun axis_run(int p, int rlo, int rhi, int n) {
+    AxisRun a;
+    a.u0 = p - rhi;
+    a.cnt = rhi - rlo + 1;
+    const int ulast = p - rlo;
+    a.t0 = a.u0 < 0 ? -a.u0 : (ulast >= n ? n - a.u0 : 0);
+    return a;
+}
+__device__ __forceinline__ int axis_cell(const AxisRun& a, int i, int n) {
+    int t = a.t0 + i;
+    t -= t >= a.cnt ? a.cnt : 0;
+    int c = a.u0 + t;
+    c += c < 0 ? n : 0;
+    c -= c >= n ? n : 0;
+    return c;
+}
+
+// first sorted position in [s0, s1) of x-line points whose cell x is >= cx (skey % n
+// ascends within a line)
+__device__ __forceinline__ int line_lower(const uint32_t* __restrict__ skey, int s0, int s1, int n, int cx) {
+    while (s0 < s1) {
+        const int mid = (s0 + s1) >> 1;
+        if ((int)(skey[mid] % (uint32_t)n) < cx) s0 = mid + 1; else s1 = mid;
+    }
+    return s0;
+}
+
+// One active node per thread: its entries are the points of the cells c = node - r
+// over the stencil offsets r, taken in ascending cell key and, within a cell, in
+// sorted order -- the order of sorted positions (cell key, then caller index).  A
+// row of cells along x at fixed (y, z) is one or two ranges of sorted positions,
+// found in the x-line's points.  Writes the sorted position and the node of each
+// entry; a count that differs from the node's raises bad[3] and writes nothing past
+// the node's range.
+__global__ void k_fill(const uint32_t* __restrict__ act_node, const int32_t* __restrict__ act_ptr, int nact,
+                       int dim, int n, int dipole, const int32_t* __restrict__ line_start,
+                       const uint32_t* __restrict__ skey, uint32_t* ent_s, uint32_t* ent_node, int32_t* bad) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nact) return;
+    const uint32_t node = act_node[a];
+    const int pc[3] = {(int)(node % (uint32_t)n), (int)((node / (uint32_t)n) % (uint32_t)n),
+                       dim == 3 ? (int)(node / ((uint32_t)n * (uint32_t)n)) : 0};
+    const int e1 = act_ptr[a + 1];
+    int e = act_ptr[a];
+    // offsets per axis: dipole -2..3 with at most one axis outside -1..2, monopole -1..2
+    const int lo = dipole ? -2 : -1, hi = dipole ? 3 : 2;
+    const AxisRun rz = dim == 3 ? axis_run(pc[2], lo, hi, n) : AxisRun{0, 1, 0};
+    const AxisRun ry = axis_run(pc[1], lo, hi, n);
+    for (int iz = 0; iz < rz.cnt; ++iz) {
+        const int cz = dim == 3 ? axis_cell(rz, iz, n) : 0;
+        const int oz = dim == 3 ? ((pc[2] - cz + 2 + 2 * n) % n) - 2 : 0;
+        for (int iy = 0; iy < ry.cnt; ++iy) {
+            const int cy = axis_cell(ry, iy, n);
+            const int oy = ((pc[1] - cy + 2 + 2 * n) % n) - 2;
+            const int outside = (oy < -1 || oy > 2) + (oz < -1 || oz > 2);
+            if (outside > 1) continue;
+            const int line = cz * n + cy;
+            const int l0 = line_start[line], l1 = line_start[line + 1];
+            if (l0 == l1) continue;
+            const int xlo = outside ? -1 : lo, xhi = outside ? 2 : hi;
+            // cells pc[0] - xhi .. pc[0] - xlo along x: one range, or two across the seam
+            const int u0 = pc[0] - xhi, u1 = pc[0] - xlo;
+            int seg[2][2];
+            int nseg = 1;
+            if (u0 < 0) {
+                seg[0][0] = 0; seg[0][1] = u1; seg[1][0] = u0 + n; seg[1][1] = n - 1; nseg = 2;
+            } else if (u1 >= n) {
+                seg[0][0] = 0; seg[0][1] = u1 - n; seg[1][0] = u0; seg[1][1] = n - 1; nseg = 2;
+            } else {
+                seg[0][0] = u0; seg[0][1] = u1;
+            }
+            for (int g = 0; g < nseg; ++g) {
+                const int s0 = line_lower(skey, l0, l1, n, seg[g][0]);
+                const int s1 = line_lower(skey, s0, l1, n, seg[g][1] + 1);
+                if (e + (s1 - s0) > e1) {
+                    bad[3] = 1;
+                    return;
+                }
+                for (int s = s0; s < s1; ++s, ++e) {
+                    ent_s[e] = (uint32_t)s;
+                    ent_node[e] = node;
+                }
+            }
+        }
+    }
+    if (e != e1) bad[3] = 1;
+}
+
+// entry weights, one entry per thread; K holds the sorted position on entry and the
+// caller index on exit
+__global__ void k_entry_weights(size_t nnz, const uint32_t* __restrict__ ent_node, int dim, int n,
+                                const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
+                                const double* __restrict__ taps64, const double* __restrict__ nrm3,
+                                const double* __restrict__ w1, double h, int dipole, uint32_t* K, double* W64,
+                                float* W32) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const uint32_t s = K[e];
+    uint32_t rem = ent_node[e];
+    int r[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        const int p = (int)(rem % (uint32_t)n);
+        rem /= (uint32_t)n;
+        r[d] = ((p - cell_s[3 * s + d] + 2 + 2 * n) % n) - 2;   // in -2..3
+    }
+    const uint32_t k = perm[s];
+    const double wv = entry_weight(taps64 + 12 * (size_t)s, nrm3, w1[k], k, r, dim, h, dipole);
     K[e] = k;
     W64[e] = wv;
     W32[e] = (float)wv;
-    head[e] = (e == 0) || ((uint32_t)(srt[e - 1] >> 32) != node);
-}
-
-__global__ void k_compact_heads(const uint64_t* __restrict__ srt, size_t nnz,
-                                const int32_t* __restrict__ head, const int32_t* __restrict__ idx,
-                                uint32_t* act_node, int32_t* act_ptr) {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nnz) return;
-    if (head[e]) {
-        act_node[idx[e]] = (uint32_t)(srt[e] >> 32);
-        act_ptr[idx[e]] = (int32_t)e;
-    }
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
@@ -660,34 +804,47 @@ static int compact(ibdl_plan p, const int32_t* flag, int n, int32_t** list, hipS
     return cnt;
 }
 
-static void build_csr(ibdl_plan p, Csr& c, bool dipole, hipStream_t st) {
+// Dense per-node counts and their flag scan, shared by the spread matrices of one plan
+struct CsrScratch {
+    size_t ncell = 0;
+    int32_t* cnt = nullptr;  // [ncell]
+    int32_t* idx = nullptr;  // [ncell]
+    int32_t* bad = nullptr;
+};
+
+static void build_csr(ibdl_plan p, Csr& c, bool dipole, const CsrScratch& cs, hipStream_t st) {
     const int dim = p->dim, n = p->n, M = p->M;
     const int npp = dipole ? (dim == 2 ? 32 : 160) : (dim == 2 ? 16 : 64);
     const size_t nnz = (size_t)M * npp;
     if (nnz * sizeof(double) >= (size_t)INT32_MAX) throw Error{IBDL_ERR_ARG, "too many spread entries"};
-    const size_t n2 = pow2_at_least(nnz, BIT_BLOCK);
-    uint64_t* keys = tmp_n<uint64_t>(p, n2);
-    hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, (const uint32_t*)nullptr,
-                       0, n2, keys);  // fill with padding
-    hipLaunchKernelGGL(k_emit, dim3(nblocks(nnz, 256)), dim3(256), 0, st, p->cell, p->perm, M, dim, n,
-                       dipole ? 1 : 0, npp, keys);
-    bitonic_sort(keys, n2, st);
+    const size_t ncell = cs.ncell;
+    // rows: nodes with at least one entry, ascending; their counts and offsets
+    IBDL_HIP_TRY(hipMemsetAsync(cs.cnt, 0, ncell * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_node_count, dim3(nblocks(nnz, 256)), dim3(256), 0, st, p->cell, M, dim, n,
+                       dipole ? 1 : 0, npp, cs.cnt);
+    scan_excl(p, cs.cnt, cs.idx, ncell, st, true);
+    // flag of the last node: its count, positive or zero (read_count adds it as is)
+    int32_t* last_flag = tmp_n<int32_t>(p, 1);
+    hipLaunchKernelGGL(k_flag_of, dim3(1), dim3(1), 0, st, cs.cnt + ncell - 1, last_flag);
+    c.nact = read_count(p, cs.idx + ncell - 1, last_flag, st);
+    c.act_node = alloc_n<uint32_t>(p, (size_t)std::max(c.nact, 1));
+    c.act_ptr = alloc_n<int32_t>(p, (size_t)c.nact + 1);
+    int32_t* act_cnt = tmp_n<int32_t>(p, (size_t)std::max(c.nact, 1));
+    hipLaunchKernelGGL(k_compact_nodes, dim3(nblocks(ncell, 256)), dim3(256), 0, st, cs.cnt, cs.idx, ncell,
+                       c.act_node, act_cnt);
+    scan_excl(p, act_cnt, c.act_ptr, (size_t)c.nact, st);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, st, c.act_ptr + c.nact, (int32_t)nnz);
+    // entries, collected per node from the x-lines around it (no sort of the entries),
+    // then weighed one per thread
     c.nnz = (int64_t)nnz;
     c.k = alloc_n<uint32_t>(p, nnz);
     c.w64 = alloc_n<double>(p, nnz);
     c.w32 = alloc_n<float>(p, nnz);
-    int32_t* head = tmp_n<int32_t>(p, nnz);
-    int32_t* idx = tmp_n<int32_t>(p, nnz);
-    hipLaunchKernelGGL(k_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, p->invperm,
-                       p->cell, p->taps64, p->nrm, p->wgt, dim, n, p->h, dipole ? 1 : 0, c.k, c.w64,
-                       c.w32, head);
-    scan_excl(p, head, idx, nnz, st);
-    c.nact = read_count(p, idx + nnz - 1, head + nnz - 1, st);
-    c.act_node = alloc_n<uint32_t>(p, (size_t)c.nact);
-    c.act_ptr = alloc_n<int32_t>(p, (size_t)c.nact + 1);
-    hipLaunchKernelGGL(k_compact_heads, dim3(nblocks(nnz, 256)), dim3(256), 0, st, keys, nnz, head, idx,
-                       c.act_node, c.act_ptr);
-    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, st, c.act_ptr + c.nact, (int32_t)nnz);
+    uint32_t* ent_node = tmp_n<uint32_t>(p, nnz);
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(c.nact, 256)), dim3(256), 0, st, c.act_node, c.act_ptr, c.nact, dim, n,
+                       dipole ? 1 : 0, p->line_start, p->skey, c.k, ent_node, cs.bad);
+    hipLaunchKernelGGL(k_entry_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, nnz, ent_node, dim, n, p->cell,
+                       p->perm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64, c.w32);
     c.line_act = alloc_n<int32_t>(p, (size_t)p->nlines + 1);
     hipLaunchKernelGGL(k_line_act, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
                        c.act_node, c.nact, n, p->nlines, c.line_act);
@@ -719,15 +876,20 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
                        dim, p->X, p->nrm, p->wgt);
 
     // stable order of (key, index)
-    const size_t n2 = pow2_at_least((size_t)M, BIT_BLOCK);
-    uint64_t* comp = tmp_n<uint64_t>(p, n2);
-    hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, p->key, M, n2, comp);
-    bitonic_sort(comp, n2, st);
     p->perm = alloc_n<uint32_t>(p, M);
     p->skey = alloc_n<uint32_t>(p, M);
     p->invperm = alloc_n<uint32_t>(p, M);
-    hipLaunchKernelGGL(k_unpack, dim3(nblocks(M, 256)), dim3(256), 0, st, comp, M, p->perm, p->skey,
-                       p->invperm);
+    if (M <= RANK_SORT_MAX) {
+        hipLaunchKernelGGL(k_rank_sort, dim3(nblocks(M, RS_K)), dim3(RS_T), 0, st, p->key, M, p->perm, p->skey,
+                           p->invperm);
+    } else {
+        const size_t n2 = pow2_at_least((size_t)M, BIT_BLOCK);
+        uint64_t* comp = tmp_n<uint64_t>(p, n2);
+        hipLaunchKernelGGL(k_composite, dim3(nblocks(n2, 256)), dim3(256), 0, st, p->key, M, n2, comp);
+        bitonic_sort(comp, n2, st);
+        hipLaunchKernelGGL(k_unpack, dim3(nblocks(M, 256)), dim3(256), 0, st, comp, M, p->perm, p->skey,
+                           p->invperm);
+    }
 
     p->cell = alloc_n<int32_t>(p, 3 * (size_t)M);
     p->taps64 = alloc_n<double>(p, 12 * (size_t)M);
@@ -738,9 +900,15 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
     hipLaunchKernelGGL(k_line_start, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
                        p->skey, M, n, p->nlines, p->line_start);
 
-    build_csr(p, p->dip, true, st);
+    // per-node counts, shared by the spread matrices
+    CsrScratch cs;
+    cs.ncell = (size_t)p->nlines * n;
+    cs.cnt = tmp_n<int32_t>(p, cs.ncell);
+    cs.idx = tmp_n<int32_t>(p, cs.ncell);
+    cs.bad = bad;
+    build_csr(p, p->dip, true, cs, st);
     // the single layer: Neumann data (S V_b) and the completion (eta S Q)
-    if (p->bc == IBDL_NEUMANN || p->form != IBDL_FORM_DOUBLE_LAYER) build_csr(p, p->mono, false, st);
+    if (p->bc == IBDL_NEUMANN || p->form != IBDL_FORM_DOUBLE_LAYER) build_csr(p, p->mono, false, cs, st);
 
     // line and plane sets
     int32_t* flag = tmp_n<int32_t>(p, (size_t)std::max(p->nlines, n));
@@ -782,7 +950,9 @@ void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st) {
                            total, p->s2_64, p->alpha, 2.0 / ((double)p->nlines * (double)n), p->sym32);
     }
     IBDL_HIP_TRY(hipGetLastError());
+    IBDL_HIP_TRY(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, st));
     IBDL_HIP_TRY(hipStreamSynchronize(st));
+    if (hb[3]) throw Error{IBDL_ERR_STATE, "internal: spread matrix entry count mismatch"};
     free_build_tmp(p);
 }
 

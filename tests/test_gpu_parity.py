@@ -68,7 +68,9 @@ def random_problem(dim, n, m, seed, bc=W.DIRICHLET, alpha=1.0, lo=None, length=1
 
 
 # ------------------------------------------------------------------ binning
-@pytest.mark.parametrize("dim,n,m,seed", [(2, 64, 1000, 1), (2, 12, 333, 2), (3, 16, 2000, 3), (2, 1024, 4096, 4)])
+# the last three sit at and above the point count where ranking gives way to the bitonic sort
+@pytest.mark.parametrize("dim,n,m,seed", [(2, 64, 1000, 1), (2, 12, 333, 2), (3, 16, 2000, 3), (2, 1024, 4096, 4),
+                                          (2, 256, 16384, 5), (2, 256, 16385, 6), (3, 32, 30000, 7)])
 def test_binning_bit_exact(dim, n, m, seed):
     p = random_problem(dim, n, m, seed)
     # force ties and points on cell faces
