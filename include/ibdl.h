@@ -414,18 +414,19 @@ ibdl_status ibdl_set_autotune(int32_t enable);
 int32_t ibdl_autotune_report(char* buf, size_t cap);
 
 /* Iteration graphs.  Once the operator pass of a solver's Krylov workspace has
- * run once (which settles the tuned variants), a GMRES-Arnoldi step (Sec. 5.3:
- * one operator application followed by the orthogonalisation of the new basis
- * vector) is recorded as a HIP graph whose kernels read the step index from
- * device memory; the workspace keeps it, and every later step, in this and later
- * solves of the same plan, batch or cohort, is one replay on the solve's stream.
- * Results are bit-identical to launching the kernels one by one.  On (1) or off
- * (0, the default: the eager launches already keep the device queue full, and a
- * replay adds device time); solves of plans with stage timing on never use
- * graphs.  Takes effect for solves started after the call. */
+ * run once (which settles the tuned variants), runs of 1, 2, 4 and 8 GMRES-Arnoldi
+ * steps (Sec. 5.3: one operator application followed by the orthogonalisation of
+ * the new basis vector, for every instance of the plan, batch or cohort) are
+ * recorded as HIP graphs whose kernels read the base of the step index from
+ * device memory; the workspace keeps them, and every later run of c steps, in
+ * this and later solves, is at most one replay of each length (largest first) on
+ * the solve's stream.  Results are bit-identical to launching the kernels one by
+ * one.  On (1) or off (0, the default: the eager launches already keep the device
+ * queue full, and replays measure no faster); solves of plans with stage timing
+ * on never use graphs.  Takes effect for solves started after the call. */
 ibdl_status ibdl_set_graphs(int32_t enable);
-/* Process totals since load: out_host[0] = graphs recorded (one per Krylov run
- * that replays), out_host[1] = replays.  out_host: HOST array of 2. */
+/* Process totals since load: out_host[0] = graphs recorded (four per Krylov
+ * workspace and operator), out_host[1] = replays.  out_host: HOST array of 2. */
 ibdl_status ibdl_graph_stats(int64_t* out_host);
 
 /* Message for the last failing call on this host thread ("" if none). */

@@ -56,7 +56,8 @@ struct KArgs {
     int32_t* state;     // [R][4]
     const int32_t* skip;
     const int32_t* maxv;  // [R] Arnoldi steps each rhs may take in the current Krylov run
-    const int32_t* jp;  // Arnoldi step index in device memory, or null: the launch argument
+    const int32_t* jp;  // base of the Arnoldi step index in device memory (added to the
+                        // launch argument), or null: the launch argument alone
     int32_t* jcur;      // the step index that replayed steps read; reset with each cycle
 };
 
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(GT) void k_orth(KArgs a, int j) {
     __shared__ double hs[256];
     __shared__ double msh[(GT / 64) * 16];
     __shared__ double mout[16];
-    if (a.jp) j = *a.jp;
+    if (a.jp) j += *a.jp;
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     if (a.state[4 * r + ST_DONE] || (int)blockIdx.x >= nb) return;
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(GT) void k_orth_final(KArgs a, int j) {
     __shared__ double hs[256];
     __shared__ double hn_s[2];
     __shared__ double hc_s[256], cs_s[256], sn_s[256];
-    if (a.jp) j = *a.jp;
+    if (a.jp) j += *a.jp;
     const int r = blockIdx.y, M = a.Mr[r];
     const int nb = nblocks_of(M);
     int32_t* st = a.state + 4 * r;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(GT) void k_update_x(KArgs a, double* xpool) {
 
 // the device-side step index of replayed iterations
 __global__ void k_set_j(int32_t* jp, int v) { *jp = v; }
-__global__ void k_next_j(int32_t* jp) { *jp += 1; }
+__global__ void k_add_j(int32_t* jp, int c) { *jp += c; }
 
 __global__ void k_reset_j(KArgs a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,8 +416,10 @@ static void copy_multi(KrylovSet& ks, const std::vector<CopyJob>& jobs, hipStrea
 
 void free_krylov(KWork& k) {
     // no replay is in flight here: a solve task waits for its replays before it ends
-    if (k.gexec) (void)hipGraphExecDestroy(k.gexec);
-    k.gexec = nullptr;
+    for (hipGraphExec_t& g : k.gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     k.graph_valid = k.op_ran = false;
     k.op.reset();
     k.op_key.clear();
@@ -719,15 +722,17 @@ static hipStream_t capture_stream() {
     return cs.s;
 }
 
-// Records one Arnoldi step (operator pass, both Gram-Schmidt passes, step index
-// increment) with the step index read from device memory, and instantiates it,
-// or updates the set's executable graph in place.  On failure: false, and the
-// solve goes on without graphs.
-bool SolveTask::capture_step() {
+// Records 2^g Arnoldi steps (each: operator pass, both Gram-Schmidt passes) whose
+// step indices are a base read from device memory plus 0, 1, ... 2^g - 1, and one
+// increment of the base by 2^g; instantiates the graph or updates the set's
+// executable graph of that length in place.  On failure: false, and the solve goes
+// on without graphs.
+bool SolveTask::capture_steps(int g) {
     KWork& k = ks_.w;
     KArgs a = kargs(ks_, m_);
     a.jp = k.jcur;
     const dim3 vg(k.nblk, R_);
+    const int c = 1 << g;
     const hipStream_t cs = capture_stream();
     hipGraph_t graph = nullptr;
     IBDL_HIP_TRY(hipGetLastError());
@@ -738,30 +743,33 @@ bool SolveTask::capture_step() {
     capturing() = true;
     bool ok = true;
     try {
-        k.op->run_dev(k.jcur, cs);
-        hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, cs, a, 0);
-        hipLaunchKernelGGL(k_orth_final, vg, dim3(GT), 0, cs, a, 0);
-        hipLaunchKernelGGL(k_next_j, dim3(1), dim3(1), 0, cs, k.jcur);
+        for (int t = 0; t < c; ++t) {
+            k.op->run_dev(k.jcur, t, cs);
+            hipLaunchKernelGGL(k_orth, vg, dim3(GT), 0, cs, a, t);
+            hipLaunchKernelGGL(k_orth_final, vg, dim3(GT), 0, cs, a, t);
+        }
+        hipLaunchKernelGGL(k_add_j, dim3(1), dim3(1), 0, cs, k.jcur, c);
     } catch (const Error&) {
         ok = false;
     }
     capturing() = false;
     if (hipStreamEndCapture(cs, &graph) != hipSuccess || !graph) ok = false;
     if (hipGetLastError() != hipSuccess) ok = false;
-    if (ok && k.gexec) {
+    hipGraphExec_t& ex = k.gexec[g];
+    if (ok && ex) {
         // replays of the previous recording queued since the last wait point finish first
         if (graph_unmarked_) IBDL_HIP_TRY(hipStreamSynchronize(st_));
         hipGraphExecUpdateResult res;
         hipGraphNode_t bad = nullptr;
-        if (hipGraphExecUpdate(k.gexec, graph, &bad, &res) != hipSuccess) {
+        if (hipGraphExecUpdate(ex, graph, &bad, &res) != hipSuccess) {
             (void)hipGetLastError();
-            (void)hipGraphExecDestroy(k.gexec);
-            k.gexec = nullptr;
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
         }
     }
-    if (ok && !k.gexec && hipGraphInstantiate(&k.gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (ok && !ex && hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
-        k.gexec = nullptr;
+        ex = nullptr;
         ok = false;
     }
     if (graph) (void)hipGraphDestroy(graph);
@@ -769,19 +777,25 @@ bool SolveTask::capture_step() {
     return ok;
 }
 
+// c Arnoldi steps from step j0: with graphs, replays of 8, 4, 2 and 1 recorded
+// steps (largest first), else every kernel launched on its own
 void SolveTask::enqueue_iters(int j0, int c) {
     KWork& k = ks_.w;
     if (c <= 0) return;
     if (use_graph_ && k.op_ran && !k.graph_valid) {
-        k.graph_valid = capture_step();
-        if (!k.graph_valid) use_graph_ = false;
+        bool ok = true;
+        for (int g = 0; g < KWork::kGraphLevels && ok; ++g) ok = capture_steps(g);
+        k.graph_valid = ok;
+        if (!ok) use_graph_ = false;
     }
     if (use_graph_ && k.graph_valid) {
         if (dev_j_ != j0) hipLaunchKernelGGL(k_set_j, dim3(1), dim3(1), 0, st_, k.jcur, j0);
-        for (int t = 0; t < c; ++t) IBDL_HIP_TRY(hipGraphLaunch(k.gexec, st_));
+        int left = c, replays = 0;
+        for (int g = KWork::kGraphLevels - 1; g >= 0; --g)
+            for (; left >= (1 << g); left -= 1 << g, ++replays) IBDL_HIP_TRY(hipGraphLaunch(k.gexec[g], st_));
         dev_j_ = j0 + c;
         graph_unmarked_ = true;
-        note_graphs(0, c);
+        note_graphs(0, replays);
         return;
     }
     KArgs a = kargs(ks_, m_);

@@ -245,7 +245,8 @@ struct Jobs {
     const A* list;
     const int* start;     // n + 1 entries
     int n;
-    const int32_t* itp;   // iteration index in device memory, or null: the launch argument
+    const int32_t* itp;   // base of the iteration index in device memory (added to the
+                          // launch argument), or null: the launch argument alone
 };
 __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     int lo = 0, hi = n;
@@ -256,7 +257,7 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     return lo;
 }
 #define IBDL_JOB_ENTRY(BODY, A, a0, js, it)                          \
-    const int it_ = js.itp ? *js.itp : it;                            \
+    const int it_ = (js.itp ? *js.itp : 0) + it;                      \
     if constexpr (MULTI) {                                            \
         const int j_ = job_of(js.start, js.n, (int)blockIdx.x);       \
         BODY(js.list[j_], (int)blockIdx.x - js.start[j_], it_);       \

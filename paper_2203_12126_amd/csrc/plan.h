@@ -104,8 +104,10 @@ struct KWork {
     std::vector<const void*> op_key;
     Arena op_arena;
     bool op_ran = false;       // has run eagerly: the tuned variants are settled
-    bool graph_valid = false;  // gexec records the current op
-    hipGraphExec_t gexec = nullptr;
+    // gexec[g] records 2^g Arnoldi steps of the current op (valid: all recorded)
+    static constexpr int kGraphLevels = 4;
+    bool graph_valid = false;
+    hipGraphExec_t gexec[kGraphLevels] = {};
 };
 void free_krylov(KWork& k);
 
@@ -295,10 +297,10 @@ struct PreparedPass {
     virtual ~PreparedPass() {}
     virtual void upload(Arena& arena, hipStream_t st) = 0;  // several jobs only; stages, caller flushes
     virtual void run(int it, hipStream_t st) = 0;            // it: iteration index
-    // the same with the iteration index read on the device from *itp
-    void run_dev(const int32_t* itp, hipStream_t st) {
+    // the same with the iteration index *itp + off, *itp read on the device
+    void run_dev(const int32_t* itp, int off, hipStream_t st) {
         itp_ = itp;
-        run(0, st);
+        run(off, st);
         itp_ = nullptr;
     }
 
@@ -313,8 +315,8 @@ struct GroupedPass {
     void run(int it, hipStream_t st) {
         for (auto& p : parts) p->run(it, st);
     }
-    void run_dev(const int32_t* itp, hipStream_t st) {
-        for (auto& p : parts) p->run_dev(itp, st);
+    void run_dev(const int32_t* itp, int off, hipStream_t st) {
+        for (auto& p : parts) p->run_dev(itp, off, st);
     }
 };
 std::unique_ptr<PreparedPass> prepare_f64(const std::vector<PassJob>& jobs);

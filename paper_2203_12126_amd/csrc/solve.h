@@ -50,7 +50,7 @@ private:
     void kstart(const double* b, double* x, bool x_zero);
     void enqueue_iters(int j0, int c);
     void prepare_op();                            // the set's Arnoldi operator step, current
-    bool capture_step();                          // record one Arnoldi step as a graph
+    bool capture_steps(int g);  // record 2^g Arnoldi steps as one graph
     void enqueue_chunk(int c);
     void snapshot(int buf);
     void after_krylov();
