@@ -13,8 +13,7 @@
 namespace ibdl {
 
 // Sparse spread operator over the active grid nodes, rows sorted by node id and
-// entries within a row in sorted-point order, i.e. by (cell key, caller index) of
-// the point (a fixed summation order).
+// entries within a row by caller point index (a fixed summation order).
 struct Csr {
     int64_t nnz = 0;
     int32_t nact = 0;

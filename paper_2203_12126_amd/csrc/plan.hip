@@ -10,8 +10,8 @@
 //    plans, the monopole spread S (the discrete spread of Sec. 5.2),
 //    as rows over the active grid nodes: entries per node are counted from the
 //    points' stencils, and each node then collects its entries from the cells
-//    around it in sorted-point order (cell key, then caller index) -- no sort of
-//    the entries; every (node, point) pair the stencil reaches is one entry;
+//    around it and orders them by caller index -- no global sort of the entries;
+//    every (node, point) pair the stencil reaches is one entry;
 //  * the x-lines that receive forcing and the x-lines interpolated from;
 //  * twiddles exp(-2 pi i m/n) and the symbol terms: (4/h^2) sin^2(pi m/n) for the
 //    finite-difference Laplacian (Sec. 5.1), (2 pi k/L)^2 with k the signed
@@ -610,22 +610,23 @@ __device__ __forceinline__ int line_lower(const uint32_t* __restrict__ skey, int
 }
 
 // One active node per thread: its entries are the points of the cells c = node - r
-// over the stencil offsets r, taken in ascending cell key and, within a cell, in
-// sorted order -- the order of sorted positions (cell key, then caller index).  A
-// row of cells along x at fixed (y, z) is one or two ranges of sorted positions,
-// found in the x-line's points.  Writes the sorted position and the node of each
-// entry; a count that differs from the node's raises bad[3] and writes nothing past
-// the node's range.
+// over the stencil offsets r.  A row of cells along x at fixed (y, z) is one or two
+// ranges of sorted positions, found in the x-line's points; the rows are visited in
+// ascending cell key, so the node's entries arrive as runs ordered by caller index
+// (one per cell), which an insertion sort then puts in caller order -- the summation
+// order of the spread.  Writes the caller index and the node of each entry; a count
+// that differs from the node's raises bad[3] and writes nothing past the node's range.
 __global__ void k_fill(const uint32_t* __restrict__ act_node, const int32_t* __restrict__ act_ptr, int nact,
                        int dim, int n, int dipole, const int32_t* __restrict__ line_start,
-                       const uint32_t* __restrict__ skey, uint32_t* ent_s, uint32_t* ent_node, int32_t* bad) {
+                       const uint32_t* __restrict__ skey, const uint32_t* __restrict__ perm, uint32_t* ent_k,
+                       uint32_t* ent_node, int32_t* bad) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nact) return;
     const uint32_t node = act_node[a];
     const int pc[3] = {(int)(node % (uint32_t)n), (int)((node / (uint32_t)n) % (uint32_t)n),
                        dim == 3 ? (int)(node / ((uint32_t)n * (uint32_t)n)) : 0};
-    const int e1 = act_ptr[a + 1];
-    int e = act_ptr[a];
+    const int e0 = act_ptr[a], e1 = act_ptr[a + 1];
+    int e = e0;
     // offsets per axis: dipole -2..3 with at most one axis outside -1..2, monopole -1..2
     const int lo = dipole ? -2 : -1, hi = dipole ? 3 : 2;
     const AxisRun rz = dim == 3 ? axis_run(pc[2], lo, hi, n) : AxisRun{0, 1, 0};
@@ -661,25 +662,39 @@ __global__ void k_fill(const uint32_t* __restrict__ act_node, const int32_t* __r
                     return;
                 }
                 for (int s = s0; s < s1; ++s, ++e) {
-                    ent_s[e] = (uint32_t)s;
+                    ent_k[e] = perm[s];
                     ent_node[e] = node;
                 }
             }
         }
     }
-    if (e != e1) bad[3] = 1;
+    if (e != e1) {
+        bad[3] = 1;
+        return;
+    }
+    // caller order (all indices distinct)
+    for (int i = e0 + 1; i < e1; ++i) {
+        const uint32_t v = ent_k[i];
+        int j = i;
+        for (; j > e0; --j) {
+            const uint32_t u = ent_k[j - 1];
+            if (u < v) break;
+            ent_k[j] = u;
+        }
+        ent_k[j] = v;
+    }
 }
 
-// entry weights, one entry per thread; K holds the sorted position on entry and the
-// caller index on exit
+// entry weights, one entry per thread (K: the entries' caller indices)
 __global__ void k_entry_weights(size_t nnz, const uint32_t* __restrict__ ent_node, int dim, int n,
-                                const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ perm,
+                                const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ invperm,
                                 const double* __restrict__ taps64, const double* __restrict__ nrm3,
-                                const double* __restrict__ w1, double h, int dipole, uint32_t* K, double* W64,
-                                float* W32) {
+                                const double* __restrict__ w1, double h, int dipole, const uint32_t* __restrict__ K,
+                                double* W64, float* W32) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nnz) return;
-    const uint32_t s = K[e];
+    const uint32_t k = K[e];
+    const uint32_t s = invperm[k];
     uint32_t rem = ent_node[e];
     int r[3] = {0, 0, 0};
     for (int d = 0; d < dim; ++d) {
@@ -687,9 +702,7 @@ __global__ void k_entry_weights(size_t nnz, const uint32_t* __restrict__ ent_nod
         rem /= (uint32_t)n;
         r[d] = ((p - cell_s[3 * s + d] + 2 + 2 * n) % n) - 2;   // in -2..3
     }
-    const uint32_t k = perm[s];
     const double wv = entry_weight(taps64 + 12 * (size_t)s, nrm3, w1[k], k, r, dim, h, dipole);
-    K[e] = k;
     W64[e] = wv;
     W32[e] = (float)wv;
 }
@@ -842,9 +855,9 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, const CsrScratch& cs, hi
     c.w32 = alloc_n<float>(p, nnz);
     uint32_t* ent_node = tmp_n<uint32_t>(p, nnz);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(c.nact, 256)), dim3(256), 0, st, c.act_node, c.act_ptr, c.nact, dim, n,
-                       dipole ? 1 : 0, p->line_start, p->skey, c.k, ent_node, cs.bad);
+                       dipole ? 1 : 0, p->line_start, p->skey, p->perm, c.k, ent_node, cs.bad);
     hipLaunchKernelGGL(k_entry_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, nnz, ent_node, dim, n, p->cell,
-                       p->perm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64, c.w32);
+                       p->invperm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64, c.w32);
     c.line_act = alloc_n<int32_t>(p, (size_t)p->nlines + 1);
     hipLaunchKernelGGL(k_line_act, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
                        c.act_node, c.nact, n, p->nlines, c.line_act);
