@@ -115,8 +115,9 @@ def stage_touched_bytes(st, dim, n, m, prec, nrhs):
     return out
 
 
-def stage_kernel(stage, dim, n, prec):
-    """Kernel template behind a stage name (the row variants are tuned per shape)."""
+def stage_kernel(stage, dim, n, prec, z_rows=1):
+    """Kernel template behind a stage name (the row variants are tuned per shape;
+    z_rows: the 3-D symbol pass's column rows per workgroup, from the plan)."""
     R = "double" if prec == 0 else "float"
     names = {"spread+fft_x": f"k_row_fwd<{R}, {n}>", "ifft_x+interp": f"k_row_inv<{R}, {n}, 0>",
              "finish": f"k_finish<{R}>"}
@@ -124,7 +125,7 @@ def stage_kernel(stage, dim, n, prec):
         names["fft_y+symbol"] = f"k_col<{R}, {n}, 1, 1>"
     else:
         names["fft_y"] = f"k_col<{R}, {n}, 0, 1>"
-        names["fft_z+symbol"] = f"k_col<{R}, {n}, 1, K>"
+        names["fft_z+symbol"] = f"k_col<{R}, {n}, 1, {z_rows}>"
         names["ifft_y"] = f"k_col<{R}, {n}, 2, 1>"
     return names.get(stage, stage)
 
@@ -543,7 +544,7 @@ def main():
         apply_ms = sum(ms.values())
         opb = operator_bytes(dim, n, m, prec) * nrhs
         op_gbs = opb / (apply_ms * 1e-3) / 1e9
-        kname = stage_kernel(dom, dim, n, prec)
+        kname = stage_kernel(dom, dim, n, prec, rstats["z_rows"])
         return {
             "bound": "hbm", "kernel": kname, "stage": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -267,6 +267,10 @@ typedef struct {
     int32_t dip_active_nodes;  /* grid nodes reached by the dipole spread                  */
     int64_t dip_nnz;           /* (node, point) entries of the dipole spread               */
     int64_t mono_nnz;          /* entries of the monopole spread (Neumann plans, else 0)   */
+    int32_t col_tile;          /* columns per tile of the half spectrum, in the precision
+                                  of the plan's Arnoldi operator (FP32 for MIXED)          */
+    int32_t z_rows;            /* 3-D: z-columns per workgroup of the symbol pass in that
+                                  precision (k_col's K); 2-D: 1                             */
 } ibdl_plan_stats;
 
 ibdl_status ibdl_plan_get_stats(ibdl_plan plan, ibdl_plan_stats* out_host);

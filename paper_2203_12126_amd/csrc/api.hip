@@ -420,10 +420,10 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += nlines * 18 + n * 64;
     if (dim == 2 && d->prec == IBDL_PREC_MIXED) b += (size_t)tile_pitch_f32(d->n) * n * 4;
     // construction temporaries, alive together at most: the points' sort keys, dense
-    // per-node counts and their scan, active-node counts, the node of every entry,
-    // scan partials
+    // per-node counts and their scan, active-node counts, the entries as found (point
+    // and node), scan partials
     const size_t ncell = nlines * n;
-    b += M * 36 + pow2(M) * 8 + ncell * 8 + 2 * std::min(ncell, nd) * 4 + (nd + nm) * 4 + (ncell / 256 + 64) * 8 +
+    b += M * 36 + pow2(M) * 8 + ncell * 8 + 2 * std::min(ncell, nd) * 4 + (nd + nm) * 8 + (ncell / 256 + 64) * 8 +
          nlines * 12;
     // Krylov state: basis, five pools, two banks of block partial sums, Hessenberg and rotations
     const size_t nblk = (M + 255) / 256;
@@ -666,6 +666,9 @@ ibdl_status ibdl_plan_get_stats(ibdl_plan p, ibdl_plan_stats* o) {
     o->dip_active_nodes = p->dip.nact;
     o->dip_nnz = p->dip.nnz;
     o->mono_nnz = p->mono.nnz;
+    const bool f32 = p->prec == IBDL_PREC_MIXED;
+    o->col_tile = f32 ? col_width_f32(p->n) : col_width_f64(p->n);
+    o->z_rows = p->dim == 3 ? (f32 ? z_rows_f32(p->n) : z_rows_f64(p->n)) : 1;
     return IBDL_OK;
 }
 

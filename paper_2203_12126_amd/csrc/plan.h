@@ -326,7 +326,11 @@ void run_pipeline(ibdl_plan p, int nrhs, const PipeIn& in, const PipeOut& out, h
                   bool fp64 = false);
 int tile_pitch_f64(int n);
 int tile_pitch_f32(int n);
+int col_width_f64(int n);
 int col_width_f32(int n);
+// column rows per workgroup of the 3-D symbol pass (the K of k_col)
+int z_rows_f64(int n);
+int z_rows_f32(int n);
 void build_plan(ibdl_plan p, const ibdl_desc* d, hipStream_t st);
 // near-boundary step (nearfix.hip): App. D indicator and flags, App. A fix-up
 void nearfix_indicator(ibdl_plan p, double* chi, uint8_t* flags, hipStream_t st);

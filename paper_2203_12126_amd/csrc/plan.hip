@@ -611,15 +611,13 @@ __device__ __forceinline__ int line_lower(const uint32_t* __restrict__ skey, int
 
 // One active node per thread: its entries are the points of the cells c = node - r
 // over the stencil offsets r.  A row of cells along x at fixed (y, z) is one or two
-// ranges of sorted positions, found in the x-line's points; the rows are visited in
-// ascending cell key, so the node's entries arrive as runs ordered by caller index
-// (one per cell), which an insertion sort then puts in caller order -- the summation
-// order of the spread.  Writes the caller index and the node of each entry; a count
-// that differs from the node's raises bad[3] and writes nothing past the node's range.
+// ranges of sorted positions, found in the x-line's points.  Writes the caller index
+// and the node's active index of each entry, in the order found; a count that
+// differs from the node's raises bad[3] and writes nothing past the node's range.
 __global__ void k_fill(const uint32_t* __restrict__ act_node, const int32_t* __restrict__ act_ptr, int nact,
                        int dim, int n, int dipole, const int32_t* __restrict__ line_start,
                        const uint32_t* __restrict__ skey, const uint32_t* __restrict__ perm, uint32_t* ent_k,
-                       uint32_t* ent_node, int32_t* bad) {
+                       int32_t* ent_a, int32_t* bad) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nact) return;
     const uint32_t node = act_node[a];
@@ -663,30 +661,33 @@ __global__ void k_fill(const uint32_t* __restrict__ act_node, const int32_t* __r
                 }
                 for (int s = s0; s < s1; ++s, ++e) {
                     ent_k[e] = perm[s];
-                    ent_node[e] = node;
+                    ent_a[e] = a;
                 }
             }
         }
     }
-    if (e != e1) {
-        bad[3] = 1;
-        return;
-    }
-    // caller order (all indices distinct)
-    for (int i = e0 + 1; i < e1; ++i) {
-        const uint32_t v = ent_k[i];
-        int j = i;
-        for (; j > e0; --j) {
-            const uint32_t u = ent_k[j - 1];
-            if (u < v) break;
-            ent_k[j] = u;
-        }
-        ent_k[j] = v;
-    }
+    if (e != e1) bad[3] = 1;
 }
 
-// entry weights, one entry per thread (K: the entries' caller indices)
-__global__ void k_entry_weights(size_t nnz, const uint32_t* __restrict__ ent_node, int dim, int n,
+// Caller order within each node, one entry per thread: the entry's rank among its
+// node's entries (caller indices are distinct) is its place -- the summation order
+// of the spread.  K receives the ordered caller indices.
+__global__ void k_entry_order(size_t nnz, const uint32_t* __restrict__ ent_k, const int32_t* __restrict__ ent_a,
+                              const int32_t* __restrict__ act_ptr, uint32_t* K) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int a = ent_a[e];
+    const int e0 = act_ptr[a], e1 = act_ptr[a + 1];
+    const uint32_t v = ent_k[e];
+    int rank = 0;
+    for (int i = e0; i < e1; ++i) rank += ent_k[i] < v;
+    K[e0 + rank] = v;
+}
+
+// entry weights, one entry per thread (K: the entries' caller indices, ent_a: their
+// nodes' active indices)
+__global__ void k_entry_weights(size_t nnz, const int32_t* __restrict__ ent_a,
+                                const uint32_t* __restrict__ act_node, int dim, int n,
                                 const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ invperm,
                                 const double* __restrict__ taps64, const double* __restrict__ nrm3,
                                 const double* __restrict__ w1, double h, int dipole, const uint32_t* __restrict__ K,
@@ -695,7 +696,7 @@ __global__ void k_entry_weights(size_t nnz, const uint32_t* __restrict__ ent_nod
     if (e >= nnz) return;
     const uint32_t k = K[e];
     const uint32_t s = invperm[k];
-    uint32_t rem = ent_node[e];
+    uint32_t rem = act_node[ent_a[e]];
     int r[3] = {0, 0, 0};
     for (int d = 0; d < dim; ++d) {
         const int p = (int)(rem % (uint32_t)n);
@@ -853,11 +854,13 @@ static void build_csr(ibdl_plan p, Csr& c, bool dipole, const CsrScratch& cs, hi
     c.k = alloc_n<uint32_t>(p, nnz);
     c.w64 = alloc_n<double>(p, nnz);
     c.w32 = alloc_n<float>(p, nnz);
-    uint32_t* ent_node = tmp_n<uint32_t>(p, nnz);
+    uint32_t* ent_k = tmp_n<uint32_t>(p, nnz);
+    int32_t* ent_a = tmp_n<int32_t>(p, nnz);
     hipLaunchKernelGGL(k_fill, dim3(nblocks(c.nact, 256)), dim3(256), 0, st, c.act_node, c.act_ptr, c.nact, dim, n,
-                       dipole ? 1 : 0, p->line_start, p->skey, p->perm, c.k, ent_node, cs.bad);
-    hipLaunchKernelGGL(k_entry_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, nnz, ent_node, dim, n, p->cell,
-                       p->invperm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64, c.w32);
+                       dipole ? 1 : 0, p->line_start, p->skey, p->perm, ent_k, ent_a, cs.bad);
+    hipLaunchKernelGGL(k_entry_order, dim3(nblocks(nnz, 256)), dim3(256), 0, st, nnz, ent_k, ent_a, c.act_ptr, c.k);
+    hipLaunchKernelGGL(k_entry_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, nnz, ent_a, c.act_node, dim, n,
+                       p->cell, p->invperm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64, c.w32);
     c.line_act = alloc_n<int32_t>(p, (size_t)p->nlines + 1);
     hipLaunchKernelGGL(k_line_act, dim3(nblocks((size_t)p->nlines + 1, 256)), dim3(256), 0, st,
                        c.act_node, c.nact, n, p->nlines, c.line_act);

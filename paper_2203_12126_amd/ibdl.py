@@ -49,7 +49,7 @@ class PlanStats(ctypes.Structure):
                 ("n_spread_lines", ctypes.c_int32), ("n_gather_lines", ctypes.c_int32),
                 ("n_spread_planes", ctypes.c_int32), ("n_gather_planes", ctypes.c_int32),
                 ("dip_active_nodes", ctypes.c_int32), ("dip_nnz", ctypes.c_int64),
-                ("mono_nnz", ctypes.c_int64)]
+                ("mono_nnz", ctypes.c_int64), ("col_tile", ctypes.c_int32), ("z_rows", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
