@@ -257,6 +257,25 @@ def test_dirichlet_convergence_rates():
     assert far[0] / far[1] > 1.8 and far[1] / far[2] > 1.8, far
 
 
+def test_norms_are_rescaled_by_the_area():
+    """Sec. 5.1: the discrete L1 and L2 norms over Omega are sums times h^d divided
+    by |Omega|, so a constant error c has norms c (up to the O(h) difference
+    between the node count times h^d and |Omega|), and the max norm is c."""
+    p = W.table1_problem(256, 0.75)
+    st = O.setup_from_problem(p)
+    nodes = np.stack([c.ravel() for c in p.grid.nodes()], axis=1)
+    inside = p.geom.inside(nodes)
+    c = 3.0
+    err = np.full(nodes.shape[0], -c)
+    err[::2] = c
+    area = math.pi * 0.25 ** 2
+    l1, l2, mx = O.norms(st, err, inside, area)
+    assert abs(l1 / c - 1.0) < 0.02 and abs(l2 / c - 1.0) < 0.02 and mx == c, (l1, l2, mx)
+    # the whole periodic cell: exactly c
+    l1, l2, mx = O.norms(st, err, np.ones(nodes.shape[0], bool), 1.0)
+    assert abs(l1 - c) < 1e-12 and abs(l2 - c) < 1e-12 and mx == c
+
+
 def test_neumann_iterations_and_accuracy():
     """Sec. 6.6: 4-6 iterations; first-order convergence of U_b and of u."""
     gold = _golden()["neumann_circle"]
