@@ -419,12 +419,11 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     // line and plane masks, lists, line starts, FFT and symbol tables
     b += nlines * 18 + n * 64;
     if (dim == 2 && d->prec == IBDL_PREC_MIXED) b += (size_t)tile_pitch_f32(d->n) * n * 4;
-    // construction temporaries, alive together at most: the points' sort keys, dense
-    // per-node counts and their scan, active-node counts, the entries as found (point
-    // and node), scan partials
-    const size_t ncell = nlines * n;
-    b += M * 36 + pow2(M) * 8 + ncell * 8 + 2 * std::min(ncell, nd) * 4 + (nd + nm) * 8 + (ncell / 256 + 64) * 8 +
-         nlines * 12;
+    // construction temporaries, alive together at most: the points' sort keys, line
+    // counts and their scans (two spread matrices), line and plane flags and scans,
+    // the entries as found (point and node), scan partials
+    b += M * 36 + pow2(M) * 8 + (nd + nm) * 8 + (nlines + 1) * 4 * 10 + (n + 1) * 4 * 4 +
+         (nlines / 256 + 64) * 8 * 8;
     // Krylov state: basis, five pools, two banks of block partial sums, Hessenberg and rotations
     const size_t nblk = (M + 255) / 256;
     b += R * ((m + 1) * M * 8 + 5 * M * 8 + 2 * nblk * (m + 2) * 8 + (m * (m + 1) + 4 * m + 3 * (m + 2)) * 8 + 64);
