@@ -226,12 +226,16 @@ int timing_read(Timing& t, double* ms, const char** names, int64_t* calls, int c
 }
 
 void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, double* out, size_t ostride,
-                    hipStream_t st) {
+                    hipStream_t st, bool pack_q) {
     // A q = -S* L^-1 S~ q + s q/2, s = +1 Dirichlet, -1 Neumann
     PipeIn in;
     in.q_dip = q;
     in.c_dip = 1.0;
     in.q_stride = qstride;
+    // FP32 passes of several right-hand sides over a large spread read the strengths
+    // packed four right-hand sides to a segment (the same FP32 values: results do not
+    // change)
+    in.pack_q = pack_q;
     PipeOut o;
     o.out = out;
     o.out_stride = ostride;
@@ -408,8 +412,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     size_t b = 0;
     // workspace, FP64-sized: half spectra and gather partial sums
     b += R * nlines * P * 16 + R * M * gpp * 8;
-    // mixed: the Arnoldi step's strengths as FP32 in groups of four right-hand sides
-    if (d->prec == IBDL_PREC_MIXED) b += (R + 3) / 4 * 4 * M * 4;
+    // packed strengths in groups of four right-hand sides (FP32 for mixed plans)
+    b += (R + 3) / 4 * 4 * M * (d->prec == IBDL_PREC_MIXED ? 4 : 8);
     // sorted geometry: key, perm, skey, invperm, cell, coordinates, normals, weights, taps (FP64 + FP32)
     b += M * (16 + 12 + 24 + 24 + 8 + 96 + 48);
     // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
@@ -454,7 +458,7 @@ ibdl_status ibdl_apply(ibdl_plan p, int32_t nrhs, const double* q, double* Aq, v
         ibsl_apply(p, nrhs, q, Aq, S(stream));
         return IBDL_OK;
     }
-    apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
+    apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream), true);
     return IBDL_OK;
     IBDL_GUARD_END
 }
@@ -485,7 +489,8 @@ ibdl_status ibdl_apply_noalloc(ibdl_plan p, int32_t nrhs, const double* q, doubl
     p->ws.cap_rhs = nrhs;
     capturing() = true;
     try {
-        apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream));
+        // no packed strengths: their buffer is not part of the scratch
+        apply_operator(p, nrhs, q, (size_t)p->M, Aq, (size_t)p->M, S(stream), false);
     } catch (...) {
         p->ws = saved;
         capturing() = was_capturing;

@@ -1225,8 +1225,13 @@ struct PreparedT : PreparedPass {
     void run(int it, hipStream_t st) override {
         int stage = 0;
         go(pk, [&](bool m) {
-            if (m) hipLaunchKernelGGL((k_pack<R, true>), dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
-            else hipLaunchKernelGGL((k_pack<R, false>), dim3(pk.blocks()), dim3(256), 0, st, pk.args[0], pk.jobs(itp_), it);
+            const StageEv e = stage_events(tplan, stage++, "pack");
+            if (m)
+                hipExtLaunchKernelGGL((k_pack<R, true>), dim3(pk.blocks()), dim3(256), 0, st, e.a, e.b, 0, pk.args[0],
+                                      pk.jobs(itp_), it);
+            else
+                hipExtLaunchKernelGGL((k_pack<R, false>), dim3(pk.blocks()), dim3(256), 0, st, e.a, e.b, 0,
+                                      pk.args[0], pk.jobs(itp_), it);
         });
         {
             const int v = pick(0, it, st, [&](int c, StageEv e) { fwd(c, it, st, e); });
@@ -1338,14 +1343,16 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         };
         ra.dip = view(p->dip, in.q_dip, in.c_dip);
         // packing costs a launch per pass: it pays where a block serves several
-        // right-hand sides of a large spread (measured: sphere 256^3 at 32 rhs 6.5%
-        // faster, star 1024^2 at 32 rhs 1.4%; at 1 rhs and in the batch of small
-        // instances the extra launch made solves 2-4% slower)
-        constexpr int64_t kPackMinWork = (int64_t)1 << 21;  // spread entries x right-hand sides
-        // FP32 only: FP64 packing was measured to gain nothing (star 1024^2 and sphere
-        // 256^3 FP64 solves at 32 rhs unchanged), and mixed plans alone hold ws.qf
-        const bool fp32_mixed = sizeof(R) == 4 && p->prec == IBDL_PREC_MIXED;
-        if (in.pack_q && in.q_dip && fp32_mixed && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
+        // right-hand sides of a large spread.  Measured, FP32: sphere 256^3 at 32 rhs
+        // spread 0.75 -> 0.37 ms per apply, star 1024^2 at 32 rhs 45 -> 37 us (the
+        // pack 4 us); at 1 rhs and in the batch of small instances the extra launch
+        // made solves 2-4% slower.  FP64 (32-byte segments): sphere 256^3 spread
+        // 1.03 -> 0.91 ms, star 1024^2 no gain (68.7 -> 67 us against a 4 us pack).
+        constexpr int64_t kPackMinWork = sizeof(R) == 4 ? (int64_t)1 << 21 : (int64_t)1 << 24;  // entries x rhs
+        // the pass's precision must be the plan's own: ws.qf holds R values (a mixed
+        // plan's FP64 passes read q directly)
+        const bool own_prec = (sizeof(R) == 4) == (p->prec == IBDL_PREC_MIXED);
+        if (in.pack_q && in.q_dip && own_prec && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
             if (!p->ws.qf) throw Error{IBDL_ERR_HIP, "packed strengths requested without their workspace"};
             PackArgs<R> pa{};
             pa.q = in.q_dip;

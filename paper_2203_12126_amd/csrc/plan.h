@@ -29,7 +29,7 @@ struct Workspace {
     int cap_rhs = 0;
     void* spec = nullptr;       // [cap][nlines*P] complex
     void* part = nullptr;       // [cap][M][4^(dim-1)] gather partial sums
-    void* qf = nullptr;         // mixed plans: [ceil(cap/4)][M][4] FP32 strengths of the Arnoldi step
+    void* qf = nullptr;         // [ceil(cap/4)][M][4] strengths in the plan's precision (FP32 for mixed plans)
 };
 
 // Staging of per-job argument tables: pinned host blocks with device twins.

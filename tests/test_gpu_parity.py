@@ -175,6 +175,25 @@ def test_multi_rhs_equals_single_rhs():
         assert torch.equal(pl.apply(q[r:r + 1].contiguous())[0], allr[r])
 
 
+@pytest.mark.parametrize("prec,m", [(ibdl.MIXED, 2000), (ibdl.FP64, 20000)])
+def test_packed_apply_equals_single_rhs(prec, m):
+    """An apply of eight right-hand sides over a large spread reads its strengths
+    packed four to a segment in the pass's precision (timed as its own stage); the
+    values are the ones the sum rounds q to, so every right-hand side equals its
+    apply alone (one right-hand side: no packing).  The spreads here pass the pack
+    thresholds: 2^21 entries x right-hand sides in FP32, 2^24 in FP64."""
+    p = random_problem(3, 64, m, seed=8)
+    pl = plan_for(p, prec=prec)
+    q = T(W.random_density(m, seed=5, nrhs=8))
+    pl.set_timing(True)
+    allr = pl.apply(q)
+    names = [nm for nm, _, _ in pl.stage_times()]
+    pl.set_timing(False)
+    assert "pack" in names, names
+    for r in range(8):
+        assert torch.equal(pl.apply(q[r:r + 1].contiguous())[0], allr[r])
+
+
 # ------------------------------------------------------------------ full-size workloads
 @pytest.mark.parametrize("bc,alpha", [(W.DIRICHLET, 1.0), (W.NEUMANN, 100.0)])
 def test_star1024_apply(bc, alpha):

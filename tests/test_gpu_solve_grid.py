@@ -152,15 +152,37 @@ def test_solve_grid_mixed_tol_near_first_stage(bc):
 def test_packed_strengths_change_nothing(prec):
     """A mixed solve of 16 right-hand sides on the star 1024^2 plan takes the
     Arnoldi step's spread through strengths packed as FP32 in groups of four; the
-    same right-hand sides solved two at a time read them directly (FP64 solves
-    read them directly either way).  Solutions, grid solutions and iteration
-    counts are bit-identical."""
+    same right-hand sides solved two at a time read them directly (FP64 solves of
+    this size read them directly either way: the FP64 threshold is 2^24 entries x
+    right-hand sides).  Solutions, grid solutions and iteration counts are
+    bit-identical."""
     p = W.config_star1024(m=4096, alpha=1.0, seed=31)
     rng = np.random.default_rng(5)
     R = 16
     data = np.stack([p.data * (1.0 + 0.1 * r) + 0.01 * rng.standard_normal(p.geom.m) for r in range(R)])
     g = np.stack([p.g_tilde * (1.0 - 0.05 * r) for r in range(R)])
     pl = ibdl.Plan.from_problem(p, prec=prec)
+    sol, u, info = pl.solve_grid(T(data), T(g), tol=1e-8)
+    for r0 in range(0, R, 2):
+        s2, u2, i2 = pl.solve_grid(T(data[r0:r0 + 2]), T(g[r0:r0 + 2]), tol=1e-8)
+        assert torch.equal(s2, sol[r0:r0 + 2]), r0
+        assert torch.equal(u2, u[r0:r0 + 2]), r0
+        assert [x["iters"] for x in i2] == [x["iters"] for x in info[r0:r0 + 2]], r0
+    pl.close()
+
+
+def test_packed_fp64_solves_change_nothing():
+    """FP64 solves past the FP64 pack threshold (a 64^3 sphere with 20000 points,
+    eight right-hand sides: 2.6e7 entries x right-hand sides >= 2^24) read the
+    Arnoldi step's strengths packed as FP64 four to a segment; solved two at a time
+    they read them directly.  Solutions, grid solutions and iteration counts are
+    bit-identical."""
+    p = W.table2_problem(64, 20000)
+    rng = np.random.default_rng(9)
+    R = 8
+    data = np.stack([p.data * (1.0 + 0.1 * r) + 0.01 * rng.standard_normal(p.geom.m) for r in range(R)])
+    g = np.stack([p.g_tilde * (1.0 - 0.05 * r) for r in range(R)])
+    pl = ibdl.Plan.from_problem(p, prec=ibdl.FP64)
     sol, u, info = pl.solve_grid(T(data), T(g), tol=1e-8)
     for r0 in range(0, R, 2):
         s2, u2, i2 = pl.solve_grid(T(data[r0:r0 + 2]), T(g[r0:r0 + 2]), tol=1e-8)
