@@ -217,6 +217,55 @@ def test_largest_2d_grid():
     assert relerr(N(plan_for(p, prec=ibdl.MIXED).apply(T(q)))[0], ref) < MODEL_FACTOR * mixed_model(st, q[0], ref)
 
 
+def test_largest_3d_grid():
+    """The largest 3-D grid the library takes (512^3, its own radix plan and tile
+    shapes): a 4000-point sphere, FP64 within 1e-12 of the oracle and mixed within
+    its rounding-error model (the oracle's apply takes about 20 s and 10 GB here)."""
+    g = W.Grid(3, 512, (0.0, 0.0, 0.0), 1.0)
+    geom = W.fibonacci_sphere((0.5, 0.5, 0.5), 0.3, 4000)
+    p = W.make_problem(g, geom, 10.0, W.DIRICHLET, W.sol_harmonic3d(1), forcing=False)
+    st = O.setup_from_problem(p)
+    q = W.random_density(4000, seed=3, nrhs=1)
+    ref = O.apply_A(st, q[0], W.DIRICHLET)
+    e64 = relerr(N(plan_for(p).apply(T(q)))[0], ref)
+    e32 = relerr(N(plan_for(p, prec=ibdl.MIXED).apply(T(q)))[0], ref)
+    model = mixed_model(st, q[0], ref)
+    print(f"  512^3: FP64 rel err {e64:.2e}, mixed {e32:.2e} (model {model:.2e})", flush=True)
+    assert e64 < FP64_TOL
+    assert e32 < MODEL_FACTOR * model
+
+
+@pytest.mark.parametrize("case", ["3d_one_point", "2d_one_cell", "2d_on_nodes", "3d_on_nodes", "3d_wrapped"])
+def test_degenerate_geometries(case):
+    """Degenerate point sets: a single 3-D point; 64 points inside one cell (one
+    x-line carries every entry, and every node's entries come from one cell);
+    points exactly on grid nodes (fractional offset 0, taps at the kernel's
+    support edge); coordinates far outside the box, which wrap periodically.  FP64
+    operator within 1e-12 of the oracle."""
+    rng = np.random.default_rng(17)
+    if case == "3d_one_point":
+        p = random_problem(3, 16, 1, seed=3)
+    elif case == "2d_one_cell":
+        p = random_problem(2, 64, 64, seed=4)
+        p.geom.X[:] = (np.array([17.0, 40.0]) + rng.uniform(0.0, 1.0, size=(64, 2))) / 64.0
+    elif case == "2d_on_nodes":
+        p = random_problem(2, 64, 300, seed=5)
+        p.geom.X[:] = rng.integers(0, 64, size=(300, 2)) / 64.0
+    elif case == "3d_on_nodes":
+        p = random_problem(3, 24, 400, seed=6)
+        p.geom.X[:] = rng.integers(0, 24, size=(400, 3)) / 24.0
+    else:
+        p = random_problem(3, 24, 400, seed=7)
+        p.geom.X[:] = p.geom.X + rng.integers(-5, 6, size=(400, 3))
+    m = p.geom.m
+    st = O.setup_from_problem(p)
+    q = W.random_density(m, seed=8, nrhs=2)
+    out = N(plan_for(p).apply(T(q)))
+    for r in range(2):
+        ref = O.apply_A(st, q[r], W.DIRICHLET)
+        assert relerr(out[r], ref) < FP64_TOL, (case, r)
+
+
 # ------------------------------------------------------------------ solves
 def test_circle64_solve_fp64():
     p = W.config_circle64()
