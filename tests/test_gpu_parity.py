@@ -25,7 +25,7 @@ from paper_2203_12126_amd import ibdl  # noqa: E402
 DEV = "cuda"
 FP64_TOL = 1e-12
 # Mixed solves refine with the FP64 operator until its residual meets tol, so
-# they must match the oracle's solution to the spec bar.
+# they must match the oracle's solution within 1e-6 relative.
 SOLVE_MIXED_TOL = 1e-6
 
 
