@@ -416,10 +416,11 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     b += (R + 3) / 4 * 4 * M * (d->prec == IBDL_PREC_MIXED ? 4 : 8);
     // sorted geometry: key, perm, skey, invperm, cell, coordinates, normals, weights, taps (FP64 + FP32)
     b += M * (16 + 12 + 24 + 24 + 8 + 96 + 48);
-    // spread structures (entry: point, FP64 and FP32 weight; active node id and offset)
+    // spread structures (entry: point as caller index and sorted position, FP64 and
+    // FP32 weight; active node id and offset)
     const size_t nd = M * (dim == 2 ? 32 : 160);
     const size_t nm = (d->bc == IBDL_NEUMANN || d->form != IBDL_FORM_DOUBLE_LAYER) ? M * (dim == 2 ? 16 : 64) : 0;
-    b += (nd + nm) * 24 + 2 * (nlines + 2) * 4;
+    b += (nd + nm) * 28 + 2 * (nlines + 2) * 4;
     // line and plane masks, lists, line starts, FFT and symbol tables
     b += nlines * 18 + n * 64;
     if (dim == 2 && d->prec == IBDL_PREC_MIXED) b += (size_t)tile_pitch_f32(d->n) * n * 4;

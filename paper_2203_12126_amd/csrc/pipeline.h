@@ -164,10 +164,11 @@ struct CsrView {
     const int32_t* act_ptr;
     const uint32_t* act_node;
     const uint32_t* k;
+    const uint32_t* s;   // sorted position of each entry's point (index of qf)
     const R* w;
     uint32_t nnz;        // entries of k and w (nnz * sizeof(double) < 2^31)
     const double* q;     // q + rhs * q_stride + it * q_jstride: strengths of one right-hand side
-    const R* qf;         // or null: the same strengths in R, [rhs / 4][M][rhs % 4]
+    const R* qf;         // or null: the same strengths in R, [rhs / 4][sorted point][rhs % 4]
     int M;
     size_t q_stride;
     size_t q_jstride;    // offset per iteration index (Krylov basis vectors), else 0
@@ -266,24 +267,28 @@ __device__ __forceinline__ int job_of(const int* start, int n, int b) {
     }
 
 // ------------------------------------------------------------ strength packing
-// qf[g][k][rr] = (R) q[(4g + rr) * q_stride + it * q_jstride + k], 0 past nrhs:
-// the four right-hand sides of a group sit in one 16- (FP32) or 32-byte (FP64)
-// segment, so the spread's adjacent lanes of one node (its right-hand sides) read
-// one cache line per entry
+// qf[g][s][rr] = (R) q[(4g + rr) * q_stride + it * q_jstride + perm[s]], 0 past
+// nrhs: the four right-hand sides of a group sit in one 16- (FP32) or 32-byte
+// (FP64) segment, so the spread's adjacent lanes of one node (its right-hand
+// sides) read one cache line per entry; the points go in sorted (cell) order, so
+// the entries of nearby nodes, which come from the same few cells, read nearby
+// segments
 template <typename R>
 struct PackArgs {
     const double* q;
     size_t q_stride, q_jstride;
     int M, nrhs;
     int nkb;  // blocks of 256 points per group
+    const uint32_t* perm;  // caller index of each sorted position
     R* qf;
 };
 template <typename R>
 __device__ __forceinline__ void pack_body(const PackArgs<R>& a, int lb, int it) {
     const int g = lb / a.nkb;
-    const int k = (lb % a.nkb) * 256 + (int)threadIdx.x;
-    if (k >= a.M) return;
-    R* out = a.qf + ((size_t)g * a.M + k) * 4;
+    const int s = (lb % a.nkb) * 256 + (int)threadIdx.x;
+    if (s >= a.M) return;
+    const int k = (int)a.perm[s];
+    R* out = a.qf + ((size_t)g * a.M + s) * 4;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int r = 4 * g + rr;
@@ -332,7 +337,8 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
         // node or lie past the arrays (read as 0) and enter with weight 0 (adding
         // 0 * q leaves both parts of the sum exactly as they were), so the group has
         // no branch
-        const __amdgpu_buffer_rsrc_t rk = buf_rsrc(c.k, c.nnz * 4u);
+        // packed strengths are indexed by sorted position, the caller's by caller index
+        const __amdgpu_buffer_rsrc_t rk = buf_rsrc(qf ? c.s : c.k, c.nnz * 4u);
         const __amdgpu_buffer_rsrc_t rw = buf_rsrc(c.w, c.nnz * (uint32_t)sizeof(R));
         for (int e = c.act_ptr[a]; e < e1; e += 8) {
             const int cnt = e1 - e;
@@ -1334,6 +1340,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             v.act_ptr = c.act_ptr;
             v.act_node = c.act_node;
             v.k = c.k;
+            v.s = c.s;
             v.w = PP::w(c);
             v.nnz = (uint32_t)c.nnz;
             v.q = q;
@@ -1361,6 +1368,7 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             pa.M = p->M;
             pa.nrhs = nrhs;
             pa.nkb = (p->M + 255) / 256;
+            pa.perm = p->perm;
             pa.qf = reinterpret_cast<R*>(p->ws.qf);
             P->pk.add(pa, pa.nkb * ((nrhs + 3) / 4));
             ra.dip.qf = pa.qf;

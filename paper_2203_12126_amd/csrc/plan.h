@@ -20,6 +20,7 @@ struct Csr {
     uint32_t* act_node = nullptr;   // [nact] flat node id (x fastest)
     int32_t* act_ptr = nullptr;     // [nact+1] first entry of each active node
     uint32_t* k = nullptr;          // [nnz] caller point index
+    uint32_t* s = nullptr;          // [nnz] sorted position of the same point
     double* w64 = nullptr;          // [nnz] weight
     float* w32 = nullptr;           // [nnz] weight rounded to FP32
     int32_t* line_act = nullptr;    // [nlines+1] first active node of each x-line

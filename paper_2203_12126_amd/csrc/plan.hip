@@ -629,14 +629,14 @@ __global__ void k_entry_order(size_t nnz, const uint32_t* __restrict__ ent_k, co
     K[e0 + rank] = v;
 }
 
-// entry weights, one entry per thread (K: the entries' caller indices, ent_a: their
-// nodes' active indices)
+// entry weights and sorted positions, one entry per thread (K: the entries' caller
+// indices, ent_a: their nodes' active indices)
 __global__ void k_entry_weights(size_t nnz, const int32_t* __restrict__ ent_a,
                                 const uint32_t* __restrict__ act_node, int dim, int n,
                                 const int32_t* __restrict__ cell_s, const uint32_t* __restrict__ invperm,
                                 const double* __restrict__ taps64, const double* __restrict__ nrm3,
                                 const double* __restrict__ w1, double h, int dipole, const uint32_t* __restrict__ K,
-                                double* W64, float* W32) {
+                                uint32_t* S, double* W64, float* W32) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nnz) return;
     const uint32_t k = K[e];
@@ -649,6 +649,7 @@ __global__ void k_entry_weights(size_t nnz, const int32_t* __restrict__ ent_a,
         r[d] = ((p - cell_s[3 * s + d] + 2 + 2 * n) % n) - 2;   // in -2..3
     }
     const double wv = entry_weight(taps64 + 12 * (size_t)s, nrm3, w1[k], k, r, dim, h, dipole);
+    S[e] = s;
     W64[e] = wv;
     W32[e] = (float)wv;
 }
@@ -807,6 +808,7 @@ static void csr_fill(ibdl_plan p, Csr& c, bool dipole, const int32_t* nnz_off, i
     c.act_node = alloc_n<uint32_t>(p, (size_t)nact);
     c.act_ptr = alloc_n<int32_t>(p, (size_t)nact + 1);
     c.k = alloc_n<uint32_t>(p, (size_t)nnz);
+    c.s = alloc_n<uint32_t>(p, (size_t)nnz);
     c.w64 = alloc_n<double>(p, (size_t)nnz);
     c.w32 = alloc_n<float>(p, (size_t)nnz);
     uint32_t* ent_k = tmp_n<uint32_t>(p, (size_t)nnz);
@@ -819,8 +821,8 @@ static void csr_fill(ibdl_plan p, Csr& c, bool dipole, const int32_t* nnz_off, i
     hipLaunchKernelGGL(k_entry_order, dim3(nblocks(nnz, 256)), dim3(256), 0, st, (size_t)nnz, ent_k, ent_a,
                        c.act_ptr, c.k);
     hipLaunchKernelGGL(k_entry_weights, dim3(nblocks(nnz, 256)), dim3(256), 0, st, (size_t)nnz, ent_a, c.act_node,
-                       p->dim, n, p->cell, p->invperm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.w64,
-                       c.w32);
+                       p->dim, n, p->cell, p->invperm, p->taps64, p->nrm, p->wgt, p->h, dipole ? 1 : 0, c.k, c.s,
+                       c.w64, c.w32);
     IBDL_HIP_TRY(hipGetLastError());
 }
 
