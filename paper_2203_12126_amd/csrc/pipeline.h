@@ -57,6 +57,9 @@ constexpr int rup64(int x) { return (x + 63) / 64 * 64; }
 #ifndef IBDL_COL_LDS
 #define IBDL_COL_LDS 65536
 #endif
+#ifndef IBDL_TWL_FULL_BYTES
+#define IBDL_TWL_FULL_BYTES 8192  // largest twiddle table held whole in LDS
+#endif
 #ifndef IBDL_ROW_ELEMS
 #define IBDL_ROW_ELEMS 2048
 #endif
@@ -378,7 +381,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     __shared__ cplx<R> s[CF::ROWS * GB];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G], rhs_s[RB];
-    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= IBDL_TWL_FULL_BYTES)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     R* sr = reinterpret_cast<R*>(s);
     const int rg = lb / a.nblk;
@@ -559,7 +562,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     __shared__ R srow[MODE == 1 ? N : 1];
     __shared__ R scol[MODE == 1 ? LC : 1];
     // the full twiddle table in LDS where it keeps two blocks per compute unit
-    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= IBDL_TWL_FULL_BYTES)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     // A last tile that holds only the column kx = n/2 is transformed alone (below),
     // and its blocks come after all full tiles so that the full tiles spread
@@ -704,7 +707,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     // the storage
     __shared__ cplx<R> s[imax(XP, CF::ROWS) * GB];
     cplx<R>* xs = s;
-    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= 8192)>;
+    using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= IBDL_TWL_FULL_BYTES)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     __shared__ int lines_s[G], rhs_s[RB];
     R* sr = reinterpret_cast<R*>(s);
