@@ -90,6 +90,28 @@ def test_indicator_and_fixup_match_oracle(name, prob, m1, m2, lap):
     pl.close()
 
 
+def test_fixup_after_a_neumann_solve():
+    """Neumann data: the boundary values of the re-interpolation are the solved U_b
+    (the unknown of the Neumann system, Sec. 4.4), the grid solution that of the
+    same solve; against the oracle's fix-up of the same arrays."""
+    prob = W.neumann_circle_problem(128)
+    st = O.setup_from_problem(prob)
+    pl = ibdl.Plan.from_problem(prob)
+    _, flags = pl.indicator()
+    flags = N(flags)
+    sol, u, info = pl.solve_grid(T(prob.data[None]), T(prob.g_tilde[None]), tol=1e-10)
+    fl = torch.as_tensor(flags, dtype=torch.uint8, device="cuda").contiguous()
+    fixed = N(pl.fixup(u, sol, fl, m1=6.0, m2=8.0))[0]
+    un, ub = N(u)[0], N(sol)[0]
+    ref, done = O.near_boundary_fixup(st, un, ub, flags, 6.0, 8.0)
+    nodes = np.stack([c.ravel() for c in prob.grid.nodes()], axis=1)
+    d1 = O.distance_to_points(st, nodes, prob.geom.X).reshape(flags.shape)
+    edge = np.abs(d1 - 6.0 * st.h) < 1e-12
+    assert np.max(np.abs(fixed - ref)[~edge]) < 1e-12 * np.max(np.abs(un))
+    assert int(done.sum()) > 100
+    pl.close()
+
+
 def test_fixup_argument_errors():
     p = W.table1_problem(64, 1.0)
     pl = ibdl.Plan.from_problem(p)
