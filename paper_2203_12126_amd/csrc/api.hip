@@ -411,7 +411,7 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     };
     size_t b = 0;
     // workspace, FP64-sized: half spectra and gather partial sums
-    b += R * nlines * P * 16 + R * M * gpp * 8;
+    b += R * nlines * P * 16 + R * M * gpp * 8 + R * (nlines + n);
     // packed strengths in groups of four right-hand sides (FP32 for mixed plans)
     b += (R + 3) / 4 * 4 * M * (d->prec == IBDL_PREC_MIXED ? 4 : 8);
     // sorted geometry: key, perm, skey, invperm, cell, coordinates, normals, weights, taps (FP64 + FP32)
@@ -487,6 +487,7 @@ ibdl_status ibdl_apply_noalloc(ibdl_plan p, int32_t nrhs, const double* q, doubl
     p->ws.spec = base;
     p->ws.part = base + spec_b;
     p->ws.qf = nullptr;
+    p->ws.dmask = nullptr;
     p->ws.cap_rhs = nrhs;
     capturing() = true;
     try {

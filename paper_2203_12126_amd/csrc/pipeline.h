@@ -194,6 +194,8 @@ struct RowFwdArgs {
     int P;
     const cplx<R>* tw;
     int nrhs;
+    uint8_t* lnz;          // grid-forcing passes: per rhs (stride lnz_rhs), 1 for lines written
+    size_t lnz_rhs;
 };
 
 template <typename R>
@@ -208,8 +210,11 @@ struct ColArgs {
     int width;            // n/2 + 1 columns
     const uint8_t* lmask;
     int lm_outer, lm_stride;
+    size_t lm_rhs;        // per right-hand side (masks written by the previous pass), else 0
     const uint8_t* smask;
     int sm_outer, sm_stride;
+    uint8_t* onz;         // 3-D y pass of a grid-forcing pass: per rhs (stride onz_rhs), 1 for
+    size_t onz_rhs;       // the planes it writes; a plane whose lines are all unwritten is skipped
     const cplx<R>* tw;
     const R* s2;
     R alpha;
@@ -381,6 +386,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     __shared__ cplx<R> s[CF::ROWS * GB];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G], rhs_s[RB];
+    __shared__ int nzl[GB];  // grid-forcing passes: 1 for block lines with a nonzero grid row
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= IBDL_TWL_FULL_BYTES)>;
     __shared__ cplx<R> twl[TWL::SIZE];
     R* sr = reinterpret_cast<R*>(s);
@@ -419,6 +425,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     }
     if (!live) return;
     if (threadIdx.x < RB) rhs_s[threadIdx.x] = rv[threadIdx.x];
+    if (threadIdx.x < GB) nzl[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < CF::ROWS * GB; i += T) s[i] = cplx<R>{R(0), R(0)};
     __syncthreads();
     if (threadIdx.x < 2) {
@@ -442,7 +449,10 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         for (int u = 0; u < PER; ++u) {
             const int id = threadIdx.x + u * T;
             const int l = id / N, x = id % N;
-            if (id < N * GB) sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
+            if (id < N * GB) {
+                sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
+                if (v[u] != 0.0) nzl[l] = 1;  // every writer stores the same value
+            }
         }
     }
     __syncthreads();
@@ -451,6 +461,16 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
 
     run_fft<R, L, GB, T, N, -1, PS>(s, tw, LdsLoad<R, GB, PS>{s}, LdsStore<R, GB, PS>{s},
                                     FwdRadices<L, RMax<R>::value>{});
+    // grid-forcing passes: a line with a zero grid row and no spread entries has a
+    // zero spectrum; it is flagged 0 for the column passes, which read it as zero,
+    // and not stored
+    if (a.lnz && threadIdx.x < GB) {
+        const int l = threadIdx.x, g = l % G;
+        const int line = lines_s[g], r = rhs_s[l / G];
+        const int nz = nzl[l] | (a.dip.q && rs[0][g + 1] > rs[0][g]) | (a.mono.q && rs[1][g + 1] > rs[1][g]);
+        nzl[l] = nz;
+        if (line >= 0 && r >= 0) a.lnz[(size_t)r * a.lnz_rhs + line] = (uint8_t)nz;
+    }
     __syncthreads();
 
     // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
@@ -463,7 +483,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         const int k = t * C + c;
         const int line = lines_s[l % G];
         const int r = rhs_s[l / G];
-        if (k > L || line < 0 || r < 0) continue;
+        if (k > L || line < 0 || r < 0 || (a.lnz && !nzl[l])) continue;
         const cplx<R> zk = s[lds_row<PS>(k % L) * GB + l];
         const cplx<R> zm = s[lds_row<PS>((L - k) % L) * GB + l];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
@@ -591,7 +611,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
     for (int u = 0; u < PN; ++u) {
         const int i = threadIdx.x + u * T;
         if (i < N) {
-            lmv[u] = a.lmask ? a.lmask[o * a.lm_outer + i * a.lm_stride] : 1;
+            lmv[u] = a.lmask ? a.lmask[(size_t)rhs * a.lm_rhs + o * a.lm_outer + i * a.lm_stride] : 1;
             smv[u] = a.smask ? a.smask[o * a.sm_outer + i * a.sm_stride] : 1;
             if constexpr (MODE == 1) s2v[u] = a.s2[i];
         }
@@ -628,6 +648,15 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
         }
     }
     if (skipv) return;
+    if (a.onz) {
+        // a plane none of whose lines was written is zero: its transform is zero too
+        int any = 0;
+#pragma unroll
+        for (int u = 0; u < PN; ++u) any |= (threadIdx.x + u * T < N) && lmv[u];
+        any = __syncthreads_or(any);
+        if (threadIdx.x == 0) a.onz[(size_t)rhs * a.onz_rhs + o] = (uint8_t)(any != 0);
+        if (!any) return;
+    }
     // the block's elements i * es + l (i < N, l < LC) from its base: at most
     // (511 * 65 * 512 * 4 + 16) * 16 bytes (3-D, n <= 512, FP64), below 2^31
     const cplx<R>* base = a.spec + (size_t)rhs * a.rhs_stride + (size_t)t * a.tile_stride + (size_t)o * a.outer_stride;
@@ -1385,6 +1414,13 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         ra.P = p->P;
         ra.tw = PP::tw(p);
         ra.nrhs = nrhs;
+        // grid forcing: the row pass flags the lines it writes, per right-hand side;
+        // the 3-D y pass then flags the planes it writes
+        uint8_t* const lnz = dense_in ? p->ws.dmask : nullptr;
+        uint8_t* const pnz = dense_in ? p->ws.dmask + (size_t)p->ws.cap_rhs * p->nlines : nullptr;
+        if (dense_in && !p->ws.dmask) throw Error{IBDL_ERR_HIP, "grid-forcing pass without its line masks"};
+        ra.lnz = lnz;
+        ra.lnz_rhs = (size_t)p->nlines;
         for (int v = 0; v < kRowVars; ++v) {
             const int G = row_lines_per_block<R>(n, v);
             ra.nblk = (ra.nproc + G - 1) / G;
@@ -1413,8 +1449,9 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             ca.outer_list = nullptr;
             ca.outer_stride = 0;
             ca.es = C;
-            ca.lmask = dense_in ? nullptr : p->spread_line_mask;
+            ca.lmask = dense_in ? lnz : p->spread_line_mask;
             ca.lm_outer = 0; ca.lm_stride = 1;
+            ca.lm_rhs = dense_in ? (size_t)p->nlines : 0;
             ca.smask = dense_out ? nullptr : p->gather_line_mask;
             ca.sm_outer = 0; ca.sm_stride = 1;
             ca.nouter = 1;
@@ -1424,8 +1461,11 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             y1.outer_list = dense_in ? nullptr : p->spread_planes;
             y1.outer_stride = plane;
             y1.es = C;
-            y1.lmask = dense_in ? nullptr : p->spread_line_mask;
+            y1.lmask = dense_in ? lnz : p->spread_line_mask;
             y1.lm_outer = n; y1.lm_stride = 1;
+            y1.lm_rhs = dense_in ? (size_t)p->nlines : 0;
+            y1.onz = pnz;
+            y1.onz_rhs = (size_t)n;
             y1.smask = nullptr;
             y1.nouter = dense_in ? n : p->n_spread_planes;
             P->col[0].add(y1, NT * y1.nouter * nrhs);
@@ -1433,8 +1473,9 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
             z.outer_list = nullptr;
             z.outer_stride = (size_t)KZ * C;
             z.es = plane;
-            z.lmask = dense_in ? nullptr : p->spread_plane_mask;
+            z.lmask = dense_in ? pnz : p->spread_plane_mask;
             z.lm_outer = 0; z.lm_stride = 1;
+            z.lm_rhs = dense_in ? (size_t)n : 0;
             z.smask = dense_out ? nullptr : p->gather_plane_mask;
             z.sm_outer = 0; z.sm_stride = 1;
             z.nouter = n / KZ;

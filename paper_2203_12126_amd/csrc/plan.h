@@ -31,6 +31,10 @@ struct Workspace {
     void* spec = nullptr;       // [cap][nlines*P] complex
     void* part = nullptr;       // [cap][M][4^(dim-1)] gather partial sums
     void* qf = nullptr;         // [ceil(cap/4)][M][4] strengths in the plan's precision (FP32 for mixed plans)
+    // passes with grid forcing: per right-hand side, 1 for the x-lines whose spectrum
+    // the forward row pass wrote ([cap][nlines]), then (3-D) for the z-planes the
+    // y pass wrote ([cap][n]); the column passes read only those
+    uint8_t* dmask = nullptr;
 };
 
 // Staging of per-job argument tables: pinned host blocks with device twins.

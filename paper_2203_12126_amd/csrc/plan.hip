@@ -975,18 +975,20 @@ void ensure_workspace(ibdl_plan p, int nrhs) {
     // grow: the old buffers are freed in stream order after the work already queued
     // on the plan's stream (a switch of stream waits for the old one first)
     if (p->ws.spec && p->last_stream != alloc_stream()) IBDL_HIP_TRY(hipStreamSynchronize(p->last_stream));
-    for (void* old : {p->ws.spec, p->ws.part, p->ws.qf}) {
+    for (void* old : {p->ws.spec, p->ws.part, p->ws.qf, (void*)p->ws.dmask}) {
         if (!old) continue;
         p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), old), p->allocs.end());
         dev_free(old);
     }
     p->ws.spec = p->ws.part = p->ws.qf = nullptr;
+    p->ws.dmask = nullptr;
     p->ws.cap_rhs = 0;
     p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
     p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);
     // packed strengths of the plan's own precision, four right-hand sides to a segment
     p->ws.qf = dev_alloc(p, (size_t)((nrhs + 3) / 4) * 4 * p->M *
                                 (p->prec == IBDL_PREC_MIXED ? sizeof(float) : sizeof(double)));
+    p->ws.dmask = reinterpret_cast<uint8_t*>(dev_alloc(p, (size_t)nrhs * ((size_t)p->nlines + p->n)));
     p->ws.cap_rhs = nrhs;
 }
 
