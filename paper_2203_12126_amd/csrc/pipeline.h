@@ -459,18 +459,22 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
     if (a.dip.q) spread_phase<R, N, G, RB, T, PS>(sr, a.dip, it, la[0], rs[0], rhs_s);
     if (a.mono.q) spread_phase<R, N, G, RB, T, PS>(sr, a.mono, it, la[1], rs[1], rhs_s);
 
-    run_fft<R, L, GB, T, N, -1, PS>(s, tw, LdsLoad<R, GB, PS>{s}, LdsStore<R, GB, PS>{s},
-                                    FwdRadices<L, RMax<R>::value>{});
     // grid-forcing passes: a line with a zero grid row and no spread entries has a
     // zero spectrum; it is flagged 0 for the column passes, which read it as zero,
-    // and not stored
-    if (a.lnz && threadIdx.x < GB) {
-        const int l = threadIdx.x, g = l % G;
-        const int line = lines_s[g], r = rhs_s[l / G];
-        const int nz = nzl[l] | (a.dip.q && rs[0][g + 1] > rs[0][g]) | (a.mono.q && rs[1][g + 1] > rs[1][g]);
-        nzl[l] = nz;
-        if (line >= 0 && r >= 0) a.lnz[(size_t)r * a.lnz_rhs + line] = (uint8_t)nz;
+    // and not stored; a block all of whose lines are zero skips its transform
+    if (a.lnz) {
+        int nz = 0;
+        if (threadIdx.x < GB) {
+            const int l = threadIdx.x, g = l % G;
+            const int line = lines_s[g], r = rhs_s[l / G];
+            nz = nzl[l] | (a.dip.q && rs[0][g + 1] > rs[0][g]) | (a.mono.q && rs[1][g + 1] > rs[1][g]);
+            nzl[l] = nz;
+            if (line >= 0 && r >= 0) a.lnz[(size_t)r * a.lnz_rhs + line] = (uint8_t)nz;
+        }
+        if (!__syncthreads_or(nz)) return;
     }
+    run_fft<R, L, GB, T, N, -1, PS>(s, tw, LdsLoad<R, GB, PS>{s}, LdsStore<R, GB, PS>{s},
+                                    FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     // split step: X[k] = (Z_k + conj Z_{L-k})/2 - i W_N^k (Z_k - conj Z_{L-k})/2, k = 0..L,
