@@ -310,28 +310,47 @@ __device__ __forceinline__ void reg_dft(cplx<R>* v) {
 }
 
 // ------------------------------------------------------------------ stages
-// LDS row of element i with one padding row after every 2^PS rows (PS = 0: none).
+// LDS layouts of a transform's rows: idx(i, c) is the element index of column c
+// (one of C) of row i.
+//
+// PadRows: row-major with one padding row after every 2^PS rows (PS = 0: none).
 // The first stage of a transform writes rows RAD apart; with RAD = 2^PS the
 // padding moves consecutive butterflies' rows to different LDS banks.
-template <int PS>
-__device__ __forceinline__ constexpr int lds_row(int i) {
-    if constexpr (PS == 0) return i;
-    else return i + (i >> PS);
-}
-template <int L, int PS>
-struct PaddedRows { static constexpr int value = PS == 0 ? L : L + ((L - 1) >> PS) + 1; };
+template <int C, int PS = 0>
+struct PadRows {
+    static constexpr int rows(int L) { return PS == 0 ? L : L + ((L - 1) >> PS) + 1; }
+    __device__ __forceinline__ static constexpr int idx(int i, int c) {
+        if constexpr (PS == 0) return i * C + c;
+        else return (i + (i >> PS)) * C + c;
+    }
+};
+// XorRows: row-major and unpadded, column c of row i held at column c ^ g(i), where
+// g(i) is the XOR of M_b over the set bits b of i (every M_b < C, so a row keeps
+// its C slots).  Rows that one instruction touches in the same column then sit in
+// different banks.
+template <int C, int M0, int M1, int M2, int M3, int M4>
+struct XorRows {
+    static constexpr int rows(int L) { return L; }
+    __device__ __forceinline__ static constexpr int g(int i) {
+        return ((i & 1) ? M0 : 0) ^ ((i & 2) ? M1 : 0) ^ ((i & 4) ? M2 : 0) ^ ((i & 8) ? M3 : 0) ^
+               ((i & 16) ? M4 : 0);
+    }
+    __device__ __forceinline__ static constexpr int idx(int i, int c) { return i * C + (c ^ g(i)); }
+};
 
-// LDS functors (C elements per row)
-template <typename R, int C, int PS = 0>
+// LDS functors over a layout
+template <typename R, class LAY>
 struct LdsLoad {
     const cplx<R>* s;
-    __device__ __forceinline__ cplx<R> operator()(int i, int c) const { return s[lds_row<PS>(i) * C + c]; }
+    __device__ __forceinline__ cplx<R> operator()(int i, int c) const { return s[LAY::idx(i, c)]; }
 };
-template <typename R, int C, int PS = 0>
+template <typename R, class LAY>
 struct LdsStore {
     cplx<R>* s;
-    __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[lds_row<PS>(i) * C + c] = v; }
+    __device__ __forceinline__ void operator()(int i, int c, cplx<R> v) const { s[LAY::idx(i, c)] = v; }
 };
+
+constexpr bool is_pow2(int a) { return a > 0 && (a & (a - 1)) == 0; }
 
 // Every stage hands output slot k = b * RAD + r of a thread (its b-th butterfly,
 // r-th output) to the store functor through store_out; a functor that needs the
@@ -348,8 +367,12 @@ constexpr int last_radix() {
     return make_plan(L, RMAX).r[make_plan(L, RMAX).n - 1];
 }
 
-// One stage: TH threads cover the C*L/RAD butterflies, PER per thread.
-template <typename R, int L, int C, int TH, int NT, int SIGN, int PS, int NS, int RAD, int... REST, class TW,
+// One stage: TH threads cover the C*L/RAD butterflies, PER per thread.  A thread's
+// rows are j + r NB (loads, j < NB) and base + r NS (stores, base % NS < NS and
+// base a multiple of NS RAD above that); with power-of-two sizes the two terms
+// share no bits and the sum is written as an OR, so that a layout's function of
+// the row bits splits into a per-butterfly part and a per-r constant.
+template <typename R, int L, int C, int TH, int NT, int SIGN, class LAY, int NS, int RAD, int... REST, class TW,
           class LD, class ST>
 __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST st) {
     constexpr int NB = L / RAD;
@@ -362,7 +385,7 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST s
         if (TOT % TH == 0 || id < TOT) {
             const int c = id % C, j = id / C;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) v[b][r] = ld(j + r * NB, c);
+            for (int r = 0; r < RAD; ++r) v[b][r] = ld(is_pow2(NB) ? (j | (r * NB)) : (j + r * NB), c);
             if constexpr (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
@@ -380,7 +403,9 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST s
                 const int c = id % C, j = id / C;
                 const int base = (j / NS) * NS * RAD + (j % NS);
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) store_out(out, base + r * NS, c, v[b][r], b * RAD + r);
+                for (int r = 0; r < RAD; ++r)
+                    store_out(out, is_pow2(NS) && is_pow2(RAD) ? (base | (r * NS)) : (base + r * NS), c, v[b][r],
+                              b * RAD + r);
             }
         }
     };
@@ -389,17 +414,18 @@ __device__ __forceinline__ void run_stages(cplx<R>* s, const TW& tw, LD ld, ST s
         emit(st);
     } else {
         __syncthreads();  // every input of this stage has been read
-        emit(LdsStore<R, C, PS>{s});
+        emit(LdsStore<R, LAY>{s});
         __syncthreads();
-        run_stages<R, L, C, TH, NT, SIGN, PS, NS * RAD, REST...>(s, tw, LdsLoad<R, C, PS>{s}, st);
+        run_stages<R, L, C, TH, NT, SIGN, LAY, NS * RAD, REST...>(s, tw, LdsLoad<R, LAY>{s}, st);
     }
 }
 
-// PS: padding of the intermediate LDS rows (lds_row); the caller's functors use
-// the same layout where they touch those rows.
-template <typename R, int L, int C, int TH, int NT, int SIGN, int PS = 0, class TW, class LD, class ST, int... Rs>
+// LAY: layout of the intermediate LDS rows; the caller's functors use the same
+// layout where they touch those rows.
+template <typename R, int L, int C, int TH, int NT, int SIGN, class LAY = PadRows<C>, class TW, class LD, class ST,
+          int... Rs>
 __device__ __forceinline__ void run_fft(cplx<R>* s, const TW& tw, LD ld, ST st, Radices<Rs...>) {
-    run_stages<R, L, C, TH, NT, SIGN, PS, 1, Rs...>(s, tw, ld, st);
+    run_stages<R, L, C, TH, NT, SIGN, LAY, 1, Rs...>(s, tw, ld, st);
 }
 
 // log2 of the first radix of a plan when it is a power of two >= 4, else 0

@@ -80,6 +80,52 @@ constexpr int staggered_pitch(int need, int m, int d) {
     return p;
 }
 
+// Column swizzle of the row transforms' LDS rows: XorRows generator M_b for row bit b
+// (E: complex element bytes, W: columns per row, a power of two >= 8).
+// The LDS has 64 banks of 4 bytes (S = 256 / E elements per bank row, rho = S / W
+// rows of a block per bank row) and serves one instruction in phases: 16-byte reads
+// in four phases of 16 lanes, lanes {0-3, 12-15, 20-27} and {4-11, 16-19, 28-31}
+// and the same sets plus 32; 16-byte writes in eight phases of 8 consecutive lanes;
+// 8-byte reads in two phases of 32 and 8-byte writes in four of 16.  Within a phase
+// two lanes at different addresses in one bank take a cycle each.  The accesses
+// that meet in one phase:
+//  * transform stages: consecutive lanes take consecutive columns of a row, the
+//    next row for the next W lanes;
+//  * split steps (tile order, K = 64 / E consecutive rows per column, the next
+//    columns in the next lanes): E = 16: the K = 4 rows of columns {0,3,5,6} (or
+//    {1,2,4,7}, plus 8) meet in a read phase, which needs the four rows in four
+//    cosets of that set (generators 2 and 12 of row bits 0 and 1; the read of row
+//    L - k pairs odd and even rows, so bit 3 ^ bit 2 of g is the same for all
+//    rows, and the writes of two adjacent columns need g != g' ^ 1: 2 and 12
+//    meet all three);  E = 8: the K = 8 rows of 4 adjacent columns meet in a read
+//    phase, rows of one bank half (rho = 2) or of a whole bank row, in cosets of
+//    {0, 1, 2, 3}: generators 4, 8, 16 for the row bits above those that pick the
+//    bank part;
+//  * grid rows (x consecutive in the lanes, x / 2 the row, one column): eight or
+//    more consecutive rows in one column, spread by generators that keep the
+//    cosets above (3 for E = 16; 1 and 2 for E = 8).
+constexpr int row_swizzle_gen(int E, int W, int b) {
+    const int rho = (256 / E) / W > 1 ? (256 / E) / W : 1;
+    int lr = 0;
+    while ((1 << lr) < rho) ++lr;
+    if (E == 16) {
+        const int g1[5] = {2, 12, 3, 0, 0};  // one block row per bank row (or more)
+        const int g2[5] = {0, 2, 3, 0, 0};   // two block rows per bank row
+        const int m = rho == 1 ? g1[b] : rho == 2 ? g2[b] : 0;
+        return m < W ? m : 0;
+    }
+    if (b < 3) {
+        if (b < lr) return 0;
+        const int m = 4 << (b - lr);
+        return m < W ? m : 0;
+    }
+    const int m = b == 3 ? 1 : 2;
+    return m < W ? m : 0;
+}
+template <int E, int W>
+using RowSwizzle = XorRows<W, row_swizzle_gen(E, W, 0), row_swizzle_gen(E, W, 1), row_swizzle_gen(E, W, 2),
+                           row_swizzle_gen(E, W, 3), row_swizzle_gen(E, W, 4)>;
+
 // Row passes: a block transforms G lines of each of RB right-hand sides (GB lines
 // in all); the right-hand sides of a block share the spread and interpolation tables.
 // Variants V (chosen per configuration by the autotuner): RB = 1, 2, 4 with as
@@ -99,16 +145,25 @@ struct RowCfg {
                                              : imax(1, imin(64, IBDL_ROW_ELEMS / L) / RB);
     static constexpr int GB = G * RB;                                         // lines per block
     static constexpr int T = imax(kRowVarG[V] > 0 ? 64 : 256, fft_threads<L, GB, RMax<R>::value>());
-    // LDS rows of the block's lines narrower than the 64 four-byte banks: pad the
-    // transform's rows (lds_row) and stagger the row-inverse input lines (pitch XP)
-    // so that one half-wave's accesses spread over distinct banks
+    // LDS rows of the block's lines (row k holds element k of every line):
+    // power-of-two sizes with at least 8 lines: column-swizzled rows (RowSwizzle),
+    // the inverse's input rows X[0..L] in the same layout (SWZ);
+    // else rows narrower than the 64 four-byte banks: padded rows (PadRows) and the
+    // row-inverse input lines staggered (line-major, pitch XP), so that one
+    // half-wave's accesses spread over distinct banks
+    static constexpr bool SWZ = is_pow2(GB) && GB >= 8 && is_pow2(L);
     static constexpr bool NARROW = GB * 2 * (int)sizeof(R) < 256;
-    static constexpr int PS = NARROW ? first_radix_shift<L, RMax<R>::value>() : 0;
-    static constexpr int ROWS = PaddedRows<L, PS>::value;
+    static constexpr int PS = !SWZ && NARROW ? first_radix_shift<L, RMax<R>::value>() : 0;
+    using LAY = std::conditional_t<SWZ, RowSwizzle<2 * (int)sizeof(R), GB>, PadRows<GB, PS>>;
+    static constexpr int ROWS = LAY::rows(L);
     // lanes served per LDS cycle: 256 bytes of elements; consecutive lines start
     // (that many lanes / GB) elements apart in the banks
     static constexpr int XP =
         NARROW && GB > 1 ? staggered_pitch(L + 1, 128 / (int)sizeof(R), 128 / (int)sizeof(R) / GB) : L + 1;
+    // element X[k] of block line l of the inverse's input, and the elements its
+    // block holds in LDS (input rows and transform rows share the storage)
+    __device__ __forceinline__ static int xidx(int k, int l) { return SWZ ? LAY::idx(k, l) : l * XP + k; }
+    static constexpr int SIN = SWZ ? (L + 1) * GB : imax(XP, ROWS) * GB;
 };
 template <typename R, int N>
 struct ColCfg {
@@ -314,7 +369,7 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs<R> a0, Jobs<PackArgs<R>> 
 // the entries of a node are loaded once for all of them.  Each node is written
 // by exactly one thread, its entries summed in their stored order.  la[g] is the
 // first active node of line g and rs the prefix sums of the lines' node counts.
-template <typename R, int N, int G, int RB, int T, int PS>
+template <typename R, int N, int G, int RB, int T, class LAY>
 __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it, const int* la, const int* rs,
                                              const int* rhs_s) {
     constexpr int GB = G * RB;
@@ -369,7 +424,7 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc.add(ww[u], qq[u]);
         }
-        R& node = sr[2 * (lds_row<PS>(x >> 1) * GB + rr * G + g) + (x & 1)];
+        R& node = sr[2 * LAY::idx(x >> 1, rr * G + g) + (x & 1)];
         node = fmac((R)c.coef, acc.value(), node);
     }
     __syncthreads();
@@ -382,7 +437,8 @@ __device__ __forceinline__ void spread_phase(R* sr, const CsrView<R>& c, int it,
 template <typename R, int N, int V>
 __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int it) {
     using CF = RowCfg<R, N, V>;
-    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS;
+    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
+    using LAY = typename CF::LAY;
     __shared__ cplx<R> s[CF::ROWS * GB];
     __shared__ int rs[2][G + 1], la[2][G];
     __shared__ int lines_s[G], rhs_s[RB];
@@ -450,14 +506,14 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
             const int id = threadIdx.x + u * T;
             const int l = id / N, x = id % N;
             if (id < N * GB) {
-                sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)] = (R)(a.cg * v[u]);
+                sr[2 * LAY::idx(x >> 1, l) + (x & 1)] = (R)(a.cg * v[u]);
                 if (v[u] != 0.0) nzl[l] = 1;  // every writer stores the same value
             }
         }
     }
     __syncthreads();
-    if (a.dip.q) spread_phase<R, N, G, RB, T, PS>(sr, a.dip, it, la[0], rs[0], rhs_s);
-    if (a.mono.q) spread_phase<R, N, G, RB, T, PS>(sr, a.mono, it, la[1], rs[1], rhs_s);
+    if (a.dip.q) spread_phase<R, N, G, RB, T, LAY>(sr, a.dip, it, la[0], rs[0], rhs_s);
+    if (a.mono.q) spread_phase<R, N, G, RB, T, LAY>(sr, a.mono, it, la[1], rs[1], rhs_s);
 
     // grid-forcing passes: a line with a zero grid row and no spread entries has a
     // zero spectrum; it is flagged 0 for the column passes, which read it as zero,
@@ -473,7 +529,7 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         }
         if (!__syncthreads_or(nz)) return;
     }
-    run_fft<R, L, GB, T, N, -1, PS>(s, tw, LdsLoad<R, GB, PS>{s}, LdsStore<R, GB, PS>{s},
+    run_fft<R, L, GB, T, N, -1, LAY>(s, tw, LdsLoad<R, LAY>{s}, LdsStore<R, LAY>{s},
                                     FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
@@ -488,8 +544,8 @@ __device__ __forceinline__ void row_fwd_body(const RowFwdArgs<R>& a, int lb, int
         const int line = lines_s[l % G];
         const int r = rhs_s[l / G];
         if (k > L || line < 0 || r < 0 || (a.lnz && !nzl[l])) continue;
-        const cplx<R> zk = s[lds_row<PS>(k % L) * GB + l];
-        const cplx<R> zm = s[lds_row<PS>((L - k) % L) * GB + l];
+        const cplx<R> zk = s[LAY::idx(k % L, l)];
+        const cplx<R> zm = s[LAY::idx((L - k) % L, l)];
         const cplx<R> e = cscale(cadd(zk, cconj(zm)), R(0.5));
         const cplx<R> d = cscale(csub(zk, cconj(zm)), R(0.5));
         a.spec[(size_t)r * a.spec_stride + TL::idx(line, k)] = cadd(e, cmul(tw.get(k), cmul_si<-1>(d)));
@@ -700,7 +756,7 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
                 const SymStore<R, 1> sym1{s, srow, scol, a.norm};
                 run_fft<R, N, 1, T, N, -1>(s, tw, ld1, sym1, FwdRadices<N, RM>{});
                 __syncthreads();
-                run_fft<R, N, 1, T, N, +1>(s, tw, LdsLoad<R, 1>{s}, st1, RevRadices<N, RM>{});
+                run_fft<R, N, 1, T, N, +1>(s, tw, LdsLoad<R, PadRows<1>>{s}, st1, RevRadices<N, RM>{});
             }
             return;
         }
@@ -715,12 +771,12 @@ __device__ __forceinline__ void col_body(const ColArgs<R>& a, int lb, int) {
         static_assert(std::is_same<R, float>::value, "symbol table is FP32");
         run_fft<R, N, LC, T, N, -1>(s, tw, ld, SymTabStore<R, LC>{s, sigv}, FwdRadices<N, RM>{});
         __syncthreads();
-        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, PadRows<LC>>{s}, st, RevRadices<N, RM>{});
     } else {
         const SymStore<R, LC> sym{s, srow, scol, a.norm};
         run_fft<R, N, LC, T, N, -1>(s, tw, ld, sym, FwdRadices<N, RM>{});
         __syncthreads();
-        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, LC>{s}, st, RevRadices<N, RM>{});
+        run_fft<R, N, LC, T, N, +1>(s, tw, LdsLoad<R, PadRows<LC>>{s}, st, RevRadices<N, RM>{});
     }
 }
 template <typename R, int N, int MODE, int K, bool MULTI>
@@ -734,11 +790,11 @@ __global__ __launch_bounds__((ColK<R, N, K>::T)) void k_col(ColArgs<R> a0, Jobs<
 template <typename R, int N, int OUT, int V>
 __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int) {
     using CF = RowCfg<R, N, V>;
-    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T, PS = CF::PS, XP = CF::XP;
-    // the block's spectrum rows X[0..L] (line-major with pitch XP, xs) are only read
-    // by the first stage of the inverse transform, whose outputs (s) therefore share
-    // the storage
-    __shared__ cplx<R> s[imax(XP, CF::ROWS) * GB];
+    constexpr int RB = CF::RB, L = CF::L, G = CF::G, GB = CF::GB, T = CF::T;
+    using LAY = typename CF::LAY;
+    // the block's spectrum rows X[0..L] (xs, at CF::xidx) are only read by the first
+    // stage of the inverse transform, whose outputs (s) therefore share the storage
+    __shared__ cplx<R> s[CF::SIN];
     cplx<R>* xs = s;
     using TWL = TwLds<R, N, (N * 2 * (int)sizeof(R) <= IBDL_TWL_FULL_BYTES)>;
     __shared__ cplx<R> twl[TWL::SIZE];
@@ -789,7 +845,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             const int t = id / (GB * C), rem = id % (GB * C);
             const int l = rem / C, c = rem % C;
             const int k = t * C + c;
-            if (id < TOT && k <= L) xs[l * XP + k] = v[u];
+            if (id < TOT && k <= L) xs[CF::xidx(k, l)] = v[u];
         }
     }
     if constexpr (OUT != 1) {
@@ -857,13 +913,13 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
     }
     // inverse split step: Z_k = (X_k + conj X_{L-k})/2 + i W_N^-k (X_k - conj X_{L-k})/2
     auto split = [&](int k, int l) -> cplx<R> {
-        const cplx<R> xk = xs[l * XP + k];
-        const cplx<R> xm = xs[l * XP + L - k];
+        const cplx<R> xk = xs[CF::xidx(k, l)];
+        const cplx<R> xm = xs[CF::xidx(L - k, l)];
         const cplx<R> e = cscale(cadd(xk, cconj(xm)), R(0.5));
         const cplx<R> d = cscale(csub(xk, cconj(xm)), R(0.5));
         return cadd(e, cmul_si<1>(cmul(cconj(tw.get(k)), d)));
     };
-    run_fft<R, L, GB, T, N, +1, PS>(s, tw, split, LdsStore<R, GB, PS>{s}, FwdRadices<L, RMax<R>::value>{});
+    run_fft<R, L, GB, T, N, +1, LAY>(s, tw, split, LdsStore<R, LAY>{s}, FwdRadices<L, RMax<R>::value>{});
     __syncthreads();
 
     if constexpr (OUT != 0) {
@@ -873,7 +929,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
             const int r = rhs_s[l / G];
             if (line >= 0 && r >= 0)
                 a.u[(size_t)r * a.u_stride + (size_t)line * N + x] =
-                    (double)sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)];
+                    (double)sr[2 * LAY::idx(x >> 1, l) + (x & 1)];
         }
     }
     if constexpr (OUT != 1) {
@@ -893,7 +949,7 @@ __device__ __forceinline__ void row_inv_body(const RowInvArgs<R>& a, int lb, int
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int x = (cx - 1 + t + N) % N;
-                acc = fmac(tp[t], sr[2 * (lds_row<PS>(x >> 1) * GB + l) + (x & 1)], acc);
+                acc = fmac(tp[t], sr[2 * LAY::idx(x >> 1, l) + (x & 1)], acc);
             }
             acc *= tp[4 + oy];
             int o = oy;
