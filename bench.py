@@ -221,6 +221,30 @@ def host_cores():
     return max(1, min(CPU_WORKERS_MAX, n))
 
 
+def copy_rate_gbs(mib=1024, reps=5):
+    """Device-to-device copy rate of the card: read plus write bytes over the best of
+    `reps` timed copies of `mib` MiB (torch's copy kernel, events on its stream).
+    It is the streaming rate a memory-bound kernel reaches in practice; `peak`
+    stays the published figure."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (best * 1e-3) / 1e9
+
+
 def batch_stage_bytes(metas):
     """Algorithmic bytes of one batched mixed apply, per stage, summed over instances."""
     tot = {}
@@ -290,6 +314,7 @@ def run_batch(args):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(sb.get(dom, 0)), "ms_per_launch": round(per_apply[dom], 5),
             "note": "stage summed over the (grid size) groups of one batched apply",
+            "copy_GBps": round(copy_rate_gbs(), 1),
             "operator": {"achieved": round(op_gbs, 1), "frac": round(op_gbs / HBM_PEAK_GBS, 4),
                          "bytes_per_apply": int(op_bytes), "ms_per_apply": round(apply_ms, 5)}}
 
@@ -555,11 +580,14 @@ def main():
         opb = operator_bytes(dim, n, m, prec) * nrhs
         op_gbs = opb / (apply_ms * 1e-3) / 1e9
         kname = stage_kernel(dom, dim, n, prec, rstats["z_rows"])
+        traffic = read_traffic(args.workload, nrhs, kname)
         return {
             "bound": "hbm", "kernel": kname, "stage": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": read_traffic(args.workload, nrhs, kname),
+            "traffic": traffic,
             "bytes_per_launch": int(bpl), "ms_per_launch": round(ms[dom], 5), "launches": ROOF_APPLIES,
+            "traffic_GBps": None if traffic is None else round(traffic / (ms[dom] * 1e-3) / 1e9, 1),
+            "copy_GBps": copy_gbs,
             "touched_bytes_per_launch": int(touched[dom]),
             "operator": {"achieved": round(op_gbs, 1), "frac": round(op_gbs / HBM_PEAK_GBS, 4),
                          "bytes_per_apply": int(opb), "ms_per_apply": round(apply_ms, 5),
@@ -571,6 +599,7 @@ def main():
 
     fp64 = run(ibdl.FP64, args.steps, args.warmup)
     mixed = run(ibdl.MIXED, args.steps, args.warmup)
+    copy_gbs = round(copy_rate_gbs(), 1)
     roof64 = roofline(0)
     roof32 = roofline(1)
 

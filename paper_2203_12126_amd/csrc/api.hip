@@ -232,9 +232,9 @@ void apply_operator(ibdl_plan p, int nrhs, const double* q, size_t qstride, doub
     in.q_dip = q;
     in.c_dip = 1.0;
     in.q_stride = qstride;
-    // FP32 passes of several right-hand sides over a large spread read the strengths
-    // packed four right-hand sides to a segment (the same FP32 values: results do not
-    // change)
+    // passes of several right-hand sides over a large spread read the strengths
+    // packed four right-hand sides to a segment in the pass's precision (the values
+    // the spread rounds them to: results do not change)
     in.pack_q = pack_q;
     PipeOut o;
     o.out = out;
@@ -412,8 +412,8 @@ size_t ibdl_plan_footprint(const ibdl_desc* d, int32_t nrhs, int32_t restart) {
     size_t b = 0;
     // workspace, FP64-sized: half spectra and gather partial sums
     b += R * nlines * P * 16 + R * M * gpp * 8 + R * (nlines + n);
-    // packed strengths in groups of four right-hand sides (FP32 for mixed plans)
-    b += (R + 3) / 4 * 4 * M * (d->prec == IBDL_PREC_MIXED ? 4 : 8);
+    // packed strengths in groups of four right-hand sides (FP64-sized)
+    b += (R + 3) / 4 * 4 * M * 8;
     // sorted geometry: key, perm, skey, invperm, cell, coordinates, normals, weights, taps (FP64 + FP32)
     b += M * (16 + 12 + 24 + 24 + 8 + 96 + 48);
     // spread structures (entry: point as caller index and sorted position, FP64 and
@@ -610,6 +610,7 @@ ibdl_status ibdl_eval_grid(ibdl_plan p, int32_t nrhs, const double* sol, const d
     PipeIn in;
     in.q_dip = sol;
     in.c_dip = -1.0;
+    in.pack_q = true;
     if (p->bc == IBDL_NEUMANN) {
         in.q_mono = vb;
         in.c_mono = -1.0;

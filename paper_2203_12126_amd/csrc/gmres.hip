@@ -653,6 +653,7 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64,
             PipeIn pi;
             pi.q_dip = x + off;
             pi.c_dip = -1.0;
+            pi.pack_q = true;
             if (in.p->bc == IBDL_NEUMANN) {
                 pi.q_mono = io_.data[i];
                 pi.c_mono = -1.0;
@@ -677,6 +678,7 @@ void SolveTask::residual(const double* b, const double* x, double* r, bool fp64,
         PipeIn pi;
         pi.q_dip = x + off;
         pi.c_dip = 1.0;
+        pi.pack_q = true;
         if (in.p->form == IBDL_FORM_COMPLETED) {
             // the completion's single layer: A x = -S* D0^-1 (S~ + eta S) x + x/2
             pi.q_mono = x + off;
@@ -1007,6 +1009,7 @@ void SolveTask::output() {
             PipeIn pi;
             pi.q_dip = k.x + k.hxoff[in.r0];
             pi.c_dip = -1.0;
+            pi.pack_q = true;
             if (in.p->bc == IBDL_NEUMANN) {
                 pi.q_mono = io_.vb[i];
                 pi.c_mono = -1.0;

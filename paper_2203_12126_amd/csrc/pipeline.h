@@ -1448,10 +1448,8 @@ std::unique_ptr<PreparedPass> prepare_t(const std::vector<PassJob>& jobs) {
         // made solves 2-4% slower.  FP64 (32-byte segments): sphere 256^3 spread
         // 1.03 -> 0.91 ms, star 1024^2 no gain (68.7 -> 67 us against a 4 us pack).
         constexpr int64_t kPackMinWork = sizeof(R) == 4 ? (int64_t)1 << 21 : (int64_t)1 << 24;  // entries x rhs
-        // the pass's precision must be the plan's own: ws.qf holds R values (a mixed
-        // plan's FP64 passes read q directly)
-        const bool own_prec = (sizeof(R) == 4) == (p->prec == IBDL_PREC_MIXED);
-        if (in.pack_q && in.q_dip && own_prec && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
+        // ws.qf is FP64-sized, so a mixed plan's FP64 passes pack too
+        if (in.pack_q && in.q_dip && nrhs >= 4 && p->dip.nnz * (int64_t)nrhs >= kPackMinWork) {
             if (!p->ws.qf) throw Error{IBDL_ERR_HIP, "packed strengths requested without their workspace"};
             PackArgs<R> pa{};
             pa.q = in.q_dip;

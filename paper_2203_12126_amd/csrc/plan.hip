@@ -985,9 +985,8 @@ void ensure_workspace(ibdl_plan p, int nrhs) {
     p->ws.cap_rhs = 0;
     p->ws.spec = dev_alloc(p, (size_t)nrhs * p->spec_elems * cs);
     p->ws.part = dev_alloc(p, (size_t)nrhs * p->M * p->gpp * rs);
-    // packed strengths of the plan's own precision, four right-hand sides to a segment
-    p->ws.qf = dev_alloc(p, (size_t)((nrhs + 3) / 4) * 4 * p->M *
-                                (p->prec == IBDL_PREC_MIXED ? sizeof(float) : sizeof(double)));
+    // packed strengths, four right-hand sides to a segment, in the pass's precision
+    p->ws.qf = dev_alloc(p, (size_t)((nrhs + 3) / 4) * 4 * p->M * rs);
     p->ws.dmask = reinterpret_cast<uint8_t*>(dev_alloc(p, (size_t)nrhs * ((size_t)p->nlines + p->n)));
     p->ws.cap_rhs = nrhs;
 }
