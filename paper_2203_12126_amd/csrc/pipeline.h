@@ -1111,10 +1111,21 @@ inline int col_tiles(int n) {
     }
     return 1;
 }
-// y-rows per block of the 3-D z transform: up to 4 while the block's lines fit 128 KiB of LDS
+// y-rows per block of the 3-D z transform while the block's lines fit 128 KiB of LDS:
+// up to 4 in FP64 and 2 in FP32.  Measured on the sphere 256^3 at 32 rhs: FP32 2 rows
+// (32 KiB, four blocks per CU) 0.72 -> 0.68 ms against 4; FP64 2 rows 1.26 -> 1.35 ms
+// (its 154 VGPRs hold it at two waves per SIMD either way)
+#ifndef IBDL_ZROWS_MAX_F64
+#define IBDL_ZROWS_MAX_F64 4
+#endif
+#ifndef IBDL_ZROWS_MAX_F32
+#define IBDL_ZROWS_MAX_F32 2
+#endif
 template <typename R, int N>
 struct ZRows {
-    static constexpr int value = imax(1, imin(4, 131072 / (N * ColCfg<R, N>::C * 2 * (int)sizeof(R))));
+    static constexpr int value =
+        imax(1, imin(sizeof(R) == 4 ? IBDL_ZROWS_MAX_F32 : IBDL_ZROWS_MAX_F64,
+                     131072 / (N * ColCfg<R, N>::C * 2 * (int)sizeof(R))));
 };
 template <typename R>
 inline int z_rows(int n) {

@@ -70,11 +70,14 @@ def test_timing_on_a_pass_that_tunes():
     pl.close()
 
 
+@pytest.mark.parametrize("n", [192, 256])
 @pytest.mark.parametrize("prec", [ibdl.MIXED, ibdl.FP64])
-def test_every_row_shape_bit_identical(prec):
+def test_every_row_shape_bit_identical(prec, n):
     """Each of the four row-block shapes, forced in turn, gives the same apply,
-    grid solution and solve, bit for bit."""
-    p = W.config_star1024(m=1500, n=192, alpha=2.0, seed=12)
+    grid solution and solve, bit for bit.  At n = 256 the blocks of 16 lines keep
+    their LDS rows column-swizzled and the one-line shape keeps them plain; at
+    n = 192 (21, 20 and 20 lines) all shapes use padded rows."""
+    p = W.config_star1024(m=1500, n=n, alpha=2.0, seed=12)
     rng = np.random.default_rng(8)
     q = torch.as_tensor(rng.standard_normal((3, p.geom.m)), device="cuda")
     g = torch.as_tensor(np.stack([p.g_tilde.ravel()] * 3), device="cuda")
